@@ -1,0 +1,231 @@
+/*
+ * chees_smc.h -- C ABI of libchees_smc.so: a sequential Monte Carlo (SMC)
+ * sampler whose proposal is a ChEES-HMC trajectory, for Bayesian logistic
+ * regression posteriors, on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Millard, Murphy, Frisch, Maskell, "Incorporating the ChEES Criterion
+ * into Sequential Monte Carlo Samplers" (arXiv 2504.02627).
+ *   - target pi(theta) = p(y | X, theta) q0(theta), theta in R^d      (Sec. II)
+ *   - likelihood y_n ~ Bernoulli(sigmoid(theta^T x_n))       (Sec. IV, German Credit)
+ *   - SMC loop: normalise, ESS, resample if J_eff < J/2, move, reweight
+ *                                                            (Sec. III, Alg. smc_BNN)
+ *   - move: leapfrog with jittered length l = h L, ceil(l/eps) steps
+ *                                          (Sec. II-A, II-C, Alg. smc_ChEES)
+ *   - weight: momentum change-of-variables L-kernel, log w += -Delta H
+ *                                          (Sec. III-A, eqs. proposal_momentum,
+ *                                           l-kernel_momentum, l_weights)
+ *   - ChEES gradient, alpha-weighted, Adam on log L, moving average, freeze
+ *                                          (Sec. II-C, Alg. smc_ChEES)
+ *
+ * Memory model.  Every device buffer is caller-owned: the data X, y, the
+ * workspace (size from smc_workspace_bytes) and the HIP stream must outlive
+ * the context.  The library allocates no device memory at all; the context
+ * header is host memory released by smc_destroy.  Every call is
+ * stream-ordered and asynchronous unless it says it synchronises.
+ *
+ * Errors.  Functions return smc_status and never abort.  smc_last_error gives
+ * a message for the last failing call on a context.  A single particle whose
+ * energy is not finite is not an error: it gets alpha = 0 and log w = -inf.
+ */
+#ifndef CHEES_SMC_H
+#define CHEES_SMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SMC_OK = 0,
+  SMC_EINVAL = -1,      /* bad argument, size or call parameter            */
+  SMC_EDEVICE = -2,     /* a HIP call failed (see smc_last_error)          */
+  SMC_EDEGENERATE = -3, /* every log-weight is -inf or NaN                 */
+  SMC_ESTATE = -4,      /* calls out of order (e.g. chees_adapt before a step) */
+  SMC_ENOMEM = -5       /* workspace smaller than smc_workspace_bytes      */
+} smc_status;
+
+/* data type of X */
+enum { SMC_F32 = 0, SMC_BF16 = 1 };
+/* jitter schemes of Sec. III-B-1 */
+enum { SMC_JITTER_HALTON1D = 0, /* 1-d Halton, base 2, index (k-1) J + j      */
+       SMC_JITTER_NONE = 1,     /* h = 1                                       */
+       SMC_JITTER_HALTONND = 2  /* h_jk = phi_{P_k}(j), P_k the k-th prime     */ };
+/* resampling schemes (Sec. III) */
+enum { SMC_RESAMPLE_SYSTEMATIC = 0, SMC_RESAMPLE_MULTINOMIAL = 1 };
+/* arithmetic of the trajectory gradients */
+enum { SMC_PRECISION_F32 = 0, SMC_PRECISION_BF16 = 1 };
+/* mass matrix */
+enum { SMC_PRECOND_NONE = 0, SMC_PRECOND_DIAG = 1 };
+
+typedef struct smc_ctx smc_ctx;
+
+/* The posterior: pi(theta) = p(y | X, theta) q0(theta), q0 = N(0, prior_var I)
+ * (Sec. II problem statement; Sec. IV model).  num_posteriors independent
+ * problems may share one context (batched form); they are sampled with the
+ * same parameters and independent particle populations. */
+typedef struct {
+  int32_t num_posteriors;     /* B >= 1                                         */
+  const int32_t *n_rows;      /* host [B]: N_b >= 1 data rows                    */
+  const int32_t *dims;        /* host [B]: d_b in [1, 208] features             */
+  const void *const *X;       /* host [B] of DEVICE pointers: row-major N_b x d_b,
+                                 element type x_dtype                           */
+  const float *const *y;      /* host [B] of DEVICE pointers: N_b labels in {0,1} */
+  int32_t x_dtype;            /* SMC_F32 or SMC_BF16                            */
+  double prior_var;           /* q0 variance (the paper's N(0, I): 1.0)         */
+} smc_problem;
+
+typedef struct {
+  int32_t num_particles;      /* J per posterior, 1..65536                      */
+  int32_t max_leapfrog;       /* n_max >= 1: cap on ceil(l/eps)                 */
+  int32_t num_warmup;         /* M_warmup of Alg. smc_ChEES (>= 1)              */
+  int32_t jitter;             /* SMC_JITTER_*                                   */
+  int32_t mh_accept;          /* 0: SMC-ChEES, no accept/reject (Sec. III-A);
+                                 1: accept iff u < alpha (eq. mh_ratio_rn), and
+                                    the weight increment is 0                   */
+  int32_t resampling;         /* SMC_RESAMPLE_*                                 */
+  int32_t precision;          /* SMC_PRECISION_*                                */
+  int32_t precond;            /* SMC_PRECOND_*                                  */
+  double step_size;           /* eps_0 > 0                                      */
+  double traj_length;         /* L_0 > 0 (the paper's experiments: 5)           */
+  double ess_frac;            /* resample iff J_eff < ess_frac J (paper: 0.5)   */
+  double adam_lr, adam_b1, adam_b2, adam_eps; /* Adam on log L (ascent)         */
+  double avg_decay;           /* Lbar <- avg_decay Lbar + (1 - avg_decay) L (0.9) */
+  int32_t adapt_step_size;    /* 1: Adam on log eps toward target_accept during
+                                 warm-up (not in the paper, whose eps is fixed) */
+  double target_accept;       /* harmonic-mean acceptance target (e.g. 0.651)   */
+  uint64_t seed;              /* key of the Philox4x32-10 streams               */
+} smc_params;
+
+/* Host-supplied randomness for one smc_step (all fields nullable, DEVICE
+ * pointers).  A NULL field is drawn from the library's Philox4x32-10 streams. */
+typedef struct {
+  const float *momenta;       /* (B*J) x d_b standard normals xi, row-major per
+                                 posterior block; momentum p = xi M^{1/2}        */
+  const double *mh_uniforms;  /* B*J uniforms in [0,1) (used iff mh_accept)     */
+  const double *resample_u;   /* B values (systematic) or B*J (multinomial)     */
+} smc_inject;
+
+/* Per-iteration statistics (posterior 0 for a batched context). */
+typedef struct {
+  double ess;          /* J_eff after the move (eq. ess_smc)                   */
+  double ess_before;   /* J_eff that decided the resampling                    */
+  double mean_accept;  /* mean alpha                                           */
+  double chees;        /* 1/4 mean a_j^2: ChEES sample estimate                */
+  double chees_grad;   /* alpha-weighted gradient g_hat                        */
+  double L, eps;       /* trajectory length and step size used by this step    */
+  double log_z;        /* log-evidence estimate after this step                */
+  int32_t resampled;   /* 1 if resampling ran at the start of this step        */
+  int32_t iteration;   /* k, 1-based                                           */
+  int64_t grad_evals;  /* sum_j n_j of this step (leapfrog gradients)          */
+} smc_stats;
+
+/* Totals since smc_init, accumulated on the device (all posteriors). */
+typedef struct {
+  int64_t iterations;
+  int64_t grad_evals;  /* sum over steps and particles of n_j                  */
+  double ess_sum;      /* sum over steps and posteriors of the post-move J_eff */
+  int64_t resamples;
+} smc_counters;
+
+/* Per-particle device views of the last step.  Rows are posterior-major with
+ * a padded stride: particle j of posterior b is row b * jcap + j. */
+typedef struct {
+  const double *h;      /* jitter h_j                                          */
+  const double *l;      /* jittered length l_j = h_j L                         */
+  const int32_t *n;     /* leapfrog steps n_j                                  */
+  const double *dH;     /* energy error Delta H (+inf if not finite)           */
+  const double *alpha;  /* min(1, exp(-Delta H))                               */
+  const int32_t *ancestors; /* ancestors (index within the posterior) of the
+                               last resampling                                */
+  const float *p_final; /* momenta p' after the trajectory, (B*J) x dpad      */
+  const float *theta_prop; /* proposals theta', (B*J) x dpad                  */
+  int32_t dpad;         /* row stride (floats) of p_final and theta_prop       */
+  int32_t jcap;         /* particle rows per posterior (J padded)              */
+} smc_trace;
+
+/* Workspace size for a problem and parameters; 0 if they are invalid. */
+size_t smc_workspace_bytes(const smc_problem *prob, const smc_params *par);
+
+/* Build a context: pack X, draw or copy theta_0, evaluate log pi and its
+ * gradient at theta_0 (the gradient taken before the first leapfrog loop,
+ * Sec. V) and set log w_j = log pi(theta_0^j) - log q0(theta_0^j) - log J
+ * (eqs. init_sample, init_weights; the -log J makes sum_j w_j an evidence
+ * estimate).  theta0: nullable DEVICE (B*J) x d_b FP32; NULL draws
+ * theta_0 ~ q0 from Philox.  hip_stream: a hipStream_t (NULL = default).
+ * Does not synchronise. */
+smc_status smc_init(const smc_problem *prob, const smc_params *par, void *workspace,
+                    size_t workspace_bytes, void *hip_stream, const float *theta0,
+                    smc_ctx **out);
+
+/* One SMC iteration k (Alg. smc_BNN body): normalise and ESS (eqs.
+ * normalise_smc2, ess_smc), resample iff J_eff < ess_frac J and reset weights
+ * to 1/J (Sec. III), draw momenta, jitter h_jk and n_j = clamp(ceil(h L/eps),
+ * 1, n_max) (Alg. smc_ChEES), run the leapfrog trajectories, compute Delta H
+ * and alpha (eq. HMC_accept_reject), update log w += -Delta H (SMC-ChEES) or
+ * accept iff u < alpha (MH mode), and the ChEES statistics.  stats: nullable
+ * host pointer; non-NULL synchronises the stream and fills it. */
+smc_status smc_step(smc_ctx *ctx, const smc_inject *inject, smc_stats *stats);
+
+/* Warm-up adaptation after step k (Alg. smc_ChEES): k < M_warmup: Adam
+ * ascent on log L with g_hat (skipped when sum alpha = 0) and
+ * Lbar <- 0.9 Lbar + 0.1 L; k = M_warmup: L <- Lbar.  Runs on the device.
+ * SMC_ESTATE if no step ran since the last adaptation.  stats: as smc_step. */
+smc_status chees_adapt(smc_ctx *ctx, smc_stats *stats);
+
+/* Unconditional resampling of the current population (Sec. III), then the
+ * weights are reset to 1/J.  u: nullable DEVICE uniforms (B for systematic,
+ * B*J for multinomial); ancestors_out: nullable DEVICE B*J int32. */
+smc_status resample(smc_ctx *ctx, const double *u, int32_t *ancestors_out);
+
+/* Stateless resampling of J nonnegative weights w (DEVICE, any scale, not all
+ * zero): e_j = w_j / max w, Q_j = floor(e_j 2^40), then systematic
+ * (a_i = min{j : C_j > (i + U/2^32) T / J}, U = floor(u_0 2^32)) or multinomial
+ * (a_i = min{j : C_j > (U_i/2^32) T}) on the exact integer cumulative sum C,
+ * T = C_J.  u: DEVICE, 1 (systematic) or J (multinomial) uniforms in [0,1).
+ * ancestors: DEVICE J int32.  workspace: DEVICE, resample_workspace_bytes(J).
+ * SMC_EDEGENERATE if every weight is zero (checked after a synchronisation). */
+size_t resample_workspace_bytes(int32_t J);
+smc_status resample_indices(const double *w, int32_t J, const double *u, int32_t scheme,
+                            int32_t *ancestors, void *workspace, size_t workspace_bytes,
+                            void *hip_stream);
+
+/* log Z_hat = C + LSE(log w), C the sum of LSE(log w) over past resamplings
+ * (the standard SMC evidence estimator).  Synchronises.  log_z_host: posterior
+ * 0; per_posterior_host: nullable host [B]. */
+smc_status log_evidence(smc_ctx *ctx, double *log_z_host, double *per_posterior_host);
+
+/* Copy the state into caller DEVICE buffers (each nullable): theta (B*J) x d_b
+ * FP32, logw (B*J) FP64, logpi (B*J) FP64.  Stream-ordered. */
+smc_status smc_get_state(smc_ctx *ctx, float *theta, double *logw, double *logpi);
+
+/* Device views of the last step's per-particle quantities (see smc_trace). */
+smc_status smc_get_trace(smc_ctx *ctx, smc_trace *trace);
+
+/* Totals since init (synchronises). */
+smc_status smc_get_counters(smc_ctx *ctx, smc_counters *counters);
+
+/* Kernel timing with HIP events recorded on the context's stream around every
+ * launch of the fused leapfrog kernel and of the log-likelihood kernel.  Off by
+ * default.  smc_get_timing synchronises, returns the totals since timing was
+ * enabled (or last read) and resets them. */
+typedef struct {
+  double leapfrog_ms;          /* summed event time of the leapfrog launches   */
+  int64_t leapfrog_launches;
+  double loglik_ms;
+  int64_t loglik_launches;
+} smc_timing;
+smc_status smc_set_timing(smc_ctx *ctx, int32_t enable);
+smc_status smc_get_timing(smc_ctx *ctx, smc_timing *out);
+
+/* Set the adapted parameters L and eps (stream-ordered; host values). */
+smc_status smc_set_params(smc_ctx *ctx, double L, double eps);
+
+void smc_destroy(smc_ctx *ctx);
+const char *smc_last_error(const smc_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CHEES_SMC_H */

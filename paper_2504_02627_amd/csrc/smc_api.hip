@@ -1,0 +1,572 @@
+// Host side of libchees_smc.so: argument checks, workspace layout, and the
+// order of kernel launches for each ABI call (include/chees_smc.h).
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "chees_smc.h"
+#include "smc_internal.h"
+
+using namespace smc;
+
+struct smc_ctx {
+  Dev D;
+  hipStream_t st = nullptr;
+  std::vector<HostPost> hp;
+  std::vector<Post> posts;
+  std::vector<PState> ps_host;
+  std::vector<int> c2s;        // distinct GEMM2 tile counts among the posteriors
+  std::vector<int4> ll_items;
+  std::vector<int> primes;
+  std::vector<float> minv;
+  int stepped = 0;             // a step ran since the last adaptation
+  int steps = 0;
+  std::string err;
+  // event timing of the hot kernels
+  int timing = 0;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<std::pair<int, size_t>> ev_marks;  // (kind, index of the start event)
+  ~smc_ctx() {
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+  }
+};
+
+namespace {
+
+struct Layout {
+  int B = 0, J = 0, Jcap = 0, DS = 0, nmax = 0;
+  int lf_target = 0, lf_grid = 0, ll_smax = 0, ll_nitems = 0, col_chunks = 0;
+  std::vector<HostPost> hp;
+  std::vector<Post> posts;
+  std::vector<int4> items;
+  size_t total = 0;
+  // byte offsets
+  size_t o_posts, o_ps, o_xa, o_xb, o_yp, o_theta, o_grad, o_theta_t, o_p_t, o_grad_t;
+  size_t o_logpi, o_logpi_t, o_logw, o_h, o_l, o_H0, o_dH, o_alpha, o_ca, o_cg;
+  size_t o_n, o_perm, o_hist, o_active, o_anc, o_acc, o_cdf, o_gpart, o_tilecnt, o_llpart;
+  size_t o_items, o_colpart, o_means, o_minv, o_primes;
+};
+
+size_t take(size_t &cur, size_t bytes) {
+  const size_t o = (cur + 255) & ~(size_t)255;
+  cur = o + bytes;
+  return o;
+}
+
+const char *check(const smc_problem *pr, const smc_params *pa) {
+  if (!pr || !pa) return "null problem or params";
+  if (pr->num_posteriors < 1) return "num_posteriors must be >= 1";
+  if (!pr->n_rows || !pr->dims || !pr->X || !pr->y) return "null problem arrays";
+  for (int b = 0; b < pr->num_posteriors; ++b) {
+    if (pr->n_rows[b] < 1) return "n_rows must be >= 1";
+    if (pr->dims[b] < 1 || pr->dims[b] > 16 * MAX_C2) return "dims must be in [1, 208]";
+    if (!pr->X[b] || !pr->y[b]) return "null X or y";
+  }
+  if (pr->x_dtype != SMC_F32 && pr->x_dtype != SMC_BF16) return "x_dtype";
+  if (!(pr->prior_var > 0.0)) return "prior_var must be > 0";
+  if (pa->num_particles < 1 || pa->num_particles > 65536) return "num_particles in [1, 65536]";
+  if (pa->max_leapfrog < 1 || pa->max_leapfrog > MAX_NMAX) return "max_leapfrog in [1, 4096]";
+  if (pa->num_warmup < 1) return "num_warmup must be >= 1";
+  if (pa->jitter < 0 || pa->jitter > 2) return "jitter";
+  if (pa->resampling < 0 || pa->resampling > 1) return "resampling";
+  if (pa->precision != SMC_PRECISION_F32) return "precision: only SMC_PRECISION_F32";
+  if (pa->precond < 0 || pa->precond > 1) return "precond";
+  if (!(pa->step_size > 0.0) || !(pa->traj_length > 0.0)) return "step_size, traj_length > 0";
+  if (!(pa->ess_frac >= 0.0 && pa->ess_frac <= 1.0)) return "ess_frac in [0, 1]";
+  if (!(pa->adam_lr >= 0.0) || !(pa->adam_b1 >= 0.0 && pa->adam_b1 < 1.0) ||
+      !(pa->adam_b2 >= 0.0 && pa->adam_b2 < 1.0) || !(pa->adam_eps > 0.0))
+    return "Adam hyperparameters";
+  if (!(pa->avg_decay >= 0.0 && pa->avg_decay <= 1.0)) return "avg_decay in [0, 1]";
+  return nullptr;
+}
+
+void plan(const smc_problem *pr, const smc_params *pa, Layout &L) {
+  const int B = pr->num_posteriors;
+  L.B = B;
+  L.J = pa->num_particles;
+  L.Jcap = (L.J + TJ - 1) / TJ * TJ;
+  L.nmax = pa->max_leapfrog;
+  int maxc2 = 1;
+  long long xoff = 0, yoff = 0, uoff = 0;
+  L.hp.resize(B);
+  L.posts.resize(B);
+  for (int b = 0; b < B; ++b) {
+    HostPost &h = L.hp[b];
+    h.N = pr->n_rows[b];
+    h.d = pr->dims[b];
+    h.C1 = (h.d + 3) / 4;
+    h.C2 = (h.d + 15) / 16;
+    h.NT = (h.N + 15) / 16;
+    h.xa = h.xb = xoff;
+    h.yo = yoff;
+    xoff += (long long)h.NT * 64 * 4 * h.C2;
+    yoff += 16LL * h.NT;
+    maxc2 = std::max(maxc2, h.C2);
+    Post &p = L.posts[b];
+    memset(&p, 0, sizeof(p));
+    p.N = h.N;
+    p.d = h.d;
+    p.C1 = h.C1;
+    p.C2 = h.C2;
+    p.NT = h.NT;
+    p.row0 = b * L.Jcap;
+    p.xa = p.xb = h.xa;
+    p.yo = h.yo;
+    p.uoff = uoff;
+    uoff += (long long)L.J * h.d;
+  }
+  L.DS = 16 * maxc2;
+  // leapfrog launches: about two work groups per compute unit
+  L.lf_target = 512;
+  const int ntile = L.Jcap / TJ;
+  L.lf_grid = L.lf_target + B * ntile;
+  // log-likelihood pass: every tile, static splits
+  long long U = 0;
+  for (int b = 0; b < B; ++b) U += (long long)ntile * L.hp[b].NT;
+  const long long chunk = std::max(1LL, (U + L.lf_target - 1) / L.lf_target);
+  L.items.clear();
+  L.ll_smax = 1;
+  for (int b = 0; b < B; ++b) {
+    long long S = (L.hp[b].NT + chunk - 1) / chunk;
+    S = std::max(1LL, std::min<long long>(S, L.hp[b].NT));
+    L.posts[b].ll_splits = (int)S;
+    L.posts[b].ll_base = (int)L.items.size();
+    L.ll_smax = std::max(L.ll_smax, (int)S);
+    for (int t = 0; t < ntile; ++t)
+      for (int s = 0; s < S; ++s) L.items.push_back(make_int4(b, t, s, 0));
+  }
+  L.ll_nitems = (int)L.items.size();
+  L.col_chunks = std::max(1, std::min(64, (L.J + 127) / 128));
+
+  const size_t rows = (size_t)B * L.Jcap, st = rows * L.DS * sizeof(float);
+  size_t c = 0;
+  L.o_posts = take(c, B * sizeof(Post));
+  L.o_ps = take(c, B * sizeof(PState));
+  L.o_xa = take(c, xoff * sizeof(float));
+  L.o_xb = take(c, xoff * sizeof(float));
+  L.o_yp = take(c, yoff * sizeof(float));
+  L.o_theta = take(c, st);
+  L.o_grad = take(c, st);
+  L.o_theta_t = take(c, st);
+  L.o_p_t = take(c, st);
+  L.o_grad_t = take(c, st);
+  L.o_logpi = take(c, rows * 8);
+  L.o_logpi_t = take(c, rows * 8);
+  L.o_logw = take(c, rows * 8);
+  L.o_h = take(c, rows * 8);
+  L.o_l = take(c, rows * 8);
+  L.o_H0 = take(c, rows * 8);
+  L.o_dH = take(c, rows * 8);
+  L.o_alpha = take(c, rows * 8);
+  L.o_ca = take(c, rows * 8);
+  L.o_cg = take(c, rows * 8);
+  L.o_n = take(c, rows * 4);
+  L.o_perm = take(c, rows * 4);
+  L.o_hist = take(c, (size_t)B * (L.nmax + 1) * 4);
+  L.o_active = take(c, (size_t)B * (L.nmax + 1) * 4);
+  L.o_anc = take(c, rows * 4);
+  L.o_acc = take(c, rows * 4);
+  L.o_cdf = take(c, rows * 8);
+  L.o_gpart = take(c, (size_t)L.lf_grid * TJ * L.DS * sizeof(float));
+  L.o_tilecnt = take(c, (size_t)B * ntile * 4);
+  L.o_llpart = take(c, (size_t)L.ll_smax * rows * sizeof(float2));
+  L.o_items = take(c, (size_t)L.ll_nitems * sizeof(int4));
+  L.o_colpart = take(c, (size_t)B * L.col_chunks * 2 * L.DS * 8);
+  L.o_means = take(c, (size_t)B * 2 * L.DS * 8);
+  L.o_minv = take(c, (size_t)B * L.DS * 4);
+  L.o_primes = take(c, NPRIMES * 4);
+  L.total = (c + 255) & ~(size_t)255;
+}
+
+std::vector<int> first_primes(int n) {
+  std::vector<int> p;
+  for (int c = 2; (int)p.size() < n; ++c) {
+    bool ok = true;
+    for (int q : p) {
+      if (q * q > c) break;
+      if (c % q == 0) {
+        ok = false;
+        break;
+      }
+    }
+    if (ok) p.push_back(c);
+  }
+  return p;
+}
+
+#define CK(call)                                                                     \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess) {                                                          \
+      ctx->err = std::string(#call) + ": " + hipGetErrorString(e_);                   \
+      return SMC_EDEVICE;                                                            \
+    }                                                                                \
+  } while (0)
+
+smc_status fill_stats(smc_ctx *ctx, smc_stats *stats) {
+  CK(hipMemcpyAsync(ctx->ps_host.data(), ctx->D.ps, ctx->D.B * sizeof(PState),
+                    hipMemcpyDeviceToHost, ctx->st));
+  CK(hipStreamSynchronize(ctx->st));
+  const PState &S = ctx->ps_host[0];
+  stats->ess = S.ess;
+  stats->ess_before = S.ess_before;
+  stats->mean_accept = S.sum_alpha_all / ctx->D.J;
+  stats->chees = S.chees;
+  stats->chees_grad = S.ghat;
+  stats->L = S.L_used;
+  stats->eps = S.eps_used;
+  stats->log_z = S.log_c + S.m + log(S.S);
+  stats->resampled = S.resampled;
+  stats->iteration = S.k;
+  stats->grad_evals = S.grad_evals_step;
+  for (int b = 0; b < ctx->D.B; ++b)
+    if (ctx->ps_host[b].degenerate) {
+      ctx->err = "degenerate weights";
+      return SMC_EDEGENERATE;
+    }
+  return SMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t smc_workspace_bytes(const smc_problem *prob, const smc_params *par) {
+  if (check(prob, par)) return 0;
+  Layout L;
+  plan(prob, par, L);
+  return L.total;
+}
+
+smc_status smc_init(const smc_problem *prob, const smc_params *par, void *workspace,
+                    size_t workspace_bytes, void *hip_stream, const float *theta0,
+                    smc_ctx **out) {
+  if (!out) return SMC_EINVAL;
+  *out = nullptr;
+  if (const char *why = check(prob, par)) {
+    fprintf(stderr, "smc_init: %s\n", why);
+    return SMC_EINVAL;
+  }
+  Layout L;
+  plan(prob, par, L);
+  if (!workspace || workspace_bytes < L.total) return SMC_ENOMEM;
+  if (((uintptr_t)workspace & 255) != 0) return SMC_EINVAL;
+
+  smc_ctx *ctx = new smc_ctx();
+  ctx->st = (hipStream_t)hip_stream;
+  char *w = (char *)workspace;
+  Dev &D = ctx->D;
+  memset(&D, 0, sizeof(D));
+  D.B = L.B;
+  D.J = L.J;
+  D.Jcap = L.Jcap;
+  D.DS = L.DS;
+  D.nmax = L.nmax;
+  D.jitter = par->jitter;
+  D.mh = par->mh_accept ? 1 : 0;
+  D.resampling = par->resampling;
+  D.precond = par->precond;
+  D.prior_var = prob->prior_var;
+  D.ess_frac = par->ess_frac;
+  D.adam_lr = par->adam_lr;
+  D.adam_b1 = par->adam_b1;
+  D.adam_b2 = par->adam_b2;
+  D.adam_eps = par->adam_eps;
+  D.avg_decay = par->avg_decay;
+  D.target_accept = par->target_accept;
+  D.adapt_eps = par->adapt_step_size ? 1 : 0;
+  D.num_warmup = par->num_warmup;
+  D.seed = par->seed;
+  D.posts = (Post *)(w + L.o_posts);
+  D.ps = (PState *)(w + L.o_ps);
+  D.xa = (float *)(w + L.o_xa);
+  D.xb = (float *)(w + L.o_xb);
+  D.yp = (float *)(w + L.o_yp);
+  D.theta = (float *)(w + L.o_theta);
+  D.grad = (float *)(w + L.o_grad);
+  D.theta_t = (float *)(w + L.o_theta_t);
+  D.p_t = (float *)(w + L.o_p_t);
+  D.grad_t = (float *)(w + L.o_grad_t);
+  D.logpi = (double *)(w + L.o_logpi);
+  D.logpi_t = (double *)(w + L.o_logpi_t);
+  D.logw = (double *)(w + L.o_logw);
+  D.h = (double *)(w + L.o_h);
+  D.l = (double *)(w + L.o_l);
+  D.H0 = (double *)(w + L.o_H0);
+  D.dH = (double *)(w + L.o_dH);
+  D.alpha = (double *)(w + L.o_alpha);
+  D.ca = (double *)(w + L.o_ca);
+  D.cg = (double *)(w + L.o_cg);
+  D.n = (int *)(w + L.o_n);
+  D.perm = (int *)(w + L.o_perm);
+  D.hist = (int *)(w + L.o_hist);
+  D.active = (int *)(w + L.o_active);
+  D.anc = (int *)(w + L.o_anc);
+  D.accepted = (int *)(w + L.o_acc);
+  D.cdf = (unsigned long long *)(w + L.o_cdf);
+  D.gpart = (float *)(w + L.o_gpart);
+  D.gpart_slots = L.lf_grid;
+  D.tilecnt = (int *)(w + L.o_tilecnt);
+  D.llpart = (float2 *)(w + L.o_llpart);
+  D.ll_smax = L.ll_smax;
+  D.ll_items = (int4 *)(w + L.o_items);
+  D.ll_nitems = L.ll_nitems;
+  D.colpart = (double *)(w + L.o_colpart);
+  D.col_chunks = L.col_chunks;
+  D.means = (double *)(w + L.o_means);
+  D.minv = (float *)(w + L.o_minv);
+  D.primes = (int *)(w + L.o_primes);
+  D.lf_target = L.lf_target;
+  D.lf_grid = L.lf_grid;
+
+  ctx->hp = L.hp;
+  ctx->posts = L.posts;
+  ctx->ll_items = L.items;
+  for (const HostPost &h : L.hp)
+    if (std::find(ctx->c2s.begin(), ctx->c2s.end(), h.C2) == ctx->c2s.end())
+      ctx->c2s.push_back(h.C2);
+  ctx->primes = first_primes(NPRIMES);
+  ctx->minv.assign((size_t)L.B * L.DS, 1.0f);
+  ctx->ps_host.resize(L.B);
+  for (PState &s : ctx->ps_host) {
+    memset(&s, 0, sizeof(s));
+    s.L = par->traj_length;
+    s.eps = par->step_size;
+    s.adapted_k = 0;
+  }
+
+  smc_status rc = SMC_OK;
+  auto fail = [&](smc_status r) {
+    fprintf(stderr, "smc_init: %s\n", ctx->err.c_str());
+    delete ctx;
+    return r;
+  };
+#define CKI(call)                                                                    \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess) {                                                          \
+      ctx->err = std::string(#call) + ": " + hipGetErrorString(e_);                   \
+      return fail(SMC_EDEVICE);                                                      \
+    }                                                                                \
+  } while (0)
+  CKI(fill_i32((int *)w, (long long)(L.total / 4), 0, ctx->st));
+  CKI(hipMemcpyAsync(D.posts, ctx->posts.data(), L.B * sizeof(Post), hipMemcpyHostToDevice,
+                     ctx->st));
+  CKI(hipMemcpyAsync(D.ps, ctx->ps_host.data(), L.B * sizeof(PState), hipMemcpyHostToDevice,
+                     ctx->st));
+  CKI(hipMemcpyAsync(D.primes, ctx->primes.data(), NPRIMES * sizeof(int), hipMemcpyHostToDevice,
+                     ctx->st));
+  CKI(hipMemcpyAsync(D.minv, ctx->minv.data(), ctx->minv.size() * sizeof(float),
+                     hipMemcpyHostToDevice, ctx->st));
+  CKI(hipMemcpyAsync(D.ll_items, ctx->ll_items.data(), ctx->ll_items.size() * sizeof(int4),
+                     hipMemcpyHostToDevice, ctx->st));
+  for (int b = 0; b < L.B; ++b)
+    CKI(launch_pack_one(D, prob->X[b], prob->y[b], prob->x_dtype, L.hp[b], ctx->st));
+  CKI(launch_init_theta(D, theta0, ctx->st));
+  for (int c2 : ctx->c2s) CKI(launch_leapfrog(D, c2, 0, 1, ctx->st));
+  for (int c2 : ctx->c2s) CKI(launch_loglik(D, c2, ctx->st));
+  CKI(launch_init_weights(D, ctx->st));
+  CKI(launch_ess(D, 0, ctx->st));
+  // the host copies above must stay alive until they have run
+  CKI(hipStreamSynchronize(ctx->st));
+  (void)rc;
+  *out = ctx;
+  return SMC_OK;
+#undef CKI
+}
+
+namespace {
+// Record an event pair around a launch when timing is on.
+hipError_t timed_begin(smc_ctx *ctx, int kind, size_t &idx) {
+  if (!ctx->timing) return hipSuccess;
+  while (ctx->ev_pool.size() < ctx->ev_used + 2) {
+    hipEvent_t e;
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) return r;
+    ctx->ev_pool.push_back(e);
+  }
+  idx = ctx->ev_used;
+  ctx->ev_used += 2;
+  ctx->ev_marks.push_back({kind, idx});
+  return hipEventRecord(ctx->ev_pool[idx], ctx->st);
+}
+hipError_t timed_end(smc_ctx *ctx, size_t idx) {
+  if (!ctx->timing) return hipSuccess;
+  return hipEventRecord(ctx->ev_pool[idx + 1], ctx->st);
+}
+}  // namespace
+
+smc_status smc_step(smc_ctx *ctx, const smc_inject *inject, smc_stats *stats) {
+  if (!ctx) return SMC_EINVAL;
+  const Dev &D = ctx->D;
+  size_t ei = 0;
+  CK(launch_begin_step(D, 1, inject ? inject->resample_u : nullptr, 1, ctx->st));
+  CK(launch_gather(D, nullptr, ctx->st));
+  CK(launch_setup(D, inject ? inject->momenta : nullptr, 0, ctx->st));
+  CK(launch_sort(D, ctx->st));
+  for (int s = 0; s < D.nmax; ++s)
+    for (int c2 : ctx->c2s) {
+      CK(timed_begin(ctx, 0, ei));
+      CK(launch_leapfrog(D, c2, s, 0, ctx->st));
+      CK(timed_end(ctx, ei));
+    }
+  for (int c2 : ctx->c2s) {
+    CK(timed_begin(ctx, 1, ei));
+    CK(launch_loglik(D, c2, ctx->st));
+    CK(timed_end(ctx, ei));
+  }
+  CK(launch_weights(D, inject ? inject->mh_uniforms : nullptr, 0, ctx->st));
+  CK(launch_chees(D, ctx->st));
+  CK(launch_commit(D, ctx->st));
+  CK(launch_ess(D, 1, ctx->st));
+  ctx->stepped = 1;
+  ctx->steps += 1;
+  if (stats) return fill_stats(ctx, stats);
+  return SMC_OK;
+}
+
+smc_status chees_adapt(smc_ctx *ctx, smc_stats *stats) {
+  if (!ctx) return SMC_EINVAL;
+  if (!ctx->stepped) {
+    ctx->err = "chees_adapt needs a step since the last adaptation";
+    return SMC_ESTATE;
+  }
+  CK(launch_adapt(ctx->D, ctx->st));
+  ctx->stepped = 0;
+  if (stats) {
+    smc_status r = fill_stats(ctx, stats);
+    stats->L = ctx->ps_host[0].L;
+    stats->eps = ctx->ps_host[0].eps;
+    return r;
+  }
+  return SMC_OK;
+}
+
+smc_status resample(smc_ctx *ctx, const double *u, int32_t *ancestors_out) {
+  if (!ctx) return SMC_EINVAL;
+  const Dev &D = ctx->D;
+  CK(launch_begin_step(D, 0, u, 0, ctx->st));
+  CK(launch_gather(D, ancestors_out, ctx->st));
+  CK(launch_setup(D, nullptr, 2, ctx->st));
+  CK(launch_ess(D, 0, ctx->st));
+  return SMC_OK;
+}
+
+size_t resample_workspace_bytes(int32_t J) {
+  if (J < 1 || J > (1 << 24)) return 0;
+  return ((size_t)J * 8 + 255) / 256 * 256 + 256;
+}
+
+smc_status resample_indices(const double *w, int32_t J, const double *u, int32_t scheme,
+                            int32_t *ancestors, void *workspace, size_t workspace_bytes,
+                            void *hip_stream) {
+  if (!w || !u || !ancestors || !workspace || J < 1 || J > (1 << 24) ||
+      (scheme != SMC_RESAMPLE_SYSTEMATIC && scheme != SMC_RESAMPLE_MULTINOMIAL))
+    return SMC_EINVAL;
+  if (workspace_bytes < resample_workspace_bytes(J)) return SMC_ENOMEM;
+  hipStream_t st = (hipStream_t)hip_stream;
+  unsigned long long *cdf = (unsigned long long *)workspace;
+  int *err = (int *)((char *)workspace + ((size_t)J * 8 + 255) / 256 * 256);
+  if (launch_resample_indices(w, J, u, scheme, ancestors, cdf, nullptr, err, st) != hipSuccess)
+    return SMC_EDEVICE;
+  int herr = 0;
+  if (hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess)
+    return SMC_EDEVICE;
+  if (hipStreamSynchronize(st) != hipSuccess) return SMC_EDEVICE;
+  return herr ? SMC_EDEGENERATE : SMC_OK;
+}
+
+smc_status log_evidence(smc_ctx *ctx, double *log_z_host, double *per_posterior_host) {
+  if (!ctx) return SMC_EINVAL;
+  CK(hipMemcpyAsync(ctx->ps_host.data(), ctx->D.ps, ctx->D.B * sizeof(PState),
+                    hipMemcpyDeviceToHost, ctx->st));
+  CK(hipStreamSynchronize(ctx->st));
+  smc_status r = SMC_OK;
+  for (int b = 0; b < ctx->D.B; ++b) {
+    const PState &S = ctx->ps_host[b];
+    const double lz = S.S > 0.0 ? S.log_c + S.m + log(S.S) : -INFINITY;
+    if (!(S.S > 0.0)) r = SMC_EDEGENERATE;
+    if (b == 0 && log_z_host) *log_z_host = lz;
+    if (per_posterior_host) per_posterior_host[b] = lz;
+  }
+  return r;
+}
+
+smc_status smc_get_state(smc_ctx *ctx, float *theta, double *logw, double *logpi) {
+  if (!ctx) return SMC_EINVAL;
+  CK(launch_export_state(ctx->D, theta, logw, logpi, ctx->st));
+  return SMC_OK;
+}
+
+smc_status smc_get_trace(smc_ctx *ctx, smc_trace *t) {
+  if (!ctx || !t) return SMC_EINVAL;
+  t->h = ctx->D.h;
+  t->l = ctx->D.l;
+  t->n = ctx->D.n;
+  t->dH = ctx->D.dH;
+  t->alpha = ctx->D.alpha;
+  t->ancestors = ctx->D.anc;
+  t->p_final = ctx->D.p_t;
+  t->theta_prop = ctx->D.theta_t;
+  t->dpad = ctx->D.DS;
+  t->jcap = ctx->D.Jcap;
+  return SMC_OK;
+}
+
+smc_status smc_get_counters(smc_ctx *ctx, smc_counters *c) {
+  if (!ctx || !c) return SMC_EINVAL;
+  CK(hipMemcpyAsync(ctx->ps_host.data(), ctx->D.ps, ctx->D.B * sizeof(PState),
+                    hipMemcpyDeviceToHost, ctx->st));
+  CK(hipStreamSynchronize(ctx->st));
+  memset(c, 0, sizeof(*c));
+  c->iterations = ctx->ps_host[0].tot_iters;
+  for (const PState &S : ctx->ps_host) {
+    c->grad_evals += S.tot_grad_evals;
+    c->ess_sum += S.tot_ess;
+    c->resamples += S.tot_resamples;
+  }
+  return SMC_OK;
+}
+
+smc_status smc_set_timing(smc_ctx *ctx, int32_t enable) {
+  if (!ctx) return SMC_EINVAL;
+  ctx->timing = enable ? 1 : 0;
+  return SMC_OK;
+}
+
+smc_status smc_get_timing(smc_ctx *ctx, smc_timing *out) {
+  if (!ctx || !out) return SMC_EINVAL;
+  memset(out, 0, sizeof(*out));
+  CK(hipStreamSynchronize(ctx->st));
+  for (const auto &m : ctx->ev_marks) {
+    float ms = 0.f;
+    CK(hipEventElapsedTime(&ms, ctx->ev_pool[m.second], ctx->ev_pool[m.second + 1]));
+    if (m.first == 0) {
+      out->leapfrog_ms += ms;
+      out->leapfrog_launches += 1;
+    } else {
+      out->loglik_ms += ms;
+      out->loglik_launches += 1;
+    }
+  }
+  ctx->ev_marks.clear();
+  ctx->ev_used = 0;
+  return SMC_OK;
+}
+
+smc_status smc_set_params(smc_ctx *ctx, double L, double eps) {
+  if (!ctx || !(L > 0.0) || !(eps > 0.0)) return SMC_EINVAL;
+  CK(launch_set_params(ctx->D, L, eps, ctx->st));
+  return SMC_OK;
+}
+
+void smc_destroy(smc_ctx *ctx) { delete ctx; }
+
+const char *smc_last_error(const smc_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+}  // extern "C"

@@ -1,0 +1,124 @@
+// Internal declarations shared by the kernels and the host orchestration of
+// libchees_smc.so.  Not part of the public ABI (include/chees_smc.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace smc {
+
+// Particle tile of the fused leapfrog/likelihood kernels: 4 waves x 2 subtiles
+// x 16 particles.  Particle counts are padded to a multiple of TJ per posterior.
+constexpr int TJ = 128;
+constexpr int WAVES = 4;
+constexpr int SUB = 2;
+constexpr int WG = 64 * WAVES;
+constexpr int MAX_C2 = 13;          // d <= 16 * 13 = 208
+constexpr int MAX_NMAX = 4096;      // cap on max_leapfrog
+constexpr int QUANT_BITS = 40;      // fixed-point resolution of resampling weights
+constexpr int NPRIMES = 1024;       // primes table for N-d Halton
+
+// Philox stream ids (counter word 3)
+constexpr uint32_t STREAM_INIT = 1, STREAM_MOMENTUM = 2, STREAM_MH = 3, STREAM_RESAMPLE = 4;
+
+// Constants of one posterior, resident in device memory.
+struct Post {
+  int N, d;        // data rows and features
+  int C1, C2;      // GEMM1 K-chunks ceil(d/4); GEMM2 column tiles ceil(d/16)
+  int NT;          // 16-row data tiles ceil(N/16)
+  int row0;        // first particle row of this posterior
+  int ll_splits;   // N-splits of the log-likelihood pass
+  int ll_base;     // first work item of this posterior in the log-likelihood plan
+  long long xa, xb;  // float offsets into the packed X layouts
+  long long yo;      // float offset into padded y
+  long long uoff;    // offset of this posterior's block in caller (B*J) x d_b arrays
+};
+
+// Per-posterior scalar state, resident in device memory.
+struct PState {
+  double L, eps, Lbar;          // trajectory length, step size, moving average
+  double am, av;                // Adam moments for log L
+  double em, ev;                // Adam moments for log eps
+  int at, et;                   // Adam step counts
+  int k;                        // iteration counter (1-based after the first step)
+  int adapted_k;                // last iteration adapted
+  double log_c;                 // evidence accumulator
+  double m, S, S2, ess;         // LSE terms and ESS of the current weights
+  double ess_before;            // ESS that decided this step's resampling
+  int flag_resample;            // resample at the start of the next step
+  int resampled;                // resampling ran in this step
+  int degenerate;               // every weight -inf/NaN
+  int pad0;
+  double L_used, eps_used;      // parameters used by this step
+  double ghat, sum_alpha, chees, sum_alpha_all, sum_inv_alpha;
+  long long grad_evals_step;
+  long long tot_grad_evals, tot_resamples, tot_iters;
+  double tot_ess;
+};
+
+struct Dev {                    // pointers carved from the workspace
+  Post *posts;
+  PState *ps;
+  int B, J, Jcap, DS;           // posteriors, particles, padded particles, row stride
+  int nmax, jitter, mh, resampling, precond;
+  double prior_var, ess_frac;
+  double adam_lr, adam_b1, adam_b2, adam_eps, avg_decay, target_accept;
+  int adapt_eps, num_warmup;
+  uint64_t seed;
+  float *xa, *xb, *yp;          // packed X (A and B operand layouts), padded y
+  float *theta, *grad;          // current state, B*Jcap x DS
+  float *theta_t, *p_t, *grad_t;// trajectory buffers
+  double *logpi, *logpi_t, *logw;
+  double *h, *l, *H0, *dH, *alpha, *ca, *cg;
+  int *n, *perm, *hist, *cursor, *active, *anc, *accepted;
+  unsigned long long *cdf;
+  float *gpart;                 // split partial gradients, [wg][TJ][DS]
+  int gpart_slots;              // number of [TJ][DS] slots
+  int *tilecnt;                 // arrival counters per (posterior, tile)
+  float2 *llpart;               // log-likelihood partials [split][row]
+  int ll_smax;
+  int4 *ll_items;               // (posterior, tile, split, -) work items of the log-lik pass
+  int ll_nitems;
+  double *colpart;              // column partial sums [B][chunks][2][DS]
+  int col_chunks;
+  double *means;                // [B][2][DS]
+  float *minv;                  // [B][DS] inverse mass diagonal
+  int *primes;                  // NPRIMES
+  int lf_target;                // target work-group count of a leapfrog launch
+  int lf_grid;                  // grid of a leapfrog launch
+};
+
+// Host copy of one posterior's packing sizes.
+struct HostPost {
+  int N, d, C1, C2, NT;
+  long long xa, xb, yo;
+};
+
+// Launchers (smc_kernels.hip).  All stream-ordered.
+hipError_t launch_pack_one(const Dev &D, const void *X, const float *y, int x_dtype,
+                           const HostPost &P, hipStream_t st);
+hipError_t fill_f32(float *p, long long n, float v, hipStream_t st);
+hipError_t fill_i32(int *p, long long n, int v, hipStream_t st);
+hipError_t fill_f64(double *p, long long n, double v, hipStream_t st);
+hipError_t launch_init_theta(const Dev &D, const float *theta0, hipStream_t st);
+hipError_t launch_init_weights(const Dev &D, hipStream_t st);
+hipError_t launch_begin_step(const Dev &D, int conditional, const double *u, int count_iteration,
+                             hipStream_t st);
+hipError_t launch_gather(const Dev &D, int *anc_out, hipStream_t st);
+hipError_t launch_setup(const Dev &D, const float *momenta, int init_mode, hipStream_t st);
+hipError_t launch_sort(const Dev &D, hipStream_t st);
+hipError_t launch_leapfrog(const Dev &D, int c2, int step, int zero_eps, hipStream_t st);
+hipError_t launch_loglik(const Dev &D, int c2, hipStream_t st);
+hipError_t launch_weights(const Dev &D, const double *mh_u, int init_mode, hipStream_t st);
+hipError_t launch_chees(const Dev &D, hipStream_t st);
+hipError_t launch_commit(const Dev &D, hipStream_t st);
+hipError_t launch_ess(const Dev &D, int count, hipStream_t st);
+hipError_t launch_adapt(const Dev &D, hipStream_t st);
+hipError_t launch_set_params(const Dev &D, double L, double eps, hipStream_t st);
+hipError_t launch_export_state(const Dev &D, float *theta, double *logw, double *logpi,
+                               hipStream_t st);
+hipError_t launch_resample_indices(const double *w, int J, const double *u, int scheme,
+                                   int *anc, unsigned long long *cdf, double *wmax, int *err,
+                                   hipStream_t st);
+
+}  // namespace smc

@@ -1,0 +1,1305 @@
+// Device kernels of libchees_smc.so for gfx950 (CDNA4, wave64).
+//
+// Method: SMC sampler with a ChEES-HMC proposal (arXiv 2504.02627).  Each
+// kernel names the passage of the paper it computes.  Floating-point
+// contraction is off in this file: every fused multiply-add is written as an
+// explicit fmaf so that the two places that compute the same drift produce the
+// same bits.
+#pragma clang fp contract(off)
+
+#include <math.h>
+
+#include "smc_internal.h"
+
+namespace smc {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC 2011) and Box--Muller normals.
+// Counter = (block, particle, iteration, stream), key = (seed lo, seed hi).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c.x), lo0 = 0xD2511F53u * c.x;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z), lo1 = 0xCD9E8D57u * c.z;
+    c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return c;
+}
+
+__device__ __forceinline__ double u01(uint32_t x) { return ((double)x + 0.5) / 4294967296.0; }
+
+__device__ __forceinline__ uint4 philox_at(uint64_t seed, uint32_t block, uint32_t particle,
+                                           uint32_t iteration, uint32_t stream) {
+  return philox10(make_uint4(block, particle, iteration, stream), (uint32_t)seed,
+                  (uint32_t)(seed >> 32));
+}
+
+// Four standard normals from one Philox block: pairs (w0, w1), (w2, w3).
+__device__ __forceinline__ void box_muller4(uint4 w, double out[4]) {
+  const double two_pi = 2.0 * 3.141592653589793;
+  double r = sqrt(-2.0 * log(u01(w.x)));
+  double t = two_pi * u01(w.y);
+  out[0] = r * cos(t);
+  out[1] = r * sin(t);
+  r = sqrt(-2.0 * log(u01(w.z)));
+  t = two_pi * u01(w.w);
+  out[2] = r * cos(t);
+  out[3] = r * sin(t);
+}
+
+// ---------------------------------------------------------------------------
+// Wave64 reductions in a fixed order (butterfly), deterministic.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Block reduction helpers for 1024-thread single-posterior kernels.
+template <typename T, typename Op>
+__device__ T block_reduce(T v, T *sh, Op op) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = op(v, __shfl_xor(v, o, 64));
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  T r = sh[0];
+  for (int i = 1; i < nw; ++i) r = op(r, sh[i]);
+  __syncthreads();
+  return r;
+}
+
+struct OpAdd {
+  template <typename T>
+  __device__ T operator()(T a, T b) const { return a + b; }
+};
+struct OpMax {
+  __device__ double operator()(double a, double b) const { return a > b ? a : b; }
+};
+
+// ---------------------------------------------------------------------------
+// Packing of X into the two MFMA operand layouts (once, at init).
+//
+// A layout (GEMM1, Z^T = X Theta^T, v_mfma_f32_16x16x4f32 with M = data rows):
+//   lane l of data tile t holds X[16t + l%16][(l/16) C1 + c] in slot c < C1.
+// B layout (GEMM2, G = R X, M = particles, N = 16 features, K = 4 data rows):
+//   lane l of data tile t holds X[16t + 4(l/16) + i][16 ct + l%16] in slot 4 ct + i.
+// Both: [tile][lane][4 C2] floats, so a lane reads C2 16-byte vectors per tile.
+// Padded y: y[n] for n < N, 1/2 beyond, which makes the padded residual
+// y - sigmoid(0) exactly zero.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ float to_f32(T v);
+template <>
+__device__ __forceinline__ float to_f32<float>(float v) { return v; }
+template <>
+__device__ __forceinline__ float to_f32<uint16_t>(uint16_t v) {
+  return __uint_as_float(((uint32_t)v) << 16);  // bfloat16 -> float is exact
+}
+
+template <typename T>
+__global__ void k_pack(const T *__restrict__ X, const float *__restrict__ y, int N, int d, int C1,
+                       int C2, int NT, float *__restrict__ xa, float *__restrict__ xb,
+                       float *__restrict__ yp) {
+  const int K1 = 4 * C2;
+  const long long tot = (long long)NT * 64 * K1;
+  for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < tot;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const int slot = (int)(idx % K1);
+    const long long r = idx / K1;
+    const int lane = (int)(r % 64);
+    const int t = (int)(r / 64);
+    int n = 16 * t + (lane & 15);
+    int k = (lane >> 4) * C1 + slot;
+    xa[idx] = (slot < C1 && n < N && k < d) ? to_f32<T>(X[(long long)n * d + k]) : 0.f;
+    const int ct = slot >> 2, i = slot & 3;
+    n = 16 * t + 4 * (lane >> 4) + i;
+    k = 16 * ct + (lane & 15);
+    xb[idx] = (n < N && k < d) ? to_f32<T>(X[(long long)n * d + k]) : 0.f;
+  }
+  for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < 16LL * NT;
+       n += (long long)gridDim.x * blockDim.x)
+    yp[n] = n < N ? y[n] : 0.5f;
+}
+
+hipError_t launch_pack_one(const Dev &D, const void *X, const float *y, int x_dtype,
+                           const HostPost &P, hipStream_t st) {
+  const long long tot = (long long)P.NT * 64 * 4 * P.C2;
+  int grid = (int)((tot + 255) / 256);
+  if (grid > 65535) grid = 65535;
+  if (x_dtype == 0)
+    hipLaunchKernelGGL(k_pack<float>, dim3(grid), dim3(256), 0, st, (const float *)X, y, P.N, P.d,
+                       P.C1, P.C2, P.NT, D.xa + P.xa, D.xb + P.xb, D.yp + P.yo);
+  else
+    hipLaunchKernelGGL(k_pack<uint16_t>, dim3(grid), dim3(256), 0, st, (const uint16_t *)X, y,
+                       P.N, P.d, P.C1, P.C2, P.NT, D.xa + P.xa, D.xb + P.xb, D.yp + P.yo);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Fill helpers.
+// ---------------------------------------------------------------------------
+__global__ void k_fill_f32(float *p, long long n, float v) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+__global__ void k_fill_i32(int *p, long long n, int v) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+__global__ void k_fill_f64(double *p, long long n, double v) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+hipError_t fill_f32(float *p, long long n, float v, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_f32, dim3(1024), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+hipError_t fill_i32(int *p, long long n, int v, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_i32, dim3(256), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+hipError_t fill_f64(double *p, long long n, double v, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_f64, dim3(256), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Initial draw theta_0 ~ q0 = N(0, prior_var I)  (eq. init_sample), or a copy of
+// the caller's theta_0, into the trajectory buffer; momenta and gradients zero.
+// One thread per (row, 4-column Philox block).
+// ---------------------------------------------------------------------------
+__global__ void k_init_theta(Dev D, const float *__restrict__ theta0) {
+  const int nblk = D.DS / 4;
+  const long long tot = (long long)D.B * D.Jcap * nblk;
+  for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < tot;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const int blk = (int)(idx % nblk);
+    const int row = (int)(idx / nblk);
+    const int b = row / D.Jcap, j = row % D.Jcap;
+    const Post P = D.posts[b];
+    double v[4] = {0, 0, 0, 0};
+    if (j < D.J) {
+      if (theta0) {
+        for (int q = 0; q < 4; ++q) {
+          const int c = 4 * blk + q;
+          if (c < P.d) v[q] = theta0[P.uoff + (long long)j * P.d + c];
+        }
+      } else if (4 * blk < P.d) {
+        box_muller4(philox_at(D.seed, blk, (uint32_t)(b * D.J + j), 0, STREAM_INIT), v);
+        const double s = sqrt(D.prior_var);
+        for (int q = 0; q < 4; ++q) v[q] = (4 * blk + q < P.d) ? s * v[q] : 0.0;
+      }
+    }
+    for (int q = 0; q < 4; ++q) {
+      const long long o = (long long)row * D.DS + 4 * blk + q;
+      D.theta_t[o] = (float)v[q];
+      D.p_t[o] = 0.f;
+      D.grad_t[o] = 0.f;
+    }
+    if (blk == 0) {
+      D.n[row] = j < D.J ? 1 : 0;
+      D.perm[row] = j;
+    }
+  }
+  // one leapfrog "step" of size zero evaluates the gradient at theta_0
+  const long long tb = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tb < D.B) {
+    int *a = D.active + tb * (D.nmax + 1);
+    a[0] = D.J;
+    for (int s = 1; s <= D.nmax; ++s) a[s] = 0;
+  }
+}
+
+hipError_t launch_init_theta(const Dev &D, const float *theta0, hipStream_t st) {
+  hipLaunchKernelGGL(k_init_theta, dim3(1024), dim3(256), 0, st, D, theta0);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Fused leapfrog step with the batched logistic-regression gradient.
+//
+// Leapfrog (Sec. II-A, eqs. LF_p1/2, LF_theta, LF_p) with the gradient cached
+// from the previous step:
+//   p_half = p + eps/2 g;  theta' = theta + eps M^{-1} p_half;
+//   g' = X^T (y - sigmoid(X theta')) - theta'/prior_var;  p' = p_half + eps/2 g'.
+// Particles with n_j <= s are left alone (per-particle trajectory length).
+//
+// Work item = (posterior, 128-particle tile, data split).  Each of the 4 waves
+// owns 2 x 16 particles.  Per 16-row data tile:
+//   GEMM1  Z^T (16 rows x 16 particles) += X_A (16 x 4) Theta'^T (4 x 16),
+//          C1 MFMAs (v_mfma_f32_16x16x4f32) accumulate over the features;
+//   R = y - sigmoid(Z) elementwise on the accumulator registers;
+//   GEMM2  G (16 particles x 16 features) += R (16 x 4) X_B (4 x 16), the
+//          accumulator of GEMM1 being directly the A operand of GEMM2 (the
+//          data-row index of GEMM2's K dimension follows GEMM1's row layout).
+// Z never leaves registers.  Splits write partial G; the last work group of a
+// tile (arrival counter) sums the partials in split order and applies the
+// second half kick, so the result does not depend on arrival order.
+// ---------------------------------------------------------------------------
+struct Plan {
+  int b, tile, split, S, wbase;
+};
+
+// Deterministic plan of a leapfrog launch at step s: every work group computes
+// the same table from the active counts and finds its own item.
+__device__ bool lf_plan(const Dev &D, int c2, int s, int wid, Plan &pl) {
+  long long U = 0;
+  const int ntile = D.Jcap / TJ;
+  for (int b = 0; b < D.B; ++b) {
+    const Post &P = D.posts[b];
+    if (P.C2 != c2) continue;
+    const int A = D.active[b * (D.nmax + 1) + s];
+    U += (long long)((A + TJ - 1) / TJ) * P.NT;
+  }
+  if (U == 0) return false;
+  const long long chunk = (U + D.lf_target - 1) / D.lf_target;
+  int base = 0;
+  for (int b = 0; b < D.B; ++b) {
+    const Post &P = D.posts[b];
+    if (P.C2 != c2) continue;
+    const int A = D.active[b * (D.nmax + 1) + s];
+    const int T = (A + TJ - 1) / TJ;
+    if (T == 0) continue;
+    long long S = (P.NT + chunk - 1) / chunk;
+    if (S < 1) S = 1;
+    if (S > P.NT) S = P.NT;
+    const int cnt = T * (int)S;
+    if (wid < base + cnt) {
+      pl.b = b;
+      pl.tile = (wid - base) / (int)S;
+      pl.split = (wid - base) % (int)S;
+      pl.S = (int)S;
+      pl.wbase = base + pl.tile * (int)S;
+      return pl.tile < ntile;
+    }
+    base += cnt;
+  }
+  return false;
+}
+
+__device__ __forceinline__ float sigmoidf_fast(float z) {
+  // 1 / (1 + 2^(-z log2 e)) with the hardware exp2 and reciprocal
+  const float e = __builtin_amdgcn_exp2f(-z * 1.4426950408889634f);
+  return __builtin_amdgcn_rcpf(1.0f + e);
+}
+
+template <int C2>
+__global__ __launch_bounds__(WG) void k_leapfrog(Dev D, int s, int zero_eps) {
+  constexpr int K1 = 4 * C2;
+  __shared__ Plan spl;
+  __shared__ int slast;
+  if (threadIdx.x == 0) {
+    Plan pl;
+    if (!lf_plan(D, C2, s, blockIdx.x, pl)) pl.b = -1;
+    spl = pl;
+  }
+  __syncthreads();
+  const Plan pl = spl;
+  if (pl.b < 0) return;
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const Post P = D.posts[pl.b];
+  const PState &PS = D.ps[pl.b];
+  const float eps = zero_eps ? 0.f : (float)PS.eps;
+  const float he = 0.5f * eps;
+  const int C1 = P.C1;
+  const int kq = lane >> 4;
+  const float *minv = D.minv + (long long)pl.b * D.DS;
+  const int *perm = D.perm + P.row0;
+
+  // theta' of this wave's particles in the B-operand layout of GEMM1
+  float th[SUB][K1];
+#pragma unroll
+  for (int sb = 0; sb < SUB; ++sb) {
+    const int slot = pl.tile * TJ + wave * 32 + sb * 16 + (lane & 15);
+    const long long base = (long long)(P.row0 + perm[slot]) * D.DS;
+#pragma unroll
+    for (int c = 0; c < K1; ++c) {
+      float v = 0.f;
+      if (c < C1) {
+        const int k = kq * C1 + c;
+        const float t0 = D.theta_t[base + k], p0 = D.p_t[base + k], g0 = D.grad_t[base + k];
+        const float ph = fmaf(he, g0, p0);
+        v = fmaf(eps * minv[k], ph, t0);
+      }
+      th[sb][c] = v;
+    }
+  }
+
+  v4f gacc[SUB][C2];
+#pragma unroll
+  for (int sb = 0; sb < SUB; ++sb)
+#pragma unroll
+    for (int ct = 0; ct < C2; ++ct) gacc[sb][ct] = v4f{0.f, 0.f, 0.f, 0.f};
+
+  const int t0 = (int)((long long)pl.split * P.NT / pl.S);
+  const int t1 = (int)((long long)(pl.split + 1) * P.NT / pl.S);
+  const float4 *xa = reinterpret_cast<const float4 *>(D.xa + P.xa);
+  const float4 *xb = reinterpret_cast<const float4 *>(D.xb + P.xb);
+  const float4 *yv = reinterpret_cast<const float4 *>(D.yp + P.yo);
+
+  for (int t = t0; t < t1; ++t) {
+    float4 a4[C2], b4[C2];
+    const long long o = ((long long)t * 64 + lane) * C2;
+#pragma unroll
+    for (int q = 0; q < C2; ++q) {
+      a4[q] = xa[o + q];
+      b4[q] = xb[o + q];
+    }
+    const float4 y4 = yv[t * 4 + kq];
+    const float ya[4] = {y4.x, y4.y, y4.z, y4.w};
+    const float *af = reinterpret_cast<const float *>(a4);
+#pragma unroll
+    for (int sb = 0; sb < SUB; ++sb) {
+      v4f z = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int c = 0; c < K1; ++c)
+        if (c < C1) z = __builtin_amdgcn_mfma_f32_16x16x4f32(af[c], th[sb][c], z, 0, 0, 0);
+      float r[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) r[i] = ya[i] - sigmoidf_fast(z[i]);
+#pragma unroll
+      for (int ct = 0; ct < C2; ++ct) {
+        const float bb[4] = {b4[ct].x, b4[ct].y, b4[ct].z, b4[ct].w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          gacc[sb][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(r[i], bb[i], gacc[sb][ct], 0, 0, 0);
+      }
+    }
+  }
+
+  // partial gradient of this split: gpart[work item][slot][k]
+  float *gp = D.gpart + (long long)blockIdx.x * TJ * D.DS;
+#pragma unroll
+  for (int sb = 0; sb < SUB; ++sb)
+#pragma unroll
+    for (int ct = 0; ct < C2; ++ct)
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int slot = wave * 32 + sb * 16 + 4 * kq + rr;
+        gp[(long long)slot * D.DS + 16 * ct + (lane & 15)] = gacc[sb][ct][rr];
+      }
+
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int last = 1;
+    if (pl.S > 1) {
+      int *cnt = D.tilecnt + pl.b * (D.Jcap / TJ) + pl.tile;
+      const int old = atomicAdd(cnt, 1);
+      last = (old == pl.S - 1);
+      if (last) atomicExch(cnt, 0);
+    }
+    slast = last;
+  }
+  __syncthreads();
+  if (!slast) return;
+  __threadfence();
+
+  // epilogue: sum partials in split order, prior term, second half kick
+  const int dp = 16 * C2;
+  const float inv_pv = (float)(1.0 / D.prior_var);
+  const float *g0p = D.gpart + (long long)pl.wbase * TJ * D.DS;
+  for (int idx = threadIdx.x; idx < TJ * dp; idx += WG) {
+    const int slot = idx / dp, k = idx % dp;
+    const int j = perm[pl.tile * TJ + slot];
+    const long long row = P.row0 + j;
+    if (D.n[row] <= s) continue;
+    float G = 0.f;
+    for (int sp = 0; sp < pl.S; ++sp) G += g0p[((long long)sp * TJ + slot) * D.DS + k];
+    const long long e = row * D.DS + k;
+    const float t0 = D.theta_t[e], p0 = D.p_t[e], g0 = D.grad_t[e];
+    const float ph = fmaf(he, g0, p0);
+    const float th1 = fmaf(eps * minv[k], ph, t0);
+    G = G - th1 * inv_pv;
+    D.theta_t[e] = th1;
+    D.p_t[e] = fmaf(he, G, ph);
+    D.grad_t[e] = G;
+  }
+}
+
+template <int C2>
+static hipError_t launch_lf_c2(const Dev &D, int step, int zero_eps, hipStream_t st) {
+  hipLaunchKernelGGL(k_leapfrog<C2>, dim3(D.lf_grid), dim3(WG), 0, st, D, step, zero_eps);
+  return hipGetLastError();
+}
+
+hipError_t launch_leapfrog(const Dev &D, int c2, int step, int zero_eps, hipStream_t st) {
+  switch (c2) {
+    case 1: return launch_lf_c2<1>(D, step, zero_eps, st);
+    case 2: return launch_lf_c2<2>(D, step, zero_eps, st);
+    case 3: return launch_lf_c2<3>(D, step, zero_eps, st);
+    case 4: return launch_lf_c2<4>(D, step, zero_eps, st);
+    case 5: return launch_lf_c2<5>(D, step, zero_eps, st);
+    case 6: return launch_lf_c2<6>(D, step, zero_eps, st);
+    case 7: return launch_lf_c2<7>(D, step, zero_eps, st);
+    case 8: return launch_lf_c2<8>(D, step, zero_eps, st);
+    case 9: return launch_lf_c2<9>(D, step, zero_eps, st);
+    case 10: return launch_lf_c2<10>(D, step, zero_eps, st);
+    case 11: return launch_lf_c2<11>(D, step, zero_eps, st);
+    case 12: return launch_lf_c2<12>(D, step, zero_eps, st);
+    case 13: return launch_lf_c2<13>(D, step, zero_eps, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// Log-likelihood at the trajectory end points, recomputed for the energies:
+//   sum_n [ y_n z_n - log(1 + e^{z_n}) ],  z = X theta'   (Sec. IV model)
+// with accurate expf/log1pf and a Neumaier-compensated FP32 sum per lane;
+// lane partials are merged with error-free TwoSum, splits in order later.
+// ---------------------------------------------------------------------------
+struct Neu {
+  float s, c;
+};
+__device__ __forceinline__ void neu_add(Neu &a, float x) {
+  const float t = a.s + x;
+  if (fabsf(a.s) >= fabsf(x))
+    a.c += (a.s - t) + x;
+  else
+    a.c += (x - t) + a.s;
+  a.s = t;
+}
+__device__ __forceinline__ Neu neu_merge(Neu a, Neu b) {
+  Neu r;
+  const float t = a.s + b.s;
+  const float bp = t - a.s;
+  const float e = (a.s - (t - bp)) + (b.s - bp);  // TwoSum error
+  r.s = t;
+  r.c = (a.c + b.c) + e;
+  return r;
+}
+
+template <int C2>
+__global__ __launch_bounds__(WG) void k_loglik(Dev D) {
+  constexpr int K1 = 4 * C2;
+  const int4 it = D.ll_items[blockIdx.x];
+  const int b = it.x, tile = it.y, split = it.z;
+  const Post P = D.posts[b];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, kq = lane >> 4;
+  const int C1 = P.C1;
+  float th[SUB][K1];
+#pragma unroll
+  for (int sb = 0; sb < SUB; ++sb) {
+    const long long base =
+        (long long)(P.row0 + tile * TJ + wave * 32 + sb * 16 + (lane & 15)) * D.DS;
+#pragma unroll
+    for (int c = 0; c < K1; ++c) th[sb][c] = (c < C1) ? D.theta_t[base + kq * C1 + c] : 0.f;
+  }
+  Neu acc[SUB];
+#pragma unroll
+  for (int sb = 0; sb < SUB; ++sb) acc[sb] = Neu{0.f, 0.f};
+  const int S = P.ll_splits;
+  const int t0 = (int)((long long)split * P.NT / S);
+  const int t1 = (int)((long long)(split + 1) * P.NT / S);
+  const float4 *xa = reinterpret_cast<const float4 *>(D.xa + P.xa);
+  const float4 *yv = reinterpret_cast<const float4 *>(D.yp + P.yo);
+  for (int t = t0; t < t1; ++t) {
+    float4 a4[C2];
+    const long long o = ((long long)t * 64 + lane) * C2;
+#pragma unroll
+    for (int q = 0; q < C2; ++q) a4[q] = xa[o + q];
+    const float4 y4 = yv[t * 4 + kq];
+    const float ya[4] = {y4.x, y4.y, y4.z, y4.w};
+    const float *af = reinterpret_cast<const float *>(a4);
+#pragma unroll
+    for (int sb = 0; sb < SUB; ++sb) {
+      v4f z = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int c = 0; c < K1; ++c)
+        if (c < C1) z = __builtin_amdgcn_mfma_f32_16x16x4f32(af[c], th[sb][c], z, 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int n = 16 * t + 4 * kq + i;
+        if (n < P.N) {
+          // y z - softplus(z) = -softplus(-z) for y = 1, -softplus(z) for y = 0
+          const float zz = ya[i] > 0.5f ? -z[i] : z[i];
+          const float sp = fmaxf(zz, 0.f) + log1pf(expf(-fabsf(zz)));
+          neu_add(acc[sb], -sp);
+        }
+      }
+    }
+  }
+  // merge the four lanes (kq = 0..3) that hold the same particle
+#pragma unroll
+  for (int sb = 0; sb < SUB; ++sb) {
+    Neu a = acc[sb];
+    for (int o = 16; o <= 32; o <<= 1) {
+      Neu bq;
+      bq.s = __shfl_xor(a.s, o, 64);
+      bq.c = __shfl_xor(a.c, o, 64);
+      // merge in a fixed (lower lane first) order so both lanes agree
+      a = (lane & o) ? neu_merge(bq, a) : neu_merge(a, bq);
+    }
+    if (kq == 0) {
+      const long long row = P.row0 + tile * TJ + wave * 32 + sb * 16 + lane;
+      D.llpart[(long long)split * D.B * D.Jcap + row] = make_float2(a.s, a.c);
+    }
+  }
+}
+
+template <int C2>
+static hipError_t launch_ll_c2(const Dev &D, hipStream_t st) {
+  hipLaunchKernelGGL(k_loglik<C2>, dim3(D.ll_nitems), dim3(WG), 0, st, D);
+  return hipGetLastError();
+}
+
+hipError_t launch_loglik(const Dev &D, int c2, hipStream_t st) {
+  switch (c2) {
+    case 1: return launch_ll_c2<1>(D, st);
+    case 2: return launch_ll_c2<2>(D, st);
+    case 3: return launch_ll_c2<3>(D, st);
+    case 4: return launch_ll_c2<4>(D, st);
+    case 5: return launch_ll_c2<5>(D, st);
+    case 6: return launch_ll_c2<6>(D, st);
+    case 7: return launch_ll_c2<7>(D, st);
+    case 8: return launch_ll_c2<8>(D, st);
+    case 9: return launch_ll_c2<9>(D, st);
+    case 10: return launch_ll_c2<10>(D, st);
+    case 11: return launch_ll_c2<11>(D, st);
+    case 12: return launch_ll_c2<12>(D, st);
+    case 13: return launch_ll_c2<13>(D, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// Per-row helpers: one wave per particle row.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double row_loglik(const Dev &D, const Post &P, long long row) {
+  double ll = 0.0;
+  for (int sp = 0; sp < P.ll_splits; ++sp) {
+    const float2 v = D.llpart[(long long)sp * D.B * D.Jcap + row];
+    ll += (double)v.x + (double)v.y;
+  }
+  return ll;
+}
+
+// log q0(theta) = -|theta|^2 / (2 prior_var) - d/2 log(2 pi prior_var), FP64.
+__device__ __forceinline__ double row_log_prior(const Dev &D, const Post &P, const float *th,
+                                                int lane) {
+  double sq = 0.0;
+  for (int c = lane; c < P.d; c += 64) sq += (double)th[c] * (double)th[c];
+  sq = wave_sum(sq);
+  return -0.5 * sq / D.prior_var - 0.5 * P.d * log(2.0 * 3.141592653589793 * D.prior_var);
+}
+
+// 1/2 p^T M^{-1} p, FP64 (kinetic energy, Sec. II-A).
+__device__ __forceinline__ double row_kinetic(const Dev &D, const Post &P, const float *p,
+                                              const float *mv, int lane) {
+  double k = 0.0;
+  for (int c = lane; c < P.d; c += 64) k += (double)mv[c] * (double)p[c] * (double)p[c];
+  return 0.5 * wave_sum(k);
+}
+
+// ---------------------------------------------------------------------------
+// Initial weights (eq. init_weights): log w = log pi - log q0 - log J, which is
+// the log-likelihood minus log J; log pi and the gradient become the state.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_init_weights(Dev D) {
+  const int lane = threadIdx.x & 63;
+  const long long row = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= (long long)D.B * D.Jcap) return;
+  const int b = (int)(row / D.Jcap), j = (int)(row % D.Jcap);
+  const Post P = D.posts[b];
+  const float *th = D.theta_t + row * D.DS;
+  for (int c = lane; c < D.DS; c += 64) {
+    D.theta[row * D.DS + c] = th[c];
+    D.grad[row * D.DS + c] = D.grad_t[row * D.DS + c];
+  }
+  if (j >= D.J) {
+    if (lane == 0) {
+      D.logw[row] = -INFINITY;
+      D.logpi[row] = 0.0;
+    }
+    return;
+  }
+  const double ll = row_loglik(D, P, row);
+  const double lp = row_log_prior(D, P, th, lane);
+  if (lane == 0) {
+    D.logpi[row] = ll + lp;
+    D.logw[row] = ll - log((double)D.J);
+  }
+}
+
+hipError_t launch_init_weights(const Dev &D, hipStream_t st) {
+  const long long rows = (long long)D.B * D.Jcap;
+  hipLaunchKernelGGL(k_init_weights, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st, D);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Start of an SMC iteration (Alg. smc_BNN): count k, and when J_eff < ess_frac J
+// (or unconditionally for an explicit resample) resample with probability
+// w~ (Sec. III).  One 1024-thread work group per posterior.
+//
+// Integer fixed-point scheme: Q_j = floor(exp(log w_j - m) 2^40), exact uint64
+// inclusive scan C, T = C_J.  Systematic: a_i = min{j : C_j (J 2^32) >
+// (i 2^32 + U) T} with U = floor(u 2^32), compared exactly in 128 bits.
+// Multinomial: a_i = min{j : C_j 2^32 > U_i T}.  The evidence accumulator
+// takes LSE(log w) = m + log S before the weights are reset to 1/J.
+// ---------------------------------------------------------------------------
+__device__ int upper_search(const unsigned long long *C, int J, unsigned __int128 lhs_num,
+                            unsigned long long scale) {
+  // smallest j with C[j] * scale > lhs_num
+  int lo = 0, hi = J - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if ((unsigned __int128)C[mid] * scale > lhs_num)
+      hi = mid;
+    else
+      lo = mid + 1;
+  }
+  return lo;
+}
+
+__device__ void quantise_scan(const double *lw, double m, int J, unsigned long long *cdf,
+                              unsigned long long *sh) {
+  // each thread takes a contiguous chunk; chunk sums are scanned in LDS
+  const int nt = blockDim.x, t = threadIdx.x;
+  const int chunk = (J + nt - 1) / nt;
+  const int j0 = min(J, t * chunk), j1 = min(J, j0 + chunk);
+  unsigned long long local = 0;
+  for (int j = j0; j < j1; ++j) {
+    const double v = lw[j];
+    unsigned long long q = 0;
+    if (v == v && v > -INFINITY) q = (unsigned long long)floor(exp(v - m) * 1099511627776.0);
+    local += q;
+    cdf[j] = local;
+  }
+  sh[t] = local;
+  __syncthreads();
+  // inclusive Hillis-Steele scan over the chunk sums
+  for (int o = 1; o < nt; o <<= 1) {
+    const unsigned long long v = t >= o ? sh[t - o] : 0ull;
+    __syncthreads();
+    sh[t] += v;
+    __syncthreads();
+  }
+  const unsigned long long off = t > 0 ? sh[t - 1] : 0ull;
+  for (int j = j0; j < j1; ++j) cdf[j] += off;
+  __syncthreads();
+}
+
+__device__ __forceinline__ unsigned long long u_to_u32(double u) {
+  double v = floor(u * 4294967296.0);
+  if (v < 0.0) v = 0.0;
+  if (v > 4294967295.0) v = 4294967295.0;
+  return (unsigned long long)v;
+}
+
+__global__ __launch_bounds__(1024) void k_begin_step(Dev D, int conditional, const double *u,
+                                                     int count_iteration) {
+  __shared__ unsigned long long sh[1024];
+  const int b = blockIdx.x, t = threadIdx.x;
+  PState &S = D.ps[b];
+  const Post P = D.posts[b];
+  const int J = D.J;
+  // per-step counters and the step-count histogram
+  for (int i = t; i <= D.nmax; i += blockDim.x) D.hist[b * (D.nmax + 1) + i] = 0;
+  __syncthreads();
+  const int k = S.k + (count_iteration ? 1 : 0);
+  const int doit = conditional ? S.flag_resample : 1;
+  const int ok = S.S > 0.0;
+  __syncthreads();
+  if (t == 0) {
+    if (count_iteration) {
+      S.k = k;
+      S.grad_evals_step = 0;
+      S.ess_before = S.ess;
+    }
+    S.resampled = (doit && ok) ? 1 : 0;
+  }
+  if (!(doit && ok)) return;
+  unsigned long long *cdf = D.cdf + P.row0;
+  quantise_scan(D.logw + P.row0, S.m, J, cdf, sh);
+  const unsigned long long T = cdf[J - 1];
+  const int chunk = (J + blockDim.x - 1) / blockDim.x;
+  const int i0 = min(J, t * chunk), i1 = min(J, i0 + chunk);
+  if (D.resampling == 0) {
+    const double u0 = u ? u[b] : u01(philox_at(D.seed, 0, (uint32_t)b, (uint32_t)k, STREAM_RESAMPLE).x);
+    const unsigned long long U = u_to_u32(u0);
+    const unsigned long long scale = (unsigned long long)J << 32;
+    for (int i = i0; i < i1; ++i) {
+      const unsigned __int128 lhs = (unsigned __int128)(((unsigned long long)i << 32) + U) * T;
+      D.anc[P.row0 + i] = upper_search(cdf, J, lhs, scale);
+    }
+  } else {
+    for (int i = i0; i < i1; ++i) {
+      const double ui = u ? u[(long long)b * J + i]
+                          : u01(philox_at(D.seed, 0, (uint32_t)(b * J + i), (uint32_t)k, STREAM_RESAMPLE).x);
+      const unsigned __int128 lhs = (unsigned __int128)u_to_u32(ui) * T;
+      D.anc[P.row0 + i] = upper_search(cdf, J, lhs, 4294967296ull);
+    }
+  }
+  if (t == 0) {
+    S.log_c += S.m + log(S.S);
+    S.tot_resamples += 1;
+  }
+}
+
+hipError_t launch_begin_step(const Dev &D, int conditional, const double *u, int count_iteration,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_begin_step, dim3(D.B), dim3(1024), 0, st, D, conditional, u,
+                     count_iteration);
+  return hipGetLastError();
+}
+
+// Gather the chosen ancestors into the trajectory buffers and reset the weights
+// to 1/J (Alg. smc_BNN).  One wave per row.
+__global__ __launch_bounds__(256) void k_gather(Dev D, int *anc_out) {
+  const int lane = threadIdx.x & 63;
+  const long long row = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= (long long)D.B * D.Jcap) return;
+  const int b = (int)(row / D.Jcap), j = (int)(row % D.Jcap);
+  if (j >= D.J || !D.ps[b].resampled) return;
+  const long long src = (long long)b * D.Jcap + D.anc[row];
+  for (int c = lane; c < D.DS; c += 64) {
+    D.theta_t[row * D.DS + c] = D.theta[src * D.DS + c];
+    D.grad_t[row * D.DS + c] = D.grad[src * D.DS + c];
+  }
+  if (lane == 0) {
+    D.logpi_t[row] = D.logpi[src];
+    D.logw[row] = -log((double)D.J);
+    if (anc_out) anc_out[(long long)b * D.J + j] = D.anc[row];
+  }
+}
+
+hipError_t launch_gather(const Dev &D, int *anc_out, hipStream_t st) {
+  const long long rows = (long long)D.B * D.Jcap;
+  hipLaunchKernelGGL(k_gather, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st, D, anc_out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Trajectory set-up (Alg. smc_ChEES): momenta p = xi M^{1/2}, jitter h_jk,
+// l_j = h_j L, n_j = min(max(ceil(l_j / eps), 1), n_max) in binary64, initial
+// energy H0 = -log pi + 1/2 p^T M^{-1} p, and the step-count histogram.
+// Also moves a freshly resampled population back into the state buffers, or
+// copies the state into the trajectory buffers.  One wave per row.
+// init_mode = 2: copy the trajectory buffers back only (explicit resample).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double radical_inverse(unsigned long long i, unsigned long long base) {
+  unsigned long long r = 0, bm = 1;
+  while (i > 0) {
+    const unsigned long long dig = i % base;
+    i /= base;
+    r = r * base + dig;
+    bm *= base;
+  }
+  return (double)r / (double)bm;
+}
+
+__device__ __forceinline__ double radical_inverse2(unsigned long long i) {
+  const int m = 64 - __clzll((long long)i);
+  const unsigned long long r = __builtin_bitreverse64(i) >> (64 - m);
+  return (double)r / (double)(1ull << m);
+}
+
+__global__ __launch_bounds__(256) void k_setup(Dev D, const float *__restrict__ momenta,
+                                               int init_mode) {
+  const int lane = threadIdx.x & 63;
+  const long long row = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= (long long)D.B * D.Jcap) return;
+  const int b = (int)(row / D.Jcap), j = (int)(row % D.Jcap);
+  PState &S = D.ps[b];
+  const Post P = D.posts[b];
+  const long long o = row * D.DS;
+  if (j >= D.J) {
+    if (lane == 0 && init_mode != 2) {
+      D.n[row] = 0;
+      D.h[row] = 0.0;
+      D.l[row] = 0.0;
+    }
+    return;
+  }
+  const int resampled = S.resampled;
+  if (resampled) {
+    for (int c = lane; c < D.DS; c += 64) {
+      D.theta[o + c] = D.theta_t[o + c];
+      D.grad[o + c] = D.grad_t[o + c];
+    }
+    if (lane == 0) D.logpi[row] = D.logpi_t[row];
+  } else if (init_mode != 2) {
+    for (int c = lane; c < D.DS; c += 64) {
+      D.theta_t[o + c] = D.theta[o + c];
+      D.grad_t[o + c] = D.grad[o + c];
+    }
+  }
+  if (init_mode == 2) return;
+  const int k = S.k;
+  const float *mv = D.minv + (long long)b * D.DS;
+  // momenta: lane q covers columns 4q .. 4q+3 (one Philox block); the kinetic
+  // energy is accumulated from the values written
+  double kin = 0.0;
+  for (int q = lane; q * 4 < D.DS; q += 64) {
+    double xi[4] = {0, 0, 0, 0};
+    if (4 * q < P.d) {
+      if (momenta) {
+        for (int r = 0; r < 4; ++r)
+          if (4 * q + r < P.d) xi[r] = momenta[P.uoff + (long long)j * P.d + 4 * q + r];
+      } else {
+        box_muller4(philox_at(D.seed, q, (uint32_t)(b * D.J + j), (uint32_t)k, STREAM_MOMENTUM), xi);
+      }
+    }
+    for (int r = 0; r < 4; ++r) {
+      const int c = 4 * q + r;
+      float pv = 0.f;
+      if (c < P.d) {
+        const float x = (float)xi[r];
+        pv = D.precond ? x / sqrtf(mv[c]) : x;
+        kin += (double)mv[c] * (double)pv * (double)pv;
+      }
+      D.p_t[o + c] = pv;
+    }
+  }
+  const double K0 = 0.5 * wave_sum(kin);
+  if (lane == 0) {
+    double h;
+    if (D.jitter == 1)
+      h = 1.0;
+    else if (D.jitter == 2)
+      h = radical_inverse((unsigned long long)(j + 1), (unsigned long long)D.primes[min(k, NPRIMES) - 1]);
+    else
+      h = radical_inverse2((unsigned long long)(k - 1) * D.J + (unsigned long long)(j + 1));
+    const double L = S.L, eps = S.eps;
+    const double l = h * L;
+    double nn = ceil(l / eps);
+    nn = fmin(fmax(nn, 1.0), (double)D.nmax);
+    const int n = (int)nn;
+    D.h[row] = h;
+    D.l[row] = l;
+    D.n[row] = n;
+    D.H0[row] = -D.logpi[row] + K0;
+    atomicAdd(&D.hist[b * (D.nmax + 1) + n], 1);
+    atomicAdd((unsigned long long *)&S.grad_evals_step, (unsigned long long)n);
+    if (j == 0) {
+      S.L_used = L;
+      S.eps_used = eps;
+    }
+  }
+}
+
+hipError_t launch_setup(const Dev &D, const float *momenta, int init_mode, hipStream_t st) {
+  const long long rows = (long long)D.B * D.Jcap;
+  hipLaunchKernelGGL(k_setup, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st, D, momenta,
+                     init_mode);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Counting sort of the particles by n_j, longest first, so that a leapfrog
+// tile holds particles of similar trajectory length; active[s] = #{j: n_j > s}.
+// Placement within a bin is arbitrary: each particle's arithmetic does not
+// depend on its tile or lane.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_sort(Dev D) {
+  extern __shared__ int cur[];  // nmax + 1
+  const int b = blockIdx.x;
+  const int *hist = D.hist + b * (D.nmax + 1);
+  if (threadIdx.x == 0) {
+    int pos = 0;
+    for (int n = D.nmax; n >= 0; --n) {
+      cur[n] = pos;
+      pos += (n == 0) ? (D.Jcap - D.J) + hist[0] : hist[n];
+    }
+    int *act = D.active + b * (D.nmax + 1);
+    for (int s = 0; s <= D.nmax; ++s) act[s] = (s < D.nmax) ? cur[s] : 0;
+  }
+  __syncthreads();
+  const int row0 = b * D.Jcap;
+  for (int j = threadIdx.x; j < D.Jcap; j += blockDim.x) {
+    const int n = D.n[row0 + j];
+    const int p = atomicAdd(&cur[n], 1);
+    D.perm[row0 + p] = j;
+  }
+}
+
+hipError_t launch_sort(const Dev &D, hipStream_t st) {
+  hipLaunchKernelGGL(k_sort, dim3(D.B), dim3(1024), (D.nmax + 1) * sizeof(int), st, D);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Energies and weights after the trajectories.
+//   Delta H = H(theta', p') - H(theta, p), non-finite -> +inf   (Sec. II-A)
+//   alpha = min(1, exp(-Delta H))                 (eq. HMC_accept_reject)
+//   SMC-ChEES (no accept/reject, Sec. III-A): log w += -Delta H, the
+//     momentum change-of-variables L-kernel (eqs. proposal_momentum,
+//     l-kernel_momentum, l_weights) whose Jacobians cancel;
+//   MH mode: accept iff u < alpha (eq. mh_ratio_rn), weight unchanged.
+// One wave per row.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_weights(Dev D, const double *__restrict__ mh_u) {
+  const int lane = threadIdx.x & 63;
+  const long long row = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= (long long)D.B * D.Jcap) return;
+  const int b = (int)(row / D.Jcap), j = (int)(row % D.Jcap);
+  if (j >= D.J) return;
+  const Post P = D.posts[b];
+  const PState &S = D.ps[b];
+  const float *th = D.theta_t + row * D.DS;
+  const float *mv = D.minv + (long long)b * D.DS;
+  const double ll = row_loglik(D, P, row);
+  const double lp = row_log_prior(D, P, th, lane);
+  const double K1 = row_kinetic(D, P, D.p_t + row * D.DS, mv, lane);
+  if (lane != 0) return;
+  const double logpi1 = ll + lp;
+  double dh = (-logpi1 + K1) - D.H0[row];
+  if (!(dh == dh) || dh == INFINITY || dh == -INFINITY) dh = INFINITY;
+  const double alpha = fmin(1.0, exp(-dh));
+  D.logpi_t[row] = logpi1;
+  D.dH[row] = dh;
+  D.alpha[row] = alpha;
+  if (D.mh) {
+    const double u = mh_u ? mh_u[(long long)b * D.J + j]
+                          : u01(philox_at(D.seed, 0, (uint32_t)(b * D.J + j), (uint32_t)S.k, STREAM_MH).x);
+    D.accepted[row] = u < alpha ? 1 : 0;
+  } else {
+    D.accepted[row] = 1;
+    const double w = D.logw[row];
+    D.logw[row] = (dh == INFINITY) ? -INFINITY : w - dh;
+  }
+}
+
+hipError_t launch_weights(const Dev &D, const double *mh_u, int init_mode, hipStream_t st) {
+  (void)init_mode;
+  const long long rows = (long long)D.B * D.Jcap;
+  hipLaunchKernelGGL(k_weights, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st, D, mh_u);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// ChEES statistics (Sec. II-C, Alg. smc_ChEES), FP64 accumulation:
+//   theta_hat' = mean theta', theta_hat = mean theta (unweighted),
+//   a_j = |theta'_j - theta_hat'|^2 - |theta_j - theta_hat|^2,
+//   g_j = l_j a_j (theta'_j - theta_hat')^T M^{-1} p'_j,
+//   g_hat = sum alpha_j g_j / sum alpha_j,  ChEES = 1/4 mean a_j^2.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_colsum(Dev D) {
+  // grid (col_chunks, B); 4 row lanes x 64 columns per column group
+  __shared__ double sh[2][4][64];
+  const int b = blockIdx.y, ch = blockIdx.x;
+  const int rl = threadIdx.x >> 6, cl = threadIdx.x & 63;
+  const int rows_per = (D.J + D.col_chunks - 1) / D.col_chunks;
+  const int r0 = ch * rows_per, r1 = min(D.J, r0 + rows_per);
+  for (int cg = 0; cg * 64 < D.DS; ++cg) {
+    const int c = cg * 64 + cl;
+    double s0 = 0.0, s1 = 0.0;
+    if (c < D.DS)
+      for (int r = r0 + rl; r < r1; r += 4) {
+        const long long o = ((long long)b * D.Jcap + r) * D.DS + c;
+        s0 += (double)D.theta[o];
+        s1 += (double)D.theta_t[o];
+      }
+    sh[0][rl][cl] = s0;
+    sh[1][rl][cl] = s1;
+    __syncthreads();
+    if (rl == 0 && c < D.DS) {
+      double *out = D.colpart + (((long long)b * D.col_chunks + ch) * 2) * D.DS;
+      out[c] = ((sh[0][0][cl] + sh[0][1][cl]) + sh[0][2][cl]) + sh[0][3][cl];
+      out[D.DS + c] = ((sh[1][0][cl] + sh[1][1][cl]) + sh[1][2][cl]) + sh[1][3][cl];
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_colmean(Dev D) {
+  const int b = blockIdx.x;
+  for (int c = threadIdx.x; c < 2 * D.DS; c += blockDim.x) {
+    const int which = c / D.DS, col = c % D.DS;
+    double s = 0.0;
+    for (int ch = 0; ch < D.col_chunks; ++ch)
+      s += D.colpart[(((long long)b * D.col_chunks + ch) * 2 + which) * D.DS + col];
+    D.means[((long long)b * 2 + which) * D.DS + col] = s / D.J;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_chees_row(Dev D) {
+  const int lane = threadIdx.x & 63;
+  const long long row = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= (long long)D.B * D.Jcap) return;
+  const int b = (int)(row / D.Jcap), j = (int)(row % D.Jcap);
+  if (j >= D.J) return;
+  const Post P = D.posts[b];
+  const double *mo = D.means + (long long)b * 2 * D.DS;  // theta_hat
+  const double *mn = mo + D.DS;                           // theta_hat'
+  const float *mv = D.minv + (long long)b * D.DS;
+  const long long o = row * D.DS;
+  double an = 0.0, ao = 0.0, dt = 0.0;
+  for (int c = lane; c < P.d; c += 64) {
+    const double cn = (double)D.theta_t[o + c] - mn[c];
+    const double co = (double)D.theta[o + c] - mo[c];
+    an += cn * cn;
+    ao += co * co;
+    dt += cn * (double)mv[c] * (double)D.p_t[o + c];
+  }
+  an = wave_sum(an);
+  ao = wave_sum(ao);
+  dt = wave_sum(dt);
+  if (lane == 0) {
+    const double a = an - ao;
+    D.ca[row] = a;
+    D.cg[row] = D.l[row] * a * dt;
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_chees_reduce(Dev D) {
+  __shared__ double sh[16];
+  const int b = blockIdx.x;
+  const long long r0 = (long long)b * D.Jcap;
+  const int chunk = (D.J + blockDim.x - 1) / blockDim.x;
+  const int j0 = min(D.J, (int)threadIdx.x * chunk), j1 = min(D.J, j0 + chunk);
+  double sag = 0, sa = 0, sa2 = 0, sinv = 0;
+  for (int j = j0; j < j1; ++j) {
+    const double al = D.alpha[r0 + j], a = D.ca[r0 + j];
+    sag += al * D.cg[r0 + j];
+    sa += al;
+    sa2 += a * a;
+    sinv += 1.0 / fmax(al, 1e-20);
+  }
+  sag = block_reduce(sag, sh, OpAdd());
+  sa = block_reduce(sa, sh, OpAdd());
+  sa2 = block_reduce(sa2, sh, OpAdd());
+  sinv = block_reduce(sinv, sh, OpAdd());
+  if (threadIdx.x == 0) {
+    PState &S = D.ps[b];
+    S.sum_alpha = sa;
+    S.ghat = sa > 0.0 ? sag / sa : 0.0;
+    S.chees = 0.25 * sa2 / D.J;
+    S.sum_alpha_all = sa;
+    S.sum_inv_alpha = sinv;
+  }
+}
+
+hipError_t launch_chees(const Dev &D, hipStream_t st) {
+  const long long rows = (long long)D.B * D.Jcap;
+  hipLaunchKernelGGL(k_colsum, dim3(D.col_chunks, D.B), dim3(256), 0, st, D);
+  hipLaunchKernelGGL(k_colmean, dim3(D.B), dim3(256), 0, st, D);
+  hipLaunchKernelGGL(k_chees_row, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st, D);
+  hipLaunchKernelGGL(k_chees_reduce, dim3(D.B), dim3(1024), 0, st, D);
+  return hipGetLastError();
+}
+
+// Accepted proposals become the state (all of them in SMC-ChEES mode).
+__global__ void k_commit(Dev D) {
+  const long long tot = (long long)D.B * D.Jcap * D.DS;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+       e += (long long)gridDim.x * blockDim.x) {
+    const long long row = e / D.DS;
+    const int j = (int)(row % D.Jcap);
+    if (j >= D.J || !D.accepted[row]) continue;
+    D.theta[e] = D.theta_t[e];
+    D.grad[e] = D.grad_t[e];
+    if (e % D.DS == 0) D.logpi[row] = D.logpi_t[row];
+  }
+}
+
+hipError_t launch_commit(const Dev &D, hipStream_t st) {
+  hipLaunchKernelGGL(k_commit, dim3(2048), dim3(256), 0, st, D);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Normalisation terms and ESS (eqs. normalise_smc2, ess_smc), FP64:
+//   m = max log w, S = sum e^{log w - m}, S2 = sum e^{2(log w - m)},
+//   J_eff = S^2 / S2; resample next iff J_eff < ess_frac J.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_ess(Dev D, int count) {
+  __shared__ double sh[16];
+  const int b = blockIdx.x;
+  const double *lw = D.logw + (long long)b * D.Jcap;
+  const int chunk = (D.J + blockDim.x - 1) / blockDim.x;
+  const int j0 = min(D.J, (int)threadIdx.x * chunk), j1 = min(D.J, j0 + chunk);
+  double m = -INFINITY;
+  for (int j = j0; j < j1; ++j) {
+    const double v = lw[j];
+    if (v == v && v > m) m = v;
+  }
+  m = block_reduce(m, sh, OpMax());
+  double s = 0.0, s2 = 0.0;
+  if (m > -INFINITY)
+    for (int j = j0; j < j1; ++j) {
+      const double v = lw[j];
+      if (v == v && v > -INFINITY) {
+        const double e = exp(v - m);
+        s += e;
+        s2 += e * e;
+      }
+    }
+  s = block_reduce(s, sh, OpAdd());
+  s2 = block_reduce(s2, sh, OpAdd());
+  if (threadIdx.x == 0) {
+    PState &S = D.ps[b];
+    S.m = m;
+    S.S = s;
+    S.S2 = s2;
+    S.ess = s > 0.0 ? s * s / s2 : 0.0;
+    S.degenerate = !(s > 0.0);
+    S.flag_resample = S.ess < D.ess_frac * D.J;
+    if (count) {
+      S.tot_iters += 1;
+      S.tot_ess += S.ess;
+      S.tot_grad_evals += S.grad_evals_step;
+    }
+  }
+}
+
+hipError_t launch_ess(const Dev &D, int count, hipStream_t st) {
+  hipLaunchKernelGGL(k_ess, dim3(D.B), dim3(1024), 0, st, D, count);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Warm-up adaptation after step k (Alg. smc_ChEES): Adam ascent on log L with
+// g_hat (Kingma and Ba), L_bar moving average, freeze at k = M_warmup.
+// Optional Adam on log eps toward a harmonic-mean acceptance target.
+// ---------------------------------------------------------------------------
+__device__ double adam_ascend(double x, double g, double &m, double &v, int &t, double lr,
+                              double b1, double b2, double ae) {
+  t += 1;
+  m = b1 * m + (1.0 - b1) * g;
+  v = b2 * v + (1.0 - b2) * g * g;
+  const double mhat = m / (1.0 - pow(b1, (double)t));
+  const double vhat = v / (1.0 - pow(b2, (double)t));
+  return x + lr * mhat / (sqrt(vhat) + ae);
+}
+
+__global__ void k_adapt(Dev D) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= D.B) return;
+  PState &S = D.ps[b];
+  const int k = S.k;
+  if (k < D.num_warmup) {
+    if (S.sum_alpha > 0.0)
+      S.L = exp(adam_ascend(log(S.L), S.ghat, S.am, S.av, S.at, D.adam_lr, D.adam_b1, D.adam_b2,
+                            D.adam_eps));
+    S.Lbar = D.avg_decay * S.Lbar + (1.0 - D.avg_decay) * S.L;
+    if (D.adapt_eps) {
+      const double hm = (double)D.J / S.sum_inv_alpha;
+      S.eps = exp(adam_ascend(log(S.eps), hm - D.target_accept, S.em, S.ev, S.et, D.adam_lr,
+                              D.adam_b1, D.adam_b2, D.adam_eps));
+    }
+  } else if (k == D.num_warmup) {
+    S.L = S.Lbar;
+  }
+  S.adapted_k = k;
+}
+
+hipError_t launch_adapt(const Dev &D, hipStream_t st) {
+  hipLaunchKernelGGL(k_adapt, dim3((D.B + 63) / 64), dim3(64), 0, st, D);
+  return hipGetLastError();
+}
+
+__global__ void k_set_params(Dev D, double L, double eps) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= D.B) return;
+  D.ps[b].L = L;
+  D.ps[b].eps = eps;
+}
+
+hipError_t launch_set_params(const Dev &D, double L, double eps, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_params, dim3((D.B + 63) / 64), dim3(64), 0, st, D, L, eps);
+  return hipGetLastError();
+}
+
+// State export to caller layouts: theta (B*J) x d_b FP32, logw, logpi (B*J).
+__global__ void k_export(Dev D, float *theta, double *logw, double *logpi) {
+  const long long tot = (long long)D.B * D.J * D.DS;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int c = (int)(e % D.DS);
+    const long long bj = e / D.DS;
+    const int b = (int)(bj / D.J), j = (int)(bj % D.J);
+    const Post &P = D.posts[b];
+    const long long row = (long long)b * D.Jcap + j;
+    if (theta && c < P.d) theta[P.uoff + (long long)j * P.d + c] = D.theta[row * D.DS + c];
+    if (c == 0) {
+      if (logw) logw[bj] = D.logw[row];
+      if (logpi) logpi[bj] = D.logpi[row];
+    }
+  }
+}
+
+hipError_t launch_export_state(const Dev &D, float *theta, double *logw, double *logpi,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(k_export, dim3(1024), dim3(256), 0, st, D, theta, logw, logpi);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Stateless resampling of nonnegative weights (same integer scheme as above,
+// with e_j = w_j / max w).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_resample_indices(const double *w, int J, const double *u,
+                                                           int scheme, int *anc,
+                                                           unsigned long long *cdf, int *err) {
+  __shared__ unsigned long long sh[1024];
+  __shared__ double shd[16];
+  const int t = threadIdx.x;
+  const int chunk = (J + blockDim.x - 1) / blockDim.x;
+  const int j0 = min(J, t * chunk), j1 = min(J, j0 + chunk);
+  double mx = 0.0;
+  for (int j = j0; j < j1; ++j) mx = fmax(mx, w[j]);
+  mx = block_reduce(mx, shd, OpMax());
+  if (!(mx > 0.0)) {
+    if (t == 0) *err = 1;
+    return;
+  }
+  unsigned long long local = 0;
+  for (int j = j0; j < j1; ++j) {
+    const double v = w[j] / mx;
+    const unsigned long long q = (v > 0.0) ? (unsigned long long)floor(v * 1099511627776.0) : 0ull;
+    local += q;
+    cdf[j] = local;
+  }
+  sh[t] = local;
+  __syncthreads();
+  for (int o = 1; o < (int)blockDim.x; o <<= 1) {
+    const unsigned long long v = t >= o ? sh[t - o] : 0ull;
+    __syncthreads();
+    sh[t] += v;
+    __syncthreads();
+  }
+  const unsigned long long off = t > 0 ? sh[t - 1] : 0ull;
+  for (int j = j0; j < j1; ++j) cdf[j] += off;
+  __syncthreads();
+  const unsigned long long T = cdf[J - 1];
+  if (t == 0) *err = 0;
+  if (scheme == 0) {
+    const unsigned long long U = u_to_u32(u[0]);
+    const unsigned long long scale = (unsigned long long)J << 32;
+    for (int i = j0; i < j1; ++i) {
+      const unsigned __int128 lhs = (unsigned __int128)(((unsigned long long)i << 32) + U) * T;
+      anc[i] = upper_search(cdf, J, lhs, scale);
+    }
+  } else {
+    for (int i = j0; i < j1; ++i) {
+      const unsigned __int128 lhs = (unsigned __int128)u_to_u32(u[i]) * T;
+      anc[i] = upper_search(cdf, J, lhs, 4294967296ull);
+    }
+  }
+}
+
+hipError_t launch_resample_indices(const double *w, int J, const double *u, int scheme, int *anc,
+                                   unsigned long long *cdf, double *wmax, int *err,
+                                   hipStream_t st) {
+  (void)wmax;
+  hipLaunchKernelGGL(k_resample_indices, dim3(1), dim3(1024), 0, st, w, J, u, scheme, anc, cdf,
+                     err);
+  return hipGetLastError();
+}
+
+}  // namespace smc

@@ -1,0 +1,71 @@
+"""The C-ABI library loads and exports every function include/chees_smc.h
+declares.  No compute call is made (no GPU needed)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "chees_smc.h")
+
+
+def _declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*([a-z_][a-z0-9_]*)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def _lib():
+    from paper_2504_02627_amd import build, chees
+    if not os.path.exists(chees.LIB_PATH):
+        build.build()
+    return chees.load()
+
+
+def test_header_declares_the_boundary():
+    names = _declared_functions()
+    for required in ("smc_init", "smc_step", "chees_adapt", "resample", "log_evidence",
+                     "resample_indices", "smc_workspace_bytes", "smc_destroy"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib()
+    missing = [n for n in _declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_struct_sizes_match_c_layout():
+    from paper_2504_02627_amd import chees
+    # natural alignment: these sizes follow from the field lists of the header
+    assert ctypes.sizeof(chees.Params) == 4 * 8 + 8 * 8 + 4 + 4 + 8 + 8
+    assert ctypes.sizeof(chees.Stats) == 8 * 8 + 4 + 4 + 8
+    assert ctypes.sizeof(chees.Inject) == 3 * 8
+
+
+def test_workspace_query_validates_without_gpu():
+    from paper_2504_02627_amd import chees
+    lib = _lib()
+    n = (ctypes.c_int32 * 1)(200)
+    d = (ctypes.c_int32 * 1)(5)
+    X = (ctypes.c_void_p * 1)(0x1000)
+    y = (ctypes.c_void_p * 1)(0x2000)
+    prob = chees.Problem(1, n, d, X, y, chees.SMC_F32, 1.0)
+    par = chees.make_params(256, max_leapfrog=64)
+    assert lib.smc_workspace_bytes(ctypes.byref(prob), ctypes.byref(par)) > 0
+    bad = chees.make_params(0)
+    assert lib.smc_workspace_bytes(ctypes.byref(prob), ctypes.byref(bad)) == 0
+    d[0] = 209
+    assert lib.smc_workspace_bytes(ctypes.byref(prob), ctypes.byref(par)) == 0
+    assert lib.resample_workspace_bytes(0) == 0 and lib.resample_workspace_bytes(1000) >= 8000
+
+
+def test_binding_refuses_to_run_without_library(tmp_path, monkeypatch):
+    from paper_2504_02627_amd import chees
+    monkeypatch.setattr(chees, "_LIB", None)
+    monkeypatch.setattr(chees, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError):
+        chees.load()

@@ -1,0 +1,331 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle on the same
+seeded inputs and the same injected randomness.
+
+Bars (from the method's statement of parity):
+  * Halton jitter h and step counts n: bit-exact;
+  * resampling ancestors from identical weights and offset: bit-exact;
+  * one-iteration trajectories theta', p' on the FP32 path:
+      max_j ||theta'_j - theta'_j(oracle)||_inf / ||theta'_j(oracle)||_inf <= 1e-5;
+  * log-weights: |log w - log w(oracle)| <= 1e-5 (|H0| + |H1|) per particle.
+Discrete decisions are compared only from an identical state.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+from oracle import philox, smc as O
+from paper_2504_02627_amd import synth
+from tests._gpu_common import dev, log, oracle_for, rel_rows, to_dev
+
+pytestmark = pytest.mark.gpu
+
+TRAJ_TOL = 1e-5
+LOGW_TOL = 1e-5
+
+
+def _sampler(X, y, J, theta0=None, **kw):
+    import torch
+    from paper_2504_02627_amd import chees
+    return chees.Sampler(to_dev(X), to_dev(y), J, theta0=None if theta0 is None else to_dev(theta0), **kw)
+
+
+def _one_iteration(N, d, J, seed, mh=False, jitter="halton1d", resampling="systematic",
+                   nmax=64, eps=None, L=None, prior_var=1.0, inject=True):
+    log(f"[parity] N={N} d={d} J={J} seed={seed} mh={mh} jitter={jitter} resampling={resampling} nmax={nmax}")
+    X, y, _ = synth.logistic_iid(N, d, seed)
+    rng = np.random.default_rng(seed + 7)
+    theta0 = (rng.standard_normal((J, d)) * 0.3).astype(np.float32)
+    eps = eps if eps is not None else synth.default_step_size(N, d)
+    L = L if L is not None else eps * nmax / 2
+    params = dict(step_size=eps, traj_length=L, max_leapfrog=nmax, num_warmup=5, seed=seed,
+                  mh_accept=mh, jitter=jitter, resampling=resampling)
+    s = _sampler(X, y, J, theta0=theta0, prior_var=prior_var, **params)
+    o = oracle_for(X, y, J, theta0, prior_var=prior_var, **params)
+    if inject:
+        xi = rng.standard_normal((J, d)).astype(np.float32)
+        u_mh = rng.random(J)
+        u_rs = rng.random(J if resampling == "multinomial" else 1)
+        st = s.step(momenta=to_dev(xi), mh_uniforms=to_dev(u_mh), resample_u=to_dev(u_rs))
+        ost = o.step(momenta=xi.astype(np.float64), mh_uniforms=u_mh,
+                     resample_u=u_rs if resampling == "multinomial" else float(u_rs[0]))
+    else:
+        st = s.step()
+        ost = o.step()
+    return X, y, s, o, st, ost
+
+
+def _compare_iteration(s, o, st, ost, J, d):
+    tr = s.trace()
+    jc = tr["jcap"]
+    assert st["resampled"] == int(ost["resampled"])
+    if ost["resampled"]:
+        anc = tr["ancestors"].cpu().numpy()[:J]
+        np.testing.assert_array_equal(anc, ost["ancestors"])
+    h = tr["h"].cpu().numpy()[:J]
+    n = tr["n"].cpu().numpy()[:J]
+    np.testing.assert_array_equal(h, ost["h"])          # bit-exact
+    np.testing.assert_array_equal(n, ost["n"])          # bit-exact
+    th1 = tr["theta_prop"].cpu().numpy()[:J, :d].astype(np.float64)
+    p1 = tr["p_final"].cpu().numpy()[:J, :d].astype(np.float64)
+    et, ep = rel_rows(th1, ost["theta_prop"]), rel_rows(p1, ost["p1"])
+    log(f"  traj rel err theta {et:.2e} p {ep:.2e}")
+    assert et <= TRAJ_TOL and ep <= TRAJ_TOL
+    dh = tr["dH"].cpu().numpy()[:J]
+    scale = np.abs(ost["H0"]) + np.abs(ost["H1"])
+    assert np.all(np.abs(dh - ost["dh"]) <= LOGW_TOL * scale)
+    _, logw, logpi = s.state()
+    lw = logw.cpu().numpy()
+    fin = np.isfinite(ost["dh"])
+    err = np.abs(lw[fin] - o.logw[fin])
+    log(f"  logw max abs err {err.max():.2e}, max allowed {(LOGW_TOL * scale[fin]).min():.2e}")
+    assert np.all(err <= LOGW_TOL * scale[fin])
+    assert np.array_equal(np.isfinite(lw), np.isfinite(o.logw))
+    # ESS kernel: exact function of the device's own log-weights
+    assert st["ess"] == pytest.approx(O.ess(lw), rel=1e-12)
+    # ChEES statistics: same inputs in FP64 give the same value up to summation order
+    al = tr["alpha"].cpu().numpy()[:J]
+    ref = O.chees_statistics(ost["theta_before"], th1, p1, tr["l"].cpu().numpy()[:J], al)
+    assert st["chees_grad"] == pytest.approx(ref["ghat"], rel=1e-9, abs=1e-12)
+    assert st["chees"] == pytest.approx(ref["chees"], rel=1e-9, abs=1e-12)
+    # and against the oracle's own trajectories
+    assert st["chees"] == pytest.approx(ost["chees"], rel=1e-3, abs=1e-9)
+    return tr
+
+
+@pytest.mark.parametrize("N,d,J,seed", [
+    (200, 5, 256, 1),       # the small logistic workload
+    (1000, 37, 300, 2),     # ragged rows, features and particles; several tiles
+    (17, 1, 1, 3),          # one particle, one feature
+    (1, 3, 5, 4),           # one data row
+    (500, 208, 130, 5),     # widest supported d
+    (333, 16, 129, 6),
+])
+def test_one_iteration(N, d, J, seed):
+    X, y, s, o, st, ost = _one_iteration(N, d, J, seed)
+    _compare_iteration(s, o, st, ost, J, d)
+    # second iteration from the identical state (the oracle restarts from the
+    # device's population; typically no resampling this time)
+    rng = np.random.default_rng(seed + 99)
+    theta, logw, _ = s.state()
+    o.set_state(theta.cpu().numpy(), logw.cpu().numpy())
+    xi = rng.standard_normal((J, d)).astype(np.float32)
+    u = rng.random(1)
+    st2 = s.step(momenta=to_dev(xi), resample_u=to_dev(u))
+    ost2 = o.step(momenta=xi.astype(np.float64), resample_u=float(u[0]))
+    _compare_iteration(s, o, st2, ost2, J, d)
+
+
+def test_adaptation_parity():
+    N, d, J = 200, 5, 256
+    X, y, s, o, st, ost = _one_iteration(N, d, J, 11)
+    a = s.adapt()
+    o.last["ghat"] = st["chees_grad"]          # the device's own g_hat
+    o.last["sum_alpha"] = float(np.sum(s.trace()["alpha"].cpu().numpy()[:J]))
+    o.adapt()
+    assert a["L"] == pytest.approx(o.L, rel=1e-13)
+
+
+def test_step_size_adaptation_parity():
+    N, d, J = 200, 5, 256
+    X, y, _ = synth.logistic_iid(N, d, 12)
+    theta0 = (np.random.default_rng(3).standard_normal((J, d)) * 0.3).astype(np.float32)
+    eps = synth.default_step_size(N, d)
+    params = dict(step_size=eps, traj_length=eps * 32, max_leapfrog=64, num_warmup=5, seed=5,
+                  adapt_step_size=True, target_accept=0.651)
+    s2 = _sampler(X, y, J, theta0=theta0, **params)
+    st = s2.step()
+    al = s2.trace()["alpha"].cpu().numpy()[:J]
+    a = s2.adapt()
+    o2 = oracle_for(X, y, J, theta0, **params)
+    o2.last = dict(sum_alpha=float(al.sum()), ghat=st["chees_grad"], alpha=al)
+    o2.k = 1
+    o2.adapt()
+    assert a["eps"] == pytest.approx(o2.eps, rel=1e-13)
+    assert a["L"] == pytest.approx(o2.L, rel=1e-13)
+
+
+@pytest.mark.parametrize("mh", [True])
+def test_mh_mode(mh):
+    N, d, J = 300, 8, 256
+    X, y, s, o, st, ost = _one_iteration(N, d, J, 21, mh=True, eps=0.08, L=1.5)
+    tr = s.trace()
+    al = tr["alpha"].cpu().numpy()[:J]
+    th1 = tr["theta_prop"].cpu().numpy()[:J, :d].astype(np.float64)
+    assert rel_rows(th1, ost["theta_prop"]) <= TRAJ_TOL
+    # decisions agree wherever u is not within rounding of alpha
+    rng = np.random.default_rng(21 + 7)
+    rng.standard_normal((J, d))
+    rng.standard_normal((J, d))
+    u = rng.random(J)
+    clear = np.abs(u - ost["alpha"]) > 1e-6
+    theta, logw, _ = s.state()
+    acc_dev = np.all(theta.cpu().numpy().astype(np.float64) == th1.astype(np.float32).astype(np.float64), axis=1)
+    np.testing.assert_array_equal(acc_dev[clear], ost["accepted"][clear])
+    # MH mode keeps the weights
+    np.testing.assert_array_equal(logw.cpu().numpy(), o.logw)
+
+
+@pytest.mark.parametrize("jitter", ["none", "haltonNd"])
+def test_other_jitters(jitter):
+    X, y, s, o, st, ost = _one_iteration(200, 5, 256, 31, jitter=jitter)
+    _compare_iteration(s, o, st, ost, 256, 5)
+
+
+def test_multinomial_resampling_in_step():
+    X, y, s, o, st, ost = _one_iteration(200, 5, 256, 41, resampling="multinomial")
+    assert ost["resampled"]
+    _compare_iteration(s, o, st, ost, 256, 5)
+
+
+def test_device_philox_streams_match_oracle():
+    # no injection: momenta, resampling offset and the initial draw all come
+    # from the Philox4x32-10 streams on both sides
+    N, d, J = 200, 5, 256
+    X, y, _ = synth.logistic_iid(N, d, 1)
+    eps = synth.default_step_size(N, d)
+    params = dict(step_size=eps, traj_length=eps * 32, max_leapfrog=64, num_warmup=5, seed=123)
+    s = _sampler(X, y, J, **params)
+    theta, logw, logpi = s.state()
+    th0 = philox.normals_np(123, J, 0, philox.STREAM_INIT, d)
+    np.testing.assert_allclose(theta.cpu().numpy(), th0, rtol=2e-7, atol=1e-7)
+    o = oracle_for(X, y, J, theta.cpu().numpy(), **params)
+    st = s.step()
+    ost = o.step()
+    _compare_iteration(s, o, st, ost, J, d)
+
+
+def test_init_weights_and_logpi():
+    N, d, J = 1000, 20, 300
+    X, y, _ = synth.logistic_iid(N, d, 51)
+    theta0 = (np.random.default_rng(5).standard_normal((J, d)) * 0.5).astype(np.float32)
+    s = _sampler(X, y, J, theta0=theta0, step_size=0.01, num_warmup=3)
+    _, logw, logpi = s.state()
+    t = O.LogisticRegression(X.astype(np.float64), y.astype(np.float64))
+    lp, _ = t.log_and_grad(theta0.astype(np.float64))
+    ll = t.loglik(theta0.astype(np.float64))
+    np.testing.assert_allclose(logpi.cpu().numpy(), lp, rtol=1e-6)
+    np.testing.assert_allclose(logw.cpu().numpy(), ll - math.log(J), rtol=1e-6)
+
+
+@pytest.mark.parametrize("J", [1, 2, 7, 256, 1000, 8192, 65536])
+@pytest.mark.parametrize("scheme", ["systematic", "multinomial"])
+def test_resample_indices_bit_exact(J, scheme):
+    from paper_2504_02627_amd import chees
+    log(f"[resample_indices] J={J} scheme={scheme}")
+    rng = np.random.default_rng(J)
+    w = rng.gamma(0.2, size=J)
+    w[rng.random(J) < 0.1] = 0.0
+    if w.max() == 0:
+        w[0] = 1.0
+    u = rng.random(1 if scheme == "systematic" else J)
+    got = chees.resample_indices(to_dev(w), to_dev(u), scheme).cpu().numpy()
+    ref = O.resample_indices(w, u[0] if scheme == "systematic" else u, scheme)
+    np.testing.assert_array_equal(got, ref)
+
+
+def test_resample_indices_degenerate():
+    from paper_2504_02627_amd import chees
+    with pytest.raises(chees.SmcError) as e:
+        chees.resample_indices(to_dev(np.zeros(16)), to_dev(np.array([0.5])))
+    assert e.value.status == chees.SMC_EDEGENERATE
+
+
+def test_explicit_resample():
+    N, d, J = 200, 5, 256
+    X, y, _ = synth.logistic_iid(N, d, 61)
+    theta0 = (np.random.default_rng(6).standard_normal((J, d))).astype(np.float32)
+    s = _sampler(X, y, J, theta0=theta0, step_size=0.05, num_warmup=3)
+    _, logw0, _ = s.state()
+    anc = s.resample(u=to_dev(np.array([0.37])), return_ancestors=True).cpu().numpy()
+    np.testing.assert_array_equal(anc, O.resample_from_logw(logw0.cpu().numpy(), 0.37))
+    theta, logw, _ = s.state()
+    np.testing.assert_array_equal(theta.cpu().numpy(), theta0[anc])
+    np.testing.assert_allclose(logw.cpu().numpy(), -math.log(J))
+    # evidence is preserved by resampling
+    lz = s.log_evidence()
+    assert lz == pytest.approx(O.log_sum_exp(logw0.cpu().numpy())[0] + math.log(O.log_sum_exp(logw0.cpu().numpy())[1]), rel=1e-12)
+
+
+def test_log_evidence_bookkeeping():
+    # log Z = C + LSE(log w), with C = LSE of the weights at each resampling
+    N, d, J = 200, 5, 256
+    X, y, _ = synth.logistic_iid(N, d, 71)
+    theta0 = (np.random.default_rng(7).standard_normal((J, d))).astype(np.float32)
+    s = _sampler(X, y, J, theta0=theta0, step_size=0.05, traj_length=1.0, num_warmup=3)
+    _, lw0, _ = s.state()
+    lw0 = lw0.cpu().numpy()
+    assert s.log_evidence() == pytest.approx(_lse(lw0), rel=1e-12)
+    st = s.step()
+    _, lw1, _ = s.state()
+    ref = (_lse(lw0) if st["resampled"] else 0.0) + _lse(lw1.cpu().numpy())
+    assert st["resampled"] == int(O.ess(lw0) < 0.5 * J)
+    assert s.log_evidence() == pytest.approx(ref, rel=1e-12)
+    assert st["log_z"] == pytest.approx(ref, rel=1e-12)
+
+
+def _lse(lw):
+    m, S, _ = O.log_sum_exp(lw)
+    return m + math.log(S)
+
+
+def test_determinism_two_runs():
+    N, d, J = 500, 12, 300
+    X, y, _ = synth.logistic_iid(N, d, 81)
+    eps = synth.default_step_size(N, d)
+    out = []
+    for _ in range(2):
+        s = _sampler(X, y, J, step_size=eps, traj_length=eps * 20, num_warmup=2, seed=9)
+        for _ in range(3):
+            s.step(stats=False)
+            s.adapt(stats=False)
+        th, lw, lp = s.state()
+        out.append((th.cpu().numpy(), lw.cpu().numpy()))
+    np.testing.assert_array_equal(out[0][0], out[1][0])
+    np.testing.assert_array_equal(out[0][1], out[1][1])
+
+
+def test_error_paths():
+    import ctypes
+    import torch
+    from paper_2504_02627_amd import chees
+    X, y, _ = synth.logistic_iid(50, 3, 91)
+    s = _sampler(X, y, 16, step_size=0.1, num_warmup=2)
+    with pytest.raises(chees.SmcError) as e:
+        s.adapt()
+    assert e.value.status == chees.SMC_ESTATE
+    with pytest.raises(chees.SmcError):
+        _sampler(X, y, 0)
+    # workspace too small
+    lib = chees.load()
+    prob, keep = chees.make_problem([to_dev(X)], [to_dev(y)])
+    par = chees.make_params(16)
+    ws = torch.empty(1024, dtype=torch.uint8, device=dev())
+    ctx = ctypes.c_void_p()
+    rc = lib.smc_init(ctypes.byref(prob), ctypes.byref(par), ctypes.c_void_p(ws.data_ptr()), 1024,
+                      None, None, ctypes.byref(ctx))
+    assert rc == chees.SMC_ENOMEM
+
+
+def test_degenerate_weights_reported():
+    from paper_2504_02627_amd import chees
+    X, y, _ = synth.logistic_iid(50, 3, 92)
+    theta0 = np.full((16, 3), np.nan, dtype=np.float32)
+    s = _sampler(X, y, 16, theta0=theta0, step_size=0.1, num_warmup=2)
+    with pytest.raises(chees.SmcError) as e:
+        s.log_evidence()
+    assert e.value.status == chees.SMC_EDEGENERATE
+
+
+def test_single_nonfinite_particle_gets_zero_weight():
+    N, d, J = 100, 4, 64
+    X, y, _ = synth.logistic_iid(N, d, 93)
+    theta0 = (np.random.default_rng(1).standard_normal((J, d)) * 0.1).astype(np.float32)
+    theta0[5] = np.inf
+    s = _sampler(X, y, J, theta0=theta0, step_size=0.05, traj_length=0.5, num_warmup=2)
+    st = s.step(resample_u=to_dev(np.array([0.5])))
+    _, logw, _ = s.state()
+    lw = logw.cpu().numpy()
+    assert np.isfinite(lw).sum() >= J - 1
+    assert math.isfinite(s.log_evidence())
