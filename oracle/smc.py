@@ -552,6 +552,7 @@ class OracleSMC:
         alpha = accept_prob(dh)
         # a7: ChEES statistics on the proposals (Alg. smc_ChEES)
         st = chees_statistics(self.theta, th1, p1, l, alpha, self.minv)
+        theta_before, logpi_before = self.theta.copy(), self.logpi.copy()
         if P["mh_accept"]:
             u = mh_uniforms if mh_uniforms is not None else philox.uniforms_np(
                 P["seed"], J, k, philox.STREAM_MH)
@@ -570,6 +571,8 @@ class OracleSMC:
             dh=dh, alpha=alpha, accepted=acc, mean_accept=float(np.mean(alpha)),
             chees=st["chees"], ghat=st["ghat"], sum_alpha=st["sum_alpha"], a=st["a"], g=st["g"],
             grad_evals=int(np.sum(ng)), L=self.L, eps=self.eps,
+            theta_before=theta_before, logpi_before=logpi_before, theta_prop=th1, logpi_prop=lp1,
+            H0=hamiltonian(logpi_before, p0, self.minv), H1=hamiltonian(lp1, p1, self.minv),
         )
         return self.last
 
@@ -595,6 +598,13 @@ class OracleSMC:
         elif k == Mw:
             self.L = self.Lbar
         return dict(L=self.L, eps=self.eps, Lbar=self.Lbar)
+
+    def set_state(self, theta, logw, logpi=None):
+        """Replace the population (used to restart from another implementation's
+        state); log pi and the gradient are recomputed at theta."""
+        self.theta = np.array(theta, dtype=np.float64).reshape(self.J, self.d)
+        self.logpi, self.grad = self.target.log_and_grad(self.theta)
+        self.logw = np.array(logw, dtype=np.float64).copy()
 
     def log_evidence(self):
         m, S, _ = log_sum_exp(self.logw)
