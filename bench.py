@@ -151,11 +151,14 @@ def main():
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_FP32_MFMA_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4),
                 "traffic": traffic,
-                "kernel": "k_leapfrog<7>: fused leapfrog step, X theta'^T -> sigmoid -> R X on "
-                          "v_mfma_f32_16x16x4f32",
+                "kernel": "k_lf_partial<7>: fused leapfrog step (drift, X theta'^T -> sigmoid -> "
+                          "R X on v_mfma_f32_16x16x4f32) over a data-row split",
                 "algorithmic_flops_per_launch": flops / launches,
                 "avg_launch_ms": tm["leapfrog_ms"] / launches, "launches": tm["leapfrog_launches"],
-                "flop_unit": "4 N d per particle-gradient evaluation"}
+                "flop_unit": "4 N d per particle-gradient evaluation",
+                "other_kernels_ms_per_step": {
+                    "k_lf_reduce": tm["reduce_ms"] / args.steps,
+                    "k_loglik": tm["loglik_ms"] / args.steps}}
     out = {
         "metric": METRIC, "value": evals / T, "unit": "particle-gradient evals/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * T / args.steps,

@@ -207,14 +207,17 @@ smc_status smc_get_trace(smc_ctx *ctx, smc_trace *trace);
 smc_status smc_get_counters(smc_ctx *ctx, smc_counters *counters);
 
 /* Kernel timing with HIP events recorded on the context's stream around every
- * launch of the fused leapfrog kernel and of the log-likelihood kernel.  Off by
- * default.  smc_get_timing synchronises, returns the totals since timing was
- * enabled (or last read) and resets them. */
+ * launch of the fused leapfrog kernel (drift + X theta'^T -> sigmoid -> R X
+ * over a data-row split), of its split reduction (sum of partials + kick) and
+ * of the log-likelihood kernel.  Off by default.  smc_get_timing synchronises,
+ * returns the totals since timing was enabled (or last read) and resets them. */
 typedef struct {
-  double leapfrog_ms;          /* summed event time of the leapfrog launches   */
+  double leapfrog_ms;          /* summed event time of the fused leapfrog launches */
   int64_t leapfrog_launches;
   double loglik_ms;
   int64_t loglik_launches;
+  double reduce_ms;            /* split reduction + second half kick               */
+  int64_t reduce_launches;
 } smc_timing;
 smc_status smc_set_timing(smc_ctx *ctx, int32_t enable);
 smc_status smc_get_timing(smc_ctx *ctx, smc_timing *out);

@@ -75,7 +75,8 @@ class Counters(ctypes.Structure):
 
 class Timing(ctypes.Structure):
     _fields_ = [("leapfrog_ms", ctypes.c_double), ("leapfrog_launches", ctypes.c_int64),
-                ("loglik_ms", ctypes.c_double), ("loglik_launches", ctypes.c_int64)]
+                ("loglik_ms", ctypes.c_double), ("loglik_launches", ctypes.c_int64),
+                ("reduce_ms", ctypes.c_double), ("reduce_launches", ctypes.c_int64)]
 
 
 class Trace(ctypes.Structure):

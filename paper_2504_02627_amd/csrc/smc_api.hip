@@ -46,9 +46,9 @@ struct Layout {
   std::vector<int4> items;
   size_t total = 0;
   // byte offsets
-  size_t o_posts, o_ps, o_xa, o_xb, o_yp, o_theta, o_grad, o_theta_t, o_p_t, o_grad_t;
+  size_t o_posts, o_ps, o_xab, o_yp, o_theta, o_grad, o_theta_t, o_p_t, o_grad_t;
   size_t o_logpi, o_logpi_t, o_logw, o_h, o_l, o_H0, o_dH, o_alpha, o_ca, o_cg;
-  size_t o_n, o_perm, o_hist, o_active, o_anc, o_acc, o_cdf, o_gpart, o_tilecnt, o_llpart;
+  size_t o_n, o_perm, o_active, o_anc, o_acc, o_cdf, o_gpart, o_tilecnt, o_llpart;
   size_t o_items, o_colpart, o_means, o_minv, o_primes;
 };
 
@@ -99,12 +99,12 @@ void plan(const smc_problem *pr, const smc_params *pa, Layout &L) {
     HostPost &h = L.hp[b];
     h.N = pr->n_rows[b];
     h.d = pr->dims[b];
-    h.C1 = (h.d + 3) / 4;
     h.C2 = (h.d + 15) / 16;
+    h.C1 = 4 * h.C2;
     h.NT = (h.N + 15) / 16;
-    h.xa = h.xb = xoff;
+    h.xab = xoff;
     h.yo = yoff;
-    xoff += (long long)h.NT * 64 * 4 * h.C2;
+    xoff += (long long)h.NT * 64 * 8 * h.C2;
     yoff += 16LL * h.NT;
     maxc2 = std::max(maxc2, h.C2);
     Post &p = L.posts[b];
@@ -115,14 +115,14 @@ void plan(const smc_problem *pr, const smc_params *pa, Layout &L) {
     p.C2 = h.C2;
     p.NT = h.NT;
     p.row0 = b * L.Jcap;
-    p.xa = p.xb = h.xa;
+    p.xab = h.xab;
     p.yo = h.yo;
     p.uoff = uoff;
     uoff += (long long)L.J * h.d;
   }
   L.DS = 16 * maxc2;
-  // leapfrog launches: about two work groups per compute unit
-  L.lf_target = 512;
+  // leapfrog launches: one 8-wave work group per compute unit (256 CUs)
+  L.lf_target = 256;
   const int ntile = L.Jcap / TJ;
   L.lf_grid = L.lf_target + B * ntile;
   // log-likelihood pass: every tile, static splits
@@ -147,8 +147,7 @@ void plan(const smc_problem *pr, const smc_params *pa, Layout &L) {
   size_t c = 0;
   L.o_posts = take(c, B * sizeof(Post));
   L.o_ps = take(c, B * sizeof(PState));
-  L.o_xa = take(c, xoff * sizeof(float));
-  L.o_xb = take(c, xoff * sizeof(float));
+  L.o_xab = take(c, xoff * sizeof(float));
   L.o_yp = take(c, yoff * sizeof(float));
   L.o_theta = take(c, st);
   L.o_grad = take(c, st);
@@ -167,7 +166,6 @@ void plan(const smc_problem *pr, const smc_params *pa, Layout &L) {
   L.o_cg = take(c, rows * 8);
   L.o_n = take(c, rows * 4);
   L.o_perm = take(c, rows * 4);
-  L.o_hist = take(c, (size_t)B * (L.nmax + 1) * 4);
   L.o_active = take(c, (size_t)B * (L.nmax + 1) * 4);
   L.o_anc = take(c, rows * 4);
   L.o_acc = take(c, rows * 4);
@@ -284,8 +282,7 @@ smc_status smc_init(const smc_problem *prob, const smc_params *par, void *worksp
   D.seed = par->seed;
   D.posts = (Post *)(w + L.o_posts);
   D.ps = (PState *)(w + L.o_ps);
-  D.xa = (float *)(w + L.o_xa);
-  D.xb = (float *)(w + L.o_xb);
+  D.xab = (float *)(w + L.o_xab);
   D.yp = (float *)(w + L.o_yp);
   D.theta = (float *)(w + L.o_theta);
   D.grad = (float *)(w + L.o_grad);
@@ -304,7 +301,6 @@ smc_status smc_init(const smc_problem *prob, const smc_params *par, void *worksp
   D.cg = (double *)(w + L.o_cg);
   D.n = (int *)(w + L.o_n);
   D.perm = (int *)(w + L.o_perm);
-  D.hist = (int *)(w + L.o_hist);
   D.active = (int *)(w + L.o_active);
   D.anc = (int *)(w + L.o_anc);
   D.accepted = (int *)(w + L.o_acc);
@@ -412,7 +408,10 @@ smc_status smc_step(smc_ctx *ctx, const smc_inject *inject, smc_stats *stats) {
   for (int s = 0; s < D.nmax; ++s)
     for (int c2 : ctx->c2s) {
       CK(timed_begin(ctx, 0, ei));
-      CK(launch_leapfrog(D, c2, s, 0, ctx->st));
+      CK(launch_lf_partial(D, c2, s, 0, ctx->st));
+      CK(timed_end(ctx, ei));
+      CK(timed_begin(ctx, 2, ei));
+      CK(launch_lf_reduce(D, c2, s, 0, ctx->st));
       CK(timed_end(ctx, ei));
     }
   for (int c2 : ctx->c2s) {
@@ -549,9 +548,12 @@ smc_status smc_get_timing(smc_ctx *ctx, smc_timing *out) {
     if (m.first == 0) {
       out->leapfrog_ms += ms;
       out->leapfrog_launches += 1;
-    } else {
+    } else if (m.first == 1) {
       out->loglik_ms += ms;
       out->loglik_launches += 1;
+    } else {
+      out->reduce_ms += ms;
+      out->reduce_launches += 1;
     }
   }
   ctx->ev_marks.clear();

@@ -7,11 +7,12 @@
 
 namespace smc {
 
-// Particle tile of the fused leapfrog/likelihood kernels: 4 waves x 2 subtiles
-// x 16 particles.  Particle counts are padded to a multiple of TJ per posterior.
-constexpr int TJ = 128;
-constexpr int WAVES = 4;
-constexpr int SUB = 2;
+// Particle tile of the fused leapfrog/likelihood kernels: 8 waves x SUB
+// subtiles x 16 particles.  Particle counts are padded to a multiple of TJ per
+// posterior.
+constexpr int WAVES = 8;
+constexpr int SUB = 1;
+constexpr int TJ = WAVES * SUB * 16;
 constexpr int WG = 64 * WAVES;
 constexpr int MAX_C2 = 13;          // d <= 16 * 13 = 208
 constexpr int MAX_NMAX = 4096;      // cap on max_leapfrog
@@ -24,12 +25,12 @@ constexpr uint32_t STREAM_INIT = 1, STREAM_MOMENTUM = 2, STREAM_MH = 3, STREAM_R
 // Constants of one posterior, resident in device memory.
 struct Post {
   int N, d;        // data rows and features
-  int C1, C2;      // GEMM1 K-chunks ceil(d/4); GEMM2 column tiles ceil(d/16)
+  int C1, C2;      // GEMM1 K-chunks 4 C2; GEMM2 column tiles ceil(d/16)
   int NT;          // 16-row data tiles ceil(N/16)
   int row0;        // first particle row of this posterior
   int ll_splits;   // N-splits of the log-likelihood pass
   int ll_base;     // first work item of this posterior in the log-likelihood plan
-  long long xa, xb;  // float offsets into the packed X layouts
+  long long xab;     // float offset into the packed X tiles
   long long yo;      // float offset into padded y
   long long uoff;    // offset of this posterior's block in caller (B*J) x d_b arrays
 };
@@ -65,12 +66,12 @@ struct Dev {                    // pointers carved from the workspace
   double adam_lr, adam_b1, adam_b2, adam_eps, avg_decay, target_accept;
   int adapt_eps, num_warmup;
   uint64_t seed;
-  float *xa, *xb, *yp;          // packed X (A and B operand layouts), padded y
+  float *xab, *yp;              // packed X tiles ([tile][lane][A | B]), padded y
   float *theta, *grad;          // current state, B*Jcap x DS
   float *theta_t, *p_t, *grad_t;// trajectory buffers
   double *logpi, *logpi_t, *logw;
   double *h, *l, *H0, *dH, *alpha, *ca, *cg;
-  int *n, *perm, *hist, *cursor, *active, *anc, *accepted;
+  int *n, *perm, *active, *anc, *accepted;
   unsigned long long *cdf;
   float *gpart;                 // split partial gradients, [wg][TJ][DS]
   int gpart_slots;              // number of [TJ][DS] slots
@@ -91,7 +92,7 @@ struct Dev {                    // pointers carved from the workspace
 // Host copy of one posterior's packing sizes.
 struct HostPost {
   int N, d, C1, C2, NT;
-  long long xa, xb, yo;
+  long long xab, yo;
 };
 
 // Launchers (smc_kernels.hip).  All stream-ordered.
@@ -108,6 +109,8 @@ hipError_t launch_gather(const Dev &D, int *anc_out, hipStream_t st);
 hipError_t launch_setup(const Dev &D, const float *momenta, int init_mode, hipStream_t st);
 hipError_t launch_sort(const Dev &D, hipStream_t st);
 hipError_t launch_leapfrog(const Dev &D, int c2, int step, int zero_eps, hipStream_t st);
+hipError_t launch_lf_partial(const Dev &D, int c2, int step, int zero_eps, hipStream_t st);
+hipError_t launch_lf_reduce(const Dev &D, int c2, int step, int zero_eps, hipStream_t st);
 hipError_t launch_loglik(const Dev &D, int c2, hipStream_t st);
 hipError_t launch_weights(const Dev &D, const double *mh_u, int init_mode, hipStream_t st);
 hipError_t launch_chees(const Dev &D, hipStream_t st);

@@ -85,13 +85,15 @@ struct OpMax {
 };
 
 // ---------------------------------------------------------------------------
-// Packing of X into the two MFMA operand layouts (once, at init).
+// Packing of X into the MFMA operand layouts (once, at init).  dp = 16 C2.
 //
-// A layout (GEMM1, Z^T = X Theta^T, v_mfma_f32_16x16x4f32 with M = data rows):
-//   lane l of data tile t holds X[16t + l%16][(l/16) C1 + c] in slot c < C1.
-// B layout (GEMM2, G = R X, M = particles, N = 16 features, K = 4 data rows):
-//   lane l of data tile t holds X[16t + 4(l/16) + i][16 ct + l%16] in slot 4 ct + i.
-// Both: [tile][lane][4 C2] floats, so a lane reads C2 16-byte vectors per tile.
+// A part (GEMM1, Z^T = X Theta^T with v_mfma_f32_16x16x4f32, M = data rows,
+//   K = features): lane l of data tile t holds X[16t + l%16][(l/16) 4C2 + c]
+//   in slot c < 4 C2 (the K index of MFMA c is (l/16) 4C2 + c).
+// B part (GEMM2, G = R X, M = particles, N = 16 features, K = 4 data rows):
+//   lane l holds X[16t + 4(l/16) + i][16 ct + l%16] in slot 4 ct + i.
+// Interleaved per tile and lane: [tile][lane][A: 4C2 | B: 4C2] floats, so one
+// data tile is one contiguous block of 512 C2 floats.
 // Padded y: y[n] for n < N, 1/2 beyond, which makes the padded residual
 // y - sigmoid(0) exactly zero.
 // ---------------------------------------------------------------------------
@@ -105,24 +107,26 @@ __device__ __forceinline__ float to_f32<uint16_t>(uint16_t v) {
 }
 
 template <typename T>
-__global__ void k_pack(const T *__restrict__ X, const float *__restrict__ y, int N, int d, int C1,
-                       int C2, int NT, float *__restrict__ xa, float *__restrict__ xb,
-                       float *__restrict__ yp) {
+__global__ void k_pack(const T *__restrict__ X, const float *__restrict__ y, int N, int d, int C2,
+                       int NT, float *__restrict__ xab, float *__restrict__ yp) {
   const int K1 = 4 * C2;
-  const long long tot = (long long)NT * 64 * K1;
+  const long long tot = (long long)NT * 64 * 2 * K1;
   for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < tot;
        idx += (long long)gridDim.x * blockDim.x) {
-    const int slot = (int)(idx % K1);
-    const long long r = idx / K1;
+    const int slot = (int)(idx % (2 * K1));
+    const long long r = idx / (2 * K1);
     const int lane = (int)(r % 64);
     const int t = (int)(r / 64);
-    int n = 16 * t + (lane & 15);
-    int k = (lane >> 4) * C1 + slot;
-    xa[idx] = (slot < C1 && n < N && k < d) ? to_f32<T>(X[(long long)n * d + k]) : 0.f;
-    const int ct = slot >> 2, i = slot & 3;
-    n = 16 * t + 4 * (lane >> 4) + i;
-    k = 16 * ct + (lane & 15);
-    xb[idx] = (n < N && k < d) ? to_f32<T>(X[(long long)n * d + k]) : 0.f;
+    int n, k;
+    if (slot < K1) {
+      n = 16 * t + (lane & 15);
+      k = (lane >> 4) * K1 + slot;
+    } else {
+      const int sb = slot - K1, ct = sb >> 2, i = sb & 3;
+      n = 16 * t + 4 * (lane >> 4) + i;
+      k = 16 * ct + (lane & 15);
+    }
+    xab[idx] = (n < N && k < d) ? to_f32<T>(X[(long long)n * d + k]) : 0.f;
   }
   for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < 16LL * NT;
        n += (long long)gridDim.x * blockDim.x)
@@ -131,15 +135,15 @@ __global__ void k_pack(const T *__restrict__ X, const float *__restrict__ y, int
 
 hipError_t launch_pack_one(const Dev &D, const void *X, const float *y, int x_dtype,
                            const HostPost &P, hipStream_t st) {
-  const long long tot = (long long)P.NT * 64 * 4 * P.C2;
+  const long long tot = (long long)P.NT * 64 * 8 * P.C2;
   int grid = (int)((tot + 255) / 256);
   if (grid > 65535) grid = 65535;
   if (x_dtype == 0)
     hipLaunchKernelGGL(k_pack<float>, dim3(grid), dim3(256), 0, st, (const float *)X, y, P.N, P.d,
-                       P.C1, P.C2, P.NT, D.xa + P.xa, D.xb + P.xb, D.yp + P.yo);
+                       P.C2, P.NT, D.xab + P.xab, D.yp + P.yo);
   else
     hipLaunchKernelGGL(k_pack<uint16_t>, dim3(grid), dim3(256), 0, st, (const uint16_t *)X, y,
-                       P.N, P.d, P.C1, P.C2, P.NT, D.xa + P.xa, D.xb + P.xb, D.yp + P.yo);
+                       P.N, P.d, P.C2, P.NT, D.xab + P.xab, D.yp + P.yo);
   return hipGetLastError();
 }
 
@@ -236,57 +240,125 @@ hipError_t launch_init_theta(const Dev &D, const float *theta0, hipStream_t st) 
 //   g' = X^T (y - sigmoid(X theta')) - theta'/prior_var;  p' = p_half + eps/2 g'.
 // Particles with n_j <= s are left alone (per-particle trajectory length).
 //
-// Work item = (posterior, 128-particle tile, data split).  Each of the 4 waves
-// owns 2 x 16 particles.  Per 16-row data tile:
-//   GEMM1  Z^T (16 rows x 16 particles) += X_A (16 x 4) Theta'^T (4 x 16),
-//          C1 MFMAs (v_mfma_f32_16x16x4f32) accumulate over the features;
+// k_lf_partial: work item = (posterior, 128-particle tile, data-row split).
+// Each of the 4 waves owns 2 x 16 particles.  Per 16-row data tile:
+//   GEMM1  Z^T (16 rows x 16 particles) = X_A (16 x 4) Theta'^T (4 x 16),
+//          4 C2 MFMAs (v_mfma_f32_16x16x4f32) accumulating over the features;
 //   R = y - sigmoid(Z) elementwise on the accumulator registers;
-//   GEMM2  G (16 particles x 16 features) += R (16 x 4) X_B (4 x 16), the
-//          accumulator of GEMM1 being directly the A operand of GEMM2 (the
-//          data-row index of GEMM2's K dimension follows GEMM1's row layout).
-// Z never leaves registers.  Splits write partial G; the last work group of a
-// tile (arrival counter) sums the partials in split order and applies the
-// second half kick, so the result does not depend on arrival order.
+//   GEMM2  G (16 particles x 16 features) += R (16 x 4) X_B (4 x 16): the
+//          accumulator of GEMM1 is directly the A operand of GEMM2 (the data-row
+//          index of GEMM2's K follows GEMM1's row layout), so Z never leaves
+//          registers.
+// Data tiles stream through LDS, double-buffered: the 256 threads load tile
+// t+1 from global memory while the waves compute on tile t, and every wave
+// reads its operands with 16-byte LDS reads (lane stride padded by 16 bytes to
+// avoid bank conflicts).  The split writes its partial gradient.
+// k_lf_reduce: sums the partials of each tile in split order (deterministic),
+// adds the prior term and applies the second half kick.  The kernel boundary
+// makes the partials visible; no cross-work-group synchronisation is needed.
 // ---------------------------------------------------------------------------
 struct Plan {
   int b, tile, split, S, wbase;
 };
 
-// Deterministic plan of a leapfrog launch at step s: every work group computes
-// the same table from the active counts and finds its own item.
-__device__ bool lf_plan(const Dev &D, int c2, int s, int wid, Plan &pl) {
+constexpr int LF_MAX_SPLIT = 64;
+
+// Deterministic plan of a leapfrog launch at step s, computed identically by
+// every work group from the active counts.  About lf_target work items (one
+// wave of resident work groups) are spread over the active tiles in proportion
+// to their data tiles; within a posterior the tiles get split counts that
+// differ by at most one, so items carry nearly equal work.  Items are
+// enumerated posterior by posterior, tile by tile, split by split.
+struct PostPlan {
+  int T, base, extra, first;  // active tiles, splits per tile (>= 1), tiles with one more, first item
+};
+
+__device__ bool lf_post_plan(const Dev &D, int c2, int s, int bq, PostPlan &out) {
   long long U = 0;
-  const int ntile = D.Jcap / TJ;
   for (int b = 0; b < D.B; ++b) {
     const Post &P = D.posts[b];
     if (P.C2 != c2) continue;
-    const int A = D.active[b * (D.nmax + 1) + s];
-    U += (long long)((A + TJ - 1) / TJ) * P.NT;
+    U += (long long)((D.active[b * (D.nmax + 1) + s] + TJ - 1) / TJ) * P.NT;
   }
   if (U == 0) return false;
-  const long long chunk = (U + D.lf_target - 1) / D.lf_target;
-  int base = 0;
+  int first = 0;
   for (int b = 0; b < D.B; ++b) {
     const Post &P = D.posts[b];
     if (P.C2 != c2) continue;
-    const int A = D.active[b * (D.nmax + 1) + s];
-    const int T = (A + TJ - 1) / TJ;
-    if (T == 0) continue;
-    long long S = (P.NT + chunk - 1) / chunk;
-    if (S < 1) S = 1;
-    if (S > P.NT) S = P.NT;
-    const int cnt = T * (int)S;
-    if (wid < base + cnt) {
-      pl.b = b;
-      pl.tile = (wid - base) / (int)S;
-      pl.split = (wid - base) % (int)S;
-      pl.S = (int)S;
-      pl.wbase = base + pl.tile * (int)S;
-      return pl.tile < ntile;
+    const int T = (D.active[b * (D.nmax + 1) + s] + TJ - 1) / TJ;
+    int items = 0, base = 0, extra = 0;
+    if (T > 0) {
+      long long G = ((long long)D.lf_target * T * P.NT) / U;  // this posterior's share
+      if (G < T) G = T;
+      const long long cap = (long long)T * (P.NT < LF_MAX_SPLIT ? P.NT : LF_MAX_SPLIT);
+      if (G > cap) G = cap;
+      base = (int)(G / T);
+      extra = (int)(G % T);
+      items = (int)G;
     }
-    base += cnt;
+    if (b == bq) {
+      out.T = T;
+      out.base = base;
+      out.extra = extra;
+      out.first = first;
+      return T > 0;
+    }
+    first += items;
   }
   return false;
+}
+
+__device__ __forceinline__ int tile_first_item(const PostPlan &q, int tile) {
+  return q.first + tile * q.base + (tile < q.extra ? tile : q.extra);
+}
+
+__device__ bool lf_plan(const Dev &D, int c2, int s, int wid, Plan &pl) {
+  for (int b = 0; b < D.B; ++b) {
+    if (D.posts[b].C2 != c2) continue;
+    PostPlan q;
+    if (!lf_post_plan(D, c2, s, b, q)) continue;
+    const int items = q.T * q.base + q.extra;
+    if (wid >= q.first + items) continue;
+    if (wid < q.first) return false;
+    const int w = wid - q.first;
+    const int big = q.extra * (q.base + 1);
+    int tile, split, S;
+    if (w < big) {
+      tile = w / (q.base + 1);
+      split = w % (q.base + 1);
+      S = q.base + 1;
+    } else {
+      tile = q.extra + (w - big) / q.base;
+      split = (w - big) % q.base;
+      S = q.base;
+    }
+    pl.b = b;
+    pl.tile = tile;
+    pl.split = split;
+    pl.S = S;
+    pl.wbase = q.first + tile * q.base + (tile < q.extra ? tile : q.extra);
+    return true;
+  }
+  return false;
+}
+
+// Plan entry of a given (posterior, tile): its split count and first item.
+__device__ bool lf_plan_tile(const Dev &D, int c2, int s, int bq, int tile, Plan &pl) {
+  PostPlan q;
+  if (!lf_post_plan(D, c2, s, bq, q) || tile >= q.T) return false;
+  pl.b = bq;
+  pl.tile = tile;
+  pl.split = 0;
+  pl.S = q.base + (tile < q.extra ? 1 : 0);
+  pl.wbase = tile_first_item(q, tile);
+  return true;
+}
+
+// softplus(z) = max(z, 0) + ln 2 log2(1 + 2^(-|z| log2 e)) with the hardware
+// exp2/log2; the absolute error per term is a few 1e-8.
+__device__ __forceinline__ float softplusf_hw(float z) {
+  const float e = __builtin_amdgcn_exp2f(-fabsf(z) * 1.4426950408889634f);
+  return fmaxf(z, 0.f) + 0.6931471805599453f * __builtin_amdgcn_logf(1.0f + e);
 }
 
 __device__ __forceinline__ float sigmoidf_fast(float z) {
@@ -295,11 +367,51 @@ __device__ __forceinline__ float sigmoidf_fast(float z) {
   return __builtin_amdgcn_rcpf(1.0f + e);
 }
 
+// LDS staging of packed data tiles, two 16-row tiles per stage, double
+// buffered, with gfx950's direct global-to-LDS loads (global_load_lds_dwordx4:
+// each lane's 16 bytes land at the wave-uniform LDS base + 16 * lane), so the
+// prefetch of the next stage holds no registers.  In LDS a tile is
+// 64 lanes x (2 C2 + 1) float4 (A | B | pad): the 16-byte pad per lane keeps
+// the per-lane 16-byte operand reads free of bank conflicts.  Each lane of a
+// load instruction fetches the global float4 that belongs to its LDS slot; pad
+// slots re-read the tile's first float4.
 template <int C2>
-__global__ __launch_bounds__(WG) void k_leapfrog(Dev D, int s, int zero_eps) {
+struct Tiles {
+  static constexpr int GF4 = 2 * C2;          // float4 per lane and tile in global memory
+  static constexpr int LSTR = GF4 + 1;        // padded lane stride in LDS (float4)
+  static constexpr int TILE = 64 * LSTR;      // float4 per tile in LDS
+  static constexpr int STAGE = 2 * TILE;      // two tiles
+  static constexpr int NINST = STAGE / 64;    // wave-wide loads per stage
+};
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+template <int C2>
+__device__ __forceinline__ void stage_issue(float4 *xs, float4 *ys, const float4 *__restrict__ xab,
+                                            const float4 *__restrict__ yv, int t, int t1,
+                                            int wave, int lane) {
+  using TL = Tiles<C2>;
+  for (int m = wave; m < TL::NINST; m += WAVES) {
+    const int P = 64 * m + lane;
+    const int tt = P / TL::TILE, rem = P % TL::TILE;
+    const int ln = rem / TL::LSTR, q = rem % TL::LSTR;
+    const int tg = (t + tt < t1) ? t + tt : t;  // a missing second tile re-reads the first
+    const long long g = ((long long)tg * 64 + ln) * TL::GF4 + (q < TL::GF4 ? q : 0);
+    __builtin_amdgcn_global_load_lds((const void *)(xab + g), (lds_void *)(xs + 64 * m), 16, 0, 0);
+  }
+  if (wave == WAVES - 1 && lane < 8) {
+    const int tg = (t + (lane >> 2) < t1) ? t + (lane >> 2) : t;
+    ys[lane] = yv[tg * 4 + (lane & 3)];
+  }
+}
+
+template <int C2>
+__global__ __launch_bounds__(WG) void k_lf_partial(Dev D, int s, int zero_eps) {
   constexpr int K1 = 4 * C2;
+  using TL = Tiles<C2>;
+  __shared__ float4 xs[2][TL::STAGE];
+  __shared__ float4 ys[2][8];
   __shared__ Plan spl;
-  __shared__ int slast;
   if (threadIdx.x == 0) {
     Plan pl;
     if (!lf_plan(D, C2, s, blockIdx.x, pl)) pl.b = -1;
@@ -309,13 +421,10 @@ __global__ __launch_bounds__(WG) void k_leapfrog(Dev D, int s, int zero_eps) {
   const Plan pl = spl;
   if (pl.b < 0) return;
 
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, kq = lane >> 4;
   const Post P = D.posts[pl.b];
-  const PState &PS = D.ps[pl.b];
-  const float eps = zero_eps ? 0.f : (float)PS.eps;
+  const float eps = zero_eps ? 0.f : (float)D.ps[pl.b].eps;
   const float he = 0.5f * eps;
-  const int C1 = P.C1;
-  const int kq = lane >> 4;
   const float *minv = D.minv + (long long)pl.b * D.DS;
   const int *perm = D.perm + P.row0;
 
@@ -323,18 +432,13 @@ __global__ __launch_bounds__(WG) void k_leapfrog(Dev D, int s, int zero_eps) {
   float th[SUB][K1];
 #pragma unroll
   for (int sb = 0; sb < SUB; ++sb) {
-    const int slot = pl.tile * TJ + wave * 32 + sb * 16 + (lane & 15);
-    const long long base = (long long)(P.row0 + perm[slot]) * D.DS;
+    const int slot = pl.tile * TJ + (wave * SUB + sb) * 16 + (lane & 15);
+    const long long base = (long long)(P.row0 + perm[slot]) * D.DS + kq * K1;
 #pragma unroll
     for (int c = 0; c < K1; ++c) {
-      float v = 0.f;
-      if (c < C1) {
-        const int k = kq * C1 + c;
-        const float t0 = D.theta_t[base + k], p0 = D.p_t[base + k], g0 = D.grad_t[base + k];
-        const float ph = fmaf(he, g0, p0);
-        v = fmaf(eps * minv[k], ph, t0);
-      }
-      th[sb][c] = v;
+      const float t0 = D.theta_t[base + c], p0 = D.p_t[base + c], g0 = D.grad_t[base + c];
+      const float ph = fmaf(he, g0, p0);
+      th[sb][c] = fmaf(eps * minv[kq * K1 + c], ph, t0);
     }
   }
 
@@ -346,38 +450,47 @@ __global__ __launch_bounds__(WG) void k_leapfrog(Dev D, int s, int zero_eps) {
 
   const int t0 = (int)((long long)pl.split * P.NT / pl.S);
   const int t1 = (int)((long long)(pl.split + 1) * P.NT / pl.S);
-  const float4 *xa = reinterpret_cast<const float4 *>(D.xa + P.xa);
-  const float4 *xb = reinterpret_cast<const float4 *>(D.xb + P.xb);
+  const float4 *xab = reinterpret_cast<const float4 *>(D.xab + P.xab);
   const float4 *yv = reinterpret_cast<const float4 *>(D.yp + P.yo);
-
-  for (int t = t0; t < t1; ++t) {
-    float4 a4[C2], b4[C2];
-    const long long o = ((long long)t * 64 + lane) * C2;
+  stage_issue<C2>(xs[0], ys[0], xab, yv, t0, t1, wave, lane);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  int cur = 0;
+  for (int t = t0; t < t1; t += 2) {
+    const bool more = t + 2 < t1;
+    if (more) stage_issue<C2>(xs[cur ^ 1], ys[cur ^ 1], xab, yv, t + 2, t1, wave, lane);
+    const int ntt = (t + 1 < t1) ? 2 : 1;
+    for (int tt = 0; tt < ntt; ++tt) {
+      const float4 *xl = xs[cur] + tt * TL::TILE + lane * TL::LSTR;
+      const float4 y4 = ys[cur][tt * 4 + kq];
+      const float ya[4] = {y4.x, y4.y, y4.z, y4.w};
 #pragma unroll
-    for (int q = 0; q < C2; ++q) {
-      a4[q] = xa[o + q];
-      b4[q] = xb[o + q];
-    }
-    const float4 y4 = yv[t * 4 + kq];
-    const float ya[4] = {y4.x, y4.y, y4.z, y4.w};
-    const float *af = reinterpret_cast<const float *>(a4);
+      for (int sb = 0; sb < SUB; ++sb) {
+        v4f z = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int sb = 0; sb < SUB; ++sb) {
-      v4f z = {0.f, 0.f, 0.f, 0.f};
+        for (int q = 0; q < C2; ++q) {
+          const float4 a = xl[q];
+          z = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, th[sb][4 * q + 0], z, 0, 0, 0);
+          z = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, th[sb][4 * q + 1], z, 0, 0, 0);
+          z = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, th[sb][4 * q + 2], z, 0, 0, 0);
+          z = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, th[sb][4 * q + 3], z, 0, 0, 0);
+        }
+        float r[4];
 #pragma unroll
-      for (int c = 0; c < K1; ++c)
-        if (c < C1) z = __builtin_amdgcn_mfma_f32_16x16x4f32(af[c], th[sb][c], z, 0, 0, 0);
-      float r[4];
+        for (int i = 0; i < 4; ++i) r[i] = ya[i] - sigmoidf_fast(z[i]);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) r[i] = ya[i] - sigmoidf_fast(z[i]);
-#pragma unroll
-      for (int ct = 0; ct < C2; ++ct) {
-        const float bb[4] = {b4[ct].x, b4[ct].y, b4[ct].z, b4[ct].w};
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-          gacc[sb][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(r[i], bb[i], gacc[sb][ct], 0, 0, 0);
+        for (int ct = 0; ct < C2; ++ct) {
+          const float4 bb = xl[C2 + ct];
+          gacc[sb][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(r[0], bb.x, gacc[sb][ct], 0, 0, 0);
+          gacc[sb][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(r[1], bb.y, gacc[sb][ct], 0, 0, 0);
+          gacc[sb][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(r[2], bb.z, gacc[sb][ct], 0, 0, 0);
+          gacc[sb][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(r[3], bb.w, gacc[sb][ct], 0, 0, 0);
+        }
       }
     }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    cur ^= 1;
   }
 
   // partial gradient of this split: gpart[work item][slot][k]
@@ -388,55 +501,91 @@ __global__ __launch_bounds__(WG) void k_leapfrog(Dev D, int s, int zero_eps) {
     for (int ct = 0; ct < C2; ++ct)
 #pragma unroll
       for (int rr = 0; rr < 4; ++rr) {
-        const int slot = wave * 32 + sb * 16 + 4 * kq + rr;
+        const int slot = (wave * SUB + sb) * 16 + 4 * kq + rr;
         gp[(long long)slot * D.DS + 16 * ct + (lane & 15)] = gacc[sb][ct][rr];
       }
+}
 
-  __threadfence();
-  __syncthreads();
+// grid: (B * tiles per posterior, REDUCE_SLICES); each block reduces a slice
+// of one tile's 128 particles.
+constexpr int REDUCE_SLICES = 8;
+
+__global__ __launch_bounds__(256) void k_lf_reduce(Dev D, int c2, int s, int zero_eps) {
+  __shared__ Plan spl;
+  const int ntile = D.Jcap / TJ;
+  const int b = blockIdx.x / ntile, tile = blockIdx.x % ntile;
   if (threadIdx.x == 0) {
-    int last = 1;
-    if (pl.S > 1) {
-      int *cnt = D.tilecnt + pl.b * (D.Jcap / TJ) + pl.tile;
-      const int old = atomicAdd(cnt, 1);
-      last = (old == pl.S - 1);
-      if (last) atomicExch(cnt, 0);
-    }
-    slast = last;
+    Plan pl;
+    if (D.posts[b].C2 != c2 || !lf_plan_tile(D, c2, s, b, tile, pl)) pl.b = -1;
+    spl = pl;
   }
   __syncthreads();
-  if (!slast) return;
-  __threadfence();
-
-  // epilogue: sum partials in split order, prior term, second half kick
-  const int dp = 16 * C2;
+  const Plan pl = spl;
+  if (pl.b < 0) return;
+  const Post P = D.posts[b];
+  const float eps = zero_eps ? 0.f : (float)D.ps[b].eps;
+  const float he = 0.5f * eps;
   const float inv_pv = (float)(1.0 / D.prior_var);
-  const float *g0p = D.gpart + (long long)pl.wbase * TJ * D.DS;
-  for (int idx = threadIdx.x; idx < TJ * dp; idx += WG) {
-    const int slot = idx / dp, k = idx % dp;
-    const int j = perm[pl.tile * TJ + slot];
+  const float *minv = D.minv + (long long)b * D.DS;
+  const int dq = 4 * c2;  // float4 per particle row
+  constexpr int SPS = TJ / REDUCE_SLICES;
+  const int slot0 = blockIdx.y * SPS;
+  const float4 *g0p = reinterpret_cast<const float4 *>(D.gpart + (long long)pl.wbase * TJ * D.DS);
+  const long long sstride = (long long)TJ * D.DS / 4;  // float4 between splits
+  for (int idx = threadIdx.x; idx < SPS * dq; idx += blockDim.x) {
+    const int slot = slot0 + idx / dq, k4 = idx % dq;
+    const int j = D.perm[P.row0 + tile * TJ + slot];
     const long long row = P.row0 + j;
     if (D.n[row] <= s) continue;
-    float G = 0.f;
-    for (int sp = 0; sp < pl.S; ++sp) G += g0p[((long long)sp * TJ + slot) * D.DS + k];
-    const long long e = row * D.DS + k;
-    const float t0 = D.theta_t[e], p0 = D.p_t[e], g0 = D.grad_t[e];
-    const float ph = fmaf(he, g0, p0);
-    const float th1 = fmaf(eps * minv[k], ph, t0);
-    G = G - th1 * inv_pv;
-    D.theta_t[e] = th1;
-    D.p_t[e] = fmaf(he, G, ph);
-    D.grad_t[e] = G;
+    const long long o4 = (long long)slot * D.DS / 4 + k4;
+    float4 G = g0p[o4];
+    for (int sp = 1; sp < pl.S; ++sp) {
+      const float4 v = g0p[sp * sstride + o4];
+      G.x += v.x;
+      G.y += v.y;
+      G.z += v.z;
+      G.w += v.w;
+    }
+    const long long e = (row * D.DS) / 4 + k4;
+    const float4 t0 = reinterpret_cast<const float4 *>(D.theta_t)[e];
+    const float4 p0 = reinterpret_cast<const float4 *>(D.p_t)[e];
+    const float4 g0 = reinterpret_cast<const float4 *>(D.grad_t)[e];
+    const float4 mv = reinterpret_cast<const float4 *>(minv)[k4];
+    float4 th1, pn, gn;
+#define LF_LANE(c)                                       \
+  {                                                      \
+    const float ph = fmaf(he, g0.c, p0.c);               \
+    th1.c = fmaf(eps * mv.c, ph, t0.c);                  \
+    gn.c = G.c - th1.c * inv_pv;                         \
+    pn.c = fmaf(he, gn.c, ph);                           \
+  }
+    LF_LANE(x) LF_LANE(y) LF_LANE(z) LF_LANE(w)
+#undef LF_LANE
+    reinterpret_cast<float4 *>(D.theta_t)[e] = th1;
+    reinterpret_cast<float4 *>(D.p_t)[e] = pn;
+    reinterpret_cast<float4 *>(D.grad_t)[e] = gn;
   }
 }
 
 template <int C2>
 static hipError_t launch_lf_c2(const Dev &D, int step, int zero_eps, hipStream_t st) {
-  hipLaunchKernelGGL(k_leapfrog<C2>, dim3(D.lf_grid), dim3(WG), 0, st, D, step, zero_eps);
+  hipLaunchKernelGGL(k_lf_partial<C2>, dim3(D.lf_grid), dim3(WG), 0, st, D, step, zero_eps);
+  return hipGetLastError();
+}
+
+hipError_t launch_lf_reduce(const Dev &D, int c2, int step, int zero_eps, hipStream_t st) {
+  hipLaunchKernelGGL(k_lf_reduce, dim3(D.B * (D.Jcap / TJ), REDUCE_SLICES), dim3(256), 0, st, D, c2,
+                     step, zero_eps);
   return hipGetLastError();
 }
 
 hipError_t launch_leapfrog(const Dev &D, int c2, int step, int zero_eps, hipStream_t st) {
+  hipError_t e = launch_lf_partial(D, c2, step, zero_eps, st);
+  if (e != hipSuccess) return e;
+  return launch_lf_reduce(D, c2, step, zero_eps, st);
+}
+
+hipError_t launch_lf_partial(const Dev &D, int c2, int step, int zero_eps, hipStream_t st) {
   switch (c2) {
     case 1: return launch_lf_c2<1>(D, step, zero_eps, st);
     case 2: return launch_lf_c2<2>(D, step, zero_eps, st);
@@ -458,18 +607,17 @@ hipError_t launch_leapfrog(const Dev &D, int c2, int step, int zero_eps, hipStre
 // ---------------------------------------------------------------------------
 // Log-likelihood at the trajectory end points, recomputed for the energies:
 //   sum_n [ y_n z_n - log(1 + e^{z_n}) ],  z = X theta'   (Sec. IV model)
-// with accurate expf/log1pf and a Neumaier-compensated FP32 sum per lane;
-// lane partials are merged with error-free TwoSum, splits in order later.
+// GEMM1 as above (A part of the packed tiles only), accurate expf/log1pf and
+// a Neumaier-compensated FP32 sum per lane; the four lanes of a particle are
+// merged with error-free TwoSum, the splits in order by the weights kernel.
 // ---------------------------------------------------------------------------
 struct Neu {
   float s, c;
 };
 __device__ __forceinline__ void neu_add(Neu &a, float x) {
   const float t = a.s + x;
-  if (fabsf(a.s) >= fabsf(x))
-    a.c += (a.s - t) + x;
-  else
-    a.c += (x - t) + a.s;
+  const float e = (fabsf(a.s) >= fabsf(x)) ? ((a.s - t) + x) : ((x - t) + a.s);
+  a.c += e;
   a.s = t;
 }
 __device__ __forceinline__ Neu neu_merge(Neu a, Neu b) {
@@ -485,18 +633,20 @@ __device__ __forceinline__ Neu neu_merge(Neu a, Neu b) {
 template <int C2>
 __global__ __launch_bounds__(WG) void k_loglik(Dev D) {
   constexpr int K1 = 4 * C2;
+  using TL = Tiles<C2>;
+  __shared__ float4 xs[2][TL::STAGE];
+  __shared__ float4 ys[2][8];
   const int4 it = D.ll_items[blockIdx.x];
   const int b = it.x, tile = it.y, split = it.z;
   const Post P = D.posts[b];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, kq = lane >> 4;
-  const int C1 = P.C1;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, kq = lane >> 4;
   float th[SUB][K1];
 #pragma unroll
   for (int sb = 0; sb < SUB; ++sb) {
     const long long base =
-        (long long)(P.row0 + tile * TJ + wave * 32 + sb * 16 + (lane & 15)) * D.DS;
+        (long long)(P.row0 + tile * TJ + (wave * SUB + sb) * 16 + (lane & 15)) * D.DS + kq * K1;
 #pragma unroll
-    for (int c = 0; c < K1; ++c) th[sb][c] = (c < C1) ? D.theta_t[base + kq * C1 + c] : 0.f;
+    for (int c = 0; c < K1; ++c) th[sb][c] = D.theta_t[base + c];
   }
   Neu acc[SUB];
 #pragma unroll
@@ -504,33 +654,44 @@ __global__ __launch_bounds__(WG) void k_loglik(Dev D) {
   const int S = P.ll_splits;
   const int t0 = (int)((long long)split * P.NT / S);
   const int t1 = (int)((long long)(split + 1) * P.NT / S);
-  const float4 *xa = reinterpret_cast<const float4 *>(D.xa + P.xa);
+  const float4 *xab = reinterpret_cast<const float4 *>(D.xab + P.xab);
   const float4 *yv = reinterpret_cast<const float4 *>(D.yp + P.yo);
-  for (int t = t0; t < t1; ++t) {
-    float4 a4[C2];
-    const long long o = ((long long)t * 64 + lane) * C2;
+  stage_issue<C2>(xs[0], ys[0], xab, yv, t0, t1, wave, lane);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  int cur = 0;
+  for (int t = t0; t < t1; t += 2) {
+    const bool more = t + 2 < t1;
+    if (more) stage_issue<C2>(xs[cur ^ 1], ys[cur ^ 1], xab, yv, t + 2, t1, wave, lane);
+    const int ntt = (t + 1 < t1) ? 2 : 1;
+    for (int tt = 0; tt < ntt; ++tt) {
+      const float4 *xl = xs[cur] + tt * TL::TILE + lane * TL::LSTR;
+      const float4 y4 = ys[cur][tt * 4 + kq];
+      const float ya[4] = {y4.x, y4.y, y4.z, y4.w};
 #pragma unroll
-    for (int q = 0; q < C2; ++q) a4[q] = xa[o + q];
-    const float4 y4 = yv[t * 4 + kq];
-    const float ya[4] = {y4.x, y4.y, y4.z, y4.w};
-    const float *af = reinterpret_cast<const float *>(a4);
+      for (int sb = 0; sb < SUB; ++sb) {
+        v4f z = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int sb = 0; sb < SUB; ++sb) {
-      v4f z = {0.f, 0.f, 0.f, 0.f};
+        for (int q = 0; q < C2; ++q) {
+          const float4 a = xl[q];
+          z = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, th[sb][4 * q + 0], z, 0, 0, 0);
+          z = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, th[sb][4 * q + 1], z, 0, 0, 0);
+          z = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, th[sb][4 * q + 2], z, 0, 0, 0);
+          z = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, th[sb][4 * q + 3], z, 0, 0, 0);
+        }
 #pragma unroll
-      for (int c = 0; c < K1; ++c)
-        if (c < C1) z = __builtin_amdgcn_mfma_f32_16x16x4f32(af[c], th[sb][c], z, 0, 0, 0);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int n = 16 * t + 4 * kq + i;
-        if (n < P.N) {
+        for (int i = 0; i < 4; ++i) {
           // y z - softplus(z) = -softplus(-z) for y = 1, -softplus(z) for y = 0
           const float zz = ya[i] > 0.5f ? -z[i] : z[i];
-          const float sp = fmaxf(zz, 0.f) + log1pf(expf(-fabsf(zz)));
-          neu_add(acc[sb], -sp);
+          const float sp = softplusf_hw(zz);
+          const int n = 16 * (t + tt) + 4 * kq + i;
+          neu_add(acc[sb], n < P.N ? -sp : 0.f);
         }
       }
     }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    cur ^= 1;
   }
   // merge the four lanes (kq = 0..3) that hold the same particle
 #pragma unroll
@@ -544,7 +705,7 @@ __global__ __launch_bounds__(WG) void k_loglik(Dev D) {
       a = (lane & o) ? neu_merge(bq, a) : neu_merge(a, bq);
     }
     if (kq == 0) {
-      const long long row = P.row0 + tile * TJ + wave * 32 + sb * 16 + lane;
+      const long long row = P.row0 + tile * TJ + (wave * SUB + sb) * 16 + lane;
       D.llpart[(long long)split * D.B * D.Jcap + row] = make_float2(a.s, a.c);
     }
   }
@@ -707,9 +868,6 @@ __global__ __launch_bounds__(1024) void k_begin_step(Dev D, int conditional, con
   PState &S = D.ps[b];
   const Post P = D.posts[b];
   const int J = D.J;
-  // per-step counters and the step-count histogram
-  for (int i = t; i <= D.nmax; i += blockDim.x) D.hist[b * (D.nmax + 1) + i] = 0;
-  __syncthreads();
   const int k = S.k + (count_iteration ? 1 : 0);
   const int doit = conditional ? S.flag_resample : 1;
   const int ok = S.S > 0.0;
@@ -883,8 +1041,6 @@ __global__ __launch_bounds__(256) void k_setup(Dev D, const float *__restrict__ 
     D.l[row] = l;
     D.n[row] = n;
     D.H0[row] = -D.logpi[row] + K0;
-    atomicAdd(&D.hist[b * (D.nmax + 1) + n], 1);
-    atomicAdd((unsigned long long *)&S.grad_evals_step, (unsigned long long)n);
     if (j == 0) {
       S.L_used = L;
       S.eps_used = eps;
@@ -901,25 +1057,33 @@ hipError_t launch_setup(const Dev &D, const float *momenta, int init_mode, hipSt
 
 // ---------------------------------------------------------------------------
 // Counting sort of the particles by n_j, longest first, so that a leapfrog
-// tile holds particles of similar trajectory length; active[s] = #{j: n_j > s}.
-// Placement within a bin is arbitrary: each particle's arithmetic does not
-// depend on its tile or lane.
+// tile holds particles of similar trajectory length; active[s] = #{j: n_j > s}
+// and the step's gradient count sum_j n_j.  One work group per posterior; the
+// histogram is built with LDS atomics.  Placement within a bin is arbitrary:
+// each particle's arithmetic does not depend on its tile or lane.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void k_sort(Dev D) {
-  extern __shared__ int cur[];  // nmax + 1
+  extern __shared__ int lds[];  // hist[nmax + 1], cur[nmax + 1]
+  int *hist = lds, *cur = lds + (D.nmax + 1);
   const int b = blockIdx.x;
-  const int *hist = D.hist + b * (D.nmax + 1);
+  const int row0 = b * D.Jcap;
+  for (int i = threadIdx.x; i <= D.nmax; i += blockDim.x) hist[i] = 0;
+  __syncthreads();
+  for (int j = threadIdx.x; j < D.Jcap; j += blockDim.x) atomicAdd(&hist[D.n[row0 + j]], 1);
+  __syncthreads();
   if (threadIdx.x == 0) {
     int pos = 0;
+    long long evals = 0;
     for (int n = D.nmax; n >= 0; --n) {
       cur[n] = pos;
-      pos += (n == 0) ? (D.Jcap - D.J) + hist[0] : hist[n];
+      pos += hist[n];
+      evals += (long long)n * hist[n];
     }
     int *act = D.active + b * (D.nmax + 1);
     for (int s = 0; s <= D.nmax; ++s) act[s] = (s < D.nmax) ? cur[s] : 0;
+    D.ps[b].grad_evals_step = evals;
   }
   __syncthreads();
-  const int row0 = b * D.Jcap;
   for (int j = threadIdx.x; j < D.Jcap; j += blockDim.x) {
     const int n = D.n[row0 + j];
     const int p = atomicAdd(&cur[n], 1);
@@ -928,7 +1092,7 @@ __global__ __launch_bounds__(1024) void k_sort(Dev D) {
 }
 
 hipError_t launch_sort(const Dev &D, hipStream_t st) {
-  hipLaunchKernelGGL(k_sort, dim3(D.B), dim3(1024), (D.nmax + 1) * sizeof(int), st, D);
+  hipLaunchKernelGGL(k_sort, dim3(D.B), dim3(1024), 2 * (D.nmax + 1) * sizeof(int), st, D);
   return hipGetLastError();
 }
 
