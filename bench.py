@@ -26,13 +26,17 @@ sys.path.insert(0, ROOT)
 N_ROWS, DIM, PARTICLES, ITERS, NMAX = 10000, 100, 8192, 50, 64
 PEAK_FP32_MFMA_TFLOPS = 157.3
 METRIC = "particle-gradient evals/s and ESS/s vs plain FP32 GPU at matched posterior error"
-KERNEL_SRC = os.path.join(ROOT, "paper_2504_02627_amd", "csrc", "smc_kernels.hip")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2504_02627_amd", "csrc", f)
+               for f in ("smc_kernels.hip", "smc_internal.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "leapfrog_traffic.json")
 
 
 def kernel_hash():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for p in KERNEL_SRCS:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def workload_params():

@@ -46,7 +46,7 @@ struct Layout {
   std::vector<int4> items;
   size_t total = 0;
   // byte offsets
-  size_t o_posts, o_ps, o_xab, o_yp, o_theta, o_grad, o_theta_t, o_p_t, o_grad_t;
+  size_t o_posts, o_ps, o_xab, o_theta, o_grad, o_theta_t, o_p_t, o_grad_t;
   size_t o_logpi, o_logpi_t, o_logw, o_h, o_l, o_H0, o_dH, o_alpha, o_ca, o_cg;
   size_t o_n, o_perm, o_active, o_anc, o_acc, o_cdf, o_gpart, o_tilecnt, o_llpart;
   size_t o_items, o_colpart, o_means, o_minv, o_primes;
@@ -92,7 +92,7 @@ void plan(const smc_problem *pr, const smc_params *pa, Layout &L) {
   L.Jcap = (L.J + TJ - 1) / TJ * TJ;
   L.nmax = pa->max_leapfrog;
   int maxc2 = 1;
-  long long xoff = 0, yoff = 0, uoff = 0;
+  long long xoff = 0, uoff = 0;
   L.hp.resize(B);
   L.posts.resize(B);
   for (int b = 0; b < B; ++b) {
@@ -103,9 +103,8 @@ void plan(const smc_problem *pr, const smc_params *pa, Layout &L) {
     h.C1 = 4 * h.C2;
     h.NT = (h.N + 15) / 16;
     h.xab = xoff;
-    h.yo = yoff;
-    xoff += (long long)h.NT * 64 * 8 * h.C2;
-    yoff += 16LL * h.NT;
+    h.yo = 0;
+    xoff += (long long)h.NT * 64 * (8 * h.C2 + 4);
     maxc2 = std::max(maxc2, h.C2);
     Post &p = L.posts[b];
     memset(&p, 0, sizeof(p));
@@ -116,12 +115,11 @@ void plan(const smc_problem *pr, const smc_params *pa, Layout &L) {
     p.NT = h.NT;
     p.row0 = b * L.Jcap;
     p.xab = h.xab;
-    p.yo = h.yo;
     p.uoff = uoff;
     uoff += (long long)L.J * h.d;
   }
   L.DS = 16 * maxc2;
-  // leapfrog launches: one 8-wave work group per compute unit (256 CUs)
+  // leapfrog launches: one resident 8-wave work group per compute unit (256 CUs)
   L.lf_target = 256;
   const int ntile = L.Jcap / TJ;
   L.lf_grid = L.lf_target + B * ntile;
@@ -148,7 +146,6 @@ void plan(const smc_problem *pr, const smc_params *pa, Layout &L) {
   L.o_posts = take(c, B * sizeof(Post));
   L.o_ps = take(c, B * sizeof(PState));
   L.o_xab = take(c, xoff * sizeof(float));
-  L.o_yp = take(c, yoff * sizeof(float));
   L.o_theta = take(c, st);
   L.o_grad = take(c, st);
   L.o_theta_t = take(c, st);
@@ -283,7 +280,6 @@ smc_status smc_init(const smc_problem *prob, const smc_params *par, void *worksp
   D.posts = (Post *)(w + L.o_posts);
   D.ps = (PState *)(w + L.o_ps);
   D.xab = (float *)(w + L.o_xab);
-  D.yp = (float *)(w + L.o_yp);
   D.theta = (float *)(w + L.o_theta);
   D.grad = (float *)(w + L.o_grad);
   D.theta_t = (float *)(w + L.o_theta_t);

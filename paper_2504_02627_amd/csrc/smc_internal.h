@@ -31,7 +31,6 @@ struct Post {
   int ll_splits;   // N-splits of the log-likelihood pass
   int ll_base;     // first work item of this posterior in the log-likelihood plan
   long long xab;     // float offset into the packed X tiles
-  long long yo;      // float offset into padded y
   long long uoff;    // offset of this posterior's block in caller (B*J) x d_b arrays
 };
 
@@ -66,7 +65,7 @@ struct Dev {                    // pointers carved from the workspace
   double adam_lr, adam_b1, adam_b2, adam_eps, avg_decay, target_accept;
   int adapt_eps, num_warmup;
   uint64_t seed;
-  float *xab, *yp;              // packed X tiles ([tile][lane][A | B]), padded y
+  float *xab;                   // packed data tiles ([tile][lane][A | B | y])
   float *theta, *grad;          // current state, B*Jcap x DS
   float *theta_t, *p_t, *grad_t;// trajectory buffers
   double *logpi, *logpi_t, *logw;
@@ -92,7 +91,7 @@ struct Dev {                    // pointers carved from the workspace
 // Host copy of one posterior's packing sizes.
 struct HostPost {
   int N, d, C1, C2, NT;
-  long long xab, yo;
+  long long xab, yo;  // yo unused (y is packed with X)
 };
 
 // Launchers (smc_kernels.hip).  All stream-ordered.

@@ -85,17 +85,17 @@ struct OpMax {
 };
 
 // ---------------------------------------------------------------------------
-// Packing of X into the MFMA operand layouts (once, at init).  dp = 16 C2.
+// Packing of X and y into the MFMA operand layouts (once, at init).  dp = 16 C2.
 //
 // A part (GEMM1, Z^T = X Theta^T with v_mfma_f32_16x16x4f32, M = data rows,
 //   K = features): lane l of data tile t holds X[16t + l%16][(l/16) 4C2 + c]
 //   in slot c < 4 C2 (the K index of MFMA c is (l/16) 4C2 + c).
 // B part (GEMM2, G = R X, M = particles, N = 16 features, K = 4 data rows):
 //   lane l holds X[16t + 4(l/16) + i][16 ct + l%16] in slot 4 ct + i.
-// Interleaved per tile and lane: [tile][lane][A: 4C2 | B: 4C2] floats, so one
-// data tile is one contiguous block of 512 C2 floats.
-// Padded y: y[n] for n < N, 1/2 beyond, which makes the padded residual
-// y - sigmoid(0) exactly zero.
+// Y part: lane l holds y[16t + 4(l/16) + i], i = 0..3 (1/2 for padded rows,
+//   which makes the padded residual y - sigmoid(0) exactly zero).
+// Per tile and lane: [A: 4C2 | B: 4C2 | Y: 4] floats = 2 C2 + 1 float4, so a
+// data tile is one contiguous block of 64 (2 C2 + 1) float4.
 // ---------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ float to_f32(T v);
@@ -108,42 +108,43 @@ __device__ __forceinline__ float to_f32<uint16_t>(uint16_t v) {
 
 template <typename T>
 __global__ void k_pack(const T *__restrict__ X, const float *__restrict__ y, int N, int d, int C2,
-                       int NT, float *__restrict__ xab, float *__restrict__ yp) {
+                       int NT, float *__restrict__ xab) {
   const int K1 = 4 * C2;
-  const long long tot = (long long)NT * 64 * 2 * K1;
+  const int LF = 2 * K1 + 4;  // floats per lane and tile
+  const long long tot = (long long)NT * 64 * LF;
   for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < tot;
        idx += (long long)gridDim.x * blockDim.x) {
-    const int slot = (int)(idx % (2 * K1));
-    const long long r = idx / (2 * K1);
+    const int slot = (int)(idx % LF);
+    const long long r = idx / LF;
     const int lane = (int)(r % 64);
     const int t = (int)(r / 64);
-    int n, k;
+    float v;
     if (slot < K1) {
-      n = 16 * t + (lane & 15);
-      k = (lane >> 4) * K1 + slot;
-    } else {
+      const int n = 16 * t + (lane & 15), k = (lane >> 4) * K1 + slot;
+      v = (n < N && k < d) ? to_f32<T>(X[(long long)n * d + k]) : 0.f;
+    } else if (slot < 2 * K1) {
       const int sb = slot - K1, ct = sb >> 2, i = sb & 3;
-      n = 16 * t + 4 * (lane >> 4) + i;
-      k = 16 * ct + (lane & 15);
+      const int n = 16 * t + 4 * (lane >> 4) + i, k = 16 * ct + (lane & 15);
+      v = (n < N && k < d) ? to_f32<T>(X[(long long)n * d + k]) : 0.f;
+    } else {
+      const int n = 16 * t + 4 * (lane >> 4) + (slot - 2 * K1);
+      v = n < N ? y[n] : 0.5f;
     }
-    xab[idx] = (n < N && k < d) ? to_f32<T>(X[(long long)n * d + k]) : 0.f;
+    xab[idx] = v;
   }
-  for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < 16LL * NT;
-       n += (long long)gridDim.x * blockDim.x)
-    yp[n] = n < N ? y[n] : 0.5f;
 }
 
 hipError_t launch_pack_one(const Dev &D, const void *X, const float *y, int x_dtype,
                            const HostPost &P, hipStream_t st) {
-  const long long tot = (long long)P.NT * 64 * 8 * P.C2;
+  const long long tot = (long long)P.NT * 64 * (8 * P.C2 + 4);
   int grid = (int)((tot + 255) / 256);
   if (grid > 65535) grid = 65535;
   if (x_dtype == 0)
     hipLaunchKernelGGL(k_pack<float>, dim3(grid), dim3(256), 0, st, (const float *)X, y, P.N, P.d,
-                       P.C2, P.NT, D.xab + P.xab, D.yp + P.yo);
+                       P.C2, P.NT, D.xab + P.xab);
   else
     hipLaunchKernelGGL(k_pack<uint16_t>, dim3(grid), dim3(256), 0, st, (const uint16_t *)X, y,
-                       P.N, P.d, P.C2, P.NT, D.xab + P.xab, D.yp + P.yo);
+                       P.N, P.d, P.C2, P.NT, D.xab + P.xab);
   return hipGetLastError();
 }
 
@@ -262,6 +263,9 @@ struct Plan {
 };
 
 constexpr int LF_MAX_SPLIT = 64;
+// resident waves per SIMD asked of the fused leapfrog kernel: one 8-wave work
+// group per compute unit (about 150 VGPRs at d = 100)
+constexpr int LF_WAVES_PER_SIMD = 2;
 
 // Deterministic plan of a leapfrog launch at step s, computed identically by
 // every work group from the active counts.  About lf_target work items (one
@@ -370,16 +374,14 @@ __device__ __forceinline__ float sigmoidf_fast(float z) {
 // LDS staging of packed data tiles, two 16-row tiles per stage, double
 // buffered, with gfx950's direct global-to-LDS loads (global_load_lds_dwordx4:
 // each lane's 16 bytes land at the wave-uniform LDS base + 16 * lane), so the
-// prefetch of the next stage holds no registers.  In LDS a tile is
-// 64 lanes x (2 C2 + 1) float4 (A | B | pad): the 16-byte pad per lane keeps
-// the per-lane 16-byte operand reads free of bank conflicts.  Each lane of a
-// load instruction fetches the global float4 that belongs to its LDS slot; pad
-// slots re-read the tile's first float4.
+// prefetch of the next stage holds no registers.  A tile is copied verbatim:
+// 64 lanes x (2 C2 + 1) float4 (A | B | y); the odd lane stride keeps the
+// per-lane 16-byte operand reads free of bank conflicts.  Load m of a stage
+// moves float4 [64 m, 64 m + 64) of it, which lie in tile m / (2 C2 + 1).
 template <int C2>
 struct Tiles {
-  static constexpr int GF4 = 2 * C2;          // float4 per lane and tile in global memory
-  static constexpr int LSTR = GF4 + 1;        // padded lane stride in LDS (float4)
-  static constexpr int TILE = 64 * LSTR;      // float4 per tile in LDS
+  static constexpr int LSTR = 2 * C2 + 1;     // float4 per lane and tile
+  static constexpr int TILE = 64 * LSTR;      // float4 per tile
   static constexpr int STAGE = 2 * TILE;      // two tiles
   static constexpr int NINST = STAGE / 64;    // wave-wide loads per stage
 };
@@ -387,30 +389,25 @@ struct Tiles {
 typedef __attribute__((address_space(3))) void lds_void;
 
 template <int C2>
-__device__ __forceinline__ void stage_issue(float4 *xs, float4 *ys, const float4 *__restrict__ xab,
-                                            const float4 *__restrict__ yv, int t, int t1,
-                                            int wave, int lane) {
+__device__ __forceinline__ void stage_issue(float4 *xs, const float4 *__restrict__ xab, int t,
+                                            int t1, int wave, int lane) {
   using TL = Tiles<C2>;
-  for (int m = wave; m < TL::NINST; m += WAVES) {
-    const int P = 64 * m + lane;
-    const int tt = P / TL::TILE, rem = P % TL::TILE;
-    const int ln = rem / TL::LSTR, q = rem % TL::LSTR;
-    const int tg = (t + tt < t1) ? t + tt : t;  // a missing second tile re-reads the first
-    const long long g = ((long long)tg * 64 + ln) * TL::GF4 + (q < TL::GF4 ? q : 0);
-    __builtin_amdgcn_global_load_lds((const void *)(xab + g), (lds_void *)(xs + 64 * m), 16, 0, 0);
-  }
-  if (wave == WAVES - 1 && lane < 8) {
-    const int tg = (t + (lane >> 2) < t1) ? t + (lane >> 2) : t;
-    ys[lane] = yv[tg * 4 + (lane & 3)];
+  const float4 *src = xab + (long long)t * TL::TILE + lane;
+#pragma unroll
+  for (int k = 0; k < (TL::NINST + WAVES - 1) / WAVES; ++k) {
+    const int m = wave + k * WAVES;
+    // wave-uniform: skip loads past the split's last tile
+    if (m < TL::NINST && t + m / TL::LSTR < t1)
+      __builtin_amdgcn_global_load_lds((const void *)(src + 64 * m), (lds_void *)(xs + 64 * m), 16,
+                                       0, 0);
   }
 }
 
 template <int C2>
-__global__ __launch_bounds__(WG) void k_lf_partial(Dev D, int s, int zero_eps) {
+__global__ __launch_bounds__(WG, LF_WAVES_PER_SIMD) void k_lf_partial(Dev D, int s, int zero_eps) {
   constexpr int K1 = 4 * C2;
   using TL = Tiles<C2>;
   __shared__ float4 xs[2][TL::STAGE];
-  __shared__ float4 ys[2][8];
   __shared__ Plan spl;
   if (threadIdx.x == 0) {
     Plan pl;
@@ -451,18 +448,17 @@ __global__ __launch_bounds__(WG) void k_lf_partial(Dev D, int s, int zero_eps) {
   const int t0 = (int)((long long)pl.split * P.NT / pl.S);
   const int t1 = (int)((long long)(pl.split + 1) * P.NT / pl.S);
   const float4 *xab = reinterpret_cast<const float4 *>(D.xab + P.xab);
-  const float4 *yv = reinterpret_cast<const float4 *>(D.yp + P.yo);
-  stage_issue<C2>(xs[0], ys[0], xab, yv, t0, t1, wave, lane);
+  stage_issue<C2>(xs[0], xab, t0, t1, wave, lane);
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   int cur = 0;
   for (int t = t0; t < t1; t += 2) {
     const bool more = t + 2 < t1;
-    if (more) stage_issue<C2>(xs[cur ^ 1], ys[cur ^ 1], xab, yv, t + 2, t1, wave, lane);
+    if (more) stage_issue<C2>(xs[cur ^ 1], xab, t + 2, t1, wave, lane);
     const int ntt = (t + 1 < t1) ? 2 : 1;
     for (int tt = 0; tt < ntt; ++tt) {
       const float4 *xl = xs[cur] + tt * TL::TILE + lane * TL::LSTR;
-      const float4 y4 = ys[cur][tt * 4 + kq];
+      const float4 y4 = xl[2 * C2];
       const float ya[4] = {y4.x, y4.y, y4.z, y4.w};
 #pragma unroll
       for (int sb = 0; sb < SUB; ++sb) {
@@ -635,7 +631,6 @@ __global__ __launch_bounds__(WG) void k_loglik(Dev D) {
   constexpr int K1 = 4 * C2;
   using TL = Tiles<C2>;
   __shared__ float4 xs[2][TL::STAGE];
-  __shared__ float4 ys[2][8];
   const int4 it = D.ll_items[blockIdx.x];
   const int b = it.x, tile = it.y, split = it.z;
   const Post P = D.posts[b];
@@ -655,18 +650,17 @@ __global__ __launch_bounds__(WG) void k_loglik(Dev D) {
   const int t0 = (int)((long long)split * P.NT / S);
   const int t1 = (int)((long long)(split + 1) * P.NT / S);
   const float4 *xab = reinterpret_cast<const float4 *>(D.xab + P.xab);
-  const float4 *yv = reinterpret_cast<const float4 *>(D.yp + P.yo);
-  stage_issue<C2>(xs[0], ys[0], xab, yv, t0, t1, wave, lane);
+  stage_issue<C2>(xs[0], xab, t0, t1, wave, lane);
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   int cur = 0;
   for (int t = t0; t < t1; t += 2) {
     const bool more = t + 2 < t1;
-    if (more) stage_issue<C2>(xs[cur ^ 1], ys[cur ^ 1], xab, yv, t + 2, t1, wave, lane);
+    if (more) stage_issue<C2>(xs[cur ^ 1], xab, t + 2, t1, wave, lane);
     const int ntt = (t + 1 < t1) ? 2 : 1;
     for (int tt = 0; tt < ntt; ++tt) {
       const float4 *xl = xs[cur] + tt * TL::TILE + lane * TL::LSTR;
-      const float4 y4 = ys[cur][tt * 4 + kq];
+      const float4 y4 = xl[2 * C2];
       const float ya[4] = {y4.x, y4.y, y4.z, y4.w};
 #pragma unroll
       for (int sb = 0; sb < SUB; ++sb) {
