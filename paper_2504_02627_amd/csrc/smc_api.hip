@@ -20,6 +20,7 @@ struct smc_ctx {
   std::vector<Post> posts;
   std::vector<PState> ps_host;
   std::vector<int> c2s;        // distinct GEMM2 tile counts among the posteriors
+  std::vector<int3> ll_groups; // (C2, first item, count) of the log-likelihood pass
   std::vector<int4> ll_items;
   std::vector<int> primes;
   std::vector<float> minv;
@@ -44,6 +45,7 @@ struct Layout {
   std::vector<HostPost> hp;
   std::vector<Post> posts;
   std::vector<int4> items;
+  std::vector<int3> groups;  // (C2, first item, item count) of the log-likelihood pass
   size_t total = 0;
   // byte offsets
   size_t o_posts, o_ps, o_xab, o_theta, o_grad, o_theta_t, o_p_t, o_grad_t;
@@ -129,14 +131,27 @@ void plan(const smc_problem *pr, const smc_params *pa, Layout &L) {
   const long long chunk = std::max(1LL, (U + L.lf_target - 1) / L.lf_target);
   L.items.clear();
   L.ll_smax = 1;
+  // items grouped by feature-tile count C2: one launch per group covers
+  // exactly its own posteriors
+  L.groups.clear();
   for (int b = 0; b < B; ++b) {
-    long long S = (L.hp[b].NT + chunk - 1) / chunk;
-    S = std::max(1LL, std::min<long long>(S, L.hp[b].NT));
-    L.posts[b].ll_splits = (int)S;
-    L.posts[b].ll_base = (int)L.items.size();
-    L.ll_smax = std::max(L.ll_smax, (int)S);
-    for (int t = 0; t < ntile; ++t)
-      for (int s = 0; s < S; ++s) L.items.push_back(make_int4(b, t, s, 0));
+    bool seen = false;
+    for (const auto &g : L.groups) seen |= (g.x == L.hp[b].C2);
+    if (!seen) L.groups.push_back(make_int3(L.hp[b].C2, 0, 0));
+  }
+  for (auto &g : L.groups) {
+    g.y = (int)L.items.size();
+    for (int b = 0; b < B; ++b) {
+      if (L.hp[b].C2 != g.x) continue;
+      long long S = (L.hp[b].NT + chunk - 1) / chunk;
+      S = std::max(1LL, std::min<long long>(S, L.hp[b].NT));
+      L.posts[b].ll_splits = (int)S;
+      L.posts[b].ll_base = (int)L.items.size();
+      L.ll_smax = std::max(L.ll_smax, (int)S);
+      for (int t = 0; t < ntile; ++t)
+        for (int s = 0; s < S; ++s) L.items.push_back(make_int4(b, t, s, 0));
+    }
+    g.z = (int)L.items.size() - g.y;
   }
   L.ll_nitems = (int)L.items.size();
   L.col_chunks = std::max(1, std::min(64, (L.J + 127) / 128));
@@ -319,9 +334,8 @@ smc_status smc_init(const smc_problem *prob, const smc_params *par, void *worksp
   ctx->hp = L.hp;
   ctx->posts = L.posts;
   ctx->ll_items = L.items;
-  for (const HostPost &h : L.hp)
-    if (std::find(ctx->c2s.begin(), ctx->c2s.end(), h.C2) == ctx->c2s.end())
-      ctx->c2s.push_back(h.C2);
+  ctx->ll_groups = L.groups;
+  for (const int3 &g : L.groups) ctx->c2s.push_back(g.x);
   ctx->primes = first_primes(NPRIMES);
   ctx->minv.assign((size_t)L.B * L.DS, 1.0f);
   ctx->ps_host.resize(L.B);
@@ -361,7 +375,7 @@ smc_status smc_init(const smc_problem *prob, const smc_params *par, void *worksp
     CKI(launch_pack_one(D, prob->X[b], prob->y[b], prob->x_dtype, L.hp[b], ctx->st));
   CKI(launch_init_theta(D, theta0, ctx->st));
   for (int c2 : ctx->c2s) CKI(launch_leapfrog(D, c2, 0, 1, ctx->st));
-  for (int c2 : ctx->c2s) CKI(launch_loglik(D, c2, ctx->st));
+  for (const int3 &g : ctx->ll_groups) CKI(launch_loglik(D, g.x, g.y, g.z, ctx->st));
   CKI(launch_init_weights(D, ctx->st));
   CKI(launch_ess(D, 0, ctx->st));
   // the host copies above must stay alive until they have run
@@ -410,9 +424,9 @@ smc_status smc_step(smc_ctx *ctx, const smc_inject *inject, smc_stats *stats) {
       CK(launch_lf_reduce(D, c2, s, 0, ctx->st));
       CK(timed_end(ctx, ei));
     }
-  for (int c2 : ctx->c2s) {
+  for (const int3 &g : ctx->ll_groups) {
     CK(timed_begin(ctx, 1, ei));
-    CK(launch_loglik(D, c2, ctx->st));
+    CK(launch_loglik(D, g.x, g.y, g.z, ctx->st));
     CK(timed_end(ctx, ei));
   }
   CK(launch_weights(D, inject ? inject->mh_uniforms : nullptr, 0, ctx->st));

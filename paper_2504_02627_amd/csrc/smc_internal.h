@@ -110,7 +110,7 @@ hipError_t launch_sort(const Dev &D, hipStream_t st);
 hipError_t launch_leapfrog(const Dev &D, int c2, int step, int zero_eps, hipStream_t st);
 hipError_t launch_lf_partial(const Dev &D, int c2, int step, int zero_eps, hipStream_t st);
 hipError_t launch_lf_reduce(const Dev &D, int c2, int step, int zero_eps, hipStream_t st);
-hipError_t launch_loglik(const Dev &D, int c2, hipStream_t st);
+hipError_t launch_loglik(const Dev &D, int c2, int first, int count, hipStream_t st);
 hipError_t launch_weights(const Dev &D, const double *mh_u, int init_mode, hipStream_t st);
 hipError_t launch_chees(const Dev &D, hipStream_t st);
 hipError_t launch_commit(const Dev &D, hipStream_t st);

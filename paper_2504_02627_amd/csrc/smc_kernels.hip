@@ -627,11 +627,11 @@ __device__ __forceinline__ Neu neu_merge(Neu a, Neu b) {
 }
 
 template <int C2>
-__global__ __launch_bounds__(WG) void k_loglik(Dev D) {
+__global__ __launch_bounds__(WG) void k_loglik(Dev D, int first) {
   constexpr int K1 = 4 * C2;
   using TL = Tiles<C2>;
   __shared__ float4 xs[2][TL::STAGE];
-  const int4 it = D.ll_items[blockIdx.x];
+  const int4 it = D.ll_items[first + blockIdx.x];
   const int b = it.x, tile = it.y, split = it.z;
   const Post P = D.posts[b];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, kq = lane >> 4;
@@ -706,26 +706,28 @@ __global__ __launch_bounds__(WG) void k_loglik(Dev D) {
 }
 
 template <int C2>
-static hipError_t launch_ll_c2(const Dev &D, hipStream_t st) {
-  hipLaunchKernelGGL(k_loglik<C2>, dim3(D.ll_nitems), dim3(WG), 0, st, D);
+static hipError_t launch_ll_c2(const Dev &D, int first, int count, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_loglik<C2>, dim3(count), dim3(WG), 0, st, D, first);
   return hipGetLastError();
 }
 
-hipError_t launch_loglik(const Dev &D, int c2, hipStream_t st) {
+// items [first, first + count) all belong to posteriors with this C2
+hipError_t launch_loglik(const Dev &D, int c2, int first, int count, hipStream_t st) {
   switch (c2) {
-    case 1: return launch_ll_c2<1>(D, st);
-    case 2: return launch_ll_c2<2>(D, st);
-    case 3: return launch_ll_c2<3>(D, st);
-    case 4: return launch_ll_c2<4>(D, st);
-    case 5: return launch_ll_c2<5>(D, st);
-    case 6: return launch_ll_c2<6>(D, st);
-    case 7: return launch_ll_c2<7>(D, st);
-    case 8: return launch_ll_c2<8>(D, st);
-    case 9: return launch_ll_c2<9>(D, st);
-    case 10: return launch_ll_c2<10>(D, st);
-    case 11: return launch_ll_c2<11>(D, st);
-    case 12: return launch_ll_c2<12>(D, st);
-    case 13: return launch_ll_c2<13>(D, st);
+    case 1: return launch_ll_c2<1>(D, first, count, st);
+    case 2: return launch_ll_c2<2>(D, first, count, st);
+    case 3: return launch_ll_c2<3>(D, first, count, st);
+    case 4: return launch_ll_c2<4>(D, first, count, st);
+    case 5: return launch_ll_c2<5>(D, first, count, st);
+    case 6: return launch_ll_c2<6>(D, first, count, st);
+    case 7: return launch_ll_c2<7>(D, first, count, st);
+    case 8: return launch_ll_c2<8>(D, first, count, st);
+    case 9: return launch_ll_c2<9>(D, first, count, st);
+    case 10: return launch_ll_c2<10>(D, first, count, st);
+    case 11: return launch_ll_c2<11>(D, first, count, st);
+    case 12: return launch_ll_c2<12>(D, first, count, st);
+    case 13: return launch_ll_c2<13>(D, first, count, st);
   }
   return hipErrorInvalidValue;
 }
