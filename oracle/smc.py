@@ -44,6 +44,17 @@ LOG_2PI = math.log(2.0 * math.pi)
 # Targets: log pi(theta) and its gradient for a population theta (J, d)
 # ===========================================================================
 
+def bf16_round(x):
+    """Round to bfloat16 (8-bit significand), to nearest, ties to even, after
+    rounding to binary32: the conversion the precision form applies to its
+    MFMA operands.  Returned as float64.  NaN stays NaN."""
+    f = np.asarray(x, dtype=np.float64).astype(np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = ((u + np.uint64(0x7FFF) + ((u >> np.uint64(16)) & np.uint64(1))) >> np.uint64(16)) << np.uint64(16)
+    r = (u & np.uint64(0xFFFFFFFF)).astype(np.uint32).view(np.float32).astype(np.float64)
+    return np.where(np.isnan(f), np.nan, r)
+
+
 class LogisticRegression:
     """Bayesian logistic regression, Sec. IV (German Credit model):
     y_n ~ Bernoulli(sigmoid(theta^T x_n)), prior q0 = N(0, prior_var I).
@@ -77,6 +88,17 @@ class LogisticRegression:
         R = self.y - expit(Z)
         grad = R @ self.X - theta / self.prior_var
         return loglik + self.log_prior(theta), grad
+
+    def grad_bf16(self, theta):
+        """Trajectory gradient of the precision form: theta, X and the residual
+        R = y - sigmoid(X theta) rounded to bfloat16 (bf16_round) before the two
+        products, which are then exact and summed in binary64; the prior term
+        uses theta unrounded.  Only the proposal uses it: energies stay exact."""
+        theta = np.atleast_2d(theta)
+        Xb = bf16_round(self.X)
+        Z = bf16_round(theta) @ Xb.T
+        R = bf16_round(self.y - expit(Z))
+        return R @ Xb - theta / self.prior_var
 
 
 class Gaussian:
@@ -147,7 +169,7 @@ def hamiltonian(logpi, p, minv=None):
     return -np.asarray(logpi, dtype=np.float64) + kinetic(p, minv)
 
 
-def leapfrog(target, theta, p, grad, eps, n_steps, minv=None):
+def leapfrog(target, theta, p, grad, eps, n_steps, minv=None, traj_grad=None):
     """Leapfrog integrator (eqs. LF_p1/2, LF_theta, LF_p; Alg. LF_example) run
     for n_steps[j] steps on particle j, with the gradient cached between steps.
 
@@ -156,6 +178,8 @@ def leapfrog(target, theta, p, grad, eps, n_steps, minv=None):
     Reading of the gradient count (Sec. V): one evaluation per step plus one
     before the loop, which the caller already holds in `grad`.
 
+    traj_grad: optional gradient function used for the moves (the precision
+    form); log pi' is then evaluated exactly at the end point.
     Returns (theta', p', grad', logpi', n_grad) where n_grad[j] = n_steps[j].
     """
     theta = np.array(theta, dtype=np.float64)
@@ -169,13 +193,16 @@ def leapfrog(target, theta, p, grad, eps, n_steps, minv=None):
         act = n_steps > s
         p[act] += 0.5 * eps * grad[act]
         theta[act] += eps * mv * p[act]
-        lp, g = target.log_and_grad(theta[act])
+        if traj_grad is None:
+            lp, g = target.log_and_grad(theta[act])
+            logpi[act] = lp
+        else:
+            g = traj_grad(theta[act])
         grad[act] = g
-        logpi[act] = lp
         p[act] += 0.5 * eps * grad[act]
-    done = n_steps > 0
-    if not np.all(done):
-        logpi[~done], _ = target.log_and_grad(theta[~done])
+    redo = ~(n_steps > 0) if traj_grad is None else np.ones(J, dtype=bool)
+    if np.any(redo):
+        logpi[redo], _ = target.log_and_grad(theta[redo])
     return theta, p, grad, logpi, n_steps.copy()
 
 
@@ -442,7 +469,7 @@ DEFAULTS = dict(
     max_leapfrog=64, num_warmup=None, jitter="halton1d", mh_accept=False,
     resampling="systematic", step_size=0.1, traj_length=5.0, ess_frac=0.5,
     adam_lr=0.025, adam_b1=0.9, adam_b2=0.999, adam_eps=1e-8, avg_decay=0.9,
-    adapt_step_size=False, target_accept=0.651, seed=0, prior_var=1.0,
+    adapt_step_size=False, target_accept=0.651, seed=0, prior_var=1.0, precision="f64",
 )
 
 
@@ -482,7 +509,11 @@ class OracleSMC:
         if theta0 is None:
             theta0 = math.sqrt(self.prior_var) * philox.normals_np(P["seed"], J, 0, philox.STREAM_INIT, d)
         self.theta = np.array(theta0, dtype=np.float64).reshape(J, d)
+        # precision form: BF16 trajectory gradients (target.grad_bf16), exact energies
+        self.traj_grad = target.grad_bf16 if P["precision"] == "bf16" else None
         self.logpi, self.grad = target.log_and_grad(self.theta)
+        if self.traj_grad is not None:
+            self.grad = self.traj_grad(self.theta)
         logq0 = (-0.5 * np.sum(self.theta ** 2, axis=1) / self.prior_var
                  - 0.5 * d * math.log(2.0 * math.pi * self.prior_var))
         # eq. init_weights, with the -log J reading
@@ -545,7 +576,8 @@ class OracleSMC:
         h = self.jitter(k)
         l, n = step_counts(h, self.L, self.eps, P["max_leapfrog"])
         # a5: leapfrog trajectories
-        th1, p1, g1, lp1, ng = leapfrog(self.target, self.theta, p0, self.grad, self.eps, n, self.minv)
+        th1, p1, g1, lp1, ng = leapfrog(self.target, self.theta, p0, self.grad, self.eps, n, self.minv,
+                                        traj_grad=self.traj_grad)
         self.grad_evals += int(np.sum(ng))
         # a6: energies, acceptance, weights
         dh = delta_h(self.logpi, p0, lp1, p1, self.minv)
@@ -604,6 +636,8 @@ class OracleSMC:
         state); log pi and the gradient are recomputed at theta."""
         self.theta = np.array(theta, dtype=np.float64).reshape(self.J, self.d)
         self.logpi, self.grad = self.target.log_and_grad(self.theta)
+        if self.traj_grad is not None:
+            self.grad = self.traj_grad(self.theta)
         self.logw = np.array(logw, dtype=np.float64).copy()
 
     def log_evidence(self):

@@ -117,3 +117,53 @@ def test_gradient_count_convention_no_jitter_cap():
     _, n = O.step_counts(np.ones(1000), 5.0, 0.001, 500)
     assert np.all(n == 500)
     assert float(np.mean(n + 1)) == 501.0
+
+
+def test_bf16_rounding_ties_to_even_and_matches_torch():
+    import torch
+    cases = {1.0: 1.0, 1.0 + 2 ** -8: 1.0, 1.0 + 3 * 2 ** -8: 1.0 + 2 ** -6,
+             1.0 + 2 ** -8 + 2 ** -20: 1.0 + 2 ** -7, -(1.0 + 2 ** -8 + 2 ** -20): -(1.0 + 2 ** -7),
+             0.0: 0.0, 3.0e38: 226 / 128 * 2.0 ** 127}
+    for x, r in cases.items():
+        assert O.bf16_round(x) == pytest.approx(r, rel=1e-7)
+    assert np.isnan(O.bf16_round(np.nan)) and O.bf16_round(np.inf) == np.inf
+    rng = np.random.default_rng(0)
+    x = np.concatenate([rng.standard_normal(20000) * 10 ** rng.uniform(-6, 6, 20000),
+                        rng.uniform(-1, 1, 20000)]).astype(np.float32)
+    ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float64).numpy()
+    np.testing.assert_array_equal(O.bf16_round(x), ref)
+
+
+def test_bf16_gradient_is_the_exact_gradient_on_bf16_grids():
+    # When theta, X and the residual are already bfloat16 values, the
+    # precision-form gradient equals the exact one: choose y and theta so that
+    # sigmoid(X theta) = 1/2 (theta = 0) and y in {0, 1}: R = +-1/2 exactly.
+    rng = np.random.default_rng(4)
+    X = O.bf16_round(rng.standard_normal((40, 6)))
+    y = (rng.random(40) < 0.5).astype(float)
+    t = O.LogisticRegression(X, y)
+    th = np.zeros((3, 6))
+    np.testing.assert_allclose(t.grad_bf16(th), t.log_and_grad(th)[1], rtol=0, atol=1e-12)
+    # and it differs from the exact gradient at a generic point by about 2^-8
+    th = rng.standard_normal((3, 6)) * 0.3
+    rel = np.abs(t.grad_bf16(th) - t.log_and_grad(th)[1]).max() / np.abs(t.log_and_grad(th)[1]).max()
+    assert 1e-6 < rel < 2e-2
+
+
+def test_bf16_trajectories_keep_weights_exact():
+    # With any position-only force field the leapfrog map is volume preserving
+    # and reversible, so the weight increment -Delta H with exact energies
+    # remains the exact change-of-variables weight: reversing the BF16
+    # trajectory returns to the start.
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((50, 3))
+    y = (rng.random(50) < 0.5).astype(float)
+    t = O.LogisticRegression(X, y)
+    th0 = 0.2 * rng.standard_normal((4, 3))
+    p0 = rng.standard_normal((4, 3))
+    g0 = t.grad_bf16(th0)
+    n = np.array([3, 9, 15, 21])
+    th1, p1, g1, _, _ = O.leapfrog(t, th0, p0, g0, 0.05, n, traj_grad=t.grad_bf16)
+    th2, p2, _, _, _ = O.leapfrog(t, th1, -p1, g1, 0.05, n, traj_grad=t.grad_bf16)
+    np.testing.assert_allclose(th2, th0, atol=1e-11)
+    np.testing.assert_allclose(-p2, p0, atol=1e-11)
