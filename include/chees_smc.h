@@ -141,6 +141,8 @@ typedef struct {
                                last resampling                                */
   const float *p_final; /* momenta p' after the trajectory, (B*J) x dpad      */
   const float *theta_prop; /* proposals theta', (B*J) x dpad                  */
+  const float *grad;    /* trajectory gradient (after smc_init: at theta_0),
+                           (B*J) x dpad                                         */
   int32_t dpad;         /* row stride (floats) of p_final and theta_prop       */
   int32_t jcap;         /* particle rows per posterior (J padded)              */
 } smc_trace;

@@ -48,7 +48,7 @@ struct Layout {
   std::vector<int3> groups;  // (C2, first item, item count) of the log-likelihood pass
   size_t total = 0;
   // byte offsets
-  size_t o_posts, o_ps, o_xab, o_theta, o_grad, o_theta_t, o_p_t, o_grad_t;
+  size_t o_posts, o_ps, o_xab, o_xbf, o_theta, o_grad, o_theta_t, o_p_t, o_grad_t;
   size_t o_logpi, o_logpi_t, o_logw, o_h, o_l, o_H0, o_dH, o_alpha, o_ca, o_cg;
   size_t o_n, o_perm, o_active, o_anc, o_acc, o_cdf, o_gpart, o_tilecnt, o_llpart;
   size_t o_items, o_colpart, o_means, o_minv, o_primes;
@@ -76,7 +76,7 @@ const char *check(const smc_problem *pr, const smc_params *pa) {
   if (pa->num_warmup < 1) return "num_warmup must be >= 1";
   if (pa->jitter < 0 || pa->jitter > 2) return "jitter";
   if (pa->resampling < 0 || pa->resampling > 1) return "resampling";
-  if (pa->precision != SMC_PRECISION_F32) return "precision: only SMC_PRECISION_F32";
+  if (pa->precision != SMC_PRECISION_F32 && pa->precision != SMC_PRECISION_BF16) return "precision";
   if (pa->precond < 0 || pa->precond > 1) return "precond";
   if (!(pa->step_size > 0.0) || !(pa->traj_length > 0.0)) return "step_size, traj_length > 0";
   if (!(pa->ess_frac >= 0.0 && pa->ess_frac <= 1.0)) return "ess_frac in [0, 1]";
@@ -94,7 +94,8 @@ void plan(const smc_problem *pr, const smc_params *pa, Layout &L) {
   L.Jcap = (L.J + TJ - 1) / TJ * TJ;
   L.nmax = pa->max_leapfrog;
   int maxc2 = 1;
-  long long xoff = 0, uoff = 0;
+  long long xoff = 0, uoff = 0, xboff = 0;
+  const bool bf16 = pa->precision == SMC_PRECISION_BF16;
   L.hp.resize(B);
   L.posts.resize(B);
   for (int b = 0; b < B; ++b) {
@@ -104,9 +105,12 @@ void plan(const smc_problem *pr, const smc_params *pa, Layout &L) {
     h.C2 = (h.d + 15) / 16;
     h.C1 = 4 * h.C2;
     h.NT = (h.N + 15) / 16;
+    h.NT2 = (h.N + 31) / 32;
+    h.KC = (h.C2 + 1) / 2;
     h.xab = xoff;
-    h.yo = 0;
+    h.xbf = xboff;
     xoff += (long long)h.NT * 64 * (8 * h.C2 + 4);
+    if (bf16) xboff += (long long)h.NT2 * 64 * bf16_lane_stride(h.C2);
     maxc2 = std::max(maxc2, h.C2);
     Post &p = L.posts[b];
     memset(&p, 0, sizeof(p));
@@ -117,10 +121,14 @@ void plan(const smc_problem *pr, const smc_params *pa, Layout &L) {
     p.NT = h.NT;
     p.row0 = b * L.Jcap;
     p.xab = h.xab;
+    p.xbf = h.xbf;
+    p.NT2 = h.NT2;
+    p.KC = h.KC;
     p.uoff = uoff;
     uoff += (long long)L.J * h.d;
   }
-  L.DS = 16 * maxc2;
+  // row stride: the BF16 kernel reads theta' in chunks of 32 features
+  L.DS = bf16 ? 32 * ((maxc2 + 1) / 2) : 16 * maxc2;
   // leapfrog launches: one resident 8-wave work group per compute unit (256 CUs)
   L.lf_target = 256;
   const int ntile = L.Jcap / TJ;
@@ -161,6 +169,7 @@ void plan(const smc_problem *pr, const smc_params *pa, Layout &L) {
   L.o_posts = take(c, B * sizeof(Post));
   L.o_ps = take(c, B * sizeof(PState));
   L.o_xab = take(c, xoff * sizeof(float));
+  L.o_xbf = take(c, xboff * 16);
   L.o_theta = take(c, st);
   L.o_grad = take(c, st);
   L.o_theta_t = take(c, st);
@@ -295,6 +304,8 @@ smc_status smc_init(const smc_problem *prob, const smc_params *par, void *worksp
   D.posts = (Post *)(w + L.o_posts);
   D.ps = (PState *)(w + L.o_ps);
   D.xab = (float *)(w + L.o_xab);
+  D.xbf = (uint4 *)(w + L.o_xbf);
+  D.bf16 = par->precision == SMC_PRECISION_BF16 ? 1 : 0;
   D.theta = (float *)(w + L.o_theta);
   D.grad = (float *)(w + L.o_grad);
   D.theta_t = (float *)(w + L.o_theta_t);
@@ -371,8 +382,10 @@ smc_status smc_init(const smc_problem *prob, const smc_params *par, void *worksp
                      hipMemcpyHostToDevice, ctx->st));
   CKI(hipMemcpyAsync(D.ll_items, ctx->ll_items.data(), ctx->ll_items.size() * sizeof(int4),
                      hipMemcpyHostToDevice, ctx->st));
-  for (int b = 0; b < L.B; ++b)
+  for (int b = 0; b < L.B; ++b) {
     CKI(launch_pack_one(D, prob->X[b], prob->y[b], prob->x_dtype, L.hp[b], ctx->st));
+    if (D.bf16) CKI(launch_pack_bf16(D, prob->X[b], prob->y[b], prob->x_dtype, L.hp[b], ctx->st));
+  }
   CKI(launch_init_theta(D, theta0, ctx->st));
   for (int c2 : ctx->c2s) CKI(launch_leapfrog(D, c2, 0, 1, ctx->st));
   for (const int3 &g : ctx->ll_groups) CKI(launch_loglik(D, g.x, g.y, g.z, ctx->st));
@@ -522,6 +535,7 @@ smc_status smc_get_trace(smc_ctx *ctx, smc_trace *t) {
   t->ancestors = ctx->D.anc;
   t->p_final = ctx->D.p_t;
   t->theta_prop = ctx->D.theta_t;
+  t->grad = ctx->D.grad_t;
   t->dpad = ctx->D.DS;
   t->jcap = ctx->D.Jcap;
   return SMC_OK;

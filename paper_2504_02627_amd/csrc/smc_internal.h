@@ -27,10 +27,13 @@ struct Post {
   int N, d;        // data rows and features
   int C1, C2;      // GEMM1 K-chunks 4 C2; GEMM2 column tiles ceil(d/16)
   int NT;          // 16-row data tiles ceil(N/16)
+  int NT2;         // 32-row data tiles ceil(N/32) (BF16 trajectories)
+  int KC;          // BF16 GEMM1 K-chunks of 32 features, ceil(C2/2)
   int row0;        // first particle row of this posterior
   int ll_splits;   // N-splits of the log-likelihood pass
   int ll_base;     // first work item of this posterior in the log-likelihood plan
   long long xab;     // float offset into the packed X tiles
+  long long xbf;     // uint4 offset into the packed BF16 tiles
   long long uoff;    // offset of this posterior's block in caller (B*J) x d_b arrays
 };
 
@@ -66,6 +69,8 @@ struct Dev {                    // pointers carved from the workspace
   int adapt_eps, num_warmup;
   uint64_t seed;
   float *xab;                   // packed data tiles ([tile][lane][A | B | y])
+  uint4 *xbf;                   // packed BF16 32-row tiles (BF16 trajectories)
+  int bf16;                     // trajectory gradients on BF16 MFMA
   float *theta, *grad;          // current state, B*Jcap x DS
   float *theta_t, *p_t, *grad_t;// trajectory buffers
   double *logpi, *logpi_t, *logw;
@@ -90,13 +95,20 @@ struct Dev {                    // pointers carved from the workspace
 
 // Host copy of one posterior's packing sizes.
 struct HostPost {
-  int N, d, C1, C2, NT;
-  long long xab, yo;  // yo unused (y is packed with X)
+  int N, d, C1, C2, NT, NT2, KC;
+  long long xab, xbf;
 };
 
 // Launchers (smc_kernels.hip).  All stream-ordered.
 hipError_t launch_pack_one(const Dev &D, const void *X, const float *y, int x_dtype,
                            const HostPost &P, hipStream_t st);
+hipError_t launch_pack_bf16(const Dev &D, const void *X, const float *y, int x_dtype,
+                            const HostPost &P, hipStream_t st);
+// uint4 per lane and 32-row tile in the BF16 packing: [A: 2 KC | B: C2 | y: 2] (+1 if even)
+__host__ __device__ constexpr int bf16_lane_stride(int c2) {
+  return ((2 * ((c2 + 1) / 2) + c2 + 2) % 2 == 0) ? 2 * ((c2 + 1) / 2) + c2 + 3
+                                                   : 2 * ((c2 + 1) / 2) + c2 + 2;
+}
 hipError_t fill_f32(float *p, long long n, float v, hipStream_t st);
 hipError_t fill_i32(int *p, long long n, int v, hipStream_t st);
 hipError_t fill_f64(double *p, long long n, double v, hipStream_t st);

@@ -149,6 +149,84 @@ hipError_t launch_pack_one(const Dev &D, const void *X, const float *y, int x_dt
 }
 
 // ---------------------------------------------------------------------------
+// Packing for BF16 trajectory gradients (v_mfma_f32_16x16x32_bf16), per
+// 32-row data tile T and lane l, in 16-byte slots (8 bfloat16 or 4 floats):
+//   A, half h in {0,1}, chunk c < KC: X[32T + 16h + l%16][32c + 8(l/16) + e];
+//   B, feature tile ct < C2:          X[n_e][16ct + l%16], with n_e = 32T +
+//        4(l/16) + e for e < 4 and 32T + 16 + 4(l/16) + e - 4 for e >= 4 (the
+//        rows whose residuals the lane holds after GEMM1 on the two halves);
+//   y, half h: y[32T + 16h + 4(l/16) + i], i < 4 (1/2 beyond N);
+//   a zero pad slot when the count is even (odd lane stride: no LDS bank
+//   conflicts).  Values are rounded to bfloat16 to nearest even.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint16_t bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+template <typename T>
+__device__ __forceinline__ uint16_t to_bf16(T v);
+template <>
+__device__ __forceinline__ uint16_t to_bf16<float>(float v) { return bf16_rne(v); }
+template <>
+__device__ __forceinline__ uint16_t to_bf16<uint16_t>(uint16_t v) { return v; }
+
+template <typename T>
+__global__ void k_pack_bf16(const T *__restrict__ X, const float *__restrict__ y, int N, int d,
+                            int C2, int KC, int NT2, int LS, uint4 *__restrict__ xbf) {
+  const long long tot = (long long)NT2 * 64 * LS;
+  for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < tot;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const int slot = (int)(idx % LS);
+    const long long r = idx / LS;
+    const int lane = (int)(r % 64);
+    const int tl = (int)(r / 64);
+    const int g = lane >> 4, lm = lane & 15;
+    uint32_t w[4] = {0, 0, 0, 0};
+    if (slot < 2 * KC + C2) {
+      uint16_t v[8];
+      for (int e = 0; e < 8; ++e) {
+        int n, k;
+        if (slot < 2 * KC) {
+          const int h = slot / KC, c = slot % KC;
+          n = 32 * tl + 16 * h + lm;
+          k = 32 * c + 8 * g + e;
+        } else {
+          const int ct = slot - 2 * KC;
+          n = 32 * tl + (e < 4 ? 4 * g + e : 16 + 4 * g + (e - 4));
+          k = 16 * ct + lm;
+        }
+        v[e] = (n < N && k < d) ? to_bf16<T>(X[(long long)n * d + k]) : (uint16_t)0;
+      }
+      for (int q = 0; q < 4; ++q) w[q] = (uint32_t)v[2 * q] | ((uint32_t)v[2 * q + 1] << 16);
+    } else if (slot < 2 * KC + C2 + 2) {
+      const int h = slot - 2 * KC - C2;
+      for (int i = 0; i < 4; ++i) {
+        const int n = 32 * tl + 16 * h + 4 * g + i;
+        w[i] = __float_as_uint(n < N ? y[n] : 0.5f);
+      }
+    }
+    xbf[idx] = make_uint4(w[0], w[1], w[2], w[3]);
+  }
+}
+
+hipError_t launch_pack_bf16(const Dev &D, const void *X, const float *y, int x_dtype,
+                            const HostPost &P, hipStream_t st) {
+  const int LS = bf16_lane_stride(P.C2);
+  const long long tot = (long long)P.NT2 * 64 * LS;
+  int grid = (int)((tot + 255) / 256);
+  if (grid > 65535) grid = 65535;
+  if (x_dtype == 0)
+    hipLaunchKernelGGL(k_pack_bf16<float>, dim3(grid), dim3(256), 0, st, (const float *)X, y, P.N,
+                       P.d, P.C2, P.KC, P.NT2, LS, D.xbf + P.xbf);
+  else
+    hipLaunchKernelGGL(k_pack_bf16<uint16_t>, dim3(grid), dim3(256), 0, st, (const uint16_t *)X, y,
+                       P.N, P.d, P.C2, P.KC, P.NT2, LS, D.xbf + P.xbf);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Fill helpers.
 // ---------------------------------------------------------------------------
 __global__ void k_fill_f32(float *p, long long n, float v) {
@@ -277,12 +355,16 @@ struct PostPlan {
   int T, base, extra, first;  // active tiles, splits per tile (>= 1), tiles with one more, first item
 };
 
+// data tiles of a posterior in the leapfrog kernels: 16-row tiles (FP32) or
+// 32-row tiles (BF16)
+__device__ __forceinline__ int lf_units(const Dev &D, const Post &P) { return D.bf16 ? P.NT2 : P.NT; }
+
 __device__ bool lf_post_plan(const Dev &D, int c2, int s, int bq, PostPlan &out) {
   long long U = 0;
   for (int b = 0; b < D.B; ++b) {
     const Post &P = D.posts[b];
     if (P.C2 != c2) continue;
-    U += (long long)((D.active[b * (D.nmax + 1) + s] + TJ - 1) / TJ) * P.NT;
+    U += (long long)((D.active[b * (D.nmax + 1) + s] + TJ - 1) / TJ) * lf_units(D, P);
   }
   if (U == 0) return false;
   int first = 0;
@@ -292,9 +374,10 @@ __device__ bool lf_post_plan(const Dev &D, int c2, int s, int bq, PostPlan &out)
     const int T = (D.active[b * (D.nmax + 1) + s] + TJ - 1) / TJ;
     int items = 0, base = 0, extra = 0;
     if (T > 0) {
-      long long G = ((long long)D.lf_target * T * P.NT) / U;  // this posterior's share
+      const int NU = lf_units(D, P);
+      long long G = ((long long)D.lf_target * T * NU) / U;  // this posterior's share
       if (G < T) G = T;
-      const long long cap = (long long)T * (P.NT < LF_MAX_SPLIT ? P.NT : LF_MAX_SPLIT);
+      const long long cap = (long long)T * (NU < LF_MAX_SPLIT ? NU : LF_MAX_SPLIT);
       if (G > cap) G = cap;
       base = (int)(G / T);
       extra = (int)(G % T);
@@ -502,6 +585,138 @@ __global__ __launch_bounds__(WG, LF_WAVES_PER_SIMD) void k_lf_partial(Dev D, int
       }
 }
 
+// ---------------------------------------------------------------------------
+// Fused leapfrog step with BF16 trajectory gradients (precision form):
+// theta' and X in bfloat16 on v_mfma_f32_16x16x32_bf16 with FP32
+// accumulation; the residual R is rounded to bfloat16 as the A operand of the
+// second product.  Per 32-row data tile and wave (16 particles):
+//   GEMM1 on the two 16-row halves, KC MFMAs each (K = 32 features);
+//   R = y - sigmoid(Z) on the 8 accumulator values of the lane (rows
+//   4(l/16)+i of both halves), packed as the lane's 8 K-values of GEMM2;
+//   GEMM2: C2 MFMAs (K = 32 data rows, N = 16 features).
+// The drift, the partials and the reduction are those of the FP32 kernel.
+// Exactness of the weights does not depend on the gradient's precision: the
+// leapfrog map with any position-only force field is volume preserving and
+// reversible, and the energies are recomputed from the FP32 data.
+// ---------------------------------------------------------------------------
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ v8bf as_v8bf(uint4 u) { return __builtin_bit_cast(v8bf, u); }
+
+template <int C2>
+struct TilesBF {
+  static constexpr int KC = (C2 + 1) / 2;
+  static constexpr int LSTR = bf16_lane_stride(C2);  // uint4 per lane and 32-row tile
+  static constexpr int TILE = 64 * LSTR;
+  static constexpr int STAGE = 2 * TILE;
+  static constexpr int NINST = STAGE / 64;
+};
+
+template <int C2>
+__device__ __forceinline__ void stage_issue_bf(uint4 *xs, const uint4 *__restrict__ xbf, int t,
+                                               int t1, int wave, int lane) {
+  using TL = TilesBF<C2>;
+  const uint4 *src = xbf + (long long)t * TL::TILE + lane;
+#pragma unroll
+  for (int k = 0; k < (TL::NINST + WAVES - 1) / WAVES; ++k) {
+    const int m = wave + k * WAVES;
+    if (m < TL::NINST && t + m / TL::LSTR < t1)
+      __builtin_amdgcn_global_load_lds((const void *)(src + 64 * m), (lds_void *)(xs + 64 * m), 16,
+                                       0, 0);
+  }
+}
+
+template <int C2>
+__global__ __launch_bounds__(WG) void k_lf_partial_bf16(Dev D, int s, int zero_eps) {
+  using TL = TilesBF<C2>;
+  constexpr int KC = TL::KC;
+  __shared__ uint4 xs[2][TL::STAGE];
+  __shared__ Plan spl;
+  if (threadIdx.x == 0) {
+    Plan pl;
+    if (!lf_plan(D, C2, s, blockIdx.x, pl)) pl.b = -1;
+    spl = pl;
+  }
+  __syncthreads();
+  const Plan pl = spl;
+  if (pl.b < 0) return;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4;
+  const Post P = D.posts[pl.b];
+  const float eps = zero_eps ? 0.f : (float)D.ps[pl.b].eps;
+  const float he = 0.5f * eps;
+  const float *minv = D.minv + (long long)pl.b * D.DS;
+  const int *perm = D.perm + P.row0;
+
+  // theta' (bfloat16, B operand of GEMM1): chunk c holds features 32c + 8g + e
+  v8bf thb[KC];
+  {
+    const int slot = pl.tile * TJ + wave * 16 + (lane & 15);
+    const long long base = (long long)(P.row0 + perm[slot]) * D.DS;
+#pragma unroll
+    for (int c = 0; c < KC; ++c) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int k = 32 * c + 8 * g + e;
+        const float t0 = D.theta_t[base + k], p0 = D.p_t[base + k], g0 = D.grad_t[base + k];
+        const float ph = fmaf(he, g0, p0);
+        thb[c][e] = (__bf16)fmaf(eps * minv[k], ph, t0);
+      }
+    }
+  }
+
+  v4f gacc[C2];
+#pragma unroll
+  for (int ct = 0; ct < C2; ++ct) gacc[ct] = v4f{0.f, 0.f, 0.f, 0.f};
+
+  const int t0 = (int)((long long)pl.split * P.NT2 / pl.S);
+  const int t1 = (int)((long long)(pl.split + 1) * P.NT2 / pl.S);
+  const uint4 *xbf = D.xbf + P.xbf;
+  stage_issue_bf<C2>(xs[0], xbf, t0, t1, wave, lane);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  int cur = 0;
+  for (int t = t0; t < t1; t += 2) {
+    const bool more = t + 2 < t1;
+    if (more) stage_issue_bf<C2>(xs[cur ^ 1], xbf, t + 2, t1, wave, lane);
+    const int ntt = (t + 1 < t1) ? 2 : 1;
+    for (int tt = 0; tt < ntt; ++tt) {
+      const uint4 *xl = xs[cur] + tt * TL::TILE + lane * TL::LSTR;
+      v4f z0 = {0.f, 0.f, 0.f, 0.f}, z1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int c = 0; c < KC; ++c) {
+        z0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_v8bf(xl[c]), thb[c], z0, 0, 0, 0);
+        z1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_v8bf(xl[KC + c]), thb[c], z1, 0, 0, 0);
+      }
+      const uint4 yu0 = xl[2 * KC + C2], yu1 = xl[2 * KC + C2 + 1];
+      v8bf ra;
+      ra[0] = (__bf16)(__uint_as_float(yu0.x) - sigmoidf_fast(z0[0]));
+      ra[1] = (__bf16)(__uint_as_float(yu0.y) - sigmoidf_fast(z0[1]));
+      ra[2] = (__bf16)(__uint_as_float(yu0.z) - sigmoidf_fast(z0[2]));
+      ra[3] = (__bf16)(__uint_as_float(yu0.w) - sigmoidf_fast(z0[3]));
+      ra[4] = (__bf16)(__uint_as_float(yu1.x) - sigmoidf_fast(z1[0]));
+      ra[5] = (__bf16)(__uint_as_float(yu1.y) - sigmoidf_fast(z1[1]));
+      ra[6] = (__bf16)(__uint_as_float(yu1.z) - sigmoidf_fast(z1[2]));
+      ra[7] = (__bf16)(__uint_as_float(yu1.w) - sigmoidf_fast(z1[3]));
+#pragma unroll
+      for (int ct = 0; ct < C2; ++ct)
+        gacc[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ra, as_v8bf(xl[2 * KC + ct]), gacc[ct], 0, 0, 0);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    cur ^= 1;
+  }
+
+  float *gp = D.gpart + (long long)blockIdx.x * TJ * D.DS;
+#pragma unroll
+  for (int ct = 0; ct < C2; ++ct)
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      const int slot = wave * 16 + 4 * g + rr;
+      gp[(long long)slot * D.DS + 16 * ct + (lane & 15)] = gacc[ct][rr];
+    }
+}
+
 // grid: (B * tiles per posterior, REDUCE_SLICES); each block reduces a slice
 // of one tile's 128 particles.
 constexpr int REDUCE_SLICES = 8;
@@ -565,7 +780,10 @@ __global__ __launch_bounds__(256) void k_lf_reduce(Dev D, int c2, int s, int zer
 
 template <int C2>
 static hipError_t launch_lf_c2(const Dev &D, int step, int zero_eps, hipStream_t st) {
-  hipLaunchKernelGGL(k_lf_partial<C2>, dim3(D.lf_grid), dim3(WG), 0, st, D, step, zero_eps);
+  if (D.bf16)
+    hipLaunchKernelGGL(k_lf_partial_bf16<C2>, dim3(D.lf_grid), dim3(WG), 0, st, D, step, zero_eps);
+  else
+    hipLaunchKernelGGL(k_lf_partial<C2>, dim3(D.lf_grid), dim3(WG), 0, st, D, step, zero_eps);
   return hipGetLastError();
 }
 
