@@ -25,6 +25,7 @@ sys.path.insert(0, ROOT)
 
 N_ROWS, DIM, PARTICLES, ITERS, NMAX = 10000, 100, 8192, 50, 64
 PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_BF16_MFMA_TFLOPS = 2500.0
 METRIC = "particle-gradient evals/s and ESS/s vs plain FP32 GPU at matched posterior error"
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2504_02627_amd", "csrc", f)
                for f in ("smc_kernels.hip", "smc_internal.h")]
@@ -86,6 +87,119 @@ def cpu_baseline(X, y, params, seconds):
                       f"{threads} BLAS threads)"}
 
 
+def _steps(s, n):
+    for _ in range(n):
+        s.step(stats=False)
+        s.adapt(stats=False)
+
+
+def _moments(s):
+    import torch
+    theta, logw, _ = s.state()
+    w = torch.softmax(logw, 0)
+    th = theta.double()
+    mean = (w[:, None] * th).sum(0)
+    var = (w[:, None] * (th - mean) ** 2).sum(0)
+    return mean.cpu().numpy(), var.cpu().numpy()
+
+
+def run_form(Xd, yd, params, precision, args):
+    """One form of the sampler on the workload.
+
+    Pass 1 (the timed region of `value`): warm-up, then the timed steps with no
+    per-kernel instrumentation.  Pass 2: the same seed from scratch -- the run
+    is deterministic, so it replays exactly the same kernels -- with HIP events
+    around every leapfrog, reduction and log-likelihood launch on the sampler's
+    stream, for the per-kernel averages.  Replicates with other seeds give the
+    spread of the final posterior moments (untimed)."""
+    import torch
+    from paper_2504_02627_amd import chees
+
+    def timed(seed, instrument):
+        s = chees.Sampler(Xd, yd, PARTICLES, precision=precision, **dict(params, seed=seed))
+        _steps(s, args.warmup)
+        torch.cuda.synchronize()
+        c0 = s.counters()
+        if instrument:
+            s.set_timing(True)
+            s.timing()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _steps(s, args.steps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        tm = s.timing() if instrument else None
+        c1 = s.counters()
+        return s, t1 - t0, c1["grad_evals"] - c0["grad_evals"], c1["ess_sum"] - c0["ess_sum"], tm
+
+    s, T, evals, ess_sum, _ = timed(params["seed"], False)
+    print(f"[bench] {precision}: timed {args.steps} steps in {T:.3f} s", file=sys.stderr, flush=True)
+    moments = [_moments(s)]
+    s.close()
+    s2, T2, evals2, _, tm = timed(params["seed"], True)
+    s2.close()
+    if evals2 != evals:
+        raise RuntimeError("instrumented pass did not replay the timed run")
+    for r in range(1, args.replicates):
+        sr = chees.Sampler(Xd, yd, PARTICLES, precision=precision,
+                           **dict(params, seed=params["seed"] + 1000 * r))
+        _steps(sr, args.warmup + args.steps)
+        moments.append(_moments(sr))
+        sr.close()
+    print(f"[bench] {precision}: instrumented pass {T2:.3f} s, {len(moments)} replicates",
+          file=sys.stderr, flush=True)
+    return {"evals": evals, "ess_sum": ess_sum, "seconds": T, "timing": tm,
+            "instrumented_seconds": T2, "moments": moments}
+
+
+def long_reference(Xd, yd, params, precision, iters, pool):
+    """Posterior moments from one long run (seed 7777, twice the particles): the
+    weighted means and variances averaged over the last `pool` of `iters` SMC
+    iterations."""
+    import numpy as np
+    from paper_2504_02627_amd import chees
+    s = chees.Sampler(Xd, yd, 2 * PARTICLES, precision=precision, **dict(params, seed=7777))
+    ms, vs = [], []
+    for k in range(iters):
+        s.step(stats=False)
+        s.adapt(stats=False)
+        if k >= iters - pool:
+            m, v = _moments(s)
+            ms.append(m)
+            vs.append(v)
+    s.close()
+    return np.mean(ms, 0), np.mean(vs, 0)
+
+
+def moment_match(ref, a, b, ta, tb):
+    """Posterior error of the two forms at the end of the workload, over R
+    replicate seeds each, against the long-run reference moments `ref`:
+    RMS over dimensions and replicates of (mean - ref_mean) / ref_sd (bias and
+    spread together), the same for the variances relative to ref_var, the
+    per-dimension two-sample z of the forms' replicate-averaged means, and the
+    efficiency at matched error (T_a err_a^2) / (T_b err_b^2)."""
+    import numpy as np
+    rm, rv = ref
+    sd = np.sqrt(rv)
+    ma = np.array([m for m, _ in a]); mb = np.array([m for m, _ in b])
+    va = np.array([v for _, v in a]); vb = np.array([v for _, v in b])
+    R = len(a)
+    ea = float(np.sqrt(np.mean(((ma - rm) / sd) ** 2)))
+    eb = float(np.sqrt(np.mean(((mb - rm) / sd) ** 2)))
+    out = {"replicates": R, "reference": "FP32 form, 2J particles, seed 7777, moments averaged "
+                                         "over the last third of a long run",
+           "mean_error_rms_ref_sd": [ea, eb],
+           "var_error_rms_rel": [float(np.sqrt(np.mean((va / rv - 1) ** 2))),
+                                 float(np.sqrt(np.mean((vb / rv - 1) ** 2)))],
+           "efficiency_at_matched_error_vs_f32": float((ta * ea ** 2) / (tb * eb ** 2))}
+    if R >= 2:
+        sa, sb = ma.std(0, ddof=1), mb.std(0, ddof=1)
+        z = np.abs(ma.mean(0) - mb.mean(0)) / np.sqrt(sa ** 2 / R + sb ** 2 / R)
+        out.update({"max_abs_z_between_forms": float(z.max()),
+                    "frac_dims_within_3se_between_forms": float(np.mean(z <= 3.0))})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,6 +207,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-bf16", action="store_true", help="skip the BF16 precision form")
+    ap.add_argument("--ref-iters", type=int, default=300,
+                    help="iterations of the long reference runs (last third pooled)")
+    ap.add_argument("--replicates", type=int, default=10,
+                    help="seeds per form for the posterior-error comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of known size (counter scaling)")
     args = ap.parse_args()
@@ -123,31 +242,10 @@ def main():
     params = workload_params()
     Xd = torch.from_numpy(X).to(dev)
     yd = torch.from_numpy(y).to(dev)
-    s = chees.Sampler(Xd, yd, PARTICLES, **params)
-    print(f"[bench] init done: N={N_ROWS} d={DIM} J={PARTICLES}", file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
-        s.step(stats=False)
-        s.adapt(stats=False)
-    torch.cuda.synchronize()
-    c0 = s.counters()
-    s.set_timing(True)
-    s.timing()
-    print(f"[bench] warm-up done ({args.warmup} steps)", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        s.step(stats=False)
-        s.adapt(stats=False)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    tm = s.timing()
-    c1 = s.counters()
-    T = t1 - t0
-    evals = c1["grad_evals"] - c0["grad_evals"]
-    ess_sum = c1["ess_sum"] - c0["ess_sum"]
-    print(f"[bench] timed {args.steps} steps in {T:.3f} s", file=sys.stderr, flush=True)
 
-    flops = 4.0 * N_ROWS * DIM * evals
+    f32 = run_form(Xd, yd, params, "f32", args)
+    flops = 4.0 * N_ROWS * DIM * f32["evals"]
+    tm = f32["timing"]
     lf_s = tm["leapfrog_ms"] / 1e3
     achieved = flops / lf_s / 1e12 if lf_s > 0 else 0.0
     launches = max(1, tm["leapfrog_launches"])
@@ -160,11 +258,14 @@ def main():
                 "algorithmic_flops_per_launch": flops / launches,
                 "avg_launch_ms": tm["leapfrog_ms"] / launches, "launches": tm["leapfrog_launches"],
                 "flop_unit": "4 N d per particle-gradient evaluation",
+                "timing_pass": "HIP events on the sampler stream, same-seed replay of the timed steps "
+                               f"({1e3 * f32['instrumented_seconds'] / args.steps:.3f} ms/step with events)",
                 "other_kernels_ms_per_step": {
                     "k_lf_reduce": tm["reduce_ms"] / args.steps,
                     "k_loglik": tm["loglik_ms"] / args.steps}}
+    T = f32["seconds"]
     out = {
-        "metric": METRIC, "value": evals / T, "unit": "particle-gradient evals/s",
+        "metric": METRIC, "value": f32["evals"] / T, "unit": "particle-gradient evals/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * T / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
@@ -173,10 +274,41 @@ def main():
                                f"<= {NMAX} leapfrog steps, 1-d Halton jitter, systematic resampling",
                    "particles": PARTICLES, "rows": N_ROWS, "dim": DIM, "max_leapfrog": NMAX,
                    "parallelism": "single GPU"},
-        "ess_per_s": ess_sum / T,
-        "ess_per_grad_eval": ess_sum / (evals + PARTICLES * args.steps),
+        "ess_per_s": f32["ess_sum"] / T,
+        "ess_per_grad_eval": f32["ess_sum"] / (f32["evals"] + PARTICLES * args.steps),
         "roofline": roofline,
     }
+    if not args.no_bf16:
+        bf = run_form(Xd, yd, params, "bf16", args)
+        tb = bf["timing"]
+        fl_b = 4.0 * N_ROWS * DIM * bf["evals"]
+        ach_b = fl_b / (tb["leapfrog_ms"] / 1e3) / 1e12 if tb["leapfrog_ms"] > 0 else 0.0
+        print("[bench] long-run reference moments ...", file=sys.stderr, flush=True)
+        ref = long_reference(Xd, yd, params, "f32", args.ref_iters, args.ref_iters // 3)
+        ref_b = long_reference(Xd, yd, params, "bf16", args.ref_iters, args.ref_iters // 3)
+        z = moment_match(ref, f32["moments"], bf["moments"], T, bf["seconds"])
+        z["bf16_long_run_vs_reference_mean_rms_sd"] = float(
+            np.sqrt(np.mean((ref_b[0] - ref[0]) ** 2 / ref[1])))
+        z["bf16_long_run_vs_reference_var_rms_rel"] = float(
+            np.sqrt(np.mean((ref_b[1] / ref[1] - 1) ** 2)))
+        out["forms"] = {"bf16": {
+            "what": "same workload and target: X held in FP32 for the energies (compensated "
+                    "FP32 sums, weights exact for the FP32-data posterior) and in bfloat16 for "
+                    "the trajectory gradients on v_mfma_f32_16x16x32_bf16 (FP32 accumulation); "
+                    "LSE/ESS/evidence FP64",
+            "value": bf["evals"] / bf["seconds"], "unit": "particle-gradient evals/s",
+            "ms_per_step": 1e3 * bf["seconds"] / args.steps,
+            "ess_per_s": bf["ess_sum"] / bf["seconds"],
+            "speedup_vs_f32_evals": (bf["evals"] / bf["seconds"]) / (f32["evals"] / T),
+            "speedup_vs_f32_ess_per_s": (bf["ess_sum"] / bf["seconds"]) / (f32["ess_sum"] / T),
+            "leapfrog_kernel": {"achieved": round(ach_b, 2), "peak": PEAK_BF16_MFMA_TFLOPS,
+                                "unit": "TFLOP/s", "frac": round(ach_b / PEAK_BF16_MFMA_TFLOPS, 4),
+                                "avg_launch_ms": tb["leapfrog_ms"] / max(1, tb["leapfrog_launches"])},
+            "other_kernels_ms_per_step": {"k_lf_reduce": tb["reduce_ms"] / args.steps,
+                                          "k_loglik": tb["loglik_ms"] / args.steps},
+            "instrumented_ms_per_step": 1e3 * bf["instrumented_seconds"] / args.steps,
+            "posterior_vs_f32": z,
+        }}
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(X, y, params, args.cpu_seconds)

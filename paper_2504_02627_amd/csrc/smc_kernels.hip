@@ -1273,8 +1273,10 @@ hipError_t launch_setup(const Dev &D, const float *momenta, int init_mode, hipSt
 // Counting sort of the particles by n_j, longest first, so that a leapfrog
 // tile holds particles of similar trajectory length; active[s] = #{j: n_j > s}
 // and the step's gradient count sum_j n_j.  One work group per posterior; the
-// histogram is built with LDS atomics.  Placement within a bin is arbitrary:
-// each particle's arithmetic does not depend on its tile or lane.
+// histogram is built with LDS atomics (its counts do not depend on their
+// order).  Placement is stable: within a bin particles keep their index
+// order, so the tiles, and with them each particle's split count and
+// gradient summation order, are the same on every run.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void k_sort(Dev D) {
   extern __shared__ int lds[];  // hist[nmax + 1], cur[nmax + 1]
@@ -1298,10 +1300,32 @@ __global__ __launch_bounds__(1024) void k_sort(Dev D) {
     D.ps[b].grad_evals_step = evals;
   }
   __syncthreads();
-  for (int j = threadIdx.x; j < D.Jcap; j += blockDim.x) {
-    const int n = D.n[row0 + j];
-    const int p = atomicAdd(&cur[n], 1);
-    D.perm[row0 + p] = j;
+  // chunks of blockDim.x particles in index order; inside a wave, a particle's
+  // rank among the lanes below it with the same n; across the waves of a
+  // chunk, the bin cursors advance wave by wave
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  for (int c0 = 0; c0 < D.Jcap; c0 += blockDim.x) {
+    const int j = c0 + threadIdx.x;
+    const int n = j < D.Jcap ? D.n[row0 + j] : -1;
+    unsigned long long left = __ballot(1), peers = 0;
+    while (left) {
+      const int v = __shfl(n, __ffsll((long long)left) - 1);
+      const unsigned long long m = __ballot(n == v);
+      if (n == v) peers = m;
+      left &= ~m;
+    }
+    const int rank = __popcll(peers & below);
+    int base = 0;
+    for (int w = 0; w < nw; ++w) {
+      if (wave == w && rank == 0 && n >= 0) {
+        base = cur[n];
+        cur[n] = base + __popcll(peers);
+      }
+      __syncthreads();
+    }
+    base = __shfl(base, __ffsll((long long)peers) - 1);
+    if (n >= 0) D.perm[row0 + base + rank] = j;
   }
 }
 

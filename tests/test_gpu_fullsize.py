@@ -1,0 +1,84 @@
+"""Parity at full size, in the launch configuration of the throughput benchmark:
+logistic regression N = 10000, d = 100 (standardised features), J = 8192
+particles, at most 64 leapfrog steps.  Jitter and step counts are compared for
+every particle (bit-exact); trajectories and energies for a sample of
+particles that the oracle integrates one by one from the device's own
+pre-move state, over two iterations (the second after an adaptation).
+
+FP32 form: theta', p' within 1e-5 relative, Delta H within 1e-5 (|H0| + |H1|).
+BF16 form: Delta H of the device's end points equals the exact FP64 Delta H at
+those points within 1e-5 (|H0| + |H1|); trajectories against the
+BF16-emulating oracle within 5e-3 relative (stated)."""
+
+import numpy as np
+import pytest
+
+from oracle import smc as O
+from paper_2504_02627_amd import synth
+from tests._gpu_common import log, rel_rows, to_dev
+
+pytestmark = pytest.mark.gpu
+
+N, D, J, NMAX = 10000, 100, 8192, 64
+
+
+@pytest.mark.parametrize("precision", ["f32", "bf16"])
+def test_full_size_sampled_particles(precision):
+    import torch
+    from paper_2504_02627_amd import chees
+    X, y, _ = synth.large_logistic()
+    assert X.shape == (N, D)
+    bf = precision == "bf16"
+    Xo = O.bf16_round(X) if bf else X.astype(np.float64)   # the values the device holds
+    target = O.LogisticRegression(Xo, y.astype(np.float64))
+    tg = target.grad_bf16 if bf else None
+    eps0 = synth.default_step_size(N, D)
+    params = dict(step_size=eps0, traj_length=eps0 * NMAX / 2, max_leapfrog=NMAX,
+                  num_warmup=25, seed=2)
+    rng = np.random.default_rng(2024)
+    theta0 = rng.standard_normal((J, D)).astype(np.float32)     # a draw from the prior
+    Xd = to_dev(X)
+    s = chees.Sampler(Xd.to(torch.bfloat16) if bf else Xd, to_dev(y), J,
+                      theta0=to_dev(theta0), precision=precision, **params)
+    sample = np.unique(np.concatenate([np.linspace(0, J - 1, 24).astype(int),
+                                       rng.integers(0, J, 8)]))
+    theta_prev = theta0.astype(np.float64)
+    L, eps = params["traj_length"], eps0
+    for k in (1, 2):
+        log(f"[fullsize] {precision} iteration {k}: L={L:.6g} eps={eps:.6g}")
+        xi = rng.standard_normal((J, D)).astype(np.float32)
+        u = rng.random(1)
+        st = s.step(momenta=to_dev(xi), resample_u=to_dev(u))
+        tr = s.trace()
+        h = tr["h"].cpu().numpy()[:J]
+        n = tr["n"].cpu().numpy()[:J]
+        np.testing.assert_array_equal(h, O.halton_1d(k, J))
+        np.testing.assert_array_equal(n, O.step_counts(h, L, eps, NMAX)[1])
+        anc = tr["ancestors"].cpu().numpy()[:J] if st["resampled"] else np.arange(J)
+        th_b = theta_prev[anc[sample]]
+        p0 = xi[sample].astype(np.float64)
+        lp0, g0 = target.log_and_grad(th_b)
+        if bf:
+            g0 = target.grad_bf16(th_b)
+        th1o, p1o, _, lp1o, _ = O.leapfrog(target, th_b, p0, g0, eps, n[sample], traj_grad=tg)
+        th1 = tr["theta_prop"].cpu().numpy()[sample, :D].astype(np.float64)
+        p1 = tr["p_final"].cpu().numpy()[sample, :D].astype(np.float64)
+        dh = tr["dH"].cpu().numpy()[sample]
+        et, ep = rel_rows(th1, th1o), rel_rows(p1, p1o)
+        H0 = O.hamiltonian(lp0, p0)
+        if bf:
+            lp1 = target.log_and_grad(th1)[0]
+            H1 = O.hamiltonian(lp1, p1)
+        else:
+            H1 = O.hamiltonian(lp1o, p1o)
+        edh = np.abs(dh - (H1 - H0))
+        log(f"  resampled={st['resampled']} n in [{n.min()}, {n.max()}], sample {len(sample)}: "
+            f"traj rel err theta {et:.2e} p {ep:.2e}; max |dH err| {edh.max():.2e} "
+            f"(bar {(1e-5 * (np.abs(H0) + np.abs(H1))).min():.2e})")
+        assert np.all(edh <= 1e-5 * (np.abs(H0) + np.abs(H1)))
+        tol = 5e-3 if bf else 1e-5
+        assert et <= tol and ep <= tol
+        ad = s.adapt()
+        L, eps = ad["L"], ad["eps"]
+        theta_prev = s.state()[0].cpu().numpy().astype(np.float64)
+    s.close()
