@@ -143,6 +143,7 @@ typedef struct {
   const float *theta_prop; /* proposals theta', (B*J) x dpad                  */
   const float *grad;    /* trajectory gradient (after smc_init: at theta_0),
                            (B*J) x dpad                                         */
+  const float *minv;    /* diagonal inverse mass of the last step, B x dpad     */
   int32_t dpad;         /* row stride (floats) of p_final and theta_prop       */
   int32_t jcap;         /* particle rows per posterior (J padded)              */
 } smc_trace;

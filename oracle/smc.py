@@ -470,7 +470,24 @@ DEFAULTS = dict(
     resampling="systematic", step_size=0.1, traj_length=5.0, ess_frac=0.5,
     adam_lr=0.025, adam_b1=0.9, adam_b2=0.999, adam_eps=1e-8, avg_decay=0.9,
     adapt_step_size=False, target_accept=0.651, seed=0, prior_var=1.0, precision="f64",
+    precond="none",
 )
+
+
+def diag_mass(theta, logw, n_eff):
+    """Diagonal inverse mass matrix from the weighted population (the
+    diagonal-mass fallback of the preconditioned form; the paper itself uses
+    M = I).  Reading: M^{-1} = diag(Var_W[theta]), the weighted population
+    variance with W the normalised weights (eq. normalise_smc2), shrunk toward
+    1e-3 as n/(n + 5) Var + 1e-3 * 5/(n + 5) with n the effective sample size
+    of those weights (the regulariser of Stan's windowed adaptation), so that
+    a collapsed population cannot give a zero mass.  Two passes in binary64;
+    the result is held in binary32, as the device holds it."""
+    W = normalise(logw)
+    mean = W @ theta
+    var = W @ ((theta - mean) ** 2)
+    reg = (n_eff / (n_eff + 5.0)) * var + 1e-3 * (5.0 / (n_eff + 5.0))
+    return reg.astype(np.float32).astype(np.float64)
 
 
 class OracleSMC:
@@ -568,6 +585,8 @@ class OracleSMC:
             self.logpi = self.logpi[ancestors]
             self.log_c += m + math.log(S)
             self.logw = np.full(J, -math.log(J))
+        if P["precond"] == "diag":
+            self.minv = diag_mass(self.theta, self.logw, j_eff_before)
         # a4: momenta, jitter, step counts, initial energy
         if momenta is None:
             momenta = philox.normals_np(P["seed"], J, k, philox.STREAM_MOMENTUM, d)
@@ -605,6 +624,7 @@ class OracleSMC:
             grad_evals=int(np.sum(ng)), L=self.L, eps=self.eps,
             theta_before=theta_before, logpi_before=logpi_before, theta_prop=th1, logpi_prop=lp1,
             H0=hamiltonian(logpi_before, p0, self.minv), H1=hamiltonian(lp1, p1, self.minv),
+            minv=None if self.minv is None else self.minv.copy(),
         )
         return self.last
 

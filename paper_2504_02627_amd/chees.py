@@ -83,7 +83,8 @@ class Trace(ctypes.Structure):
     _fields_ = [("h", ctypes.c_void_p), ("l", ctypes.c_void_p), ("n", ctypes.c_void_p),
                 ("dH", ctypes.c_void_p), ("alpha", ctypes.c_void_p),
                 ("ancestors", ctypes.c_void_p), ("p_final", ctypes.c_void_p),
-                ("theta_prop", ctypes.c_void_p), ("grad", ctypes.c_void_p), ("dpad", ctypes.c_int32),
+                ("theta_prop", ctypes.c_void_p), ("grad", ctypes.c_void_p),
+                ("minv", ctypes.c_void_p), ("dpad", ctypes.c_int32),
                 ("jcap", ctypes.c_int32)]
 
 
@@ -299,6 +300,7 @@ class Sampler:
             p_final=view(t.p_final, rows * t.dpad, torch.float32, 4).view(rows, t.dpad),
             theta_prop=view(t.theta_prop, rows * t.dpad, torch.float32, 4).view(rows, t.dpad),
             grad=view(t.grad, rows * t.dpad, torch.float32, 4).view(rows, t.dpad),
+            minv=view(t.minv, self.B * t.dpad, torch.float32, 4).view(self.B, t.dpad),
             jcap=t.jcap, dpad=t.dpad)
         return res
 

@@ -426,6 +426,7 @@ smc_status smc_step(smc_ctx *ctx, const smc_inject *inject, smc_stats *stats) {
   size_t ei = 0;
   CK(launch_begin_step(D, 1, inject ? inject->resample_u : nullptr, 1, ctx->st));
   CK(launch_gather(D, nullptr, ctx->st));
+  if (D.precond == SMC_PRECOND_DIAG) CK(launch_mass(D, ctx->st));
   CK(launch_setup(D, inject ? inject->momenta : nullptr, 0, ctx->st));
   CK(launch_sort(D, ctx->st));
   for (int s = 0; s < D.nmax; ++s)
@@ -536,6 +537,7 @@ smc_status smc_get_trace(smc_ctx *ctx, smc_trace *t) {
   t->p_final = ctx->D.p_t;
   t->theta_prop = ctx->D.theta_t;
   t->grad = ctx->D.grad_t;
+  t->minv = ctx->D.minv;
   t->dpad = ctx->D.DS;
   t->jcap = ctx->D.Jcap;
   return SMC_OK;

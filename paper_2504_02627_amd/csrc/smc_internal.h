@@ -116,6 +116,7 @@ hipError_t launch_init_theta(const Dev &D, const float *theta0, hipStream_t st);
 hipError_t launch_init_weights(const Dev &D, hipStream_t st);
 hipError_t launch_begin_step(const Dev &D, int conditional, const double *u, int count_iteration,
                              hipStream_t st);
+hipError_t launch_mass(const Dev &D, hipStream_t st);
 hipError_t launch_gather(const Dev &D, int *anc_out, hipStream_t st);
 hipError_t launch_setup(const Dev &D, const float *momenta, int init_mode, hipStream_t st);
 hipError_t launch_sort(const Dev &D, hipStream_t st);

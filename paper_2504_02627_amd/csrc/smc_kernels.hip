@@ -1495,6 +1495,69 @@ hipError_t launch_chees(const Dev &D, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Diagonal inverse mass matrix from the pre-move population (preconditioner
+// DIAG, the diagonal-mass fallback; the paper uses M = I):
+//   M^{-1}_c = n/(n+5) Var_W[theta_c] + 1e-3 * 5/(n+5),
+// W the normalised weights (uniform right after resampling), n their
+// effective sample size before any resampling; two FP64 passes (mean, then
+// squared deviations) over the same column chunks as the ChEES means.  The
+// mean lands in the first half of `means`, which the ChEES statistics
+// overwrite later in the step.
+__global__ __launch_bounds__(256) void k_mass_colsum(Dev D, int pass) {
+  __shared__ double sh[4][64];
+  const int b = blockIdx.y, ch = blockIdx.x;
+  const int rl = threadIdx.x >> 6, cl = threadIdx.x & 63;
+  const PState &S = D.ps[b];
+  const int rs = S.resampled;
+  const float *src = rs ? D.theta_t : D.theta;
+  const double m = S.m, inv = 1.0 / S.S, uni = 1.0 / D.J;
+  const double *mean = D.means + (long long)b * 2 * D.DS;
+  const int rows_per = (D.J + D.col_chunks - 1) / D.col_chunks;
+  const int r0 = ch * rows_per, r1 = min(D.J, r0 + rows_per);
+  for (int cg = 0; cg * 64 < D.DS; ++cg) {
+    const int c = cg * 64 + cl;
+    double acc = 0.0;
+    if (c < D.DS)
+      for (int r = r0 + rl; r < r1; r += 4) {
+        const long long row = (long long)b * D.Jcap + r;
+        const double lw = D.logw[row];
+        const double w = rs ? uni : ((lw == lw && lw > -INFINITY) ? exp(lw - m) * inv : 0.0);
+        const double x = (double)src[row * D.DS + c];
+        acc += pass == 0 ? w * x : w * ((x - mean[c]) * (x - mean[c]));
+      }
+    sh[rl][cl] = acc;
+    __syncthreads();
+    if (rl == 0 && c < D.DS)
+      D.colpart[((long long)b * D.col_chunks + ch) * 2 * D.DS + c] =
+          ((sh[0][cl] + sh[1][cl]) + sh[2][cl]) + sh[3][cl];
+    __syncthreads();
+  }
+}
+
+__global__ void k_mass_finish(Dev D, int pass) {
+  const int b = blockIdx.x;
+  const Post P = D.posts[b];
+  const double n = D.ps[b].ess_before;
+  for (int c = threadIdx.x; c < D.DS; c += blockDim.x) {
+    double s = 0.0;
+    for (int ch = 0; ch < D.col_chunks; ++ch)
+      s += D.colpart[((long long)b * D.col_chunks + ch) * 2 * D.DS + c];
+    if (pass == 0)
+      D.means[(long long)b * 2 * D.DS + c] = s;
+    else
+      D.minv[(long long)b * D.DS + c] =
+          c < P.d ? (float)((n / (n + 5.0)) * s + 1e-3 * (5.0 / (n + 5.0))) : 1.0f;
+  }
+}
+
+hipError_t launch_mass(const Dev &D, hipStream_t st) {
+  for (int pass = 0; pass < 2; ++pass) {
+    hipLaunchKernelGGL(k_mass_colsum, dim3(D.col_chunks, D.B), dim3(256), 0, st, D, pass);
+    hipLaunchKernelGGL(k_mass_finish, dim3(D.B), dim3(256), 0, st, D, pass);
+  }
+  return hipGetLastError();
+}
+
 // Accepted proposals become the state (all of them in SMC-ChEES mode).
 __global__ void k_commit(Dev D) {
   const long long tot = (long long)D.B * D.Jcap * D.DS;

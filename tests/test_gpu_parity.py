@@ -32,7 +32,7 @@ def _sampler(X, y, J, theta0=None, **kw):
 
 
 def _one_iteration(N, d, J, seed, mh=False, jitter="halton1d", resampling="systematic",
-                   nmax=64, eps=None, L=None, prior_var=1.0, inject=True):
+                   nmax=64, eps=None, L=None, prior_var=1.0, inject=True, precond="none"):
     log(f"[parity] N={N} d={d} J={J} seed={seed} mh={mh} jitter={jitter} resampling={resampling} nmax={nmax}")
     X, y, _ = synth.logistic_iid(N, d, seed)
     rng = np.random.default_rng(seed + 7)
@@ -40,7 +40,7 @@ def _one_iteration(N, d, J, seed, mh=False, jitter="halton1d", resampling="syste
     eps = eps if eps is not None else synth.default_step_size(N, d)
     L = L if L is not None else eps * nmax / 2
     params = dict(step_size=eps, traj_length=L, max_leapfrog=nmax, num_warmup=5, seed=seed,
-                  mh_accept=mh, jitter=jitter, resampling=resampling)
+                  mh_accept=mh, jitter=jitter, resampling=resampling, precond=precond)
     s = _sampler(X, y, J, theta0=theta0, prior_var=prior_var, **params)
     o = oracle_for(X, y, J, theta0, prior_var=prior_var, **params)
     if inject:
@@ -86,7 +86,8 @@ def _compare_iteration(s, o, st, ost, J, d):
     assert st["ess"] == pytest.approx(O.ess(lw), rel=1e-12)
     # ChEES statistics: same inputs in FP64 give the same value up to summation order
     al = tr["alpha"].cpu().numpy()[:J]
-    ref = O.chees_statistics(ost["theta_before"], th1, p1, tr["l"].cpu().numpy()[:J], al)
+    mv = None if ost.get("minv") is None else tr["minv"].cpu().numpy()[0, :d].astype(np.float64)
+    ref = O.chees_statistics(ost["theta_before"], th1, p1, tr["l"].cpu().numpy()[:J], al, mv)
     assert st["chees_grad"] == pytest.approx(ref["ghat"], rel=1e-9, abs=1e-12)
     assert st["chees"] == pytest.approx(ref["chees"], rel=1e-9, abs=1e-12)
     # and against the oracle's own trajectories
@@ -329,3 +330,26 @@ def test_single_nonfinite_particle_gets_zero_weight():
     lw = logw.cpu().numpy()
     assert np.isfinite(lw).sum() >= J - 1
     assert math.isfinite(s.log_evidence())
+
+
+@pytest.mark.parametrize("N,d,J,seed", [(1000, 37, 300, 12), (200, 5, 256, 13)])
+def test_diag_mass_parity(N, d, J, seed):
+    """Diagonal mass from the weighted pre-move population: the device's
+    M^{-1} equals the oracle's (both binary32 roundings of binary64 sums),
+    and the iteration with that mass meets the usual bars; a second iteration
+    from the identical state uses the re-adapted mass."""
+    X, y, s, o, st, ost = _one_iteration(N, d, J, seed, precond="diag")
+    tr = _compare_iteration(s, o, st, ost, J, d)
+    np.testing.assert_allclose(tr["minv"].cpu().numpy()[0, :d], ost["minv"], rtol=3e-7)
+    assert np.all(tr["minv"].cpu().numpy()[0, d:] == 1.0)
+    rng = np.random.default_rng(seed + 5)
+    theta, logw, _ = s.state()
+    o.set_state(theta.cpu().numpy(), logw.cpu().numpy())
+    xi = rng.standard_normal((J, d)).astype(np.float32)
+    u = rng.random(1)
+    st2 = s.step(momenta=to_dev(xi), resample_u=to_dev(u))
+    ost2 = o.step(momenta=xi.astype(np.float64), resample_u=float(u[0]))
+    tr2 = _compare_iteration(s, o, st2, ost2, J, d)
+    mv = tr2["minv"].cpu().numpy()[0, :d]
+    log(f"  adapted M^-1 range [{mv.min():.3e}, {mv.max():.3e}]")
+    np.testing.assert_allclose(mv, ost2["minv"], rtol=3e-7)
