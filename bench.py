@@ -106,18 +106,23 @@ def _moments(s):
 def run_form(Xd, yd, params, precision, args):
     """One form of the sampler on the workload.
 
-    Pass 1 (the timed region of `value`): warm-up, then the timed steps with no
-    per-kernel instrumentation.  Pass 2: the same seed from scratch -- the run
-    is deterministic, so it replays exactly the same kernels -- with HIP events
-    around every leapfrog, reduction and log-likelihood launch on the sampler's
-    stream, for the per-kernel averages.  Replicates with other seeds give the
+    Pass 1 (the timed region of `value`): warm-up, then the timed iterations
+    replayed from the captured iteration graph (smc_run), with no per-kernel
+    instrumentation.  Pass 2: the same with eager smc_step + chees_adapt calls.
+    Pass 3: the same seed from scratch -- the run is deterministic, so it
+    repeats exactly the same kernels -- eager, with HIP events around every
+    leapfrog, reduction and log-likelihood launch on the sampler's stream, for
+    the per-kernel averages.  Replicates with other seeds give the
     spread of the final posterior moments (untimed)."""
     import torch
     from paper_2504_02627_amd import chees
 
-    def timed(seed, instrument):
+    def timed(seed, instrument, graph):
         s = chees.Sampler(Xd, yd, PARTICLES, precision=precision, **dict(params, seed=seed))
-        _steps(s, args.warmup)
+        if graph:
+            s.run(args.warmup)          # the first call captures the iteration graph
+        else:
+            _steps(s, args.warmup)
         torch.cuda.synchronize()
         c0 = s.counters()
         if instrument:
@@ -125,31 +130,36 @@ def run_form(Xd, yd, params, precision, args):
             s.timing()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        _steps(s, args.steps)
+        if graph:
+            s.run(args.steps)
+        else:
+            _steps(s, args.steps)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         tm = s.timing() if instrument else None
         c1 = s.counters()
         return s, t1 - t0, c1["grad_evals"] - c0["grad_evals"], c1["ess_sum"] - c0["ess_sum"], tm
 
-    s, T, evals, ess_sum, _ = timed(params["seed"], False)
+    s, T, evals, ess_sum, _ = timed(params["seed"], False, not args.eager)
     print(f"[bench] {precision}: timed {args.steps} steps in {T:.3f} s", file=sys.stderr, flush=True)
     moments = [_moments(s)]
     s.close()
-    s2, T2, evals2, _, tm = timed(params["seed"], True)
+    s1, T1, evals1, _, _ = timed(params["seed"], False, args.eager)
+    s1.close()
+    s2, T2, evals2, _, tm = timed(params["seed"], True, False)
     s2.close()
-    if evals2 != evals:
-        raise RuntimeError("instrumented pass did not replay the timed run")
+    if evals2 != evals or evals1 != evals:
+        raise RuntimeError("the replayed passes did not repeat the timed run")
     for r in range(1, args.replicates):
         sr = chees.Sampler(Xd, yd, PARTICLES, precision=precision,
                            **dict(params, seed=params["seed"] + 1000 * r))
-        _steps(sr, args.warmup + args.steps)
+        sr.run(args.warmup + args.steps)
         moments.append(_moments(sr))
         sr.close()
     print(f"[bench] {precision}: instrumented pass {T2:.3f} s, {len(moments)} replicates",
           file=sys.stderr, flush=True)
     return {"evals": evals, "ess_sum": ess_sum, "seconds": T, "timing": tm,
-            "instrumented_seconds": T2, "moments": moments}
+            "other_mode_seconds": T1, "instrumented_seconds": T2, "moments": moments}
 
 
 def long_reference(Xd, yd, params, precision, iters, pool):
@@ -208,6 +218,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bf16", action="store_true", help="skip the BF16 precision form")
+    ap.add_argument("--eager", action="store_true",
+                    help="time eager step/adapt calls for `value` (default: graph replay)")
     ap.add_argument("--ref-iters", type=int, default=300,
                     help="iterations of the long reference runs (last third pooled)")
     ap.add_argument("--replicates", type=int, default=10,
@@ -274,6 +286,9 @@ def main():
                                f"<= {NMAX} leapfrog steps, 1-d Halton jitter, systematic resampling",
                    "particles": PARTICLES, "rows": N_ROWS, "dim": DIM, "max_leapfrog": NMAX,
                    "parallelism": "single GPU"},
+        "ms_per_step_other_mode": 1e3 * f32["other_mode_seconds"] / args.steps,
+        "launch_mode": "eager smc_step + chees_adapt" if args.eager else
+                       "captured iteration graph (smc_run); other mode = eager calls",
         "ess_per_s": f32["ess_sum"] / T,
         "ess_per_grad_eval": f32["ess_sum"] / (f32["evals"] + PARTICLES * args.steps),
         "roofline": roofline,
@@ -307,6 +322,7 @@ def main():
             "other_kernels_ms_per_step": {"k_lf_reduce": tb["reduce_ms"] / args.steps,
                                           "k_loglik": tb["loglik_ms"] / args.steps},
             "instrumented_ms_per_step": 1e3 * bf["instrumented_seconds"] / args.steps,
+            "ms_per_step_other_mode": 1e3 * bf["other_mode_seconds"] / args.steps,
             "posterior_vs_f32": z,
         }}
     if not args.no_cpu_baseline:

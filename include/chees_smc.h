@@ -177,6 +177,15 @@ smc_status smc_step(smc_ctx *ctx, const smc_inject *inject, smc_stats *stats);
  * SMC_ESTATE if no step ran since the last adaptation.  stats: as smc_step. */
 smc_status chees_adapt(smc_ctx *ctx, smc_stats *stats);
 
+/* `iterations` SMC iterations, each smc_step (randomness from the library's
+ * Philox streams, nothing injected) followed by chees_adapt, with no host
+ * synchronisation.  The first call captures one iteration's launches as a
+ * HIP graph on a private stream; every call replays it on the context's
+ * stream, once per iteration.  Results are identical to the same number of
+ * smc_step + chees_adapt calls.  Per-kernel timing does not cover it.
+ * SMC_ESTATE after a smc_step not yet followed by chees_adapt. */
+smc_status smc_run(smc_ctx *ctx, int32_t iterations);
+
 /* Unconditional resampling of the current population (Sec. III), then the
  * weights are reset to 1/J.  u: nullable DEVICE uniforms (B for systematic,
  * B*J for multinomial); ancestors_out: nullable DEVICE B*J int32. */

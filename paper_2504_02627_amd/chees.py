@@ -108,6 +108,7 @@ def load():
             "smc_init": (i32, [P(Problem), P(Params), vp, sz, vp, vp, P(vp)]),
             "smc_step": (i32, [vp, P(Inject), P(Stats)]),
             "chees_adapt": (i32, [vp, P(Stats)]),
+            "smc_run": (i32, [vp, i32]),
             "resample": (i32, [vp, vp, vp]),
             "resample_workspace_bytes": (sz, [i32]),
             "resample_indices": (i32, [vp, i32, vp, i32, vp, vp, sz, vp]),
@@ -250,6 +251,11 @@ class Sampler:
         rc = self.lib.chees_adapt(self.ctx, ctypes.byref(st) if st is not None else None)
         self._check(rc, "chees_adapt")
         return st.as_dict() if st is not None else None
+
+    def run(self, iterations):
+        """`iterations` x (step + adapt) by replaying a captured HIP graph of one
+        iteration (library randomness only); no host synchronisation."""
+        self._check(self.lib.smc_run(self.ctx, int(iterations)), "smc_run")
 
     def resample(self, u=None, return_ancestors=False):
         torch = _torch()

@@ -32,8 +32,15 @@ struct smc_ctx {
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   std::vector<std::pair<int, size_t>> ev_marks;  // (kind, index of the start event)
+  // one SMC iteration (step + adaptation) captured as a graph for smc_run
+  hipStream_t cap_st = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
   ~smc_ctx() {
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap_st) (void)hipStreamDestroy(cap_st);
   }
 };
 
@@ -420,8 +427,9 @@ hipError_t timed_end(smc_ctx *ctx, size_t idx) {
 }
 }  // namespace
 
-smc_status smc_step(smc_ctx *ctx, const smc_inject *inject, smc_stats *stats) {
-  if (!ctx) return SMC_EINVAL;
+namespace {
+// Every launch of one smc_step (no host synchronisation, no memset, no copy).
+smc_status enqueue_step(smc_ctx *ctx, const smc_inject *inject) {
   const Dev &D = ctx->D;
   size_t ei = 0;
   CK(launch_begin_step(D, 1, inject ? inject->resample_u : nullptr, 1, ctx->st));
@@ -447,9 +455,60 @@ smc_status smc_step(smc_ctx *ctx, const smc_inject *inject, smc_stats *stats) {
   CK(launch_chees(D, ctx->st));
   CK(launch_commit(D, ctx->st));
   CK(launch_ess(D, 1, ctx->st));
+  return SMC_OK;
+}
+}  // namespace
+
+smc_status smc_step(smc_ctx *ctx, const smc_inject *inject, smc_stats *stats) {
+  if (!ctx) return SMC_EINVAL;
+  const smc_status r = enqueue_step(ctx, inject);
+  if (r != SMC_OK) return r;
   ctx->stepped = 1;
   ctx->steps += 1;
   if (stats) return fill_stats(ctx, stats);
+  return SMC_OK;
+}
+
+smc_status smc_run(smc_ctx *ctx, int32_t iterations) {
+  if (!ctx || iterations < 0) return SMC_EINVAL;
+  if (ctx->stepped) {
+    ctx->err = "smc_run after a smc_step that was not followed by chees_adapt";
+    return SMC_ESTATE;
+  }
+  if (!ctx->gexec) {
+    // capture on a private stream; kernel arguments are fixed for the life of
+    // the context, so the graph stays valid
+    if (!ctx->cap_st) CK(hipStreamCreateWithFlags(&ctx->cap_st, hipStreamNonBlocking));
+    const hipStream_t user = ctx->st;
+    const int timing = ctx->timing;
+    ctx->st = ctx->cap_st;
+    ctx->timing = 0;
+    hipError_t e = hipStreamBeginCapture(ctx->cap_st, hipStreamCaptureModeThreadLocal);
+    smc_status r = SMC_EDEVICE;
+    if (e == hipSuccess) {
+      r = enqueue_step(ctx, nullptr);
+      if (r == SMC_OK && launch_adapt(ctx->D, ctx->cap_st) != hipSuccess) r = SMC_EDEVICE;
+      hipGraph_t g = nullptr;
+      e = hipStreamEndCapture(ctx->cap_st, &g);
+      if (e == hipSuccess && r == SMC_OK) {
+        e = hipGraphInstantiate(&ctx->gexec, g, nullptr, nullptr, 0);
+        if (e == hipSuccess) ctx->graph = g;
+      }
+      if (e != hipSuccess || r != SMC_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        ctx->gexec = nullptr;
+      }
+    }
+    ctx->st = user;
+    ctx->timing = timing;
+    if (e != hipSuccess) {
+      ctx->err = std::string("graph capture of an iteration: ") + hipGetErrorString(e);
+      return SMC_EDEVICE;
+    }
+    if (r != SMC_OK) return r;
+  }
+  for (int i = 0; i < iterations; ++i) CK(hipGraphLaunch(ctx->gexec, ctx->st));
+  ctx->steps += iterations;
   return SMC_OK;
 }
 
