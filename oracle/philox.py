@@ -30,6 +30,7 @@ STREAM_INIT = 1      # initial draw theta_0 ~ q0
 STREAM_MOMENTUM = 2  # momenta of each trajectory
 STREAM_MH = 3        # Metropolis-Hastings uniforms
 STREAM_RESAMPLE = 4  # resampling uniform(s)
+STREAM_FLOW = 5      # initial weights of the flow preconditioner
 
 
 def philox4x32_10(counter, key):

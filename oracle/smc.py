@@ -470,7 +470,8 @@ DEFAULTS = dict(
     resampling="systematic", step_size=0.1, traj_length=5.0, ess_frac=0.5,
     adam_lr=0.025, adam_b1=0.9, adam_b2=0.999, adam_eps=1e-8, avg_decay=0.9,
     adapt_step_size=False, target_accept=0.651, seed=0, prior_var=1.0, precision="f64",
-    precond="none",
+    precond="none", flow_layers=4, flow_width=128, flow_train_steps=10, flow_lr=1e-3,
+    flow_init=None,
 )
 
 
@@ -544,6 +545,13 @@ class OracleSMC:
         self.k = 0
         self.grad_evals = J  # the gradient at theta_0
         self.last = None
+        if P["precond"] == "flow":
+            from . import flow
+            self.flow_ps = (flow.unflatten(P["flow_init"], d, P["flow_layers"], P["flow_width"])[0]
+                            if P["flow_init"] is not None else
+                            flow.philox_init(P["seed"], d, P["flow_layers"], P["flow_width"]))
+            self.flow_adam = flow.FlowAdam(P["flow_lr"], P["adam_b1"], P["adam_b2"], P["adam_eps"])
+            self.flow_m = self.flow_a = None
 
     # ----- one SMC iteration -------------------------------------------------
     def jitter(self, k):
@@ -587,6 +595,19 @@ class OracleSMC:
             self.logw = np.full(J, -math.log(J))
         if P["precond"] == "diag":
             self.minv = diag_mass(self.theta, self.logw, j_eff_before)
+        flow_rec = None
+        if P["precond"] == "flow":
+            from . import flow
+            m_, a_ = flow.standardise(self.theta, self.logw, j_eff_before)
+            W = normalise(self.logw)
+            for _ in range(P["flow_train_steps"]):
+                _, g_ = flow.objective_and_grad(self.flow_ps, m_, a_, self.theta, W)
+                self.flow_ps = self.flow_adam.ascend(self.flow_ps, g_)
+            self.flow_m, self.flow_a = m_, a_
+            psb = flow.bf16_params(self.flow_ps)
+            z0, ldi = flow.inverse(psb, m_, a_, self.theta)
+            ld0 = -ldi
+            gz0 = flow.latent_grad(psb, m_, a_, z0, self.grad)
         # a4: momenta, jitter, step counts, initial energy
         if momenta is None:
             momenta = philox.normals_np(P["seed"], J, k, philox.STREAM_MOMENTUM, d)
@@ -595,14 +616,29 @@ class OracleSMC:
         h = self.jitter(k)
         l, n = step_counts(h, self.L, self.eps, P["max_leapfrog"])
         # a5: leapfrog trajectories
-        th1, p1, g1, lp1, ng = leapfrog(self.target, self.theta, p0, self.grad, self.eps, n, self.minv,
-                                        traj_grad=self.traj_grad)
+        if P["precond"] == "flow":
+            # in the latent space of the flow, unit mass: log pi_z = log pi(T(z)) + log|det J_T|
+            z1, p1, gz1, th1, g1, lp1, ld1 = flow.leapfrog_latent(
+                self.target, psb, m_, a_, z0, p0, gz0, self.eps, n, traj_grad=self.traj_grad)
+            ng = n.copy()
+            flow_rec = dict(z0=z0, z1=z1, gz0=gz0, gz1=gz1, ld0=ld0, ld1=ld1, m=m_, a=a_,
+                            params_bf16=psb)
+        else:
+            th1, p1, g1, lp1, ng = leapfrog(self.target, self.theta, p0, self.grad, self.eps, n,
+                                            self.minv, traj_grad=self.traj_grad)
         self.grad_evals += int(np.sum(ng))
         # a6: energies, acceptance, weights
-        dh = delta_h(self.logpi, p0, lp1, p1, self.minv)
+        if flow_rec is None:
+            dh = delta_h(self.logpi, p0, lp1, p1, self.minv)
+        else:
+            dh = delta_h(self.logpi + ld0, p0, lp1 + ld1, p1)
         alpha = accept_prob(dh)
-        # a7: ChEES statistics on the proposals (Alg. smc_ChEES)
-        st = chees_statistics(self.theta, th1, p1, l, alpha, self.minv)
+        # a7: ChEES statistics on the proposals (Alg. smc_ChEES); latent
+        # coordinates under the flow
+        if flow_rec is None:
+            st = chees_statistics(self.theta, th1, p1, l, alpha, self.minv)
+        else:
+            st = chees_statistics(z0, z1, p1, l, alpha)
         theta_before, logpi_before = self.theta.copy(), self.logpi.copy()
         if P["mh_accept"]:
             u = mh_uniforms if mh_uniforms is not None else philox.uniforms_np(
@@ -624,8 +660,11 @@ class OracleSMC:
             grad_evals=int(np.sum(ng)), L=self.L, eps=self.eps,
             theta_before=theta_before, logpi_before=logpi_before, theta_prop=th1, logpi_prop=lp1,
             H0=hamiltonian(logpi_before, p0, self.minv), H1=hamiltonian(lp1, p1, self.minv),
-            minv=None if self.minv is None else self.minv.copy(),
+            minv=None if self.minv is None else self.minv.copy(), flow=flow_rec,
         )
+        if flow_rec is not None:
+            self.last["H0"] = hamiltonian(logpi_before + flow_rec["ld0"], p0)
+            self.last["H1"] = hamiltonian(lp1 + flow_rec["ld1"], p1)
         return self.last
 
     def adapt(self):
