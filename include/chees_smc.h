@@ -56,8 +56,15 @@ enum { SMC_JITTER_HALTON1D = 0, /* 1-d Halton, base 2, index (k-1) J + j      */
 enum { SMC_RESAMPLE_SYSTEMATIC = 0, SMC_RESAMPLE_MULTINOMIAL = 1 };
 /* arithmetic of the trajectory gradients */
 enum { SMC_PRECISION_F32 = 0, SMC_PRECISION_BF16 = 1 };
-/* mass matrix */
-enum { SMC_PRECOND_NONE = 0, SMC_PRECOND_DIAG = 1 };
+/* preconditioning of the trajectories (none of them changes the target: the
+ * weights stay exact, Sec. III-A) */
+enum { SMC_PRECOND_NONE = 0,  /* unit mass, the paper's M = I                   */
+       SMC_PRECOND_DIAG = 1,  /* diagonal mass M^{-1} = regularised weighted
+                                 variance of the pre-move population            */
+       SMC_PRECOND_FLOW = 2   /* affine-coupling flow T fitted to the weighted
+                                 population each iteration; leapfrog in the
+                                 latent space on log pi(T(z)) + log|det J_T(z)|
+                                 (one posterior per context)                    */ };
 
 typedef struct smc_ctx smc_ctx;
 
@@ -96,6 +103,11 @@ typedef struct {
                                  warm-up (not in the paper, whose eps is fixed) */
   double target_accept;       /* harmonic-mean acceptance target (e.g. 0.651)   */
   uint64_t seed;              /* key of the Philox4x32-10 streams               */
+  /* SMC_PRECOND_FLOW only: coupling layers (1..8), conditioner width (128),
+   * Adam steps of the weighted maximum-likelihood fit per iteration (>= 0,
+   * warm-started) and their learning rate */
+  int32_t flow_layers, flow_width, flow_train_steps;
+  double flow_lr;
 } smc_params;
 
 /* Host-supplied randomness for one smc_step (all fields nullable, DEVICE
@@ -144,6 +156,10 @@ typedef struct {
   const float *grad;    /* trajectory gradient (after smc_init: at theta_0),
                            (B*J) x dpad                                         */
   const float *minv;    /* diagonal inverse mass of the last step, B x dpad     */
+  /* SMC_PRECOND_FLOW (else NULL): latent positions z0 = T^-1(theta_0) and z'
+   * after the trajectory, the latent gradient at z', (J x dpad), and
+   * log|det J_T| at z0 and at z' (J) */
+  const float *latent0, *latent, *latent_grad, *logdet0, *logdet;
   int32_t dpad;         /* row stride (floats) of p_final and theta_prop       */
   int32_t jcap;         /* particle rows per posterior (J padded)              */
 } smc_trace;
@@ -185,6 +201,22 @@ smc_status chees_adapt(smc_ctx *ctx, smc_stats *stats);
  * smc_step + chees_adapt calls.  Per-kernel timing does not cover it.
  * SMC_ESTATE after a smc_step not yet followed by chees_adapt. */
 smc_status smc_run(smc_ctx *ctx, int32_t iterations);
+
+/* Flow preconditioner (SMC_PRECOND_FLOW).  Parameters form one flat FP32
+ * vector: for each coupling layer l = 0..layers-1, with d_T = floor(d/2)
+ * transformed coordinates for even l (the first ones) and d - floor(d/2) for
+ * odd l (the last ones), d_C = d - d_T: W1 [width][d_C], b1 [width],
+ * W2 [width][width], b2 [width], W3 [2 d_T][width] (rows 0..d_T-1 give s,
+ * the rest t), b3 [2 d_T], all row-major.  smc_flow_param_count gives its
+ * length (0 for invalid sizes).  smc_get_flow copies into DEVICE buffers
+ * (each nullable) the current FP32 parameters, the standardisation m, a of
+ * the last step (d each) and the gradient of the fit objective that the last
+ * Adam step used (same layout as the parameters); smc_set_flow replaces the
+ * parameters from a DEVICE vector and restarts their Adam moments.
+ * SMC_EINVAL without a flow. */
+size_t smc_flow_param_count(int32_t d, int32_t layers, int32_t width);
+smc_status smc_get_flow(smc_ctx *ctx, float *params, float *m, float *a, float *grad);
+smc_status smc_set_flow(smc_ctx *ctx, const float *params);
 
 /* Unconditional resampling of the current population (Sec. III), then the
  * weights are reset to 1/J.  u: nullable DEVICE uniforms (B for systematic,
@@ -230,6 +262,11 @@ typedef struct {
   int64_t loglik_launches;
   double reduce_ms;            /* split reduction + second half kick               */
   int64_t reduce_launches;
+  double flow_ms;              /* flow preconditioner: drift + forward map, and
+                                  latent gradient + kick, per leapfrog step         */
+  int64_t flow_launches;
+  double train_ms;             /* flow preconditioner: one Adam step of the fit     */
+  int64_t train_launches;
 } smc_timing;
 smc_status smc_set_timing(smc_ctx *ctx, int32_t enable);
 smc_status smc_get_timing(smc_ctx *ctx, smc_timing *out);

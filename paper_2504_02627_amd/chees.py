@@ -19,7 +19,7 @@ SMC_F32, SMC_BF16 = 0, 1
 JITTER = {"halton1d": 0, "none": 1, "haltonNd": 2}
 RESAMPLING = {"systematic": 0, "multinomial": 1}
 PRECISION = {"f32": 0, "bf16": 1}
-PRECOND = {"none": 0, "diag": 1}
+PRECOND = {"none": 0, "diag": 1, "flow": 2}
 
 
 class SmcError(RuntimeError):
@@ -48,7 +48,9 @@ class Params(ctypes.Structure):
                 ("adam_b1", ctypes.c_double), ("adam_b2", ctypes.c_double),
                 ("adam_eps", ctypes.c_double), ("avg_decay", ctypes.c_double),
                 ("adapt_step_size", ctypes.c_int32), ("target_accept", ctypes.c_double),
-                ("seed", ctypes.c_uint64)]
+                ("seed", ctypes.c_uint64), ("flow_layers", ctypes.c_int32),
+                ("flow_width", ctypes.c_int32), ("flow_train_steps", ctypes.c_int32),
+                ("flow_lr", ctypes.c_double)]
 
 
 class Inject(ctypes.Structure):
@@ -76,7 +78,9 @@ class Counters(ctypes.Structure):
 class Timing(ctypes.Structure):
     _fields_ = [("leapfrog_ms", ctypes.c_double), ("leapfrog_launches", ctypes.c_int64),
                 ("loglik_ms", ctypes.c_double), ("loglik_launches", ctypes.c_int64),
-                ("reduce_ms", ctypes.c_double), ("reduce_launches", ctypes.c_int64)]
+                ("reduce_ms", ctypes.c_double), ("reduce_launches", ctypes.c_int64),
+                ("flow_ms", ctypes.c_double), ("flow_launches", ctypes.c_int64),
+                ("train_ms", ctypes.c_double), ("train_launches", ctypes.c_int64)]
 
 
 class Trace(ctypes.Structure):
@@ -84,8 +88,10 @@ class Trace(ctypes.Structure):
                 ("dH", ctypes.c_void_p), ("alpha", ctypes.c_void_p),
                 ("ancestors", ctypes.c_void_p), ("p_final", ctypes.c_void_p),
                 ("theta_prop", ctypes.c_void_p), ("grad", ctypes.c_void_p),
-                ("minv", ctypes.c_void_p), ("dpad", ctypes.c_int32),
-                ("jcap", ctypes.c_int32)]
+                ("minv", ctypes.c_void_p), ("latent0", ctypes.c_void_p),
+                ("latent", ctypes.c_void_p), ("latent_grad", ctypes.c_void_p),
+                ("logdet0", ctypes.c_void_p), ("logdet", ctypes.c_void_p),
+                ("dpad", ctypes.c_int32), ("jcap", ctypes.c_int32)]
 
 
 _LIB = None
@@ -109,6 +115,9 @@ def load():
             "smc_step": (i32, [vp, P(Inject), P(Stats)]),
             "chees_adapt": (i32, [vp, P(Stats)]),
             "smc_run": (i32, [vp, i32]),
+            "smc_flow_param_count": (sz, [i32, i32, i32]),
+            "smc_get_flow": (i32, [vp, vp, vp, vp, vp]),
+            "smc_set_flow": (i32, [vp, vp]),
             "resample": (i32, [vp, vp, vp]),
             "resample_workspace_bytes": (sz, [i32]),
             "resample_indices": (i32, [vp, i32, vp, i32, vp, vp, sz, vp]),
@@ -149,7 +158,8 @@ DEFAULT_PARAMS = dict(max_leapfrog=64, num_warmup=10, jitter="halton1d", mh_acce
                       resampling="systematic", precision="f32", precond="none",
                       step_size=0.1, traj_length=5.0, ess_frac=0.5, adam_lr=0.025,
                       adam_b1=0.9, adam_b2=0.999, adam_eps=1e-8, avg_decay=0.9,
-                      adapt_step_size=False, target_accept=0.651, seed=0)
+                      adapt_step_size=False, target_accept=0.651, seed=0,
+                      flow_layers=4, flow_width=128, flow_train_steps=10, flow_lr=1e-3)
 
 
 def make_params(num_particles, **kw):
@@ -163,7 +173,8 @@ def make_params(num_particles, **kw):
                   PRECISION[p["precision"]], PRECOND[p["precond"]], p["step_size"],
                   p["traj_length"], p["ess_frac"], p["adam_lr"], p["adam_b1"], p["adam_b2"],
                   p["adam_eps"], p["avg_decay"], int(bool(p["adapt_step_size"])),
-                  p["target_accept"], p["seed"])
+                  p["target_accept"], p["seed"], p["flow_layers"], p["flow_width"],
+                  p["flow_train_steps"], p["flow_lr"])
 
 
 def make_problem(Xs, ys, prior_var=1.0):
@@ -308,7 +319,38 @@ class Sampler:
             grad=view(t.grad, rows * t.dpad, torch.float32, 4).view(rows, t.dpad),
             minv=view(t.minv, self.B * t.dpad, torch.float32, 4).view(self.B, t.dpad),
             jcap=t.jcap, dpad=t.dpad)
+        if t.latent:
+            res.update(
+                latent0=view(t.latent0, rows * t.dpad, torch.float32, 4).view(rows, t.dpad),
+                latent=view(t.latent, rows * t.dpad, torch.float32, 4).view(rows, t.dpad),
+                latent_grad=view(t.latent_grad, rows * t.dpad, torch.float32, 4).view(rows, t.dpad),
+                logdet0=view(t.logdet0, rows, torch.float32, 4),
+                logdet=view(t.logdet, rows, torch.float32, 4))
         return res
+
+    def flow(self, with_grad=False):
+        """(FP32 coupling parameters as one flat vector, m, a[, gradient of the
+        last Adam step]) of the flow preconditioner (include/chees_smc.h gives
+        the layout)."""
+        torch = _torch()
+        d = self.dims[0]
+        n = self.lib.smc_flow_param_count(d, self.params.flow_layers, self.params.flow_width)
+        prm = torch.empty(n, dtype=torch.float32, device=self.device)
+        m = torch.empty(d, dtype=torch.float32, device=self.device)
+        a = torch.empty(d, dtype=torch.float32, device=self.device)
+        g = torch.empty(n, dtype=torch.float32, device=self.device) if with_grad else None
+        self._check(self.lib.smc_get_flow(self.ctx, _ptr(prm), _ptr(m), _ptr(a), _ptr(g)),
+                    "smc_get_flow")
+        return (prm, m, a, g) if with_grad else (prm, m, a)
+
+    def set_flow(self, params):
+        """Replace the coupling parameters (flat FP32 device vector)."""
+        torch = _torch()
+        n = self.lib.smc_flow_param_count(self.dims[0], self.params.flow_layers,
+                                          self.params.flow_width)
+        self._check_inject(params, n, torch.float32, "flow parameters")
+        self._flow_keep = params
+        self._check(self.lib.smc_set_flow(self.ctx, _ptr(params)), "smc_set_flow")
 
     def counters(self):
         c = Counters()

@@ -33,6 +33,7 @@ struct smc_ctx {
   size_t ev_used = 0;
   std::vector<std::pair<int, size_t>> ev_marks;  // (kind, index of the start event)
   // one SMC iteration (step + adaptation) captured as a graph for smc_run
+  FlowNet F{};
   hipStream_t cap_st = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
@@ -59,7 +60,42 @@ struct Layout {
   size_t o_logpi, o_logpi_t, o_logw, o_h, o_l, o_H0, o_dH, o_alpha, o_ca, o_cg;
   size_t o_n, o_perm, o_active, o_anc, o_acc, o_cdf, o_gpart, o_tilecnt, o_llpart;
   size_t o_items, o_colpart, o_means, o_minv, o_primes;
+  FlowNet F;
+  size_t o_fz = 0, o_fz0 = 0, o_fgz = 0, o_fld0 = 0, o_fld1 = 0, o_fm = 0, o_fa = 0;
+  size_t o_fp = 0, o_fpt = 0, o_fwb = 0, o_fwbt = 0, o_fbias = 0, o_fgrad = 0, o_fadm = 0,
+         o_fadv = 0, o_ftape = 0, o_fstate = 0;
 };
+
+// Layer table of the flow: even layers transform the first floor(d/2)
+// coordinates given the rest, odd layers the rest given the first ones.
+bool flow_net(int d, int layers, int width, FlowNet &F) {
+  if (d < 2 || d > 16 * MAX_C2 || layers < 1 || layers > FMAXL || width != FH) return false;
+  memset(&F, 0, sizeof(F));
+  F.L = layers;
+  F.d = d;
+  const int da = d / 2;
+  int o = 0, half = 0;
+  for (int l = 0; l < layers; ++l) {
+    FlowLayerDesc &Y = F.ly[l];
+    if (l % 2 == 0) {
+      Y.T0 = 0, Y.dt = da, Y.C0 = da, Y.dc = d - da;
+    } else {
+      Y.T0 = da, Y.dt = d - da, Y.C0 = 0, Y.dc = da;
+    }
+    Y.oW1 = o, o += FH * Y.dc;
+    Y.ob1 = o, o += FH;
+    Y.oW2 = o, o += FH * FH;
+    Y.ob2 = o, o += FH;
+    Y.oW3 = o, o += 2 * Y.dt * FH;
+    Y.ob3 = o, o += 2 * Y.dt;
+    half = std::max(half, std::max(Y.dt, Y.dc));
+  }
+  F.half = (half + 1) / 2 * 2;
+  F.tape_stride = 2 * FH + 2 * F.half;
+  F.train_stride = 5 * F.half + 4 * FH;
+  F.nparams = o;
+  return true;
+}
 
 size_t take(size_t &cur, size_t bytes) {
   const size_t o = (cur + 255) & ~(size_t)255;
@@ -84,7 +120,15 @@ const char *check(const smc_problem *pr, const smc_params *pa) {
   if (pa->jitter < 0 || pa->jitter > 2) return "jitter";
   if (pa->resampling < 0 || pa->resampling > 1) return "resampling";
   if (pa->precision != SMC_PRECISION_F32 && pa->precision != SMC_PRECISION_BF16) return "precision";
-  if (pa->precond < 0 || pa->precond > 1) return "precond";
+  if (pa->precond < 0 || pa->precond > 2) return "precond";
+  if (pa->precond == SMC_PRECOND_FLOW) {
+    FlowNet F;
+    if (pr->num_posteriors != 1) return "the flow preconditioner takes one posterior";
+    if (!flow_net(pr->dims[0], pa->flow_layers, pa->flow_width, F))
+      return "flow: d >= 2, flow_layers in [1, 8], flow_width 128";
+    if (pa->flow_train_steps < 0 || pa->flow_train_steps > 100000) return "flow_train_steps";
+    if (!(pa->flow_lr >= 0.0)) return "flow_lr >= 0";
+  }
   if (!(pa->step_size > 0.0) || !(pa->traj_length > 0.0)) return "step_size, traj_length > 0";
   if (!(pa->ess_frac >= 0.0 && pa->ess_frac <= 1.0)) return "ess_frac in [0, 1]";
   if (!(pa->adam_lr >= 0.0) || !(pa->adam_b1 >= 0.0 && pa->adam_b1 < 1.0) ||
@@ -206,6 +250,29 @@ void plan(const smc_problem *pr, const smc_params *pa, Layout &L) {
   L.o_means = take(c, (size_t)B * 2 * L.DS * 8);
   L.o_minv = take(c, (size_t)B * L.DS * 4);
   L.o_primes = take(c, NPRIMES * 4);
+  if (pa->precond == SMC_PRECOND_FLOW) {
+    flow_net(pr->dims[0], pa->flow_layers, pa->flow_width, L.F);
+    L.F.ntrain = pa->flow_train_steps;
+    L.F.lr = (float)pa->flow_lr;
+    const size_t np = (size_t)L.F.nparams;
+    L.o_fz = take(c, st);
+    L.o_fz0 = take(c, st);
+    L.o_fgz = take(c, st);
+    L.o_fld0 = take(c, rows * 4);
+    L.o_fld1 = take(c, rows * 4);
+    L.o_fm = take(c, (size_t)L.DS * 4);
+    L.o_fa = take(c, (size_t)L.DS * 4);
+    L.o_fp = take(c, np * 4);
+    L.o_fpt = take(c, np * 4);
+    L.o_fwb = take(c, np * 2);
+    L.o_fwbt = take(c, np * 2);
+    L.o_fbias = take(c, np * 4);
+    L.o_fgrad = take(c, (size_t)FKSPLIT * np * 4);
+    L.o_fadm = take(c, np * 4);
+    L.o_fadv = take(c, np * 4);
+    L.o_ftape = take(c, rows * L.F.L * std::max(L.F.tape_stride, L.F.train_stride) * 4);
+    L.o_fstate = take(c, 256);
+  }
   L.total = (c + 255) & ~(size_t)255;
 }
 
@@ -348,6 +415,27 @@ smc_status smc_init(const smc_problem *prob, const smc_params *par, void *worksp
   D.primes = (int *)(w + L.o_primes);
   D.lf_target = L.lf_target;
   D.lf_grid = L.lf_grid;
+  D.flow = par->precond == SMC_PRECOND_FLOW ? 1 : 0;
+  if (D.flow) {
+    D.fz = (float *)(w + L.o_fz);
+    D.fz0 = (float *)(w + L.o_fz0);
+    D.fgz = (float *)(w + L.o_fgz);
+    D.fld0 = (float *)(w + L.o_fld0);
+    D.fld1 = (float *)(w + L.o_fld1);
+    D.fm = (float *)(w + L.o_fm);
+    D.fa = (float *)(w + L.o_fa);
+    D.fp = (float *)(w + L.o_fp);
+    D.fpt = (float *)(w + L.o_fpt);
+    D.fwb = (uint16_t *)(w + L.o_fwb);
+    D.fwbt = (uint16_t *)(w + L.o_fwbt);
+    D.fbias = (float *)(w + L.o_fbias);
+    D.fgrad = (float *)(w + L.o_fgrad);
+    D.fadm = (float *)(w + L.o_fadm);
+    D.fadv = (float *)(w + L.o_fadv);
+    D.ftape = (float *)(w + L.o_ftape);
+    D.fstate = (int *)(w + L.o_fstate);
+  }
+  ctx->F = L.F;
 
   ctx->hp = L.hp;
   ctx->posts = L.posts;
@@ -398,6 +486,7 @@ smc_status smc_init(const smc_problem *prob, const smc_params *par, void *worksp
   for (const int3 &g : ctx->ll_groups) CKI(launch_loglik(D, g.x, g.y, g.z, ctx->st));
   CKI(launch_init_weights(D, ctx->st));
   CKI(launch_ess(D, 0, ctx->st));
+  if (D.flow) CKI(launch_flow_init(D, ctx->F, ctx->st));
   // the host copies above must stay alive until they have run
   CKI(hipStreamSynchronize(ctx->st));
   (void)rc;
@@ -434,17 +523,39 @@ smc_status enqueue_step(smc_ctx *ctx, const smc_inject *inject) {
   size_t ei = 0;
   CK(launch_begin_step(D, 1, inject ? inject->resample_u : nullptr, 1, ctx->st));
   CK(launch_gather(D, nullptr, ctx->st));
-  if (D.precond == SMC_PRECOND_DIAG) CK(launch_mass(D, ctx->st));
+  if (D.precond == SMC_PRECOND_DIAG) CK(launch_mass(D, 1, ctx->st));
+  const FlowNet &F = ctx->F;
+  if (D.flow) {
+    // standardise the pre-move population, then fit the couplings to it
+    CK(launch_mass(D, 0, ctx->st));
+    CK(launch_flow_base(D, F, ctx->st));
+    for (int i = 0; i < F.ntrain; ++i) {
+      CK(timed_begin(ctx, 4, ei));
+      CK(launch_flow_train(D, F, i, ctx->st));
+      CK(timed_end(ctx, ei));
+    }
+  }
   CK(launch_setup(D, inject ? inject->momenta : nullptr, 0, ctx->st));
+  if (D.flow) CK(launch_flow_begin(D, F, ctx->st));
   CK(launch_sort(D, ctx->st));
   for (int s = 0; s < D.nmax; ++s)
     for (int c2 : ctx->c2s) {
+      if (D.flow) {
+        CK(timed_begin(ctx, 3, ei));
+        CK(launch_flow_drift(D, F, s, ctx->st));
+        CK(timed_end(ctx, ei));
+      }
       CK(timed_begin(ctx, 0, ei));
-      CK(launch_lf_partial(D, c2, s, 0, ctx->st));
+      CK(launch_lf_partial(D, c2, s, D.flow ? 1 : 0, ctx->st));
       CK(timed_end(ctx, ei));
       CK(timed_begin(ctx, 2, ei));
-      CK(launch_lf_reduce(D, c2, s, 0, ctx->st));
+      CK(launch_lf_reduce(D, c2, s, D.flow ? 2 : 0, ctx->st));
       CK(timed_end(ctx, ei));
+      if (D.flow) {
+        CK(timed_begin(ctx, 3, ei));
+        CK(launch_flow_kick(D, F, s, ctx->st));
+        CK(timed_end(ctx, ei));
+      }
     }
   for (const int3 &g : ctx->ll_groups) {
     CK(timed_begin(ctx, 1, ei));
@@ -597,6 +708,11 @@ smc_status smc_get_trace(smc_ctx *ctx, smc_trace *t) {
   t->theta_prop = ctx->D.theta_t;
   t->grad = ctx->D.grad_t;
   t->minv = ctx->D.minv;
+  t->latent0 = ctx->D.flow ? ctx->D.fz0 : nullptr;
+  t->latent = ctx->D.flow ? ctx->D.fz : nullptr;
+  t->latent_grad = ctx->D.flow ? ctx->D.fgz : nullptr;
+  t->logdet0 = ctx->D.flow ? ctx->D.fld0 : nullptr;
+  t->logdet = ctx->D.flow ? ctx->D.fld1 : nullptr;
   t->dpad = ctx->D.DS;
   t->jcap = ctx->D.Jcap;
   return SMC_OK;
@@ -636,6 +752,12 @@ smc_status smc_get_timing(smc_ctx *ctx, smc_timing *out) {
     } else if (m.first == 1) {
       out->loglik_ms += ms;
       out->loglik_launches += 1;
+    } else if (m.first == 3) {
+      out->flow_ms += ms;
+      out->flow_launches += 1;
+    } else if (m.first == 4) {
+      out->train_ms += ms;
+      out->train_launches += 1;
     } else {
       out->reduce_ms += ms;
       out->reduce_launches += 1;
@@ -649,6 +771,38 @@ smc_status smc_get_timing(smc_ctx *ctx, smc_timing *out) {
 smc_status smc_set_params(smc_ctx *ctx, double L, double eps) {
   if (!ctx || !(L > 0.0) || !(eps > 0.0)) return SMC_EINVAL;
   CK(launch_set_params(ctx->D, L, eps, ctx->st));
+  return SMC_OK;
+}
+
+size_t smc_flow_param_count(int32_t d, int32_t layers, int32_t width) {
+  FlowNet F;
+  return flow_net(d, layers, width, F) ? (size_t)F.nparams : 0;
+}
+
+smc_status smc_get_flow(smc_ctx *ctx, float *params, float *m, float *a, float *grad) {
+  if (!ctx) return SMC_EINVAL;
+  if (!ctx->D.flow) {
+    ctx->err = "no flow preconditioner in this context";
+    return SMC_EINVAL;
+  }
+  const Dev &D = ctx->D;
+  if (params)
+    CK(hipMemcpyAsync(params, D.fp, (size_t)ctx->F.nparams * 4, hipMemcpyDeviceToDevice, ctx->st));
+  if (m) CK(hipMemcpyAsync(m, D.fm, (size_t)ctx->F.d * 4, hipMemcpyDeviceToDevice, ctx->st));
+  if (a) CK(hipMemcpyAsync(a, D.fa, (size_t)ctx->F.d * 4, hipMemcpyDeviceToDevice, ctx->st));
+  if (grad) CK(launch_flow_gradsum(D, ctx->F, grad, ctx->st));
+  return SMC_OK;
+}
+
+smc_status smc_set_flow(smc_ctx *ctx, const float *params) {
+  if (!ctx || !params) return SMC_EINVAL;
+  if (!ctx->D.flow) {
+    ctx->err = "no flow preconditioner in this context";
+    return SMC_EINVAL;
+  }
+  CK(hipMemcpyAsync(ctx->D.fp, params, (size_t)ctx->F.nparams * 4, hipMemcpyDeviceToDevice,
+                    ctx->st));
+  CK(launch_flow_set(ctx->D, ctx->F, ctx->st));
   return SMC_OK;
 }
 

@@ -20,7 +20,35 @@ constexpr int QUANT_BITS = 40;      // fixed-point resolution of resampling weig
 constexpr int NPRIMES = 1024;       // primes table for N-d Halton
 
 // Philox stream ids (counter word 3)
-constexpr uint32_t STREAM_INIT = 1, STREAM_MOMENTUM = 2, STREAM_MH = 3, STREAM_RESAMPLE = 4;
+constexpr uint32_t STREAM_INIT = 1, STREAM_MOMENTUM = 2, STREAM_MH = 3, STREAM_RESAMPLE = 4,
+                   STREAM_FLOW = 5;
+
+// Flow preconditioner: affine couplings with a two-hidden-layer conditioner
+// of width FH; FP particles per wave in the flow kernels.
+constexpr int FH = 128;
+constexpr int FMAXL = 8;
+constexpr int FP = 4;
+constexpr int FKSPLIT = 8;  // particle chunks of the flow parameter-gradient reduction
+
+// One coupling layer: transformed coordinates [T0, T0 + dt), conditioning
+// coordinates [C0, C0 + dc); offsets of its parameters in the flat vector
+// (per layer W1 [FH][dc], b1 [FH], W2 [FH][FH], b2 [FH], W3 [2dt][FH], b3 [2dt]).
+struct FlowLayerDesc {
+  int T0, C0, dt, dc;
+  int oW1, ob1, oW2, ob2, oW3, ob3;
+};
+
+struct FlowNet {
+  int L;                  // coupling layers
+  int d;                  // dimension
+  int half;               // max(dt, dc) rounded up to even
+  int tape_stride;        // floats per particle and layer of the move tape
+  int train_stride;       // floats per particle and layer of the training record
+  int nparams;            // length of the flat parameter vector
+  int ntrain;             // Adam steps per iteration
+  float lr;               // Adam learning rate
+  FlowLayerDesc ly[FMAXL];
+};
 
 // Constants of one posterior, resident in device memory.
 struct Post {
@@ -91,6 +119,17 @@ struct Dev {                    // pointers carved from the workspace
   int *primes;                  // NPRIMES
   int lf_target;                // target work-group count of a leapfrog launch
   int lf_grid;                  // grid of a leapfrog launch
+  // flow preconditioner (precond FLOW, one posterior)
+  int flow;
+  float *fz, *fz0, *fgz;        // latent position, pre-move latent, latent gradient [Jcap][DS]
+  float *fld0, *fld1;           // log|det J_T| at z0 and at the current z [Jcap]
+  float *fm, *fa;               // standardisation theta = m + exp(a) x  [DS]
+  float *fp, *fpt;              // FP32 parameters (flat) and transposed weight copies
+  uint16_t *fwb, *fwbt;         // BF16 weights for the moves, row-major and transposed
+  float *fbias;                 // BF16-rounded biases (flat offsets)
+  float *fgrad, *fadm, *fadv;   // parameter gradient and Adam moments
+  float *ftape;                 // per particle and layer activations
+  int *fstate;                  // [0]: Adam step offset
 };
 
 // Host copy of one posterior's packing sizes.
@@ -116,13 +155,15 @@ hipError_t launch_init_theta(const Dev &D, const float *theta0, hipStream_t st);
 hipError_t launch_init_weights(const Dev &D, hipStream_t st);
 hipError_t launch_begin_step(const Dev &D, int conditional, const double *u, int count_iteration,
                              hipStream_t st);
-hipError_t launch_mass(const Dev &D, hipStream_t st);
+hipError_t launch_mass(const Dev &D, int write_minv, hipStream_t st);
 hipError_t launch_gather(const Dev &D, int *anc_out, hipStream_t st);
 hipError_t launch_setup(const Dev &D, const float *momenta, int init_mode, hipStream_t st);
 hipError_t launch_sort(const Dev &D, hipStream_t st);
 hipError_t launch_leapfrog(const Dev &D, int c2, int step, int zero_eps, hipStream_t st);
 hipError_t launch_lf_partial(const Dev &D, int c2, int step, int zero_eps, hipStream_t st);
-hipError_t launch_lf_reduce(const Dev &D, int c2, int step, int zero_eps, hipStream_t st);
+// mode 0: full step; 1: zero step size (gradient at theta, state rewritten);
+// 2: gradient only (theta given by the caller, p untouched)
+hipError_t launch_lf_reduce(const Dev &D, int c2, int step, int mode, hipStream_t st);
 hipError_t launch_loglik(const Dev &D, int c2, int first, int count, hipStream_t st);
 hipError_t launch_weights(const Dev &D, const double *mh_u, int init_mode, hipStream_t st);
 hipError_t launch_chees(const Dev &D, hipStream_t st);
@@ -132,6 +173,16 @@ hipError_t launch_adapt(const Dev &D, hipStream_t st);
 hipError_t launch_set_params(const Dev &D, double L, double eps, hipStream_t st);
 hipError_t launch_export_state(const Dev &D, float *theta, double *logw, double *logpi,
                                hipStream_t st);
+// Flow preconditioner (flow_kernels.hip).
+hipError_t launch_flow_init(const Dev &D, const FlowNet &F, hipStream_t st);
+hipError_t launch_flow_base(const Dev &D, const FlowNet &F, hipStream_t st);
+hipError_t launch_flow_train(const Dev &D, const FlowNet &F, int step, hipStream_t st);
+hipError_t launch_flow_publish(const Dev &D, const FlowNet &F, hipStream_t st);
+hipError_t launch_flow_set(const Dev &D, const FlowNet &F, hipStream_t st);
+hipError_t launch_flow_gradsum(const Dev &D, const FlowNet &F, float *out, hipStream_t st);
+hipError_t launch_flow_begin(const Dev &D, const FlowNet &F, hipStream_t st);
+hipError_t launch_flow_drift(const Dev &D, const FlowNet &F, int step, hipStream_t st);
+hipError_t launch_flow_kick(const Dev &D, const FlowNet &F, int step, hipStream_t st);
 hipError_t launch_resample_indices(const double *w, int J, const double *u, int scheme,
                                    int *anc, unsigned long long *cdf, double *wmax, int *err,
                                    hipStream_t st);

@@ -10,56 +10,11 @@
 #include <math.h>
 
 #include "smc_internal.h"
+#include "dev_common.h"
 
 namespace smc {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
-
-// ---------------------------------------------------------------------------
-// Philox4x32-10 (Salmon et al., SC 2011) and Box--Muller normals.
-// Counter = (block, particle, iteration, stream), key = (seed lo, seed hi).
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1) {
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    const uint32_t hi0 = __umulhi(0xD2511F53u, c.x), lo0 = 0xD2511F53u * c.x;
-    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z), lo1 = 0xCD9E8D57u * c.z;
-    c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
-    k0 += 0x9E3779B9u;
-    k1 += 0xBB67AE85u;
-  }
-  return c;
-}
-
-__device__ __forceinline__ double u01(uint32_t x) { return ((double)x + 0.5) / 4294967296.0; }
-
-__device__ __forceinline__ uint4 philox_at(uint64_t seed, uint32_t block, uint32_t particle,
-                                           uint32_t iteration, uint32_t stream) {
-  return philox10(make_uint4(block, particle, iteration, stream), (uint32_t)seed,
-                  (uint32_t)(seed >> 32));
-}
-
-// Four standard normals from one Philox block: pairs (w0, w1), (w2, w3).
-__device__ __forceinline__ void box_muller4(uint4 w, double out[4]) {
-  const double two_pi = 2.0 * 3.141592653589793;
-  double r = sqrt(-2.0 * log(u01(w.x)));
-  double t = two_pi * u01(w.y);
-  out[0] = r * cos(t);
-  out[1] = r * sin(t);
-  r = sqrt(-2.0 * log(u01(w.z)));
-  t = two_pi * u01(w.w);
-  out[2] = r * cos(t);
-  out[3] = r * sin(t);
-}
-
-// ---------------------------------------------------------------------------
-// Wave64 reductions in a fixed order (butterfly), deterministic.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
 
 // Block reduction helpers for 1024-thread single-posterior kernels.
 template <typename T, typename Op>
@@ -518,7 +473,7 @@ __global__ __launch_bounds__(WG, LF_WAVES_PER_SIMD) void k_lf_partial(Dev D, int
     for (int c = 0; c < K1; ++c) {
       const float t0 = D.theta_t[base + c], p0 = D.p_t[base + c], g0 = D.grad_t[base + c];
       const float ph = fmaf(he, g0, p0);
-      th[sb][c] = fmaf(eps * minv[kq * K1 + c], ph, t0);
+      th[sb][c] = zero_eps ? t0 : fmaf(eps * minv[kq * K1 + c], ph, t0);
     }
   }
 
@@ -660,7 +615,7 @@ __global__ __launch_bounds__(WG) void k_lf_partial_bf16(Dev D, int s, int zero_e
         const int k = 32 * c + 8 * g + e;
         const float t0 = D.theta_t[base + k], p0 = D.p_t[base + k], g0 = D.grad_t[base + k];
         const float ph = fmaf(he, g0, p0);
-        thb[c][e] = (__bf16)fmaf(eps * minv[k], ph, t0);
+        thb[c][e] = (__bf16)(zero_eps ? t0 : fmaf(eps * minv[k], ph, t0));
       }
     }
   }
@@ -770,6 +725,13 @@ __global__ __launch_bounds__(256) void k_lf_reduce(Dev D, int c2, int s, int zer
     gn.c = G.c - th1.c * inv_pv;                         \
     pn.c = fmaf(he, gn.c, ph);                           \
   }
+    if (zero_eps == 2) {
+      // gradient only: theta' was written by the caller
+      gn = make_float4(G.x - t0.x * inv_pv, G.y - t0.y * inv_pv, G.z - t0.z * inv_pv,
+                       G.w - t0.w * inv_pv);
+      reinterpret_cast<float4 *>(D.grad_t)[e] = gn;
+      continue;
+    }
     LF_LANE(x) LF_LANE(y) LF_LANE(z) LF_LANE(w)
 #undef LF_LANE
     reinterpret_cast<float4 *>(D.theta_t)[e] = th1;
@@ -1360,6 +1322,7 @@ __global__ __launch_bounds__(256) void k_weights(Dev D, const double *__restrict
   if (lane != 0) return;
   const double logpi1 = ll + lp;
   double dh = (-logpi1 + K1) - D.H0[row];
+  if (D.flow) dh = (-logpi1 - (double)D.fld1[row] + K1) - D.H0[row];
   if (!(dh == dh) || dh == INFINITY || dh == -INFINITY) dh = INFINITY;
   const double alpha = fmin(1.0, exp(-dh));
   D.logpi_t[row] = logpi1;
@@ -1389,6 +1352,8 @@ hipError_t launch_weights(const Dev &D, const double *mh_u, int init_mode, hipSt
 //   a_j = |theta'_j - theta_hat'|^2 - |theta_j - theta_hat|^2,
 //   g_j = l_j a_j (theta'_j - theta_hat')^T M^{-1} p'_j,
 //   g_hat = sum alpha_j g_j / sum alpha_j,  ChEES = 1/4 mean a_j^2.
+// Under the flow preconditioner the positions are the latent z (the
+// trajectories run there).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_colsum(Dev D) {
   // grid (col_chunks, B); 4 row lanes x 64 columns per column group
@@ -1403,8 +1368,8 @@ __global__ __launch_bounds__(256) void k_colsum(Dev D) {
     if (c < D.DS)
       for (int r = r0 + rl; r < r1; r += 4) {
         const long long o = ((long long)b * D.Jcap + r) * D.DS + c;
-        s0 += (double)D.theta[o];
-        s1 += (double)D.theta_t[o];
+        s0 += (double)(D.flow ? D.fz0 : D.theta)[o];
+        s1 += (double)(D.flow ? D.fz : D.theta_t)[o];
       }
     sh[0][rl][cl] = s0;
     sh[1][rl][cl] = s1;
@@ -1442,8 +1407,8 @@ __global__ __launch_bounds__(256) void k_chees_row(Dev D) {
   const long long o = row * D.DS;
   double an = 0.0, ao = 0.0, dt = 0.0;
   for (int c = lane; c < P.d; c += 64) {
-    const double cn = (double)D.theta_t[o + c] - mn[c];
-    const double co = (double)D.theta[o + c] - mo[c];
+    const double cn = (double)(D.flow ? D.fz : D.theta_t)[o + c] - mn[c];
+    const double co = (double)(D.flow ? D.fz0 : D.theta)[o + c] - mo[c];
     an += cn * cn;
     ao += co * co;
     dt += cn * (double)mv[c] * (double)D.p_t[o + c];
@@ -1550,10 +1515,13 @@ __global__ void k_mass_finish(Dev D, int pass) {
   }
 }
 
-hipError_t launch_mass(const Dev &D, hipStream_t st) {
+// write_minv = 0 stops after the second column pass (the flow preconditioner
+// reads the partial sums itself).
+hipError_t launch_mass(const Dev &D, int write_minv, hipStream_t st) {
   for (int pass = 0; pass < 2; ++pass) {
     hipLaunchKernelGGL(k_mass_colsum, dim3(D.col_chunks, D.B), dim3(256), 0, st, D, pass);
-    hipLaunchKernelGGL(k_mass_finish, dim3(D.B), dim3(256), 0, st, D, pass);
+    if (pass == 0 || write_minv)
+      hipLaunchKernelGGL(k_mass_finish, dim3(D.B), dim3(256), 0, st, D, pass);
   }
   return hipGetLastError();
 }

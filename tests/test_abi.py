@@ -41,7 +41,7 @@ def test_library_exports_every_declared_symbol():
 def test_struct_sizes_match_c_layout():
     from paper_2504_02627_amd import chees
     # natural alignment: these sizes follow from the field lists of the header
-    assert ctypes.sizeof(chees.Params) == 4 * 8 + 8 * 8 + 4 + 4 + 8 + 8
+    assert ctypes.sizeof(chees.Params) == 4 * 8 + 8 * 8 + 4 + 4 + 8 + 8 + 3 * 4 + 4 + 8
     assert ctypes.sizeof(chees.Stats) == 8 * 8 + 4 + 4 + 8
     assert ctypes.sizeof(chees.Inject) == 3 * 8
 
@@ -69,3 +69,15 @@ def test_binding_refuses_to_run_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(chees, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError):
         chees.load()
+
+
+def test_flow_parameter_count_matches_the_oracle_layout():
+    import numpy as np
+    from oracle import flow as F
+    lib = _lib()
+    for d, L in ((100, 4), (5, 2), (2, 1), (208, 8), (37, 3)):
+        ps = F.init_params(d, L, 128, np.random.default_rng(0))
+        assert lib.smc_flow_param_count(d, L, 128) == len(F.flatten(ps))
+    assert lib.smc_flow_param_count(1, 4, 128) == 0
+    assert lib.smc_flow_param_count(100, 9, 128) == 0
+    assert lib.smc_flow_param_count(100, 4, 64) == 0

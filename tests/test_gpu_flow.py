@@ -1,0 +1,179 @@
+"""Flow preconditioner on the device against the flow oracle (oracle/flow.py).
+
+* initial couplings: the Philox draws of the oracle, to binary32 rounding;
+* standardisation m, a of the pre-move population: to binary32 rounding;
+* training: the device's FP32 Adam fit against the oracle's FP64 fit from the
+  same initial parameters and population (elementwise to a tolerance that
+  allows Adam's sign sensitivity on near-zero gradients, and equal objective);
+* moves: from the device's own trained parameters (BF16-rounded), latent
+  start z0 = T^-1(theta0), its log-determinant, the latent trajectory z',
+  theta' = T(z'), p' within 1e-5 relative (per particle), and Delta H within
+  1e-5 (|H0| + |H1|) -- the weights are exact for the latent target."""
+
+import math
+
+import numpy as np
+import pytest
+
+from oracle import flow as F, smc as O
+from paper_2504_02627_amd import synth
+from tests._gpu_common import log, rel_rows, to_dev
+
+pytestmark = pytest.mark.gpu
+
+LAYERS = 4
+
+
+def _near_posterior(X, y, J, rng, spread=0.7):
+    """A population around the Laplace approximation of the posterior, so that
+    the initial weights are not degenerate and the fit sees a spread."""
+    from oracle import quadrature as Q
+    X64, y64 = X.astype(np.float64), y.astype(np.float64)
+    d = X.shape[1]
+
+    def lgh(th):
+        z = X64 @ th
+        sg = 1.0 / (1.0 + np.exp(-z))
+        return None, X64.T @ (y64 - sg) - th, -(X64.T * (sg * (1 - sg))) @ X64 - np.eye(d)
+
+    mode, S = Q.laplace(lgh, d)
+    return (mode + spread * rng.standard_normal((J, d)) @ np.linalg.cholesky(S).T).astype(np.float32)
+
+
+def _setup(N, d, J, seed, ntrain, lr, **kw):
+    from paper_2504_02627_amd import chees
+    X, y, _ = synth.logistic_iid(N, d, seed)
+    rng = np.random.default_rng(seed + 7)
+    theta0 = _near_posterior(X, y, J, rng)
+    eps = kw.pop("eps", 0.3)
+    params = dict(step_size=eps, traj_length=eps * 8, max_leapfrog=24, num_warmup=5, seed=seed,
+                  precond="flow", flow_layers=LAYERS, flow_width=128, flow_train_steps=ntrain,
+                  flow_lr=lr)
+    params.update(kw)
+    s = chees.Sampler(to_dev(X), to_dev(y), J, theta0=to_dev(theta0), **params)
+    t = O.LogisticRegression(X.astype(np.float64), y.astype(np.float64))
+    return X, y, theta0, params, s, t, rng
+
+
+def test_initial_couplings_are_the_philox_draws():
+    X, y, theta0, params, s, t, rng = _setup(200, 11, 130, 3, 0, 1e-3)
+    prm, _, _ = s.flow()
+    ref = F.flatten(F.philox_init(params["seed"], 11, LAYERS, 128))
+    got = prm.cpu().numpy().astype(np.float64)
+    np.testing.assert_allclose(got, ref.astype(np.float32), rtol=2e-7, atol=1e-30)
+
+
+def _blocks_close(dev, ref, d, what, rtol=1e-4):
+    """Elementwise per parameter block: |dev - ref| <= rtol (|ref| + max|ref| of
+    the block) -- summation-order noise of FP32 sums relative to the block."""
+    worst = 0.0
+    for ql, qr in zip(F.unflatten(dev, d, LAYERS, 128)[0], F.unflatten(ref, d, LAYERS, 128)[0]):
+        for k in ql:
+            scale = np.abs(qr[k]).max() + 1e-30
+            e = np.abs(ql[k] - qr[k]) / (np.abs(qr[k]) + scale)
+            worst = max(worst, float(e.max()))
+    log(f"  {what}: worst relative deviation {worst:.2e}")
+    assert worst <= rtol
+
+
+@pytest.mark.parametrize("N,d,J,seed", [(500, 12, 256, 5), (800, 37, 130, 6)])
+def test_flow_iteration_parity(N, d, J, seed):
+    """Two iterations with one Adam step each (the fit is warm-started), no
+    resampling, so that the weighted objective sees the population's own
+    weights.  Adam normalises each coordinate of the gradient, so coordinates
+    whose exact gradient vanishes (the shift of the standardised population's
+    weighted mean, for one) amplify FP32 summation noise; the fit is therefore
+    checked through its gradient (the device's against the oracle's, at the
+    same parameters and population) and through the Adam update applied to the
+    device's gradient."""
+    lr = 1e-2
+    X, y, theta0, params, s, t, rng = _setup(N, d, J, seed, 1, lr, ess_frac=0.0)
+    log(f"[flow] N={N} d={d} J={J} seed={seed}")
+    P0 = s.flow()[0].cpu().numpy().astype(np.float64)
+    ad = F.FlowAdam(lr)
+    th_prev = theta0.astype(np.float64)
+    lw_prev = s.state()[1].cpu().numpy()
+    Pprev = P0
+    for k in (1, 2):
+        xi = rng.standard_normal((J, d)).astype(np.float32)
+        st = s.step(momenta=to_dev(xi), resample_u=to_dev(rng.random(1)))
+        s.adapt()
+        assert not st["resampled"]
+        tr = s.trace()
+        prm, m_dev, a_dev, g_dev = (v.cpu().numpy().astype(np.float64) for v in s.flow(True))
+        m, a = m_dev[:d], a_dev[:d]
+        th0 = th_prev
+        m_ref, a_ref = F.standardise(th0, lw_prev, st["ess_before"])
+        np.testing.assert_allclose(m, m_ref, rtol=1e-6, atol=1e-7)
+        np.testing.assert_allclose(a, a_ref, rtol=1e-6, atol=1e-7)
+        W = O.normalise(lw_prev)
+        _, g = F.objective_and_grad(F.unflatten(Pprev, d, LAYERS, 128)[0], m, a, th0, W)
+        _blocks_close(g_dev, F.flatten(g), d, f"iteration {k}: fit gradient")
+        P_exp = F.flatten(ad.ascend(F.unflatten(Pprev, d, LAYERS, 128)[0],
+                                    F.unflatten(g_dev, d, LAYERS, 128)[0]))
+        dP = np.abs(prm - P_exp)
+        log(f"  iteration {k}: Adam update max |dP| {dP.max():.2e}")
+        assert np.all(dP <= 1e-6 * (np.abs(P_exp) + lr))
+        # moves with the device's trained couplings, BF16-rounded
+        psb = F.bf16_params(F.unflatten(prm, d, LAYERS, 128)[0])
+        z0, ldi = F.inverse(psb, m, a, th0)
+        z0_dev = tr["latent0"].cpu().numpy()[:J, :d].astype(np.float64)
+        ez0 = rel_rows(z0_dev, z0)
+        ld0_dev = tr["logdet0"].cpu().numpy()[:J].astype(np.float64)
+        log(f"  weights ESS {st['ess_before']:.1f}; max |z0| {np.abs(z0).max():.2f}; "
+            f"z0 rel err {ez0:.2e}; max |logdet0 err| {np.max(np.abs(ld0_dev + ldi)):.2e}")
+        assert np.abs(z0).max() > 0.5   # a spread population, not a collapsed one
+        assert ez0 <= 1e-5
+        assert np.all(np.abs(ld0_dev + ldi) <= 1e-5 * (1 + np.abs(ldi)))
+        lp0, g0 = t.log_and_grad(th0)
+        gz0 = F.latent_grad(psb, m, a, z0, g0)
+        n = tr["n"].cpu().numpy()[:J]
+        z1, p1, gz1, th1, _, lp1, ld1 = F.leapfrog_latent(t, psb, m, a, z0, xi.astype(np.float64),
+                                                          gz0, params["step_size"] if k == 1
+                                                          else st["eps"], n)
+        z1_dev = tr["latent"].cpu().numpy()[:J, :d].astype(np.float64)
+        th1_dev = tr["theta_prop"].cpu().numpy()[:J, :d].astype(np.float64)
+        p1_dev = tr["p_final"].cpu().numpy()[:J, :d].astype(np.float64)
+        ez, et, ep = rel_rows(z1_dev, z1), rel_rows(th1_dev, th1), rel_rows(p1_dev, p1)
+        log(f"  n in [{n.min()}, {n.max()}]; traj rel err z {ez:.2e} theta {et:.2e} p {ep:.2e}")
+        assert ez <= 1e-5 and et <= 1e-5 and ep <= 1e-5
+        H0 = O.hamiltonian(lp0 - ldi, xi.astype(np.float64))
+        H1 = O.hamiltonian(lp1 + ld1, p1)
+        dh = tr["dH"].cpu().numpy()[:J]
+        err = np.abs(dh - (H1 - H0))
+        log(f"  max |dH err| {err.max():.2e} (bar {(1e-5 * (np.abs(H0) + np.abs(H1))).min():.2e}); "
+            f"ESS {st['ess']:.1f}")
+        assert np.all(err <= 1e-5 * (np.abs(H0) + np.abs(H1)))
+        theta, logw, _ = s.state()
+        th_prev = theta.cpu().numpy().astype(np.float64)
+        lw_prev = logw.cpu().numpy()
+        Pprev = prm
+
+
+def test_flow_with_no_training_and_identity_couplings_is_a_linear_preconditioner():
+    """Zero couplings (set through smc_set_flow) and no training: T(z) = m +
+    exp(a) z.  The latent leapfrog is then the plain leapfrog with mass
+    M^{-1} = exp(2a) up to rounding; the trajectories of the flow context and
+    of a diagonal-mass oracle with minv = exp(2a) agree."""
+    import torch
+    N, d, J = 400, 9, 256
+    X, y, theta0, params, s, t, rng = _setup(N, d, J, 8, 0, 1e-3)
+    n_par = len(F.flatten(F.init_params(d, LAYERS, 128, np.random.default_rng(0))))
+    s.set_flow(torch.zeros(n_par, dtype=torch.float32, device="cuda"))
+    xi = rng.standard_normal((J, d)).astype(np.float32)
+    st = s.step(momenta=to_dev(xi), resample_u=to_dev(np.array([0.5])))
+    tr = s.trace()
+    _, m, a = (v.cpu().numpy().astype(np.float64) for v in s.flow())
+    anc = tr["ancestors"].cpu().numpy()[:J] if st["resampled"] else np.arange(J)
+    th0 = theta0.astype(np.float64)[anc]
+    minv = np.exp(2 * a)
+    lp0, g0 = t.log_and_grad(th0)
+    # theta = m + e^a z, p_z = e^a p_theta: the plain leapfrog with M^-1 = e^{2a}
+    p_theta = xi.astype(np.float64) * np.exp(-a)
+    n = tr["n"].cpu().numpy()[:J]
+    th1, p1, _, _, _ = O.leapfrog(t, th0, p_theta, g0, params["step_size"], n, minv)
+    th1_dev = tr["theta_prop"].cpu().numpy()[:J, :d].astype(np.float64)
+    e = rel_rows(th1_dev, th1)
+    log(f"[flow identity] theta' vs diagonal-mass leapfrog rel err {e:.2e}")
+    assert e <= 1e-5
+    np.testing.assert_allclose(tr["logdet"].cpu().numpy()[:J], np.sum(a), rtol=1e-6)
