@@ -16,7 +16,8 @@ Flow T: z -> theta (fixed within an SMC iteration):
       h1 = tanh(W1 x_C + b1);  h2 = tanh(W2 h1 + b2);  o = W3 h2 + b3
       s = tanh(o[:d_T]);  t = o[d_T:]
       x_T <- x_T * exp(s) + t;         log|det| += sum s
-  theta = m + exp(a) * x;              log|det| += sum a
+  theta_c = m_c + exp(a_c) x_q(c);     log|det| += sum a
+  (q: even coordinates of theta first, then the odd ones)
 Latent target: log pi_z(z) = log pi(T(z)) + log|det J_T(z)|.
 
 Per iteration (readings, all build choices): m and a standardise the weighted
@@ -36,6 +37,16 @@ import numpy as np
 def halves(d):
     da = d // 2
     return np.arange(da), np.arange(da, d)
+
+
+def interleave(d):
+    """Position q(c) of coordinate c of theta in the coupling state x: the even
+    coordinates first, then the odd ones, so that the contiguous halves of x
+    split neighbouring coordinates of theta (coupling layers then condition
+    each coordinate on its neighbours)."""
+    c = np.arange(d)
+    ne = (d + 1) // 2
+    return np.where(c % 2 == 0, c // 2, ne + c // 2)
 
 
 def layer_sets(l, d):
@@ -82,15 +93,16 @@ def forward(ps, m, a, z):
         t = o[:, len(T):]
         x[:, T] = x[:, T] * np.exp(s) + t
         ld += s.sum(1)
-    return m + np.exp(a) * x, ld + np.sum(a)
+    return m + np.exp(a) * x[:, interleave(d)], ld + np.sum(a)
 
 
 def inverse(ps, m, a, theta):
     """z = T^-1(theta) and log|det J_{T^-1}(theta)| = -log|det J_T(z)|."""
     theta = np.atleast_2d(np.asarray(theta, dtype=np.float64))
-    x = (theta - m) * np.exp(-a)
+    d = theta.shape[1]
+    x = np.empty_like(theta)
+    x[:, interleave(d)] = (theta - m) * np.exp(-a)
     ld = np.full(len(x), -np.sum(a))
-    d = x.shape[1]
     for l in reversed(range(len(ps))):
         p = ps[l]
         T, C = layer_sets(l, d)
@@ -117,7 +129,8 @@ def latent_grad(ps, m, a, z, g_theta):
         xT = x[:, T].copy()
         tape.append((T, C, h1, h2, s, xT))
         x[:, T] = xT * np.exp(s) + t
-    gx = np.asarray(g_theta, dtype=np.float64) * np.exp(a)     # cotangent of x
+    gx = np.empty((len(z), d))
+    gx[:, interleave(d)] = np.asarray(g_theta, dtype=np.float64) * np.exp(a)   # cotangent of x
     for l in reversed(range(len(ps))):
         p = ps[l]
         T, C, h1, h2, s, xT = tape[l]
@@ -140,7 +153,8 @@ def objective_and_grad(ps, m, a, theta, W):
     (reverse accumulation through the inverse map)."""
     theta = np.atleast_2d(np.asarray(theta, dtype=np.float64))
     J, d = theta.shape
-    x = (theta - m) * np.exp(-a)
+    x = np.empty_like(theta)
+    x[:, interleave(d)] = (theta - m) * np.exp(-a)
     ld = np.full(J, -np.sum(a))
     tape = {}
     for l in reversed(range(len(ps))):

@@ -7,7 +7,8 @@
 //   log pi_z(z) = log pi(T(z)) + log|det J_T(z)|.
 // T: x = z; per coupling layer l: x_T <- x_T exp(s) + t with (s, t) from a
 // tanh MLP (width FH) of the conditioning half x_C, s = tanh(.);
-// theta = m + exp(a) x.  m, a standardise the weighted pre-move population;
+// theta_c = m_c + exp(a_c) x_q(c), q placing the even coordinates of theta
+// first, then the odd ones.  m, a standardise the weighted pre-move population;
 // the couplings are trained each iteration by a few Adam steps on the
 // weighted maximum-likelihood objective of the population.
 //
@@ -132,6 +133,11 @@ __device__ __forceinline__ void dense_bwd(const WT *W, int M, int K, const float
     }
   }
 }
+
+// Position of coordinate c of theta in the coupling state x: even
+// coordinates first, then the odd ones, so that the halves of x split
+// neighbouring coordinates.
+__device__ __forceinline__ int xpos(int c, int d) { return (c & 1) ? (d + 1) / 2 + (c >> 1) : c >> 1; }
 
 struct FlowLDS {
   float xs[FP][MAXD];  // coupling state x (or its cotangent)
@@ -372,8 +378,12 @@ __global__ __launch_bounds__(64) void k_flow_train(Dev D, FlowNet F) {
     }
     wj[p] = (float)w;
     rec[p] = ok ? D.ftape + (long long)j * F.L * F.train_stride : nullptr;
-    for (int c = lane; c < MAXD; c += 64)
-      S.xs[p][c] = (ok && c < F.d) ? (src[(long long)j * D.DS + c] - D.fm[c]) * expf(-D.fa[c]) : 0.f;
+    for (int c = lane; c < MAXD; c += 64) {
+      if (c < F.d)
+        S.xs[p][xpos(c, F.d)] = ok ? (src[(long long)j * D.DS + c] - D.fm[c]) * expf(-D.fa[c]) : 0.f;
+      else
+        S.xs[p][c] = 0.f;
+    }
   }
   __syncthreads();
   const float *Wt = D.fpt, *W = D.fp;
@@ -606,12 +616,16 @@ __global__ __launch_bounds__(64) void k_flow_begin(Dev D, FlowNet F) {
     rtape[p] = D.ftape + (long long)(ok ? j : j0) * F.L * F.tape_stride;
     ldl[p] = 0.f;
     for (int c = lane; c < MAXD; c += 64) {
-      float x = 0.f;
-      if (ok && c < F.d) {
-        x = (D.theta_t[(long long)j * D.DS + c] - D.fm[c]) * expf(-D.fa[c]);
-        ldl[p] -= D.fa[c];
+      if (c < F.d) {
+        float x = 0.f;
+        if (ok) {
+          x = (D.theta_t[(long long)j * D.DS + c] - D.fm[c]) * expf(-D.fa[c]);
+          ldl[p] -= D.fa[c];
+        }
+        S.xs[p][xpos(c, F.d)] = x;
+      } else {
+        S.xs[p][c] = 0.f;
       }
-      S.xs[p][c] = x;
     }
   }
   __syncthreads();
@@ -661,8 +675,12 @@ __global__ __launch_bounds__(64) void k_flow_begin(Dev D, FlowNet F) {
 #pragma unroll
   for (int p = 0; p < FP; ++p) {
     const int j = j0 + p;
-    for (int c = lane; c < MAXD; c += 64)
-      S.xs[p][c] = (j < D.J && c < F.d) ? D.grad_t[(long long)j * D.DS + c] * expf(D.fa[c]) : 0.f;
+    for (int c = lane; c < MAXD; c += 64) {
+      if (c < F.d)
+        S.xs[p][xpos(c, F.d)] = j < D.J ? D.grad_t[(long long)j * D.DS + c] * expf(D.fa[c]) : 0.f;
+      else
+        S.xs[p][c] = 0.f;
+    }
   }
   __syncthreads();
   vjp_couplings(F, D.fwb, S, rtape, lane);
@@ -733,7 +751,7 @@ __global__ __launch_bounds__(64) void k_flow_drift(Dev D, FlowNet F, int step) {
     if (rows[p] >= 0) {
       for (int c = lane; c < D.DS; c += 64)
         D.theta_t[(long long)rows[p] * D.DS + c] =
-            c < F.d ? fmaf(expf(D.fa[c]), S.xs[p][c], D.fm[c]) : 0.f;
+            c < F.d ? fmaf(expf(D.fa[c]), S.xs[p][xpos(c, F.d)], D.fm[c]) : 0.f;
       if (lane == 0) D.fld1[rows[p]] = ld;
     }
   }
@@ -756,10 +774,13 @@ __global__ __launch_bounds__(64) void k_flow_kick(Dev D, FlowNet F, int step) {
   for (int p = 0; p < FP; ++p) {
     const int j = rows[p] >= 0 ? rows[p] : first;
     tape[p] = D.ftape + (long long)j * F.L * F.tape_stride;
-    for (int c = lane; c < MAXD; c += 64)
-      S.xs[p][c] = (rows[p] >= 0 && c < F.d)
-                       ? D.grad_t[(long long)rows[p] * D.DS + c] * expf(D.fa[c])
-                       : 0.f;
+    for (int c = lane; c < MAXD; c += 64) {
+      if (c < F.d)
+        S.xs[p][xpos(c, F.d)] =
+            rows[p] >= 0 ? D.grad_t[(long long)rows[p] * D.DS + c] * expf(D.fa[c]) : 0.f;
+      else
+        S.xs[p][c] = 0.f;
+    }
   }
   __syncthreads();
   vjp_couplings(F, D.fwb, S, tape, lane);

@@ -151,8 +151,8 @@ def test_flow_iteration_parity(N, d, J, seed):
 
 
 def test_flow_with_no_training_and_identity_couplings_is_a_linear_preconditioner():
-    """Zero couplings (set through smc_set_flow) and no training: T(z) = m +
-    exp(a) z.  The latent leapfrog is then the plain leapfrog with mass
+    """Zero couplings (set through smc_set_flow) and no training: T(z)_c = m_c
+    + exp(a_c) z_q(c).  The latent leapfrog is then the plain leapfrog with mass
     M^{-1} = exp(2a) up to rounding; the trajectories of the flow context and
     of a diagonal-mass oracle with minv = exp(2a) agree."""
     import torch
@@ -168,8 +168,9 @@ def test_flow_with_no_training_and_identity_couplings_is_a_linear_preconditioner
     th0 = theta0.astype(np.float64)[anc]
     minv = np.exp(2 * a)
     lp0, g0 = t.log_and_grad(th0)
-    # theta = m + e^a z, p_z = e^a p_theta: the plain leapfrog with M^-1 = e^{2a}
-    p_theta = xi.astype(np.float64) * np.exp(-a)
+    # theta_c = m_c + e^a_c z_q(c), p_theta,c = e^-a_c p_z,q(c): the plain
+    # leapfrog with M^-1 = e^{2a}
+    p_theta = xi.astype(np.float64)[:, F.interleave(d)] * np.exp(-a)
     n = tr["n"].cpu().numpy()[:J]
     th1, p1, _, _, _ = O.leapfrog(t, th0, p_theta, g0, params["step_size"], n, minv)
     th1_dev = tr["theta_prop"].cpu().numpy()[:J, :d].astype(np.float64)

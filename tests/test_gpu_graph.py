@@ -26,7 +26,8 @@ def _same(a, b):
     assert a[3] == b[3] and a[4] == b[4]
 
 
-@pytest.mark.parametrize("precision,precond", [("f32", "none"), ("bf16", "none"), ("f32", "diag")])
+@pytest.mark.parametrize("precision,precond", [("f32", "none"), ("bf16", "none"), ("f32", "diag"),
+                                               ("f32", "flow")])
 def test_graph_replays_match_eager(precision, precond):
     import torch
     from paper_2504_02627_amd import chees
@@ -35,6 +36,8 @@ def test_graph_replays_match_eager(precision, precond):
     eps = synth.default_step_size(N, d)
     kw = dict(step_size=eps, traj_length=eps * 20, max_leapfrog=40, num_warmup=4, seed=9,
               precision=precision, precond=precond, adapt_step_size=True)
+    if precond == "flow":
+        kw.update(step_size=0.2, traj_length=1.0, flow_layers=2, flow_train_steps=3, flow_lr=5e-3)
     log(f"[graph] {precision} {precond} N={N} d={d} J={J}")
     eager = chees.Sampler(to_dev(X), to_dev(y), J, **kw)
     graph = chees.Sampler(to_dev(X), to_dev(y), J, **kw)

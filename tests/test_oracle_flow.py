@@ -30,10 +30,14 @@ def test_zero_last_layer_is_the_identity():
     d = 7
     ps = F.init_params(d, 4, 16, np.random.default_rng(1))
     z = np.random.default_rng(2).standard_normal((5, d))
+    q = F.interleave(d)
+    # the identity couplings leave only the interleaving: theta_c = z_q(c)
+    assert sorted(q) == list(range(d)) and list(q[:4]) == [0, 4, 1, 5]
     th, ld = F.forward(ps, np.zeros(d), np.zeros(d), z)
-    assert np.array_equal(th, z) and np.array_equal(ld, np.zeros(5))
+    assert np.array_equal(th, z[:, q]) and np.array_equal(ld, np.zeros(5))
     g = np.random.default_rng(3).standard_normal((5, d))
-    assert np.array_equal(F.latent_grad(ps, np.zeros(d), np.zeros(d), z, g), g)
+    gz = F.latent_grad(ps, np.zeros(d), np.zeros(d), z, g)
+    assert np.array_equal(gz[:, q], g)
 
 
 @pytest.mark.parametrize("d", [2, 5, 8])
@@ -143,16 +147,21 @@ def test_identity_flow_iteration_equals_the_plain_iteration():
     y = (np.random.default_rng(42).random(60) < 0.5).astype(float)
     t = O.LogisticRegression(X, y)
     ps = F.init_params(d, 4, 16, np.random.default_rng(43))
-    z0 = np.random.default_rng(44).standard_normal((8, d)) * 0.3
+    q = F.interleave(d)
+    th0 = np.random.default_rng(44).standard_normal((8, d)) * 0.3
     p0 = np.random.default_rng(45).standard_normal((8, d))
-    lp0, g0 = t.log_and_grad(z0)
+    z0 = np.empty_like(th0)
+    z0[:, q] = th0
+    pz0 = np.empty_like(p0)
+    pz0[:, q] = p0
+    lp0, g0 = t.log_and_grad(th0)
     n = np.arange(1, 9)
-    zl, pl, gl, thl, gthl, lpl, ldl = F.leapfrog_latent(t, ps, np.zeros(d), np.zeros(d), z0, p0,
-                                                        F.latent_grad(ps, np.zeros(d), np.zeros(d), z0, g0),
-                                                        0.07, n)
-    th, p, g, lp, _ = O.leapfrog(t, z0, p0, g0, 0.07, n)
-    assert np.array_equal(zl, th) and np.array_equal(pl, p) and np.array_equal(lpl, lp)
-    assert np.array_equal(ldl, np.zeros(8))
+    zl, pl, gl, thl, gthl, lpl, ldl = F.leapfrog_latent(
+        t, ps, np.zeros(d), np.zeros(d), z0, pz0,
+        F.latent_grad(ps, np.zeros(d), np.zeros(d), z0, g0), 0.07, n)
+    th, p, g, lp, _ = O.leapfrog(t, th0, p0, g0, 0.07, n)
+    assert np.array_equal(thl, th) and np.array_equal(pl[:, q], p) and np.array_equal(lpl, lp)
+    assert np.array_equal(zl[:, q], th) and np.array_equal(ldl, np.zeros(8))
 
 
 def test_training_whitens_a_correlated_population():
