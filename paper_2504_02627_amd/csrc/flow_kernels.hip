@@ -8,15 +8,18 @@
 // T: x = z; per coupling layer l: x_T <- x_T exp(s) + t with (s, t) from a
 // tanh MLP (width FH) of the conditioning half x_C, s = tanh(.);
 // theta_c = m_c + exp(a_c) x_q(c), q placing the even coordinates of theta
-// first, then the odd ones.  m, a standardise the weighted pre-move population;
-// the couplings are trained each iteration by a few Adam steps on the
-// weighted maximum-likelihood objective of the population.
+// first, then the odd ones.  m, a standardise the weighted pre-move
+// population; the couplings are trained each iteration by a few Adam steps on
+// the weighted maximum-likelihood objective of the population.
 //
-// Kernels work on FP = 4 particles per wave (one wave per block): every
-// weight loaded from L2 feeds four particles; activations of the current
-// layer sit in LDS, the per-layer activations the backward passes need in a
-// per-particle tape in global memory.  Training uses the FP32 parameters,
-// the moves the BF16-rounded weights with FP32 arithmetic.
+// A block of four waves carries 16 particles.  Every dense layer of the
+// conditioners runs on v_mfma_f32_16x16x4f32 with a 16-unit tile of the
+// weight matrix as A (the waves take the tiles in turn) and the 16 particles'
+// activations, held in LDS, as B; the weights are pre-packed in the A-operand
+// order so that each lane reads four K-steps with one 16-byte load.  The
+// per-layer activations the backward passes need sit in a per-particle tape
+// in global memory.  Training uses the FP32 parameters; the moves use the
+// weights rounded to bfloat16 (held as FP32 operands) with FP32 arithmetic.
 #pragma clang fp contract(off)
 
 #include <math.h>
@@ -28,20 +31,19 @@ namespace smc {
 
 namespace {
 
-constexpr int MAXD = 16 * MAX_C2;  // largest padded dimension
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+constexpr int MAXD = 16 * MAX_C2;  // largest dimension
+constexpr int PB = 16;             // particles per block
+constexpr int NT = 256;            // threads per block
+constexpr int XP = MAXD + 17;      // LDS pitch of state rows: a padded K chunk stays in the row
+constexpr int HP = FH + 1;         // LDS pitch of hidden rows
 constexpr int KSPLIT = FKSPLIT;
 
-__device__ __forceinline__ float2 wpair(const uint16_t *w, int i) {
-  const uint32_t u = *reinterpret_cast<const uint32_t *>(w + i);
-  return make_float2(__uint_as_float(u << 16), __uint_as_float(u & 0xFFFF0000u));
-}
-__device__ __forceinline__ float2 wpair(const float *w, int i) {
-  return *reinterpret_cast<const float2 *>(w + i);
-}
-__device__ __forceinline__ float wone(const uint16_t *w, int i) {
-  return __uint_as_float((uint32_t)w[i] << 16);
-}
-__device__ __forceinline__ float wone(const float *w, int i) { return w[i]; }
+// Position of coordinate c of theta in the coupling state x: even
+// coordinates first, then the odd ones, so that the halves of x split
+// neighbouring coordinates.
+__device__ __forceinline__ int xpos(int c, int d) { return (c & 1) ? (d + 1) / 2 + (c >> 1) : c >> 1; }
 
 __device__ __forceinline__ uint16_t bf16_bits(float f) {
   const uint32_t u = __float_as_uint(f);
@@ -49,209 +51,155 @@ __device__ __forceinline__ uint16_t bf16_bits(float f) {
   return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
 }
 
-// out[p][u] = b[u] + sum_k Wt[k][u] in[p][k] for u < M, the lane holding the
-// unit pairs (2q, 2q + 1), q = lane + 64 r.  Wt: transposed weights [K][M].
-template <typename WT>
-__device__ __forceinline__ void dense_fwd(const WT *Wt, const float *bias, int M, int K,
-                                          const float *in, int ins, int lane, float acc[FP][2][2]) {
-#pragma unroll
-  for (int r = 0; r < 2; ++r) {
-    const int u = 2 * (lane + 64 * r);
-#pragma unroll
-    for (int p = 0; p < FP; ++p) {
-      acc[p][r][0] = u < M ? bias[u] : 0.f;
-      acc[p][r][1] = u + 1 < M ? bias[u + 1] : 0.f;
-    }
-  }
-  const bool r1 = 2 * (lane + 64) < M;
-  const bool r0 = 2 * lane < M;
-#pragma unroll 4
-  for (int k = 0; k < K; ++k) {
-    float xv[FP];
-#pragma unroll
-    for (int p = 0; p < FP; ++p) xv[p] = in[p * ins + k];
-    if (r0) {
-      const float2 w = wpair(Wt, k * M + 2 * lane);
-#pragma unroll
-      for (int p = 0; p < FP; ++p) {
-        acc[p][0][0] = fmaf(w.x, xv[p], acc[p][0][0]);
-        acc[p][0][1] = fmaf(w.y, xv[p], acc[p][0][1]);
-      }
-    }
-    if (r1) {
-      const float2 w = wpair(Wt, k * M + 2 * (lane + 64));
-#pragma unroll
-      for (int p = 0; p < FP; ++p) {
-        acc[p][1][0] = fmaf(w.x, xv[p], acc[p][1][0]);
-        acc[p][1][1] = fmaf(w.y, xv[p], acc[p][1][1]);
-      }
-    }
-  }
+// Element A[u][k] of an M x K matrix in the packed A-operand order:
+// [u/16][k/16][lane][j] with lane = u%16 + 16 (k%4), j = (k%16)/4, so that
+// lane l's float4 at (tile, chunk) holds A[16 tile + l%16][16 chunk + 4 j + l/16].
+__device__ __forceinline__ int pk_index(int u, int k, int K16) {
+  const int kk = k & 15;
+  const int lane = (u & 15) + 16 * (kk & 3);
+  return (((u >> 4) * (K16 >> 4) + (k >> 4)) * 64 + lane) * 4 + (kk >> 2);
 }
 
-// Write a dense_fwd result to LDS rows out[p][u] (optionally tanh), and to the
-// tape rows tp[p] + u when given.
-__device__ __forceinline__ void store_units(float acc[FP][2][2], int M, bool act, float *out,
-                                            int outs, float *const tp[FP], int lane) {
-#pragma unroll
-  for (int r = 0; r < 2; ++r)
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      const int u = 2 * (lane + 64 * r) + e;
-      if (u < M)
-#pragma unroll
-        for (int p = 0; p < FP; ++p) {
-          const float v = act ? tanhf(acc[p][r][e]) : acc[p][r][e];
-          out[p * outs + u] = v;
-          if (tp[p]) tp[p][u] = v;
-        }
-    }
-}
-
-// out[p][k] = sum_u W[u][k] in[p][u] for k = lane + 64 r < K (K <= 128).
-// W: row-major [M][K].
-template <typename WT>
-__device__ __forceinline__ void dense_bwd(const WT *W, int M, int K, const float *in, int ins,
-                                          int lane, float out[FP][2]) {
-#pragma unroll
-  for (int p = 0; p < FP; ++p) out[p][0] = out[p][1] = 0.f;
-  const bool r0 = lane < K, r1 = lane + 64 < K;
-#pragma unroll 4
-  for (int u = 0; u < M; ++u) {
-    float g[FP];
-#pragma unroll
-    for (int p = 0; p < FP; ++p) g[p] = in[p * ins + u];
-    if (r0) {
-      const float w = wone(W, u * K + lane);
-#pragma unroll
-      for (int p = 0; p < FP; ++p) out[p][0] = fmaf(w, g[p], out[p][0]);
-    }
-    if (r1) {
-      const float w = wone(W, u * K + lane + 64);
-#pragma unroll
-      for (int p = 0; p < FP; ++p) out[p][1] = fmaf(w, g[p], out[p][1]);
-    }
-  }
-}
-
-// Position of coordinate c of theta in the coupling state x: even
-// coordinates first, then the odd ones, so that the halves of x split
-// neighbouring coordinates.
-__device__ __forceinline__ int xpos(int c, int d) { return (c & 1) ? (d + 1) / 2 + (c >> 1) : c >> 1; }
-
-struct FlowLDS {
-  float xs[FP][MAXD];  // coupling state x (or its cotangent)
-  float h1[FP][FH];
-  float h2[FP][FH];
-  float ob[FP][MAXD];  // conditioner output (s~, t) or its cotangent
+struct BlockLDS {
+  float xs[PB][XP];   // coupling state x (or its cotangent)
+  float h1[PB][HP];
+  float h2[PB][HP];
+  float ob[PB][XP];   // conditioner output (s~, t) or its cotangent
+  float *tw[PB];      // tape rows written (nullptr for absent particles)
+  const float *tr[PB];// tape rows read (a present particle's for absent ones)
+  int rows[PB];
+  float wj[PB];
 };
 
-// Forward map of the four particles in xs (latent z on entry, the coupled x
-// on exit), with the move tape [h1 | h2 | s | x_T before the update] per
-// layer when tape rows are given; returns per-lane partial sums of s.
-__device__ void forward_couplings(const FlowNet &F, const uint16_t *Wt, const float *bias,
-                                  FlowLDS &S, float *const tape[FP], float ldl[FP], int lane) {
+enum { ST_PLAIN = 0, ST_TANH = 1, ST_DTANH = 2, ST_ADD = 3 };
+
+// One dense layer for the block's 16 particles:
+//   v[p][u] = sum_k A[u][k] in[p][k] (+ bias[u]),  u < M, k < K,
+// then out[p][u] = v (ST_PLAIN), tanh(v) (ST_TANH), v (1 - aux[u]^2)
+// (ST_DTANH, aux the particle's tape of tanh outputs) or out += v (ST_ADD);
+// the stored value also goes to tape + toff when the particle has a tape.
+// Lane (pn = lane % 16, kq = lane / 16) gives B[kq][pn] = in[pn][4 c + kq].
+__device__ void mdense(const float *Ap, int M, int K, const float *bias, const float *in, int ins,
+                       float *out, int outs, int mode, const BlockLDS &S, int toff, int aoff,
+                       int wave, int lane) {
+  const int T = (M + 15) >> 4, C16 = (K + 15) >> 4;
+  const int pn = lane & 15, kq = lane >> 4;
+  const float *ip0 = in + pn * ins + kq;
+  float *tp = (toff >= 0 && S.tw[pn]) ? S.tw[pn] + toff : nullptr;
+  const float *ax = mode == ST_DTANH ? S.tr[pn] + aoff : nullptr;
+  for (int t = wave; t < T; t += NT / 64) {
+    v4f acc = {0.f, 0.f, 0.f, 0.f};
+    const float4 *ap = reinterpret_cast<const float4 *>(Ap) + (long long)t * C16 * 64 + lane;
+    for (int c = 0; c < C16; ++c) {
+      const float4 a = ap[c * 64];
+      const float *ip = ip0 + 16 * c;
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, ip[0], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, ip[4], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, ip[8], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, ip[12], acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int u = 16 * t + 4 * kq + i;
+      if (u >= M) continue;
+      float v = acc[i];
+      if (bias) v += bias[u];
+      if (mode == ST_TANH) {
+        v = tanhf(v);
+      } else if (mode == ST_DTANH) {
+        const float h = ax[u];
+        v *= 1.f - h * h;
+      }
+      if (mode == ST_ADD)
+        out[pn * outs + u] += v;
+      else
+        out[pn * outs + u] = v;
+      if (tp) tp[u] = v;
+    }
+  }
+}
+
+// Forward map of the block's particles (xs: latent z on entry, coupled x on
+// exit), with the move tape [h1 | h2 | s | x_T before the update] per layer;
+// returns the thread's partial sum of s (particle tid / 16).
+__device__ float forward_couplings(const FlowNet &F, const float *Ap, const float *bias,
+                                   BlockLDS &S, int wave, int lane, int tid) {
+  const int p = tid >> 4, r = tid & 15;
+  float ldp = 0.f;
   for (int l = 0; l < F.L; ++l) {
     const FlowLayerDesc &Y = F.ly[l];
-    float *t1[FP], *t2[FP], *ts[FP];
-#pragma unroll
-    for (int p = 0; p < FP; ++p) {
-      float *b = tape[p] ? tape[p] + (long long)l * F.tape_stride : nullptr;
-      t1[p] = b;
-      t2[p] = b ? b + FH : nullptr;
-      ts[p] = b ? b + 2 * FH : nullptr;
-    }
-    float acc[FP][2][2];
-    dense_fwd(Wt + Y.oW1, bias + Y.ob1, FH, Y.dc, &S.xs[0][Y.C0], MAXD, lane, acc);
-    store_units(acc, FH, true, &S.h1[0][0], FH, t1, lane);
+    const int lo = l * F.tape_stride;
+    mdense(Ap + Y.pW1, FH, Y.dc, bias + Y.ob1, &S.xs[0][Y.C0], XP, &S.h1[0][0], HP, ST_TANH, S,
+           lo, 0, wave, lane);
     __syncthreads();
-    dense_fwd(Wt + Y.oW2, bias + Y.ob2, FH, FH, &S.h1[0][0], FH, lane, acc);
-    store_units(acc, FH, true, &S.h2[0][0], FH, t2, lane);
+    mdense(Ap + Y.pW2, FH, FH, bias + Y.ob2, &S.h1[0][0], HP, &S.h2[0][0], HP, ST_TANH, S,
+           lo + FH, 0, wave, lane);
     __syncthreads();
-    dense_fwd(Wt + Y.oW3, bias + Y.ob3, 2 * Y.dt, FH, &S.h2[0][0], FH, lane, acc);
-    float *none[FP] = {nullptr, nullptr, nullptr, nullptr};
-    store_units(acc, 2 * Y.dt, false, &S.ob[0][0], MAXD, none, lane);
+    mdense(Ap + Y.pW3, 2 * Y.dt, FH, bias + Y.ob3, &S.h2[0][0], HP, &S.ob[0][0], XP, ST_PLAIN, S,
+           -1, 0, wave, lane);
     __syncthreads();
-    for (int f = lane; f < Y.dt; f += 64)
-#pragma unroll
-      for (int p = 0; p < FP; ++p) {
-        const float s = tanhf(S.ob[p][f]);
-        const float t = S.ob[p][Y.dt + f];
-        const float x = S.xs[p][Y.T0 + f];
-        if (ts[p]) {
-          ts[p][f] = s;
-          ts[p][F.half + f] = x;
-        }
-        S.xs[p][Y.T0 + f] = fmaf(x, expf(s), t);
-        ldl[p] += s;
+    float *tp = S.tw[p] ? S.tw[p] + lo + 2 * FH : nullptr;
+    for (int f = r; f < Y.dt; f += 16) {
+      const float s = tanhf(S.ob[p][f]);
+      const float t = S.ob[p][Y.dt + f];
+      const float x = S.xs[p][Y.T0 + f];
+      if (tp) {
+        tp[f] = s;
+        tp[F.half + f] = x;
       }
+      S.xs[p][Y.T0 + f] = fmaf(x, expf(s), t);
+      ldp += s;
+    }
     __syncthreads();
   }
+  return ldp;
 }
 
 // Cotangent of z from the cotangent of x after the couplings (in xs), by
 // reverse accumulation over the move tape; the log-determinant adds 1 to the
-// cotangent of every s.
-__device__ void vjp_couplings(const FlowNet &F, const uint16_t *W, FlowLDS &S,
-                              const float *const tape[FP], int lane) {
+// cotangent of every s.  Bp: the transposed weights, packed.
+__device__ void vjp_couplings(const FlowNet &F, const float *Bp, BlockLDS &S, int wave, int lane,
+                              int tid) {
+  const int p = tid >> 4, r = tid & 15;
   for (int l = F.L - 1; l >= 0; --l) {
     const FlowLayerDesc &Y = F.ly[l];
-    const float *t1[FP], *t2[FP], *ts[FP];
-#pragma unroll
-    for (int p = 0; p < FP; ++p) {
-      const float *b = tape[p] + (long long)l * F.tape_stride;
-      t1[p] = b;
-      t2[p] = b + FH;
-      ts[p] = b + 2 * FH;
-    }
-    for (int f = lane; f < Y.dt; f += 64)
-#pragma unroll
-      for (int p = 0; p < FP; ++p) {
-        const float s = ts[p][f], xT = ts[p][F.half + f];
-        const float gy = S.xs[p][Y.T0 + f];
-        const float es = expf(s);
-        const float gs = fmaf(gy * xT, es, 1.f);
-        S.ob[p][f] = gs * (1.f - s * s);
-        S.ob[p][Y.dt + f] = gy;
-        S.xs[p][Y.T0 + f] = gy * es;
-      }
-    __syncthreads();
-    float o[FP][2];
-    dense_bwd(W + Y.oW3, 2 * Y.dt, FH, &S.ob[0][0], MAXD, lane, o);
-#pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      const int k = lane + 64 * r;
-#pragma unroll
-      for (int p = 0; p < FP; ++p) {
-        const float h = t2[p][k];
-        S.h2[p][k] = o[p][r] * (1.f - h * h);
-      }
+    const int lo = l * F.tape_stride;
+    const float *ts = S.tr[p] + lo + 2 * FH;
+    for (int f = r; f < Y.dt; f += 16) {
+      const float s = ts[f], xT = ts[F.half + f];
+      const float gy = S.xs[p][Y.T0 + f];
+      const float es = expf(s);
+      S.ob[p][f] = fmaf(gy * xT, es, 1.f) * (1.f - s * s);
+      S.ob[p][Y.dt + f] = gy;
+      S.xs[p][Y.T0 + f] = gy * es;
     }
     __syncthreads();
-    dense_bwd(W + Y.oW2, FH, FH, &S.h2[0][0], FH, lane, o);
-#pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      const int k = lane + 64 * r;
-#pragma unroll
-      for (int p = 0; p < FP; ++p) {
-        const float h = t1[p][k];
-        S.h1[p][k] = o[p][r] * (1.f - h * h);
-      }
-    }
+    mdense(Bp + Y.qW3, FH, 2 * Y.dt, nullptr, &S.ob[0][0], XP, &S.h2[0][0], HP, ST_DTANH, S, -1,
+           lo + FH, wave, lane);
     __syncthreads();
-    dense_bwd(W + Y.oW1, FH, Y.dc, &S.h1[0][0], FH, lane, o);
-#pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      const int k = lane + 64 * r;
-      if (k < Y.dc)
-#pragma unroll
-        for (int p = 0; p < FP; ++p) S.xs[p][Y.C0 + k] += o[p][r];
-    }
+    mdense(Bp + Y.qW2, FH, FH, nullptr, &S.h2[0][0], HP, &S.h1[0][0], HP, ST_DTANH, S, -1, lo,
+           wave, lane);
+    __syncthreads();
+    mdense(Bp + Y.qW1, Y.dc, FH, nullptr, &S.h1[0][0], HP, &S.xs[0][Y.C0], XP, ST_ADD, S, -1, 0,
+           wave, lane);
     __syncthreads();
   }
 }
 
-__device__ __forceinline__ float lane_sum_to_float(float v) { return (float)wave_sum((double)v); }
+// Sum of the 16 partials of a particle (lanes 16 p .. 16 p + 15 of a wave), fixed order.
+__device__ __forceinline__ float sum16(float v) {
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, 16);
+  return v;
+}
+
+// Zero the pad columns of the LDS state rows.
+__device__ __forceinline__ void clear_rows(BlockLDS &S, int tid) {
+  for (int i = tid; i < PB * XP; i += NT) {
+    (&S.xs[0][0])[i] = 0.f;
+    (&S.ob[0][0])[i] = 0.f;
+  }
+}
 
 // ---------------------------------------------------------------------------
 // Initial couplings: W1, W2 from the Philox stream FLOW (layer l: iterations
@@ -289,10 +237,11 @@ __global__ void k_flow_init(Dev D, FlowNet F) {
 
 // ---------------------------------------------------------------------------
 // Adam ascent on the couplings (update != 0), then the copies the kernels
-// read: transposed FP32 weights (training forward), BF16 weights row-major and
-// transposed, BF16-rounded biases (moves).  The gradient is the ordered sum of
-// the KSPLIT particle-chunk partials.  Adam step t = (k - 1) ntrain + step + 1
-// - offset, k the iteration counter of the device state.
+// read: packed A-operand copies of every weight matrix and of its transpose,
+// FP32 (training) and bfloat16-rounded (moves), and the bfloat16-rounded
+// biases.  The gradient is the ordered sum of the KSPLIT particle-chunk
+// partials.  Adam step t = (k - 1) ntrain + step + 1 - offset, k the
+// iteration counter of the device state.
 // ---------------------------------------------------------------------------
 __global__ void k_flow_adam(Dev D, FlowNet F, int step, int update, const float *part) {
   const int t = (D.ps[0].k - 1) * F.ntrain + step + 1 - D.fstate[0];
@@ -309,28 +258,30 @@ __global__ void k_flow_adam(Dev D, FlowNet F, int step, int update, const float 
       pv = (float)((double)pv + (double)F.lr * (m / c1) / (sqrt(v / c2) + D.adam_eps));
       D.fp[i] = pv;
     }
-    const uint16_t hb = bf16_bits(pv);
+    const float hb = __uint_as_float((uint32_t)bf16_bits(pv) << 16);
     bool weight = false;
     for (int l = 0; l < F.L; ++l) {
       const FlowLayerDesc &Y = F.ly[l];
-      int o = -1, rows = 0, cols = 0;
+      int o = -1, rows = 0, cols = 0, pf = 0, pb = 0;
       if (i >= Y.oW1 && i < Y.ob1) {
-        o = Y.oW1, rows = FH, cols = Y.dc;
+        o = Y.oW1, rows = FH, cols = Y.dc, pf = Y.pW1, pb = Y.qW1;
       } else if (i >= Y.oW2 && i < Y.ob2) {
-        o = Y.oW2, rows = FH, cols = FH;
+        o = Y.oW2, rows = FH, cols = FH, pf = Y.pW2, pb = Y.qW2;
       } else if (i >= Y.oW3 && i < Y.ob3) {
-        o = Y.oW3, rows = 2 * Y.dt, cols = FH;
+        o = Y.oW3, rows = 2 * Y.dt, cols = FH, pf = Y.pW3, pb = Y.qW3;
       }
       if (o >= 0) {
         const int u = (i - o) / cols, k = (i - o) % cols;
-        const int ti = o + k * rows + u;
-        D.fpt[ti] = pv;
-        D.fwbt[ti] = hb;
+        const int fi = pf + pk_index(u, k, (cols + 15) / 16 * 16);
+        const int bi = pb + pk_index(k, u, (rows + 15) / 16 * 16);
+        D.fpk[fi] = pv;
+        D.fbk[fi] = hb;
+        D.fpk[bi] = pv;
+        D.fbk[bi] = hb;
         weight = true;
       }
     }
-    D.fwb[i] = hb;
-    D.fbias[i] = weight ? 0.f : __uint_as_float((uint32_t)hb << 16);
+    D.fbias[i] = weight ? 0.f : hb;
   }
 }
 
@@ -358,144 +309,96 @@ __global__ void k_flow_base(Dev D, FlowNet F) {
 //   sum_j W_j [log N(z_j; 0, I) + log|det J_{T^-1}(theta_j)|],
 // W the normalised weights (uniform right after resampling).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void k_flow_train(Dev D, FlowNet F) {
-  __shared__ FlowLDS S;
-  const int lane = threadIdx.x;
-  const int j0 = blockIdx.x * FP;
+__global__ __launch_bounds__(NT) void k_flow_train(Dev D, FlowNet F) {
+  __shared__ BlockLDS S;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int p = tid >> 4, r = tid & 15;
+  const int j0 = blockIdx.x * PB;
   const PState &PS = D.ps[0];
   const int rs = PS.resampled;
   const float *src = rs ? D.theta_t : D.theta;
-  float wj[FP];
-  float *rec[FP];
-#pragma unroll
-  for (int p = 0; p < FP; ++p) {
-    const int j = j0 + p;
+  if (tid < PB) {
+    const int j = j0 + tid;
     const bool ok = j < D.J;
     double w = 0.0;
     if (ok) {
       const double lw = D.logw[j];
       w = rs ? 1.0 / D.J : ((lw == lw && lw > -INFINITY) ? exp(lw - PS.m) / PS.S : 0.0);
     }
-    wj[p] = (float)w;
-    rec[p] = ok ? D.ftape + (long long)j * F.L * F.train_stride : nullptr;
-    for (int c = lane; c < MAXD; c += 64) {
-      if (c < F.d)
-        S.xs[p][xpos(c, F.d)] = ok ? (src[(long long)j * D.DS + c] - D.fm[c]) * expf(-D.fa[c]) : 0.f;
-      else
-        S.xs[p][c] = 0.f;
-    }
+    S.wj[tid] = (float)w;
+    S.rows[tid] = ok ? j : -1;
+    float *rec = D.ftape + (long long)(ok ? j : j0) * F.L * F.train_stride;
+    S.tw[tid] = ok ? rec : nullptr;
+    S.tr[tid] = rec;
+  }
+  clear_rows(S, tid);
+  __syncthreads();
+  for (int i = tid; i < PB * F.d; i += NT) {
+    const int q = i / F.d, c = i % F.d;
+    const int j = S.rows[q];
+    S.xs[q][xpos(c, F.d)] = j >= 0 ? (src[(long long)j * D.DS + c] - D.fm[c]) * expf(-D.fa[c]) : 0.f;
   }
   __syncthreads();
-  const float *Wt = D.fpt, *W = D.fp;
-  const int h = F.half;
+  const float *W = D.fp;
+  const int h = F.half, TS = F.train_stride;
   // inverse couplings, last layer first
   for (int l = F.L - 1; l >= 0; --l) {
     const FlowLayerDesc &Y = F.ly[l];
-    float *r[FP];
-#pragma unroll
-    for (int p = 0; p < FP; ++p) r[p] = rec[p] ? rec[p] + (long long)l * F.train_stride : nullptr;
-    for (int c = lane; c < Y.dc; c += 64)
-#pragma unroll
-      for (int p = 0; p < FP; ++p)
-        if (r[p]) r[p][c] = S.xs[p][Y.C0 + c];
-    float acc[FP][2][2];
-    float *t1[FP], *t2[FP];
-#pragma unroll
-    for (int p = 0; p < FP; ++p) {
-      t1[p] = r[p] ? r[p] + h : nullptr;
-      t2[p] = r[p] ? r[p] + h + FH : nullptr;
-    }
-    dense_fwd(Wt + Y.oW1, W + Y.ob1, FH, Y.dc, &S.xs[0][Y.C0], MAXD, lane, acc);
-    store_units(acc, FH, true, &S.h1[0][0], FH, t1, lane);
+    const int lo = l * TS;
+    if (S.tw[p])
+      for (int c = r; c < Y.dc; c += 16) S.tw[p][lo + c] = S.xs[p][Y.C0 + c];
+    mdense(D.fpk + Y.pW1, FH, Y.dc, W + Y.ob1, &S.xs[0][Y.C0], XP, &S.h1[0][0], HP, ST_TANH, S,
+           lo + h, 0, wave, lane);
     __syncthreads();
-    dense_fwd(Wt + Y.oW2, W + Y.ob2, FH, FH, &S.h1[0][0], FH, lane, acc);
-    store_units(acc, FH, true, &S.h2[0][0], FH, t2, lane);
+    mdense(D.fpk + Y.pW2, FH, FH, W + Y.ob2, &S.h1[0][0], HP, &S.h2[0][0], HP, ST_TANH, S,
+           lo + h + FH, 0, wave, lane);
     __syncthreads();
-    dense_fwd(Wt + Y.oW3, W + Y.ob3, 2 * Y.dt, FH, &S.h2[0][0], FH, lane, acc);
-    float *none[FP] = {nullptr, nullptr, nullptr, nullptr};
-    store_units(acc, 2 * Y.dt, false, &S.ob[0][0], MAXD, none, lane);
+    mdense(D.fpk + Y.pW3, 2 * Y.dt, FH, W + Y.ob3, &S.h2[0][0], HP, &S.ob[0][0], XP, ST_PLAIN, S,
+           -1, 0, wave, lane);
     __syncthreads();
-    for (int f = lane; f < Y.dt; f += 64)
-#pragma unroll
-      for (int p = 0; p < FP; ++p) {
-        const float s = tanhf(S.ob[p][f]);
-        const float t = S.ob[p][Y.dt + f];
-        const float x = (S.xs[p][Y.T0 + f] - t) * expf(-s);
-        S.xs[p][Y.T0 + f] = x;
-        if (r[p]) {
-          r[p][h + 2 * FH + f] = s;
-          r[p][2 * h + 2 * FH + f] = x;
-        }
+    for (int f = r; f < Y.dt; f += 16) {
+      const float s = tanhf(S.ob[p][f]);
+      const float t = S.ob[p][Y.dt + f];
+      const float x = (S.xs[p][Y.T0 + f] - t) * expf(-s);
+      S.xs[p][Y.T0 + f] = x;
+      if (S.tw[p]) {
+        S.tw[p][lo + h + 2 * FH + f] = s;
+        S.tw[p][lo + 2 * h + 2 * FH + f] = x;
       }
+    }
     __syncthreads();
   }
   // cotangent of z: -W_j z
-  for (int c = lane; c < MAXD; c += 64)
-#pragma unroll
-    for (int p = 0; p < FP; ++p) S.xs[p][c] = -wj[p] * S.xs[p][c];
+  for (int c = r; c < MAXD; c += 16) S.xs[p][c] = -S.wj[p] * S.xs[p][c];
   __syncthreads();
   // reverse of the inverse order: layer 0 first
   for (int l = 0; l < F.L; ++l) {
     const FlowLayerDesc &Y = F.ly[l];
-    float *r[FP];
-#pragma unroll
-    for (int p = 0; p < FP; ++p) r[p] = rec[p] ? rec[p] + (long long)l * F.train_stride : nullptr;
-    for (int f = lane; f < Y.dt; f += 64)
-#pragma unroll
-      for (int p = 0; p < FP; ++p) {
-        float s = 0.f, xT = 0.f;
-        if (r[p]) {
-          s = r[p][h + 2 * FH + f];
-          xT = r[p][2 * h + 2 * FH + f];
-        }
-        const float gx = S.xs[p][Y.T0 + f];
-        const float es = expf(-s);
-        const float gs = -gx * xT - wj[p];
-        const float d3s = gs * (1.f - s * s), d3t = -gx * es;
-        S.ob[p][f] = d3s;
-        S.ob[p][Y.dt + f] = d3t;
-        S.xs[p][Y.T0 + f] = gx * es;
-        if (r[p]) {
-          r[p][3 * h + 2 * FH + f] = d3s;
-          r[p][3 * h + 2 * FH + Y.dt + f] = d3t;
-        }
-      }
-    __syncthreads();
-    float o[FP][2];
-    dense_bwd(W + Y.oW3, 2 * Y.dt, FH, &S.ob[0][0], MAXD, lane, o);
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int k = lane + 64 * q;
-#pragma unroll
-      for (int p = 0; p < FP; ++p) {
-        const float hh = r[p] ? r[p][h + FH + k] : 0.f;
-        const float v = o[p][q] * (1.f - hh * hh);
-        S.h2[p][k] = v;
-        if (r[p]) r[p][5 * h + 2 * FH + k] = v;
+    const int lo = l * TS;
+    const float *rr = S.tr[p] + lo;
+    for (int f = r; f < Y.dt; f += 16) {
+      const float s = rr[h + 2 * FH + f], xT = rr[2 * h + 2 * FH + f];
+      const float gx = S.xs[p][Y.T0 + f];
+      const float es = expf(-s);
+      const float gs = -gx * xT - S.wj[p];
+      const float d3s = gs * (1.f - s * s), d3t = -gx * es;
+      S.ob[p][f] = d3s;
+      S.ob[p][Y.dt + f] = d3t;
+      S.xs[p][Y.T0 + f] = gx * es;
+      if (S.tw[p]) {
+        S.tw[p][lo + 3 * h + 2 * FH + f] = d3s;
+        S.tw[p][lo + 3 * h + 2 * FH + Y.dt + f] = d3t;
       }
     }
     __syncthreads();
-    dense_bwd(W + Y.oW2, FH, FH, &S.h2[0][0], FH, lane, o);
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int k = lane + 64 * q;
-#pragma unroll
-      for (int p = 0; p < FP; ++p) {
-        const float hh = r[p] ? r[p][h + k] : 0.f;
-        const float v = o[p][q] * (1.f - hh * hh);
-        S.h1[p][k] = v;
-        if (r[p]) r[p][5 * h + 3 * FH + k] = v;
-      }
-    }
+    mdense(D.fpk + Y.qW3, FH, 2 * Y.dt, nullptr, &S.ob[0][0], XP, &S.h2[0][0], HP, ST_DTANH, S,
+           lo + 5 * h + 2 * FH, lo + h + FH, wave, lane);
     __syncthreads();
-    dense_bwd(W + Y.oW1, FH, Y.dc, &S.h1[0][0], FH, lane, o);
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int k = lane + 64 * q;
-      if (k < Y.dc)
-#pragma unroll
-        for (int p = 0; p < FP; ++p) S.xs[p][Y.C0 + k] += o[p][q];
-    }
+    mdense(D.fpk + Y.qW2, FH, FH, nullptr, &S.h2[0][0], HP, &S.h1[0][0], HP, ST_DTANH, S,
+           lo + 5 * h + 3 * FH, lo + h, wave, lane);
+    __syncthreads();
+    mdense(D.fpk + Y.qW1, Y.dc, FH, nullptr, &S.h1[0][0], HP, &S.xs[0][Y.C0], XP, ST_ADD, S, -1, 0,
+           wave, lane);
     __syncthreads();
   }
 }
@@ -596,203 +499,162 @@ __global__ __launch_bounds__(256) void k_flow_wgrad(Dev D, FlowNet F, float *par
 }
 
 // ---------------------------------------------------------------------------
-// Start of the moves: z0 = T^-1(theta0) (BF16 weights), log|det J_T(z0)|,
-// then the forward map from z0 with the move tape and the latent gradient
-// grad_z log pi_z(z0) from the cached gradient of log pi at theta0; the
-// initial energy gets -log|det J_T(z0)|.
+// Start of the moves: z0 = T^-1(theta0) (BF16 weights) and log|det J_T(z0)|;
+// the initial energy gets -log|det J_T(z0)|.  The latent gradient at z0
+// follows from the forward pass with its tape and the backward pass on the
+// cached gradient of log pi at theta0 (k_flow_drift / k_flow_kick, init).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void k_flow_begin(Dev D, FlowNet F) {
-  __shared__ FlowLDS S;
-  const int lane = threadIdx.x;
-  const int j0 = blockIdx.x * FP;
-  float *tape[FP];        // written by the forward pass (valid particles only)
-  const float *rtape[FP]; // read by the backward pass
-  float ldl[FP];
-#pragma unroll
-  for (int p = 0; p < FP; ++p) {
-    const int j = j0 + p;
-    const bool ok = j < D.J;
-    tape[p] = ok ? D.ftape + (long long)j * F.L * F.tape_stride : nullptr;
-    rtape[p] = D.ftape + (long long)(ok ? j : j0) * F.L * F.tape_stride;
-    ldl[p] = 0.f;
-    for (int c = lane; c < MAXD; c += 64) {
-      if (c < F.d) {
-        float x = 0.f;
-        if (ok) {
-          x = (D.theta_t[(long long)j * D.DS + c] - D.fm[c]) * expf(-D.fa[c]);
-          ldl[p] -= D.fa[c];
-        }
-        S.xs[p][xpos(c, F.d)] = x;
-      } else {
-        S.xs[p][c] = 0.f;
-      }
-    }
+__global__ __launch_bounds__(NT) void k_flow_inverse(Dev D, FlowNet F) {
+  __shared__ BlockLDS S;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int p = tid >> 4, r = tid & 15;
+  const int j0 = blockIdx.x * PB;
+  if (tid < PB) {
+    const int j = j0 + tid;
+    S.rows[tid] = j < D.J ? j : -1;
+    S.tw[tid] = nullptr;
+    S.tr[tid] = nullptr;
+  }
+  clear_rows(S, tid);
+  __syncthreads();
+  for (int i = tid; i < PB * F.d; i += NT) {
+    const int q = i / F.d, c = i % F.d;
+    const int j = S.rows[q];
+    S.xs[q][xpos(c, F.d)] =
+        j >= 0 ? (D.theta_t[(long long)j * D.DS + c] - D.fm[c]) * expf(-D.fa[c]) : 0.f;
   }
   __syncthreads();
-  // inverse couplings (BF16 weights), last layer first
+  float ldp = 0.f;
+  for (int c = r; c < F.d; c += 16) ldp -= D.fa[c];
   for (int l = F.L - 1; l >= 0; --l) {
     const FlowLayerDesc &Y = F.ly[l];
-    float acc[FP][2][2];
-    float *none[FP] = {nullptr, nullptr, nullptr, nullptr};
-    dense_fwd(D.fwbt + Y.oW1, D.fbias + Y.ob1, FH, Y.dc, &S.xs[0][Y.C0], MAXD, lane, acc);
-    store_units(acc, FH, true, &S.h1[0][0], FH, none, lane);
+    mdense(D.fbk + Y.pW1, FH, Y.dc, D.fbias + Y.ob1, &S.xs[0][Y.C0], XP, &S.h1[0][0], HP, ST_TANH,
+           S, -1, 0, wave, lane);
     __syncthreads();
-    dense_fwd(D.fwbt + Y.oW2, D.fbias + Y.ob2, FH, FH, &S.h1[0][0], FH, lane, acc);
-    store_units(acc, FH, true, &S.h2[0][0], FH, none, lane);
+    mdense(D.fbk + Y.pW2, FH, FH, D.fbias + Y.ob2, &S.h1[0][0], HP, &S.h2[0][0], HP, ST_TANH, S,
+           -1, 0, wave, lane);
     __syncthreads();
-    dense_fwd(D.fwbt + Y.oW3, D.fbias + Y.ob3, 2 * Y.dt, FH, &S.h2[0][0], FH, lane, acc);
-    store_units(acc, 2 * Y.dt, false, &S.ob[0][0], MAXD, none, lane);
+    mdense(D.fbk + Y.pW3, 2 * Y.dt, FH, D.fbias + Y.ob3, &S.h2[0][0], HP, &S.ob[0][0], XP,
+           ST_PLAIN, S, -1, 0, wave, lane);
     __syncthreads();
-    for (int f = lane; f < Y.dt; f += 64)
-#pragma unroll
-      for (int p = 0; p < FP; ++p) {
-        const float s = tanhf(S.ob[p][f]);
-        S.xs[p][Y.T0 + f] = (S.xs[p][Y.T0 + f] - S.ob[p][Y.dt + f]) * expf(-s);
-        ldl[p] -= s;
-      }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int p = 0; p < FP; ++p) {
-    const int j = j0 + p;
-    const float ld0 = -lane_sum_to_float(ldl[p]);   // log|det J_T(z0)|
-    if (j < D.J) {
-      for (int c = lane; c < D.DS; c += 64) {
-        const float z = c < F.d ? S.xs[p][c] : 0.f;
-        D.fz[(long long)j * D.DS + c] = z;
-        D.fz0[(long long)j * D.DS + c] = z;
-      }
-      if (lane == 0) {
-        D.fld0[j] = ld0;
-        D.H0[j] -= (double)ld0;
-      }
+    for (int f = r; f < Y.dt; f += 16) {
+      const float s = tanhf(S.ob[p][f]);
+      S.xs[p][Y.T0 + f] = (S.xs[p][Y.T0 + f] - S.ob[p][Y.dt + f]) * expf(-s);
+      ldp -= s;
     }
-    ldl[p] = 0.f;
+    __syncthreads();
   }
-  __syncthreads();
-  forward_couplings(F, D.fwbt, D.fbias, S, tape, ldl, lane);
-  // cotangent of x: g_theta * exp(a), then back through the couplings
-#pragma unroll
-  for (int p = 0; p < FP; ++p) {
-    const int j = j0 + p;
-    for (int c = lane; c < MAXD; c += 64) {
-      if (c < F.d)
-        S.xs[p][xpos(c, F.d)] = j < D.J ? D.grad_t[(long long)j * D.DS + c] * expf(D.fa[c]) : 0.f;
-      else
-        S.xs[p][c] = 0.f;
+  const float ld0 = -sum16(ldp);   // log|det J_T(z0)|
+  const int j = S.rows[p];
+  if (j >= 0) {
+    for (int c = r; c < D.DS; c += 16) {
+      const float z = c < F.d ? S.xs[p][c] : 0.f;
+      D.fz[(long long)j * D.DS + c] = z;
+      D.fz0[(long long)j * D.DS + c] = z;
     }
-  }
-  __syncthreads();
-  vjp_couplings(F, D.fwb, S, rtape, lane);
-#pragma unroll
-  for (int p = 0; p < FP; ++p) {
-    const int j = j0 + p;
-    if (j < D.J)
-      for (int c = lane; c < D.DS; c += 64)
-        D.fgz[(long long)j * D.DS + c] = c < F.d ? S.xs[p][c] : 0.f;
+    if (r == 0) {
+      D.fld0[j] = ld0;
+      D.H0[j] -= (double)ld0;
+    }
   }
 }
 
-// Particles of a move launch: FP consecutive slots of the trajectory-length
-// order (longest first), active while n > step.
-__device__ __forceinline__ int move_rows(const Dev &D, int step, int rows[FP]) {
-  int any = 0;
-#pragma unroll
-  for (int p = 0; p < FP; ++p) {
-    const int slot = blockIdx.x * FP + p;
+// Particles of a move launch: 16 consecutive slots of the trajectory-length
+// order (longest first), active while n > step; init: every particle, in
+// index order.  Returns whether any is active (the same in every thread).
+__device__ __forceinline__ bool move_rows(const Dev &D, const FlowNet &F, BlockLDS &S, int step,
+                                          int init, int tid) {
+  int act = 0;
+  if (tid < PB) {
+    const int slot = blockIdx.x * PB + tid;
     int r = -1;
     if (slot < D.J) {
-      const int j = D.perm[slot];
-      if (j < D.J && D.n[j] > step) r = j;
+      const int j = init ? slot : D.perm[slot];
+      if (j < D.J && (init || D.n[j] > step)) r = j;
     }
-    rows[p] = r;
-    any |= r >= 0;
+    S.rows[tid] = r;
+    act = r >= 0;
   }
-  return any;
+  const bool any = __syncthreads_or(act);
+  if (!any) return false;
+  if (tid < PB) {
+    int first = 0;
+    for (int q = PB - 1; q >= 0; --q)
+      if (S.rows[q] >= 0) first = S.rows[q];
+    const int r = S.rows[tid];
+    S.tw[tid] = r >= 0 ? D.ftape + (long long)r * F.L * F.tape_stride : nullptr;
+    S.tr[tid] = D.ftape + (long long)(r >= 0 ? r : first) * F.L * F.tape_stride;
+  }
+  clear_rows(S, tid);
+  __syncthreads();
+  return true;
 }
 
 // Leapfrog step `step`, first half: p += eps/2 g_z; z += eps p; theta = T(z)
 // (BF16 weights) with the move tape and log|det J_T(z)|.  The likelihood
 // gradient at theta follows (k_lf_partial / k_lf_reduce in gradient mode).
-__global__ __launch_bounds__(64) void k_flow_drift(Dev D, FlowNet F, int step) {
-  __shared__ FlowLDS S;
-  int rows[FP];
-  if (!move_rows(D, step, rows)) return;
-  const int lane = threadIdx.x;
+// init: only the forward pass from z0, for the tape of the latent gradient.
+__global__ __launch_bounds__(NT) void k_flow_drift(Dev D, FlowNet F, int step, int init) {
+  __shared__ BlockLDS S;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int p = tid >> 4, r = tid & 15;
+  if (!move_rows(D, F, S, step, init, tid)) return;
   const float eps = (float)D.ps[0].eps;
   const float he = 0.5f * eps;
-  float *tape[FP];
-  float ldl[FP];
-#pragma unroll
-  for (int p = 0; p < FP; ++p) {
-    const int j = rows[p] >= 0 ? rows[p] : rows[0] >= 0 ? rows[0] : 0;
-    tape[p] = rows[p] >= 0 ? D.ftape + (long long)j * F.L * F.tape_stride : nullptr;
-    ldl[p] = 0.f;
-    for (int c = lane; c < MAXD; c += 64) {
-      float z = 0.f;
-      if (rows[p] >= 0 && c < D.DS) {
-        const long long e = (long long)rows[p] * D.DS + c;
-        const float ph = fmaf(he, D.fgz[e], D.p_t[e]);
-        z = fmaf(eps, ph, D.fz[e]);
-        if (c >= F.d) z = 0.f;
-        D.p_t[e] = c < F.d ? ph : 0.f;
-        D.fz[e] = z;
-      }
-      S.xs[p][c] = z;
+  for (int i = tid; i < PB * D.DS; i += NT) {
+    const int q = i / D.DS, c = i % D.DS;
+    const int j = S.rows[q];
+    if (j < 0 || c >= F.d) continue;
+    const long long e = (long long)j * D.DS + c;
+    float z;
+    if (init) {
+      z = D.fz[e];
+    } else {
+      const float ph = fmaf(he, D.fgz[e], D.p_t[e]);
+      z = fmaf(eps, ph, D.fz[e]);
+      D.p_t[e] = ph;
+      D.fz[e] = z;
     }
+    S.xs[q][c] = z;
   }
   __syncthreads();
-  forward_couplings(F, D.fwbt, D.fbias, S, tape, ldl, lane);
-#pragma unroll
-  for (int p = 0; p < FP; ++p) {
-    float sa = 0.f;
-    for (int c = lane; c < F.d; c += 64) sa += D.fa[c];
-    const float ld = lane_sum_to_float(ldl[p] + sa);
-    if (rows[p] >= 0) {
-      for (int c = lane; c < D.DS; c += 64)
-        D.theta_t[(long long)rows[p] * D.DS + c] =
-            c < F.d ? fmaf(expf(D.fa[c]), S.xs[p][xpos(c, F.d)], D.fm[c]) : 0.f;
-      if (lane == 0) D.fld1[rows[p]] = ld;
-    }
+  float ldp = forward_couplings(F, D.fbk, D.fbias, S, wave, lane, tid);
+  if (init) return;
+  for (int c = r; c < F.d; c += 16) ldp += D.fa[c];
+  const float ld = sum16(ldp);
+  const int j = S.rows[p];
+  if (j >= 0) {
+    for (int c = r; c < D.DS; c += 16)
+      D.theta_t[(long long)j * D.DS + c] =
+          c < F.d ? fmaf(expf(D.fa[c]), S.xs[p][xpos(c, F.d)], D.fm[c]) : 0.f;
+    if (r == 0) D.fld1[j] = ld;
   }
 }
 
 // Leapfrog step `step`, second half: g_z = J_T^T grad log pi(theta) +
-// grad log|det J_T| from the move tape; p += eps/2 g_z.
-__global__ __launch_bounds__(64) void k_flow_kick(Dev D, FlowNet F, int step) {
-  __shared__ FlowLDS S;
-  int rows[FP];
-  if (!move_rows(D, step, rows)) return;
-  const int lane = threadIdx.x;
+// grad log|det J_T| from the move tape; p += eps/2 g_z.  init: the latent
+// gradient at z0 from the cached gradient at theta0, no kick.
+__global__ __launch_bounds__(NT) void k_flow_kick(Dev D, FlowNet F, int step, int init) {
+  __shared__ BlockLDS S;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (!move_rows(D, F, S, step, init, tid)) return;
   const float he = 0.5f * (float)D.ps[0].eps;
-  const float *tape[FP];
-  int first = 0;
-#pragma unroll
-  for (int p = FP - 1; p >= 0; --p)
-    if (rows[p] >= 0) first = rows[p];
-#pragma unroll
-  for (int p = 0; p < FP; ++p) {
-    const int j = rows[p] >= 0 ? rows[p] : first;
-    tape[p] = D.ftape + (long long)j * F.L * F.tape_stride;
-    for (int c = lane; c < MAXD; c += 64) {
-      if (c < F.d)
-        S.xs[p][xpos(c, F.d)] =
-            rows[p] >= 0 ? D.grad_t[(long long)rows[p] * D.DS + c] * expf(D.fa[c]) : 0.f;
-      else
-        S.xs[p][c] = 0.f;
-    }
+  for (int i = tid; i < PB * F.d; i += NT) {
+    const int q = i / F.d, c = i % F.d;
+    const int j = S.rows[q];
+    S.xs[q][xpos(c, F.d)] = j >= 0 ? D.grad_t[(long long)j * D.DS + c] * expf(D.fa[c]) : 0.f;
   }
   __syncthreads();
-  vjp_couplings(F, D.fwb, S, tape, lane);
-#pragma unroll
-  for (int p = 0; p < FP; ++p)
-    if (rows[p] >= 0)
-      for (int c = lane; c < F.d; c += 64) {
-        const long long e = (long long)rows[p] * D.DS + c;
-        const float g = S.xs[p][c];
-        D.fgz[e] = g;
-        D.p_t[e] = fmaf(he, g, D.p_t[e]);
-      }
+  vjp_couplings(F, D.fbk, S, wave, lane, tid);
+  for (int i = tid; i < PB * F.d; i += NT) {
+    const int q = i / F.d, c = i % F.d;
+    const int j = S.rows[q];
+    if (j < 0) continue;
+    const long long e = (long long)j * D.DS + c;
+    const float g = S.xs[q][c];
+    D.fgz[e] = g;
+    if (!init) D.p_t[e] = fmaf(he, g, D.p_t[e]);
+  }
 }
 
 // New parameters from the caller: restart the Adam moments, and count Adam
@@ -813,6 +675,7 @@ __global__ void k_flow_gradsum(FlowNet F, const float *part, float *out) {
     out[i] = (float)g;
   }
 }
+
 
 }  // namespace
 
@@ -844,8 +707,7 @@ hipError_t launch_flow_base(const Dev &D, const FlowNet &F, hipStream_t st) {
 }
 
 hipError_t launch_flow_train(const Dev &D, const FlowNet &F, int step, hipStream_t st) {
-  const int blocks = (D.J + FP - 1) / FP;
-  hipLaunchKernelGGL(k_flow_train, dim3(blocks), dim3(64), 0, st, D, F);
+  hipLaunchKernelGGL(k_flow_train, dim3((D.J + PB - 1) / PB), dim3(NT), 0, st, D, F);
   int nb = 0;
   for (int l = 0; l < F.L; ++l) {
     const FlowLayerDesc &Y = F.ly[l];
@@ -859,17 +721,20 @@ hipError_t launch_flow_train(const Dev &D, const FlowNet &F, int step, hipStream
 }
 
 hipError_t launch_flow_begin(const Dev &D, const FlowNet &F, hipStream_t st) {
-  hipLaunchKernelGGL(k_flow_begin, dim3((D.J + FP - 1) / FP), dim3(64), 0, st, D, F);
+  const dim3 grid((D.J + PB - 1) / PB);
+  hipLaunchKernelGGL(k_flow_inverse, grid, dim3(NT), 0, st, D, F);
+  hipLaunchKernelGGL(k_flow_drift, grid, dim3(NT), 0, st, D, F, 0, 1);
+  hipLaunchKernelGGL(k_flow_kick, grid, dim3(NT), 0, st, D, F, 0, 1);
   return hipGetLastError();
 }
 
 hipError_t launch_flow_drift(const Dev &D, const FlowNet &F, int step, hipStream_t st) {
-  hipLaunchKernelGGL(k_flow_drift, dim3((D.J + FP - 1) / FP), dim3(64), 0, st, D, F, step);
+  hipLaunchKernelGGL(k_flow_drift, dim3((D.J + PB - 1) / PB), dim3(NT), 0, st, D, F, step, 0);
   return hipGetLastError();
 }
 
 hipError_t launch_flow_kick(const Dev &D, const FlowNet &F, int step, hipStream_t st) {
-  hipLaunchKernelGGL(k_flow_kick, dim3((D.J + FP - 1) / FP), dim3(64), 0, st, D, F, step);
+  hipLaunchKernelGGL(k_flow_kick, dim3((D.J + PB - 1) / PB), dim3(NT), 0, st, D, F, step, 0);
   return hipGetLastError();
 }
 

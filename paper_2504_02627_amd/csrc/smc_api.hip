@@ -62,7 +62,7 @@ struct Layout {
   size_t o_items, o_colpart, o_means, o_minv, o_primes;
   FlowNet F;
   size_t o_fz = 0, o_fz0 = 0, o_fgz = 0, o_fld0 = 0, o_fld1 = 0, o_fm = 0, o_fa = 0;
-  size_t o_fp = 0, o_fpt = 0, o_fwb = 0, o_fwbt = 0, o_fbias = 0, o_fgrad = 0, o_fadm = 0,
+  size_t o_fp = 0, o_fpk = 0, o_fbk = 0, o_fbias = 0, o_fgrad = 0, o_fadm = 0,
          o_fadv = 0, o_ftape = 0, o_fstate = 0;
 };
 
@@ -90,6 +90,18 @@ bool flow_net(int d, int layers, int width, FlowNet &F) {
     Y.ob3 = o, o += 2 * Y.dt;
     half = std::max(half, std::max(Y.dt, Y.dc));
   }
+  auto c16 = [](int v) { return (v + 15) / 16 * 16; };
+  int q = 0;
+  for (int l = 0; l < layers; ++l) {
+    FlowLayerDesc &Y = F.ly[l];
+    Y.pW1 = q, q += FH * c16(Y.dc);
+    Y.pW2 = q, q += FH * FH;
+    Y.pW3 = q, q += c16(2 * Y.dt) * FH;
+    Y.qW1 = q, q += c16(Y.dc) * FH;
+    Y.qW2 = q, q += FH * FH;
+    Y.qW3 = q, q += FH * c16(2 * Y.dt);
+  }
+  F.npacked = q;
   F.half = (half + 1) / 2 * 2;
   F.tape_stride = 2 * FH + 2 * F.half;
   F.train_stride = 5 * F.half + 4 * FH;
@@ -263,9 +275,8 @@ void plan(const smc_problem *pr, const smc_params *pa, Layout &L) {
     L.o_fm = take(c, (size_t)L.DS * 4);
     L.o_fa = take(c, (size_t)L.DS * 4);
     L.o_fp = take(c, np * 4);
-    L.o_fpt = take(c, np * 4);
-    L.o_fwb = take(c, np * 2);
-    L.o_fwbt = take(c, np * 2);
+    L.o_fpk = take(c, (size_t)L.F.npacked * 4);
+    L.o_fbk = take(c, (size_t)L.F.npacked * 4);
     L.o_fbias = take(c, np * 4);
     L.o_fgrad = take(c, (size_t)FKSPLIT * np * 4);
     L.o_fadm = take(c, np * 4);
@@ -425,9 +436,8 @@ smc_status smc_init(const smc_problem *prob, const smc_params *par, void *worksp
     D.fm = (float *)(w + L.o_fm);
     D.fa = (float *)(w + L.o_fa);
     D.fp = (float *)(w + L.o_fp);
-    D.fpt = (float *)(w + L.o_fpt);
-    D.fwb = (uint16_t *)(w + L.o_fwb);
-    D.fwbt = (uint16_t *)(w + L.o_fwbt);
+    D.fpk = (float *)(w + L.o_fpk);
+    D.fbk = (float *)(w + L.o_fbk);
     D.fbias = (float *)(w + L.o_fbias);
     D.fgrad = (float *)(w + L.o_fgrad);
     D.fadm = (float *)(w + L.o_fadm);

@@ -27,7 +27,6 @@ constexpr uint32_t STREAM_INIT = 1, STREAM_MOMENTUM = 2, STREAM_MH = 3, STREAM_R
 // of width FH; FP particles per wave in the flow kernels.
 constexpr int FH = 128;
 constexpr int FMAXL = 8;
-constexpr int FP = 4;
 constexpr int FKSPLIT = 8;  // particle chunks of the flow parameter-gradient reduction
 
 // One coupling layer: transformed coordinates [T0, T0 + dt), conditioning
@@ -36,6 +35,9 @@ constexpr int FKSPLIT = 8;  // particle chunks of the flow parameter-gradient re
 struct FlowLayerDesc {
   int T0, C0, dt, dc;
   int oW1, ob1, oW2, ob2, oW3, ob3;
+  // packed A-operand copies (16 x 16 granules) of W1, W2, W3 and of their
+  // transposes, offsets into the packed arrays
+  int pW1, pW2, pW3, qW1, qW2, qW3;
 };
 
 struct FlowNet {
@@ -45,6 +47,7 @@ struct FlowNet {
   int tape_stride;        // floats per particle and layer of the move tape
   int train_stride;       // floats per particle and layer of the training record
   int nparams;            // length of the flat parameter vector
+  int npacked;            // length of a packed weight array
   int ntrain;             // Adam steps per iteration
   float lr;               // Adam learning rate
   FlowLayerDesc ly[FMAXL];
@@ -124,8 +127,8 @@ struct Dev {                    // pointers carved from the workspace
   float *fz, *fz0, *fgz;        // latent position, pre-move latent, latent gradient [Jcap][DS]
   float *fld0, *fld1;           // log|det J_T| at z0 and at the current z [Jcap]
   float *fm, *fa;               // standardisation theta = m + exp(a) x  [DS]
-  float *fp, *fpt;              // FP32 parameters (flat) and transposed weight copies
-  uint16_t *fwb, *fwbt;         // BF16 weights for the moves, row-major and transposed
+  float *fp;                    // FP32 parameters (flat)
+  float *fpk, *fbk;             // packed weights (and transposes): FP32, bfloat16-rounded
   float *fbias;                 // BF16-rounded biases (flat offsets)
   float *fgrad, *fadm, *fadv;   // parameter gradient and Adam moments
   float *ftape;                 // per particle and layer activations
