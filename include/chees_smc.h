@@ -208,14 +208,18 @@ smc_status smc_run(smc_ctx *ctx, int32_t iterations);
  * odd l (the last ones), d_C = d - d_T: W1 [width][d_C], b1 [width],
  * W2 [width][width], b2 [width], W3 [2 d_T][width] (rows 0..d_T-1 give s,
  * the rest t), b3 [2 d_T], all row-major.  smc_flow_param_count gives its
- * length (0 for invalid sizes).  smc_get_flow copies into DEVICE buffers
- * (each nullable) the current FP32 parameters, the standardisation m, a of
- * the last step (d each) and the gradient of the fit objective that the last
- * Adam step used (same layout as the parameters); smc_set_flow replaces the
- * parameters from a DEVICE vector and restarts their Adam moments.
- * SMC_EINVAL without a flow. */
+ * length (0 for invalid sizes).  The couplings act on x; the base map is
+ * theta = m + L u with u_c = x_q(c) (q: even coordinates first, then the odd
+ * ones), m the weighted mean of the pre-move population and L the Cholesky
+ * factor of its weighted covariance shrunk as n/(n+5) C + 1e-3 5/(n+5) I.
+ * smc_get_flow copies into DEVICE buffers (each nullable) the current FP32
+ * parameters, m (d) and L (d x d row-major, lower triangular) of the last
+ * step, and the gradient of the fit objective that the last Adam step used
+ * (same layout as the parameters); smc_set_flow replaces the parameters from
+ * a DEVICE vector and restarts their Adam moments.  SMC_EINVAL without a
+ * flow. */
 size_t smc_flow_param_count(int32_t d, int32_t layers, int32_t width);
-smc_status smc_get_flow(smc_ctx *ctx, float *params, float *m, float *a, float *grad);
+smc_status smc_get_flow(smc_ctx *ctx, float *params, float *m, float *L, float *grad);
 smc_status smc_set_flow(smc_ctx *ctx, const float *params);
 
 /* Unconditional resampling of the current population (Sec. III), then the

@@ -16,13 +16,19 @@ Flow T: z -> theta (fixed within an SMC iteration):
       h1 = tanh(W1 x_C + b1);  h2 = tanh(W2 h1 + b2);  o = W3 h2 + b3
       s = tanh(o[:d_T]);  t = o[d_T:]
       x_T <- x_T * exp(s) + t;         log|det| += sum s
-  theta_c = m_c + exp(a_c) x_q(c);     log|det| += sum a
+  theta = m + L u,  u_c = x_q(c);      log|det| += sum_c log L_cc
   (q: even coordinates of theta first, then the odd ones)
 Latent target: log pi_z(z) = log pi(T(z)) + log|det J_T(z)|.
 
-Per iteration (readings, all build choices): m and a standardise the weighted
-pre-move population (m its weighted mean, a = 1/2 log of the regularised
-weighted variance of oracle.smc.diag_mass); the couplings are warm-started and
+Per iteration (readings, all build choices): m and L standardise the weighted
+pre-move population: m its weighted mean, L the Cholesky factor of its
+weighted covariance shrunk toward 1e-3 I as n/(n + 5) C + 1e-3 5/(n + 5) I
+(n the effective sample size; the dense counterpart of oracle.smc.diag_mass),
+so that the identity couplings give HMC with the dense mass M^-1 = L L^T.
+The fit runs only on iterations that did not resample.
+The inverse base map uses L^-1.  m, L and L^-1 are held in binary32 as on the
+device, the log-determinant sum_c log L_cc in binary32 from the binary64
+factor.  The couplings are warm-started and
 trained for a few Adam steps on the weighted maximum-likelihood objective
   l(phi) = sum_j W_j [ log N(T^-1(theta_j); 0, I) + log|det J_{T^-1}(theta_j)| ]
 (ascent), W the normalised weights.  A zero last layer (W3 = 0, b3 = 0) makes
@@ -80,7 +86,23 @@ def _mlp(p, xc):
     return h1, h2, o
 
 
-def forward(ps, m, a, z):
+class Base:
+    """Affine base map theta = m + L u of the flow: m, L, L^-1 and
+    log|det L| (see the module docstring for the binary32 convention)."""
+
+    def __init__(self, m, L, Linv=None, logdet=None):
+        self.m = np.asarray(m, dtype=np.float64)
+        self.L = np.asarray(L, dtype=np.float64)
+        self.Linv = np.linalg.inv(self.L) if Linv is None else np.asarray(Linv, dtype=np.float64)
+        self.logdet = float(np.sum(np.log(np.diag(self.L)))) if logdet is None else float(logdet)
+
+    @staticmethod
+    def diagonal(m, a):
+        a = np.asarray(a, dtype=np.float64)
+        return Base(m, np.diag(np.exp(a)), np.diag(np.exp(-a)), float(np.sum(a)))
+
+
+def forward(ps, base, z):
     """theta = T(z) and log|det J_T(z)| for a population z (J, d)."""
     z = np.atleast_2d(np.asarray(z, dtype=np.float64))
     x = z.copy()
@@ -93,16 +115,16 @@ def forward(ps, m, a, z):
         t = o[:, len(T):]
         x[:, T] = x[:, T] * np.exp(s) + t
         ld += s.sum(1)
-    return m + np.exp(a) * x[:, interleave(d)], ld + np.sum(a)
+    return base.m + x[:, interleave(d)] @ base.L.T, ld + base.logdet
 
 
-def inverse(ps, m, a, theta):
+def inverse(ps, base, theta):
     """z = T^-1(theta) and log|det J_{T^-1}(theta)| = -log|det J_T(z)|."""
     theta = np.atleast_2d(np.asarray(theta, dtype=np.float64))
     d = theta.shape[1]
     x = np.empty_like(theta)
-    x[:, interleave(d)] = (theta - m) * np.exp(-a)
-    ld = np.full(len(x), -np.sum(a))
+    x[:, interleave(d)] = (theta - base.m) @ base.Linv.T
+    ld = np.full(len(x), -base.logdet)
     for l in reversed(range(len(ps))):
         p = ps[l]
         T, C = layer_sets(l, d)
@@ -114,7 +136,7 @@ def inverse(ps, m, a, theta):
     return x, ld
 
 
-def latent_grad(ps, m, a, z, g_theta):
+def latent_grad(ps, base, z, g_theta):
     """grad_z log pi_z(z) = J_T(z)^T g_theta + grad_z log|det J_T(z)| by reverse
     accumulation through the forward map (g_theta = grad log pi at T(z))."""
     z = np.atleast_2d(np.asarray(z, dtype=np.float64))
@@ -130,7 +152,7 @@ def latent_grad(ps, m, a, z, g_theta):
         tape.append((T, C, h1, h2, s, xT))
         x[:, T] = xT * np.exp(s) + t
     gx = np.empty((len(z), d))
-    gx[:, interleave(d)] = np.asarray(g_theta, dtype=np.float64) * np.exp(a)   # cotangent of x
+    gx[:, interleave(d)] = np.asarray(g_theta, dtype=np.float64) @ base.L   # cotangent of x
     for l in reversed(range(len(ps))):
         p = ps[l]
         T, C, h1, h2, s, xT = tape[l]
@@ -147,15 +169,15 @@ def latent_grad(ps, m, a, z, g_theta):
     return gx
 
 
-def objective_and_grad(ps, m, a, theta, W):
+def objective_and_grad(ps, base, theta, W):
     """l(phi) = sum_j W_j [log N(z_j; 0, I) + log|det J_{T^-1}(theta_j)|] with
     z = T^-1(theta), and its gradient with respect to every coupling parameter
     (reverse accumulation through the inverse map)."""
     theta = np.atleast_2d(np.asarray(theta, dtype=np.float64))
     J, d = theta.shape
     x = np.empty_like(theta)
-    x[:, interleave(d)] = (theta - m) * np.exp(-a)
-    ld = np.full(J, -np.sum(a))
+    x[:, interleave(d)] = (theta - base.m) @ base.Linv.T
+    ld = np.full(J, -base.logdet)
     tape = {}
     for l in reversed(range(len(ps))):
         p = ps[l]
@@ -237,7 +259,7 @@ def philox_init(seed, d, layers, width):
 
 def flatten(ps, m=None, a=None):
     """Flat parameter vector: per layer W1 (width x d_C, row-major), b1, W2,
-    b2, W3 (2 d_T x width), b3; then m and a if given."""
+    b2, W3 (2 d_T x width), b3 (then two more vectors if given)."""
     parts = []
     for p in ps:
         for k in ("W1", "b1", "W2", "b2", "W3", "b3"):
@@ -267,17 +289,22 @@ def unflatten(v, d, layers, width):
 
 
 def standardise(theta, logw, n_eff):
-    """m = weighted mean, a = 1/2 log of the regularised weighted variance
-    (oracle.smc.diag_mass), both held in binary32 as on the device."""
-    from .smc import diag_mass, normalise
+    """Base of the flow from the weighted population: m = weighted mean,
+    L = Cholesky factor of n/(n+5) C + 1e-3 5/(n+5) I with C the weighted
+    covariance (two passes, binary64); m, L, L^-1 held in binary32."""
+    from .smc import normalise
     W = normalise(logw)
-    m = (W @ theta).astype(np.float32).astype(np.float64)
-    var = diag_mass(theta, logw, n_eff)
-    a = (0.5 * np.log(var)).astype(np.float32).astype(np.float64)
-    return m, a
+    m64 = W @ theta
+    dev = theta - m64
+    C = (dev * W[:, None]).T @ dev
+    S = (n_eff / (n_eff + 5.0)) * C + 1e-3 * (5.0 / (n_eff + 5.0)) * np.eye(theta.shape[1])
+    L64 = np.linalg.cholesky(S)
+    Li64 = np.linalg.inv(L64)
+    f32 = lambda v: np.asarray(v).astype(np.float32).astype(np.float64)
+    return Base(f32(m64), f32(L64), f32(Li64), float(np.float32(np.sum(np.log(np.diag(L64))))))
 
 
-def leapfrog_latent(target, ps, m, a, z, p, gz, eps, n_steps, traj_grad=None):
+def leapfrog_latent(target, ps, base, z, p, gz, eps, n_steps, traj_grad=None):
     """Leapfrog in the latent space (unit mass) on log pi_z, n_steps[j] steps
     for particle j, the latent gradient cached between steps.  Each step:
     p += eps/2 gz;  z += eps p;  theta = T(z);  gz = J_T^T grad log pi(theta)
@@ -288,20 +315,20 @@ def leapfrog_latent(target, ps, m, a, z, p, gz, eps, n_steps, traj_grad=None):
     gz = np.array(gz, dtype=np.float64)
     n_steps = np.asarray(n_steps)
     J, d = z.shape
-    theta, ld = forward(ps, m, a, z)
+    theta, ld = forward(ps, base, z)
     gth = np.full((J, d), np.nan)
     for s in range(int(n_steps.max(initial=0))):
         act = n_steps > s
         p[act] += 0.5 * eps * gz[act]
         z[act] += eps * p[act]
-        th, l1 = forward(ps, m, a, z[act])
+        th, l1 = forward(ps, base, z[act])
         theta[act], ld[act] = th, l1
         if traj_grad is None:
             _, g = target.log_and_grad(th)
         else:
             g = traj_grad(th)
         gth[act] = g
-        gz[act] = latent_grad(ps, m, a, z[act], g)
+        gz[act] = latent_grad(ps, base, z[act], g)
         p[act] += 0.5 * eps * gz[act]
     lp, _ = target.log_and_grad(theta)
     return z, p, gz, theta, gth, lp, ld

@@ -551,7 +551,7 @@ class OracleSMC:
                             if P["flow_init"] is not None else
                             flow.philox_init(P["seed"], d, P["flow_layers"], P["flow_width"]))
             self.flow_adam = flow.FlowAdam(P["flow_lr"], P["adam_b1"], P["adam_b2"], P["adam_eps"])
-            self.flow_m = self.flow_a = None
+            self.flow_base = None
 
     # ----- one SMC iteration -------------------------------------------------
     def jitter(self, k):
@@ -598,16 +598,18 @@ class OracleSMC:
         flow_rec = None
         if P["precond"] == "flow":
             from . import flow
-            m_, a_ = flow.standardise(self.theta, self.logw, j_eff_before)
+            base = flow.standardise(self.theta, self.logw, j_eff_before)
             W = normalise(self.logw)
-            for _ in range(P["flow_train_steps"]):
-                _, g_ = flow.objective_and_grad(self.flow_ps, m_, a_, self.theta, W)
+            # reading: no fit on a resampled iteration (a resampled population
+            # holds duplicates, onto which a maximum-likelihood fit collapses)
+            for _ in range(0 if resampled else P["flow_train_steps"]):
+                _, g_ = flow.objective_and_grad(self.flow_ps, base, self.theta, W)
                 self.flow_ps = self.flow_adam.ascend(self.flow_ps, g_)
-            self.flow_m, self.flow_a = m_, a_
+            self.flow_base = base
             psb = flow.bf16_params(self.flow_ps)
-            z0, ldi = flow.inverse(psb, m_, a_, self.theta)
+            z0, ldi = flow.inverse(psb, base, self.theta)
             ld0 = -ldi
-            gz0 = flow.latent_grad(psb, m_, a_, z0, self.grad)
+            gz0 = flow.latent_grad(psb, base, z0, self.grad)
         # a4: momenta, jitter, step counts, initial energy
         if momenta is None:
             momenta = philox.normals_np(P["seed"], J, k, philox.STREAM_MOMENTUM, d)
@@ -619,9 +621,9 @@ class OracleSMC:
         if P["precond"] == "flow":
             # in the latent space of the flow, unit mass: log pi_z = log pi(T(z)) + log|det J_T|
             z1, p1, gz1, th1, g1, lp1, ld1 = flow.leapfrog_latent(
-                self.target, psb, m_, a_, z0, p0, gz0, self.eps, n, traj_grad=self.traj_grad)
+                self.target, psb, base, z0, p0, gz0, self.eps, n, traj_grad=self.traj_grad)
             ng = n.copy()
-            flow_rec = dict(z0=z0, z1=z1, gz0=gz0, gz1=gz1, ld0=ld0, ld1=ld1, m=m_, a=a_,
+            flow_rec = dict(z0=z0, z1=z1, gz0=gz0, gz1=gz1, ld0=ld0, ld1=ld1, base=base,
                             params_bf16=psb)
         else:
             th1, p1, g1, lp1, ng = leapfrog(self.target, self.theta, p0, self.grad, self.eps, n,

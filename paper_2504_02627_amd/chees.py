@@ -329,7 +329,7 @@ class Sampler:
         return res
 
     def flow(self, with_grad=False):
-        """(FP32 coupling parameters as one flat vector, m, a[, gradient of the
+        """(FP32 coupling parameters as one flat vector, m, L[, gradient of the
         last Adam step]) of the flow preconditioner (include/chees_smc.h gives
         the layout)."""
         torch = _torch()
@@ -337,11 +337,11 @@ class Sampler:
         n = self.lib.smc_flow_param_count(d, self.params.flow_layers, self.params.flow_width)
         prm = torch.empty(n, dtype=torch.float32, device=self.device)
         m = torch.empty(d, dtype=torch.float32, device=self.device)
-        a = torch.empty(d, dtype=torch.float32, device=self.device)
+        L = torch.empty((d, d), dtype=torch.float32, device=self.device)
         g = torch.empty(n, dtype=torch.float32, device=self.device) if with_grad else None
-        self._check(self.lib.smc_get_flow(self.ctx, _ptr(prm), _ptr(m), _ptr(a), _ptr(g)),
+        self._check(self.lib.smc_get_flow(self.ctx, _ptr(prm), _ptr(m), _ptr(L), _ptr(g)),
                     "smc_get_flow")
-        return (prm, m, a, g) if with_grad else (prm, m, a)
+        return (prm, m, L, g) if with_grad else (prm, m, L)
 
     def set_flow(self, params):
         """Replace the coupling parameters (flat FP32 device vector)."""

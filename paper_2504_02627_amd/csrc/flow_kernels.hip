@@ -7,10 +7,11 @@
 //   log pi_z(z) = log pi(T(z)) + log|det J_T(z)|.
 // T: x = z; per coupling layer l: x_T <- x_T exp(s) + t with (s, t) from a
 // tanh MLP (width FH) of the conditioning half x_C, s = tanh(.);
-// theta_c = m_c + exp(a_c) x_q(c), q placing the even coordinates of theta
-// first, then the odd ones.  m, a standardise the weighted pre-move
-// population; the couplings are trained each iteration by a few Adam steps on
-// the weighted maximum-likelihood objective of the population.
+// theta = m + L u with u_c = x_q(c), q placing the even coordinates of theta
+// first, then the odd ones.  m and the Cholesky factor L standardise the
+// weighted pre-move population; the couplings are trained each iteration by a
+// few Adam steps on the weighted maximum-likelihood objective of the
+// population.
 //
 // A block of four waves carries 16 particles.  Every dense layer of the
 // conditioners runs on v_mfma_f32_16x16x4f32 with a 16-unit tile of the
@@ -232,7 +233,7 @@ __global__ void k_flow_init(Dev D, FlowNet F) {
     D.fadm[i] = 0.f;
     D.fadv[i] = 0.f;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) D.fstate[0] = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) D.fstate[1] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -240,11 +241,13 @@ __global__ void k_flow_init(Dev D, FlowNet F) {
 // read: packed A-operand copies of every weight matrix and of its transpose,
 // FP32 (training) and bfloat16-rounded (moves), and the bfloat16-rounded
 // biases.  The gradient is the ordered sum of the KSPLIT particle-chunk
-// partials.  Adam step t = (k - 1) ntrain + step + 1 - offset, k the
-// iteration counter of the device state.
+// partials.  Reading: the fit runs only on iterations that did not resample
+// (a resampled population holds duplicates, which a maximum-likelihood fit
+// would collapse onto); Adam's step count counts the steps taken.
 // ---------------------------------------------------------------------------
 __global__ void k_flow_adam(Dev D, FlowNet F, int step, int update, const float *part) {
-  const int t = (D.ps[0].k - 1) * F.ntrain + step + 1 - D.fstate[0];
+  if (update && D.ps[0].resampled) return;  // no fit on a resampled iteration
+  const int t = D.fstate[1] + 1;             // Adam steps taken so far, plus this one
   const double c1 = 1.0 - pow(D.adam_b1, (double)t), c2 = 1.0 - pow(D.adam_b2, (double)t);
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < F.nparams; i += gridDim.x * blockDim.x) {
     float pv = D.fp[i];
@@ -286,18 +289,102 @@ __global__ void k_flow_adam(Dev D, FlowNet F, int step, int update, const float 
 }
 
 // ---------------------------------------------------------------------------
-// Standardisation m, a from the weighted column moments of the pre-move
-// population (the two passes of k_mass_colsum): m = weighted mean,
-// a = 1/2 log of the regularised weighted variance held in binary32.
+// Base map theta = m + L u of the flow from the weighted pre-move population:
+// m its weighted mean (the first column pass of k_mass_colsum), L the Cholesky
+// factor of its weighted covariance shrunk toward 1e-3 I,
+//   n/(n+5) C + 1e-3 5/(n+5) I,  n the effective sample size,
+// all in FP64; then FP32 copies of m and L, the packed A-operand matrices of
+// the three base products (x -> L u, its transpose for the latent gradient,
+// theta - m -> x via L^-1, with u_c = x_q(c)) and log|det L|.
 // ---------------------------------------------------------------------------
-__global__ void k_flow_base(Dev D, FlowNet F) {
+__global__ __launch_bounds__(256) void k_flow_cov(Dev D, FlowNet F) {
+  // one 16 x 16 tile of C per block; 64 particles staged at a time
+  __shared__ double Xa[64][17], Xb[64][17];
+  __shared__ double Wc[64];
+  const int d = F.d, nt = (d + 15) / 16;
+  const int ta = blockIdx.x / nt, tb = blockIdx.x % nt;
+  if (tb > ta) return;  // lower triangle of tiles
+  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+  const int c = 16 * ta + ty, k = 16 * tb + tx;
+  const PState &PS = D.ps[0];
+  const int rs = PS.resampled;
+  const float *src = rs ? D.theta_t : D.theta;
+  const double *mean = D.means;
+  double acc = 0.0;
+  for (int j0 = 0; j0 < D.J; j0 += 64) {
+    for (int i = threadIdx.x; i < 64 * 16; i += 256) {
+      const int jj = i >> 4, cc = i & 15, j = j0 + jj;
+      const int ca = 16 * ta + cc, cb = 16 * tb + cc;
+      Xa[jj][cc] = (j < D.J && ca < d) ? (double)src[(long long)j * D.DS + ca] - mean[ca] : 0.0;
+      Xb[jj][cc] = (j < D.J && cb < d) ? (double)src[(long long)j * D.DS + cb] - mean[cb] : 0.0;
+    }
+    if (threadIdx.x < 64) {
+      const int j = j0 + threadIdx.x;
+      double w = 0.0;
+      if (j < D.J) {
+        const double lw = D.logw[j];
+        w = rs ? 1.0 / D.J : ((lw == lw && lw > -INFINITY) ? exp(lw - PS.m) / PS.S : 0.0);
+      }
+      Wc[threadIdx.x] = w;
+    }
+    __syncthreads();
+    for (int jj = 0; jj < 64; ++jj) acc += Wc[jj] * (Xa[jj][ty] * Xb[jj][tx]);
+    __syncthreads();
+  }
+  if (c < d && k < d) {
+    D.fcov[(long long)c * d + k] = acc;
+    D.fcov[(long long)k * d + c] = acc;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_flow_chol(Dev D, FlowNet F) {
+  const int d = F.d, tid = threadIdx.x;
+  double *A = D.fLd, *X = D.fLi;
   const double n = D.ps[0].ess_before;
-  for (int c = threadIdx.x; c < D.DS; c += blockDim.x) {
+  const double sc = n / (n + 5.0), sh = 1e-3 * (5.0 / (n + 5.0));
+  for (int i = tid; i < d * d; i += 256) A[i] = sc * D.fcov[i] + ((i / d == i % d) ? sh : 0.0);
+  __syncthreads();
+  // right-looking Cholesky, lower triangle in place
+  for (int k = 0; k < d; ++k) {
+    if (tid == 0) A[(long long)k * d + k] = sqrt(A[(long long)k * d + k]);
+    __syncthreads();
+    const double lkk = A[(long long)k * d + k];
+    for (int i = k + 1 + tid; i < d; i += 256) A[(long long)i * d + k] /= lkk;
+    __syncthreads();
+    const int m = d - k - 1;
+    for (int e = tid; e < m * m; e += 256) {
+      const int i = k + 1 + e / m, j = k + 1 + e % m;
+      if (j <= i) A[(long long)i * d + j] -= A[(long long)i * d + k] * A[(long long)j * d + k];
+    }
+    __syncthreads();
+  }
+  // L^-1 column by column (forward substitution)
+  for (int j = tid; j < d; j += 256)
+    for (int i = 0; i < d; ++i) {
+      double v = 0.0;
+      if (i >= j) {
+        v = (i == j) ? 1.0 : 0.0;
+        for (int q = j; q < i; ++q) v -= A[(long long)i * d + q] * X[(long long)q * d + j];
+        v /= A[(long long)i * d + i];
+      }
+      X[(long long)i * d + j] = v;
+    }
+  __syncthreads();
+  const int K16 = (d + 15) / 16 * 16;
+  for (int e = tid; e < d * d; e += 256) {
+    const int c = e / d, k = e % d;
+    const float l = k <= c ? (float)A[e] : 0.f;
+    const float li = (float)X[e];
+    D.fL[e] = l;
+    D.fAf[pk_index(c, xpos(k, d), K16)] = l;          // theta - m = L u, u_k = x_q(k)
+    D.fAb[pk_index(xpos(k, d), c, K16)] = l;          // cotangent of x: L^T g
+    D.fAi[pk_index(xpos(c, d), k, K16)] = li;         // x_q(c) = (L^-1 (theta - m))_c
+  }
+  for (int c = tid; c < D.DS; c += 256) D.fm[c] = c < d ? (float)D.means[c] : 0.f;
+  if (tid == 0) {
     double s = 0.0;
-    for (int ch = 0; ch < D.col_chunks; ++ch) s += D.colpart[(long long)ch * 2 * D.DS + c];
-    const float v = (float)((n / (n + 5.0)) * s + 1e-3 * (5.0 / (n + 5.0)));
-    D.fm[c] = c < F.d ? (float)D.means[c] : 0.f;
-    D.fa[c] = c < F.d ? (float)(0.5 * log((double)v)) : 0.f;
+    for (int c = 0; c < d; ++c) s += log(A[(long long)c * d + c]);
+    D.fbase[0] = (float)s;
   }
 }
 
@@ -310,6 +397,7 @@ __global__ void k_flow_base(Dev D, FlowNet F) {
 // W the normalised weights (uniform right after resampling).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(NT) void k_flow_train(Dev D, FlowNet F) {
+  if (D.ps[0].resampled) return;
   __shared__ BlockLDS S;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int p = tid >> 4, r = tid & 15;
@@ -336,8 +424,10 @@ __global__ __launch_bounds__(NT) void k_flow_train(Dev D, FlowNet F) {
   for (int i = tid; i < PB * F.d; i += NT) {
     const int q = i / F.d, c = i % F.d;
     const int j = S.rows[q];
-    S.xs[q][xpos(c, F.d)] = j >= 0 ? (src[(long long)j * D.DS + c] - D.fm[c]) * expf(-D.fa[c]) : 0.f;
+    S.ob[q][c] = j >= 0 ? src[(long long)j * D.DS + c] - D.fm[c] : 0.f;
   }
+  __syncthreads();
+  mdense(D.fAi, F.d, F.d, nullptr, &S.ob[0][0], XP, &S.xs[0][0], XP, ST_PLAIN, S, -1, 0, wave, lane);
   __syncthreads();
   const float *W = D.fp;
   const int h = F.half, TS = F.train_stride;
@@ -419,6 +509,7 @@ __device__ __forceinline__ Gm gm_of(const FlowNet &F, int l, int which) {
 }
 
 __global__ __launch_bounds__(256) void k_flow_wgrad(Dev D, FlowNet F, float *part) {
+  if (D.ps[0].resampled) return;
   __shared__ float4 As[32][16], Bs[32][16];
   // locate (layer, matrix, tile) or (layer, matrix, bias)
   int id = blockIdx.x, l = -1, which = 0, tile = 0, isbias = 0;
@@ -520,12 +611,12 @@ __global__ __launch_bounds__(NT) void k_flow_inverse(Dev D, FlowNet F) {
   for (int i = tid; i < PB * F.d; i += NT) {
     const int q = i / F.d, c = i % F.d;
     const int j = S.rows[q];
-    S.xs[q][xpos(c, F.d)] =
-        j >= 0 ? (D.theta_t[(long long)j * D.DS + c] - D.fm[c]) * expf(-D.fa[c]) : 0.f;
+    S.ob[q][c] = j >= 0 ? D.theta_t[(long long)j * D.DS + c] - D.fm[c] : 0.f;
   }
   __syncthreads();
-  float ldp = 0.f;
-  for (int c = r; c < F.d; c += 16) ldp -= D.fa[c];
+  mdense(D.fAi, F.d, F.d, nullptr, &S.ob[0][0], XP, &S.xs[0][0], XP, ST_PLAIN, S, -1, 0, wave, lane);
+  __syncthreads();
+  float ldp = r == 0 ? -D.fbase[0] : 0.f;
   for (int l = F.L - 1; l >= 0; --l) {
     const FlowLayerDesc &Y = F.ly[l];
     mdense(D.fbk + Y.pW1, FH, Y.dc, D.fbias + Y.ob1, &S.xs[0][Y.C0], XP, &S.h1[0][0], HP, ST_TANH,
@@ -620,13 +711,14 @@ __global__ __launch_bounds__(NT) void k_flow_drift(Dev D, FlowNet F, int step, i
   __syncthreads();
   float ldp = forward_couplings(F, D.fbk, D.fbias, S, wave, lane, tid);
   if (init) return;
-  for (int c = r; c < F.d; c += 16) ldp += D.fa[c];
+  mdense(D.fAf, F.d, F.d, nullptr, &S.xs[0][0], XP, &S.ob[0][0], XP, ST_PLAIN, S, -1, 0, wave, lane);
+  if (r == 0) ldp += D.fbase[0];
   const float ld = sum16(ldp);
+  __syncthreads();
   const int j = S.rows[p];
   if (j >= 0) {
     for (int c = r; c < D.DS; c += 16)
-      D.theta_t[(long long)j * D.DS + c] =
-          c < F.d ? fmaf(expf(D.fa[c]), S.xs[p][xpos(c, F.d)], D.fm[c]) : 0.f;
+      D.theta_t[(long long)j * D.DS + c] = c < F.d ? D.fm[c] + S.ob[p][c] : 0.f;
     if (r == 0) D.fld1[j] = ld;
   }
 }
@@ -642,8 +734,12 @@ __global__ __launch_bounds__(NT) void k_flow_kick(Dev D, FlowNet F, int step, in
   for (int i = tid; i < PB * F.d; i += NT) {
     const int q = i / F.d, c = i % F.d;
     const int j = S.rows[q];
-    S.xs[q][xpos(c, F.d)] = j >= 0 ? D.grad_t[(long long)j * D.DS + c] * expf(D.fa[c]) : 0.f;
+    S.ob[q][c] = j >= 0 ? D.grad_t[(long long)j * D.DS + c] : 0.f;
   }
+  __syncthreads();
+  mdense(D.fAb, F.d, F.d, nullptr, &S.ob[0][0], XP, &S.xs[0][0], XP, ST_PLAIN, S, -1, 0, wave, lane);
+  __syncthreads();
+  for (int i = tid; i < PB * XP; i += NT) (&S.ob[0][0])[i] = 0.f;
   __syncthreads();
   vjp_couplings(F, D.fbk, S, wave, lane, tid);
   for (int i = tid; i < PB * F.d; i += NT) {
@@ -664,7 +760,12 @@ __global__ void k_flow_reset(Dev D, FlowNet F) {
     D.fadm[i] = 0.f;
     D.fadv[i] = 0.f;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) D.fstate[0] = D.ps[0].k * F.ntrain;
+  if (blockIdx.x == 0 && threadIdx.x == 0) D.fstate[1] = 0;
+}
+
+// Count an Adam step of the fit (after k_flow_adam has read the count).
+__global__ void k_flow_tick(Dev D) {
+  if (!D.ps[0].resampled) D.fstate[1] += 1;
 }
 
 // The gradient the last Adam step used: the ordered sum of the chunk partials.
@@ -702,7 +803,9 @@ hipError_t launch_flow_publish(const Dev &D, const FlowNet &F, hipStream_t st) {
 }
 
 hipError_t launch_flow_base(const Dev &D, const FlowNet &F, hipStream_t st) {
-  hipLaunchKernelGGL(k_flow_base, dim3(1), dim3(256), 0, st, D, F);
+  const int nt = (F.d + 15) / 16;
+  hipLaunchKernelGGL(k_flow_cov, dim3(nt * nt), dim3(256), 0, st, D, F);
+  hipLaunchKernelGGL(k_flow_chol, dim3(1), dim3(256), 0, st, D, F);
   return hipGetLastError();
 }
 
@@ -717,6 +820,7 @@ hipError_t launch_flow_train(const Dev &D, const FlowNet &F, int step, hipStream
   hipLaunchKernelGGL(k_flow_wgrad, dim3(nb, KSPLIT), dim3(256), 0, st, D, F, D.fgrad);
   hipLaunchKernelGGL(k_flow_adam, dim3(256), dim3(256), 0, st, D, F, step, 1,
                      (const float *)D.fgrad);
+  hipLaunchKernelGGL(k_flow_tick, dim3(1), dim3(1), 0, st, D);
   return hipGetLastError();
 }
 

@@ -61,7 +61,8 @@ struct Layout {
   size_t o_n, o_perm, o_active, o_anc, o_acc, o_cdf, o_gpart, o_tilecnt, o_llpart;
   size_t o_items, o_colpart, o_means, o_minv, o_primes;
   FlowNet F;
-  size_t o_fz = 0, o_fz0 = 0, o_fgz = 0, o_fld0 = 0, o_fld1 = 0, o_fm = 0, o_fa = 0;
+  size_t o_fz = 0, o_fz0 = 0, o_fgz = 0, o_fld0 = 0, o_fld1 = 0, o_fm = 0, o_fL = 0, o_fAf = 0,
+         o_fAb = 0, o_fAi = 0, o_fcov = 0, o_fLd = 0, o_fLi = 0, o_fbase = 0;
   size_t o_fp = 0, o_fpk = 0, o_fbk = 0, o_fbias = 0, o_fgrad = 0, o_fadm = 0,
          o_fadv = 0, o_ftape = 0, o_fstate = 0;
 };
@@ -272,8 +273,17 @@ void plan(const smc_problem *pr, const smc_params *pa, Layout &L) {
     L.o_fgz = take(c, st);
     L.o_fld0 = take(c, rows * 4);
     L.o_fld1 = take(c, rows * 4);
+    const size_t dd = (size_t)pr->dims[0] * pr->dims[0];
+    const size_t d16 = (size_t)((pr->dims[0] + 15) / 16 * 16);
     L.o_fm = take(c, (size_t)L.DS * 4);
-    L.o_fa = take(c, (size_t)L.DS * 4);
+    L.o_fL = take(c, dd * 4);
+    L.o_fAf = take(c, d16 * d16 * 4);
+    L.o_fAb = take(c, d16 * d16 * 4);
+    L.o_fAi = take(c, d16 * d16 * 4);
+    L.o_fcov = take(c, dd * 8);
+    L.o_fLd = take(c, dd * 8);
+    L.o_fLi = take(c, dd * 8);
+    L.o_fbase = take(c, 256);
     L.o_fp = take(c, np * 4);
     L.o_fpk = take(c, (size_t)L.F.npacked * 4);
     L.o_fbk = take(c, (size_t)L.F.npacked * 4);
@@ -434,7 +444,14 @@ smc_status smc_init(const smc_problem *prob, const smc_params *par, void *worksp
     D.fld0 = (float *)(w + L.o_fld0);
     D.fld1 = (float *)(w + L.o_fld1);
     D.fm = (float *)(w + L.o_fm);
-    D.fa = (float *)(w + L.o_fa);
+    D.fL = (float *)(w + L.o_fL);
+    D.fAf = (float *)(w + L.o_fAf);
+    D.fAb = (float *)(w + L.o_fAb);
+    D.fAi = (float *)(w + L.o_fAi);
+    D.fcov = (double *)(w + L.o_fcov);
+    D.fLd = (double *)(w + L.o_fLd);
+    D.fLi = (double *)(w + L.o_fLi);
+    D.fbase = (float *)(w + L.o_fbase);
     D.fp = (float *)(w + L.o_fp);
     D.fpk = (float *)(w + L.o_fpk);
     D.fbk = (float *)(w + L.o_fbk);
@@ -789,7 +806,7 @@ size_t smc_flow_param_count(int32_t d, int32_t layers, int32_t width) {
   return flow_net(d, layers, width, F) ? (size_t)F.nparams : 0;
 }
 
-smc_status smc_get_flow(smc_ctx *ctx, float *params, float *m, float *a, float *grad) {
+smc_status smc_get_flow(smc_ctx *ctx, float *params, float *m, float *L, float *grad) {
   if (!ctx) return SMC_EINVAL;
   if (!ctx->D.flow) {
     ctx->err = "no flow preconditioner in this context";
@@ -799,7 +816,8 @@ smc_status smc_get_flow(smc_ctx *ctx, float *params, float *m, float *a, float *
   if (params)
     CK(hipMemcpyAsync(params, D.fp, (size_t)ctx->F.nparams * 4, hipMemcpyDeviceToDevice, ctx->st));
   if (m) CK(hipMemcpyAsync(m, D.fm, (size_t)ctx->F.d * 4, hipMemcpyDeviceToDevice, ctx->st));
-  if (a) CK(hipMemcpyAsync(a, D.fa, (size_t)ctx->F.d * 4, hipMemcpyDeviceToDevice, ctx->st));
+  if (L)
+    CK(hipMemcpyAsync(L, D.fL, (size_t)ctx->F.d * ctx->F.d * 4, hipMemcpyDeviceToDevice, ctx->st));
   if (grad) CK(launch_flow_gradsum(D, ctx->F, grad, ctx->st));
   return SMC_OK;
 }

@@ -126,13 +126,17 @@ struct Dev {                    // pointers carved from the workspace
   int flow;
   float *fz, *fz0, *fgz;        // latent position, pre-move latent, latent gradient [Jcap][DS]
   float *fld0, *fld1;           // log|det J_T| at z0 and at the current z [Jcap]
-  float *fm, *fa;               // standardisation theta = m + exp(a) x  [DS]
+  float *fm;                    // base map theta = m + L u: m [DS]
+  float *fL;                    // L, row-major d x d
+  float *fAf, *fAb, *fAi;       // packed base products: L P^T, P L^T, P L^-1
+  double *fcov, *fLd, *fLi;     // weighted covariance, Cholesky factor, inverse (FP64)
+  float *fbase;                 // [0]: log|det L|
   float *fp;                    // FP32 parameters (flat)
   float *fpk, *fbk;             // packed weights (and transposes): FP32, bfloat16-rounded
   float *fbias;                 // BF16-rounded biases (flat offsets)
   float *fgrad, *fadm, *fadv;   // parameter gradient and Adam moments
   float *ftape;                 // per particle and layer activations
-  int *fstate;                  // [0]: Adam step offset
+  int *fstate;                  // [1]: Adam steps taken by the fit
 };
 
 // Host copy of one posterior's packing sizes.

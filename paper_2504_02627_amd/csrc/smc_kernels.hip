@@ -1515,13 +1515,12 @@ __global__ void k_mass_finish(Dev D, int pass) {
   }
 }
 
-// write_minv = 0 stops after the second column pass (the flow preconditioner
-// reads the partial sums itself).
+// write_minv = 0: the weighted mean only (the flow preconditioner's base map
+// takes it from there).
 hipError_t launch_mass(const Dev &D, int write_minv, hipStream_t st) {
-  for (int pass = 0; pass < 2; ++pass) {
+  for (int pass = 0; pass < (write_minv ? 2 : 1); ++pass) {
     hipLaunchKernelGGL(k_mass_colsum, dim3(D.col_chunks, D.B), dim3(256), 0, st, D, pass);
-    if (pass == 0 || write_minv)
-      hipLaunchKernelGGL(k_mass_finish, dim3(D.B), dim3(256), 0, st, D, pass);
+    hipLaunchKernelGGL(k_mass_finish, dim3(D.B), dim3(256), 0, st, D, pass);
   }
   return hipGetLastError();
 }

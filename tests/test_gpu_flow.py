@@ -1,7 +1,8 @@
 """Flow preconditioner on the device against the flow oracle (oracle/flow.py).
 
 * initial couplings: the Philox draws of the oracle, to binary32 rounding;
-* standardisation m, a of the pre-move population: to binary32 rounding;
+* base map m, L (weighted mean, Cholesky factor of the shrunk weighted
+  covariance) of the pre-move population: to binary32 rounding;
 * training: the device's FP32 Adam fit against the oracle's FP64 fit from the
   same initial parameters and population (elementwise to a tolerance that
   allows Adam's sign sensitivity on near-zero gradients, and equal objective);
@@ -100,14 +101,14 @@ def test_flow_iteration_parity(N, d, J, seed):
         s.adapt()
         assert not st["resampled"]
         tr = s.trace()
-        prm, m_dev, a_dev, g_dev = (v.cpu().numpy().astype(np.float64) for v in s.flow(True))
-        m, a = m_dev[:d], a_dev[:d]
+        prm, m_dev, L_dev, g_dev = (v.cpu().numpy().astype(np.float64) for v in s.flow(True))
         th0 = th_prev
-        m_ref, a_ref = F.standardise(th0, lw_prev, st["ess_before"])
-        np.testing.assert_allclose(m, m_ref, rtol=1e-6, atol=1e-7)
-        np.testing.assert_allclose(a, a_ref, rtol=1e-6, atol=1e-7)
+        ref = F.standardise(th0, lw_prev, st["ess_before"])
+        np.testing.assert_allclose(m_dev, ref.m, rtol=1e-6, atol=1e-7)
+        np.testing.assert_allclose(L_dev, ref.L, rtol=1e-5, atol=1e-6 * np.abs(ref.L).max())
+        base = F.Base(m_dev, L_dev)
         W = O.normalise(lw_prev)
-        _, g = F.objective_and_grad(F.unflatten(Pprev, d, LAYERS, 128)[0], m, a, th0, W)
+        _, g = F.objective_and_grad(F.unflatten(Pprev, d, LAYERS, 128)[0], base, th0, W)
         _blocks_close(g_dev, F.flatten(g), d, f"iteration {k}: fit gradient")
         P_exp = F.flatten(ad.ascend(F.unflatten(Pprev, d, LAYERS, 128)[0],
                                     F.unflatten(g_dev, d, LAYERS, 128)[0]))
@@ -116,7 +117,7 @@ def test_flow_iteration_parity(N, d, J, seed):
         assert np.all(dP <= 1e-6 * (np.abs(P_exp) + lr))
         # moves with the device's trained couplings, BF16-rounded
         psb = F.bf16_params(F.unflatten(prm, d, LAYERS, 128)[0])
-        z0, ldi = F.inverse(psb, m, a, th0)
+        z0, ldi = F.inverse(psb, base, th0)
         z0_dev = tr["latent0"].cpu().numpy()[:J, :d].astype(np.float64)
         ez0 = rel_rows(z0_dev, z0)
         ld0_dev = tr["logdet0"].cpu().numpy()[:J].astype(np.float64)
@@ -126,9 +127,9 @@ def test_flow_iteration_parity(N, d, J, seed):
         assert ez0 <= 1e-5
         assert np.all(np.abs(ld0_dev + ldi) <= 1e-5 * (1 + np.abs(ldi)))
         lp0, g0 = t.log_and_grad(th0)
-        gz0 = F.latent_grad(psb, m, a, z0, g0)
+        gz0 = F.latent_grad(psb, base, z0, g0)
         n = tr["n"].cpu().numpy()[:J]
-        z1, p1, gz1, th1, _, lp1, ld1 = F.leapfrog_latent(t, psb, m, a, z0, xi.astype(np.float64),
+        z1, p1, gz1, th1, _, lp1, ld1 = F.leapfrog_latent(t, psb, base, z0, xi.astype(np.float64),
                                                           gz0, params["step_size"] if k == 1
                                                           else st["eps"], n)
         z1_dev = tr["latent"].cpu().numpy()[:J, :d].astype(np.float64)
@@ -150,11 +151,11 @@ def test_flow_iteration_parity(N, d, J, seed):
         Pprev = prm
 
 
-def test_flow_with_no_training_and_identity_couplings_is_a_linear_preconditioner():
-    """Zero couplings (set through smc_set_flow) and no training: T(z)_c = m_c
-    + exp(a_c) z_q(c).  The latent leapfrog is then the plain leapfrog with mass
-    M^{-1} = exp(2a) up to rounding; the trajectories of the flow context and
-    of a diagonal-mass oracle with minv = exp(2a) agree."""
+def test_flow_with_no_training_and_identity_couplings_is_a_dense_mass():
+    """Zero couplings (set through smc_set_flow) and no training: T(z) = m +
+    L u with u_c = z_q(c).  The latent leapfrog is then the plain leapfrog in
+    theta with the dense mass M^-1 = L L^T: theta += eps L p_u, p_u = L^T
+    p_theta; written out here in theta and compared with the device."""
     import torch
     N, d, J = 400, 9, 256
     X, y, theta0, params, s, t, rng = _setup(N, d, J, 8, 0, 1e-3)
@@ -163,18 +164,23 @@ def test_flow_with_no_training_and_identity_couplings_is_a_linear_preconditioner
     xi = rng.standard_normal((J, d)).astype(np.float32)
     st = s.step(momenta=to_dev(xi), resample_u=to_dev(np.array([0.5])))
     tr = s.trace()
-    _, m, a = (v.cpu().numpy().astype(np.float64) for v in s.flow())
+    _, m, L = (v.cpu().numpy().astype(np.float64) for v in s.flow())
     anc = tr["ancestors"].cpu().numpy()[:J] if st["resampled"] else np.arange(J)
-    th0 = theta0.astype(np.float64)[anc]
-    minv = np.exp(2 * a)
-    lp0, g0 = t.log_and_grad(th0)
-    # theta_c = m_c + e^a_c z_q(c), p_theta,c = e^-a_c p_z,q(c): the plain
-    # leapfrog with M^-1 = e^{2a}
-    p_theta = xi.astype(np.float64)[:, F.interleave(d)] * np.exp(-a)
+    th = theta0.astype(np.float64)[anc].copy()
+    _, g = t.log_and_grad(th)
+    pu = xi.astype(np.float64)[:, F.interleave(d)]      # latent momentum in theta's order
+    eps = params["step_size"]
     n = tr["n"].cpu().numpy()[:J]
-    th1, p1, _, _, _ = O.leapfrog(t, th0, p_theta, g0, params["step_size"], n, minv)
+    for k in range(int(n.max())):
+        act = n > k
+        pu[act] += 0.5 * eps * g[act] @ L
+        th[act] += eps * pu[act] @ L.T
+        _, g_new = t.log_and_grad(th[act])
+        g[act] = g_new
+        pu[act] += 0.5 * eps * g[act] @ L
     th1_dev = tr["theta_prop"].cpu().numpy()[:J, :d].astype(np.float64)
-    e = rel_rows(th1_dev, th1)
-    log(f"[flow identity] theta' vs diagonal-mass leapfrog rel err {e:.2e}")
+    e = rel_rows(th1_dev, th)
+    log(f"[flow identity] theta' vs dense-mass leapfrog rel err {e:.2e}")
     assert e <= 1e-5
-    np.testing.assert_allclose(tr["logdet"].cpu().numpy()[:J], np.sum(a), rtol=1e-6)
+    np.testing.assert_allclose(tr["logdet"].cpu().numpy()[:J], np.sum(np.log(np.diag(L))),
+                               rtol=1e-5)
