@@ -210,6 +210,99 @@ def moment_match(ref, a, b, ta, tb):
     return out
 
 
+def run_workload(Xs, ys, J, params, iters, burn):
+    """One sampler over `iters` SMC iterations (captured-graph replay for the
+    wall time, then the same seed again eagerly with per-kernel events).
+    Returns throughput, ESS figures after `burn` iterations and kernel times."""
+    import torch
+    from paper_2504_02627_amd import chees
+    s = chees.Sampler(Xs, ys, J, **params)
+    s.run(1)
+    torch.cuda.synchronize()
+    c0 = s.counters()
+    t0 = time.perf_counter()
+    s.run(iters - 1)
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    c1 = s.counters()
+    s.close()
+    s = chees.Sampler(Xs, ys, J, **params)
+    s.set_timing(True)
+    ess_post, ge_post = 0.0, 0
+    for k in range(iters):
+        st = s.step()
+        s.adapt(stats=False)
+        if k >= burn:
+            ess_post += st["ess"]
+            ge_post += st["grad_evals"] + J * s.B
+    tm = s.timing()
+    s.close()
+    evals = c1["grad_evals"] - c0["grad_evals"]
+    return {"ms_per_iteration": 1e3 * T / (iters - 1), "evals_per_s": evals / T,
+            "ess_per_s": (c1["ess_sum"] - c0["ess_sum"]) / T,
+            "ess_per_grad_eval_after_burn_in": ess_post / max(1, ge_post),
+            "kernel_ms_per_iteration": {k[:-3]: round(v / iters, 4) for k, v in tm.items()
+                                        if k.endswith("_ms")},
+            "leapfrog_launches": tm["leapfrog_launches"]}
+
+
+def other_workloads(args):
+    """The batched form, the precision form on the small model and the flow
+    preconditioner on the Toeplitz model, with their comparison forms."""
+    import numpy as np
+    import torch
+    from paper_2504_02627_amd import synth
+    dev = torch.device("cuda:0")
+    out = {}
+    # batched form: 64 posteriors, N ~ U[500, 20000], d ~ U[10, 200], J = 1024 each
+    data = synth.batched_logistic(64)
+    Xs = [torch.from_numpy(X).to(dev) for X, _, _ in data]
+    ys = [torch.from_numpy(y).to(dev) for _, y, _ in data]
+    eps = min(synth.default_step_size(X.shape[0], X.shape[1]) for X, _, _ in data)
+    p = dict(step_size=eps, traj_length=eps * 32, max_leapfrog=64, num_warmup=25, seed=4)
+    r = run_workload(Xs, ys, 1024, p, args.other_iters, args.other_iters // 2)
+    r["workload"] = ("64 logistic posteriors, N_b ~ U[500, 20000], d_b ~ U[10, 200], J = 1024 "
+                     "each, FP32 trajectories, one context")
+    r["leapfrog_kernel_note"] = ("achieved TFLOP/s not reported: the flop count per launch "
+                                 "mixes posteriors of different N_b d_b")
+    out["batched_64_posteriors"] = r
+    print("[bench] batched form done", file=sys.stderr, flush=True)
+    # precision form on the small model: N = 200, d = 5, J = 16384
+    X, y, _ = synth.small_logistic()
+    Xd, yd = torch.from_numpy(X).to(dev), torch.from_numpy(y).to(dev)
+    e5 = synth.default_step_size(200, 5)
+    p = dict(step_size=e5, traj_length=e5 * 32, max_leapfrog=64, num_warmup=10, seed=1,
+             adapt_step_size=True)
+    out["small_model_J16384"] = {
+        prec: run_workload(Xd if prec == "f32" else Xd.to(torch.bfloat16), yd, 16384,
+                           dict(p, precision=prec), 20, 10)
+        for prec in ("f32", "bf16")}
+    out["small_model_J16384"]["workload"] = ("logistic N=200, d=5, J=16384, 20 iterations; bf16: "
+                                             "X stored in bfloat16")
+    print("[bench] small model done", file=sys.stderr, flush=True)
+    # flow preconditioner on the Toeplitz model: N = 5000, d = 100, J = 4096
+    X, y, _ = synth.toeplitz_logistic()
+    Xd, yd = torch.from_numpy(X).to(dev), torch.from_numpy(y).to(dev)
+    e0 = synth.default_step_size(5000, 100)
+    base = dict(max_leapfrog=64, num_warmup=25, seed=3, adapt_step_size=True)
+    forms = {
+        "unit_mass": dict(step_size=e0, traj_length=e0 * 32),
+        "diagonal_mass": dict(step_size=0.05, traj_length=1.6, precond="diag"),
+        "flow_base_only": dict(step_size=0.3, traj_length=2.4, precond="flow", flow_layers=4,
+                               flow_train_steps=0),
+        "flow_4x128_trained": dict(step_size=0.3, traj_length=2.4, precond="flow", flow_layers=4,
+                                   flow_train_steps=10, flow_lr=2e-5),
+    }
+    fl = {}
+    for name, f in forms.items():
+        fl[name] = run_workload(Xd, yd, 4096, dict(base, **f), 50, 25)
+    fl["workload"] = ("logistic N=5000, d=100, rows ~ N(0, S), S_ij = 0.95^|i-j|, J=4096, "
+                      "50 iterations (25 warm-up), FP32 likelihood")
+    out["toeplitz_flow"] = fl
+    print("[bench] flow forms done", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -218,6 +311,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bf16", action="store_true", help="skip the BF16 precision form")
+    ap.add_argument("--no-other", action="store_true",
+                    help="skip the batched, small-model and flow workloads")
+    ap.add_argument("--other-iters", type=int, default=50)
     ap.add_argument("--eager", action="store_true",
                     help="time eager step/adapt calls for `value` (default: graph replay)")
     ap.add_argument("--ref-iters", type=int, default=300,
@@ -325,6 +421,8 @@ def main():
             "ms_per_step_other_mode": 1e3 * bf["other_mode_seconds"] / args.steps,
             "posterior_vs_f32": z,
         }}
+    if not args.no_other:
+        out["other_workloads"] = other_workloads(args)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(X, y, params, args.cpu_seconds)

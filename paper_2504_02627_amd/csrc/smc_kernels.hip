@@ -473,7 +473,9 @@ __global__ __launch_bounds__(WG, LF_WAVES_PER_SIMD) void k_lf_partial(Dev D, int
     for (int c = 0; c < K1; ++c) {
       const float t0 = D.theta_t[base + c], p0 = D.p_t[base + c], g0 = D.grad_t[base + c];
       const float ph = fmaf(he, g0, p0);
-      th[sb][c] = zero_eps ? t0 : fmaf(eps * minv[kq * K1 + c], ph, t0);
+      // eps = 0 (gradient at the given theta): t0 + 0 * ph = t0 for finite ph;
+      // written without a select, which costs this kernel its schedule
+      th[sb][c] = fmaf(eps * minv[kq * K1 + c], ph, t0);
     }
   }
 
@@ -615,7 +617,7 @@ __global__ __launch_bounds__(WG) void k_lf_partial_bf16(Dev D, int s, int zero_e
         const int k = 32 * c + 8 * g + e;
         const float t0 = D.theta_t[base + k], p0 = D.p_t[base + k], g0 = D.grad_t[base + k];
         const float ph = fmaf(he, g0, p0);
-        thb[c][e] = (__bf16)(zero_eps ? t0 : fmaf(eps * minv[k], ph, t0));
+        thb[c][e] = (__bf16)fmaf(eps * minv[k], ph, t0);
       }
     }
   }
