@@ -194,6 +194,8 @@ void plan(const smc_problem *pr, const smc_params *pa, Layout &L) {
   // row stride: the BF16 kernel reads theta' in chunks of 32 features
   L.DS = bf16 ? 32 * ((maxc2 + 1) / 2) : 16 * maxc2;
   // leapfrog launches: one resident 8-wave work group per compute unit (256 CUs)
+  // (more items per launch for the batched form measured slower: each
+  // feature-tile group already gets its own launch of lf_target items)
   L.lf_target = 256;
   const int ntile = L.Jcap / TJ;
   L.lf_grid = L.lf_target + B * ntile;
