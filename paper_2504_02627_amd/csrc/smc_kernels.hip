@@ -674,52 +674,55 @@ __global__ __launch_bounds__(WG) void k_lf_partial_bf16(Dev D, int s, int zero_e
     }
 }
 
-// grid: (B * tiles per posterior, REDUCE_SLICES); each block reduces a slice
-// of one tile's 128 particles.
-constexpr int REDUCE_SLICES = 8;
+// grid: (B * tiles per posterior, slices of 256 float4 of a tile's 128 x d
+// gradient block); one float4 per thread.  Every thread evaluates the tile's
+// plan itself (uniform loads, no barrier), then issues the row index, the
+// partials (eight splits per round) and the state loads together, so the
+// kernel costs a few memory latencies whatever the split count.
+constexpr int RED_THREADS = 256;
+constexpr int RED_ROUND = 8;
 
-__global__ __launch_bounds__(256) void k_lf_reduce(Dev D, int c2, int s, int zero_eps) {
-  __shared__ Plan spl;
+__global__ __launch_bounds__(RED_THREADS) void k_lf_reduce(Dev D, int c2, int s, int zero_eps) {
   const int ntile = D.Jcap / TJ;
   const int b = blockIdx.x / ntile, tile = blockIdx.x % ntile;
-  if (threadIdx.x == 0) {
-    Plan pl;
-    if (D.posts[b].C2 != c2 || !lf_plan_tile(D, c2, s, b, tile, pl)) pl.b = -1;
-    spl = pl;
-  }
-  __syncthreads();
-  const Plan pl = spl;
-  if (pl.b < 0) return;
+  const int dq = 4 * c2;  // float4 per particle row
+  const int idx = blockIdx.y * RED_THREADS + threadIdx.x;
+  if (D.posts[b].C2 != c2 || idx >= TJ * dq) return;
+  Plan pl;
+  if (!lf_plan_tile(D, c2, s, b, tile, pl)) return;
   const Post P = D.posts[b];
+  const int slot = idx / dq, k4 = idx - slot * dq;
+  const int j = D.perm[P.row0 + tile * TJ + slot];
+  const float4 *g0p = reinterpret_cast<const float4 *>(D.gpart + (long long)pl.wbase * TJ * D.DS);
+  const long long sstride = (long long)TJ * D.DS / 4;  // float4 between splits
+  const long long o4 = (long long)slot * D.DS / 4 + k4;
+  // ordered sum over the splits: ((p0 + p1) + p2) + ...
+  float4 G = g0p[o4];
+  for (int sp0 = 1; sp0 < pl.S; sp0 += RED_ROUND) {
+    float4 v[RED_ROUND];
+#pragma unroll
+    for (int u = 0; u < RED_ROUND; ++u)
+      if (sp0 + u < pl.S) v[u] = g0p[(sp0 + u) * sstride + o4];
+#pragma unroll
+    for (int u = 0; u < RED_ROUND; ++u)
+      if (sp0 + u < pl.S) {
+        G.x += v[u].x;
+        G.y += v[u].y;
+        G.z += v[u].z;
+        G.w += v[u].w;
+      }
+  }
+  const long long row = P.row0 + j;
+  const long long e = (row * D.DS) / 4 + k4;
+  const float4 t0 = reinterpret_cast<const float4 *>(D.theta_t)[e];
+  const float4 p0 = reinterpret_cast<const float4 *>(D.p_t)[e];
+  const float4 g0 = reinterpret_cast<const float4 *>(D.grad_t)[e];
+  const float4 mv = reinterpret_cast<const float4 *>(D.minv + (long long)b * D.DS)[k4];
+  if (D.n[row] <= s) return;
   const float eps = zero_eps ? 0.f : (float)D.ps[b].eps;
   const float he = 0.5f * eps;
   const float inv_pv = (float)(1.0 / D.prior_var);
-  const float *minv = D.minv + (long long)b * D.DS;
-  const int dq = 4 * c2;  // float4 per particle row
-  constexpr int SPS = TJ / REDUCE_SLICES;
-  const int slot0 = blockIdx.y * SPS;
-  const float4 *g0p = reinterpret_cast<const float4 *>(D.gpart + (long long)pl.wbase * TJ * D.DS);
-  const long long sstride = (long long)TJ * D.DS / 4;  // float4 between splits
-  for (int idx = threadIdx.x; idx < SPS * dq; idx += blockDim.x) {
-    const int slot = slot0 + idx / dq, k4 = idx % dq;
-    const int j = D.perm[P.row0 + tile * TJ + slot];
-    const long long row = P.row0 + j;
-    if (D.n[row] <= s) continue;
-    const long long o4 = (long long)slot * D.DS / 4 + k4;
-    float4 G = g0p[o4];
-    for (int sp = 1; sp < pl.S; ++sp) {
-      const float4 v = g0p[sp * sstride + o4];
-      G.x += v.x;
-      G.y += v.y;
-      G.z += v.z;
-      G.w += v.w;
-    }
-    const long long e = (row * D.DS) / 4 + k4;
-    const float4 t0 = reinterpret_cast<const float4 *>(D.theta_t)[e];
-    const float4 p0 = reinterpret_cast<const float4 *>(D.p_t)[e];
-    const float4 g0 = reinterpret_cast<const float4 *>(D.grad_t)[e];
-    const float4 mv = reinterpret_cast<const float4 *>(minv)[k4];
-    float4 th1, pn, gn;
+  float4 th1, pn, gn;
 #define LF_LANE(c)                                       \
   {                                                      \
     const float ph = fmaf(he, g0.c, p0.c);               \
@@ -727,19 +730,18 @@ __global__ __launch_bounds__(256) void k_lf_reduce(Dev D, int c2, int s, int zer
     gn.c = G.c - th1.c * inv_pv;                         \
     pn.c = fmaf(he, gn.c, ph);                           \
   }
-    if (zero_eps == 2) {
-      // gradient only: theta' was written by the caller
-      gn = make_float4(G.x - t0.x * inv_pv, G.y - t0.y * inv_pv, G.z - t0.z * inv_pv,
-                       G.w - t0.w * inv_pv);
-      reinterpret_cast<float4 *>(D.grad_t)[e] = gn;
-      continue;
-    }
-    LF_LANE(x) LF_LANE(y) LF_LANE(z) LF_LANE(w)
-#undef LF_LANE
-    reinterpret_cast<float4 *>(D.theta_t)[e] = th1;
-    reinterpret_cast<float4 *>(D.p_t)[e] = pn;
+  if (zero_eps == 2) {
+    // gradient only: theta' was written by the caller
+    gn = make_float4(G.x - t0.x * inv_pv, G.y - t0.y * inv_pv, G.z - t0.z * inv_pv,
+                     G.w - t0.w * inv_pv);
     reinterpret_cast<float4 *>(D.grad_t)[e] = gn;
+    return;
   }
+  LF_LANE(x) LF_LANE(y) LF_LANE(z) LF_LANE(w)
+#undef LF_LANE
+  reinterpret_cast<float4 *>(D.theta_t)[e] = th1;
+  reinterpret_cast<float4 *>(D.p_t)[e] = pn;
+  reinterpret_cast<float4 *>(D.grad_t)[e] = gn;
 }
 
 template <int C2>
@@ -752,8 +754,10 @@ static hipError_t launch_lf_c2(const Dev &D, int step, int zero_eps, hipStream_t
 }
 
 hipError_t launch_lf_reduce(const Dev &D, int c2, int step, int zero_eps, hipStream_t st) {
-  hipLaunchKernelGGL(k_lf_reduce, dim3(D.B * (D.Jcap / TJ), REDUCE_SLICES), dim3(256), 0, st, D, c2,
-                     step, zero_eps);
+  // TJ * 4 c2 float4 per tile
+  const int slices = (TJ * 4 * c2 + RED_THREADS - 1) / RED_THREADS;
+  hipLaunchKernelGGL(k_lf_reduce, dim3(D.B * (D.Jcap / TJ), slices), dim3(RED_THREADS), 0, st, D,
+                     c2, step, zero_eps);
   return hipGetLastError();
 }
 
