@@ -193,12 +193,13 @@ void plan(const smc_problem *pr, const smc_params *pa, Layout &L) {
   }
   // row stride: the BF16 kernel reads theta' in chunks of 32 features
   L.DS = bf16 ? 32 * ((maxc2 + 1) / 2) : 16 * maxc2;
-  // leapfrog launches: one resident 8-wave work group per compute unit (256 CUs)
+  // leapfrog launches: lf_target items per resident 8-wave work group of a
+  // compute unit (256 CUs; two groups for the FP32 kernel up to d = 128)
   // (more items per launch for the batched form measured slower: each
-  // feature-tile group already gets its own launch of lf_target items)
+  // feature-tile group already gets its own launch)
   L.lf_target = 256;
   const int ntile = L.Jcap / TJ;
-  L.lf_grid = L.lf_target + B * ntile;
+  L.lf_grid = L.lf_target * lf_groups_per_cu(bf16, 1) + B * ntile;
   // log-likelihood pass: every tile, static splits
   long long U = 0;
   for (int b = 0; b < B; ++b) U += (long long)ntile * L.hp[b].NT;

@@ -120,7 +120,7 @@ struct Dev {                    // pointers carved from the workspace
   double *means;                // [B][2][DS]
   float *minv;                  // [B][DS] inverse mass diagonal
   int *primes;                  // NPRIMES
-  int lf_target;                // target work-group count of a leapfrog launch
+  int lf_target;                // work groups per leapfrog launch and resident group per compute unit
   int lf_grid;                  // grid of a leapfrog launch
   // flow preconditioner (precond FLOW, one posterior)
   int flow;
@@ -151,6 +151,14 @@ hipError_t launch_pack_one(const Dev &D, const void *X, const float *y, int x_dt
 hipError_t launch_pack_bf16(const Dev &D, const void *X, const float *y, int x_dtype,
                             const HostPost &P, hipStream_t st);
 // uint4 per lane and 32-row tile in the BF16 packing: [A: 2 KC | B: C2 | y: 2] (+1 if even)
+// Resident leapfrog work groups (8 waves each) per compute unit.  The FP32
+// kernel for up to 8 feature tiles is built for two (at most 128 VGPRs, LDS at
+// most 80 KB); wider FP32 problems and the BF16 kernel (about 170 VGPRs at
+// d = 100) run one.
+__host__ __device__ constexpr int lf_groups_per_cu(bool bf16, int c2) {
+  return (!bf16 && c2 <= 8) ? 2 : 1;
+}
+
 __host__ __device__ constexpr int bf16_lane_stride(int c2) {
   return ((2 * ((c2 + 1) / 2) + c2 + 2) % 2 == 0) ? 2 * ((c2 + 1) / 2) + c2 + 3
                                                    : 2 * ((c2 + 1) / 2) + c2 + 2;

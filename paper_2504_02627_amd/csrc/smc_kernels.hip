@@ -296,13 +296,11 @@ struct Plan {
 };
 
 constexpr int LF_MAX_SPLIT = 64;
-// resident waves per SIMD asked of the fused leapfrog kernel: one 8-wave work
-// group per compute unit (about 150 VGPRs at d = 100)
-constexpr int LF_WAVES_PER_SIMD = 2;
 
 // Deterministic plan of a leapfrog launch at step s, computed identically by
-// every work group from the active counts.  About lf_target work items (one
-// wave of resident work groups) are spread over the active tiles in proportion
+// every work group from the active counts.  About lf_target times the resident
+// work groups per compute unit items (one wave of resident work groups on 256
+// compute units) are spread over the active tiles in proportion
 // to their data tiles; within a posterior the tiles get split counts that
 // differ by at most one, so items carry nearly equal work.  Items are
 // enumerated posterior by posterior, tile by tile, split by split.
@@ -330,7 +328,8 @@ __device__ bool lf_post_plan(const Dev &D, int c2, int s, int bq, PostPlan &out)
     int items = 0, base = 0, extra = 0;
     if (T > 0) {
       const int NU = lf_units(D, P);
-      long long G = ((long long)D.lf_target * T * NU) / U;  // this posterior's share
+      // this posterior's share of the launch's items
+      long long G = ((long long)D.lf_target * lf_groups_per_cu(D.bf16, c2) * T * NU) / U;
       if (G < T) G = T;
       const long long cap = (long long)T * (NU < LF_MAX_SPLIT ? NU : LF_MAX_SPLIT);
       if (G > cap) G = cap;
@@ -442,7 +441,7 @@ __device__ __forceinline__ void stage_issue(float4 *xs, const float4 *__restrict
 }
 
 template <int C2>
-__global__ __launch_bounds__(WG, LF_WAVES_PER_SIMD) void k_lf_partial(Dev D, int s, int zero_eps) {
+__global__ __launch_bounds__(WG, 2 * lf_groups_per_cu(false, C2)) void k_lf_partial(Dev D, int s, int zero_eps) {
   constexpr int K1 = 4 * C2;
   using TL = Tiles<C2>;
   __shared__ float4 xs[2][TL::STAGE];
