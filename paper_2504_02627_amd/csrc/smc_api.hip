@@ -59,6 +59,7 @@ struct Layout {
   size_t o_posts, o_ps, o_xab, o_xbf, o_theta, o_grad, o_theta_t, o_p_t, o_grad_t;
   size_t o_logpi, o_logpi_t, o_logw, o_h, o_l, o_H0, o_dH, o_alpha, o_ca, o_cg;
   size_t o_n, o_perm, o_active, o_anc, o_acc, o_cdf, o_gpart, o_tilecnt, o_llpart;
+  size_t o_lf_post = 0, o_lf_items = 0, o_lf_count = 0;
   size_t o_items, o_colpart, o_means, o_minv, o_primes;
   FlowNet F;
   size_t o_fz = 0, o_fz0 = 0, o_fgz = 0, o_fld0 = 0, o_fld1 = 0, o_fm = 0, o_fL = 0, o_fAf = 0,
@@ -255,6 +256,9 @@ void plan(const smc_problem *pr, const smc_params *pa, Layout &L) {
   L.o_n = take(c, rows * 4);
   L.o_perm = take(c, rows * 4);
   L.o_active = take(c, (size_t)B * (L.nmax + 1) * 4);
+  L.o_lf_post = take(c, (size_t)L.nmax * B * sizeof(int4));
+  L.o_lf_items = take(c, L.groups.size() * (size_t)L.nmax * L.lf_grid * sizeof(int4));
+  L.o_lf_count = take(c, L.groups.size() * (size_t)L.nmax * sizeof(int));
   L.o_anc = take(c, rows * 4);
   L.o_acc = take(c, rows * 4);
   L.o_cdf = take(c, rows * 8);
@@ -422,6 +426,15 @@ smc_status smc_init(const smc_problem *prob, const smc_params *par, void *worksp
   D.n = (int *)(w + L.o_n);
   D.perm = (int *)(w + L.o_perm);
   D.active = (int *)(w + L.o_active);
+  D.lf_post = (int4 *)(w + L.o_lf_post);
+  D.lf_items = (int4 *)(w + L.o_lf_items);
+  D.lf_count = (int *)(w + L.o_lf_count);
+  D.ngroups = (int)L.groups.size();
+  for (int c2 = 0; c2 <= MAX_C2; ++c2) D.c2_group[c2] = 0;
+  for (int g = 0; g < D.ngroups; ++g) {
+    D.group_c2[g] = L.groups[g].x;
+    D.c2_group[L.groups[g].x] = g;
+  }
   D.anc = (int *)(w + L.o_anc);
   D.accepted = (int *)(w + L.o_acc);
   D.cdf = (unsigned long long *)(w + L.o_cdf);
@@ -512,6 +525,7 @@ smc_status smc_init(const smc_problem *prob, const smc_params *par, void *worksp
     if (D.bf16) CKI(launch_pack_bf16(D, prob->X[b], prob->y[b], prob->x_dtype, L.hp[b], ctx->st));
   }
   CKI(launch_init_theta(D, theta0, ctx->st));
+  CKI(launch_lf_plan(D, ctx->st));
   for (int c2 : ctx->c2s) CKI(launch_leapfrog(D, c2, 0, 1, ctx->st));
   for (const int3 &g : ctx->ll_groups) CKI(launch_loglik(D, g.x, g.y, g.z, ctx->st));
   CKI(launch_init_weights(D, ctx->st));
@@ -568,6 +582,7 @@ smc_status enqueue_step(smc_ctx *ctx, const smc_inject *inject) {
   CK(launch_setup(D, inject ? inject->momenta : nullptr, 0, ctx->st));
   if (D.flow) CK(launch_flow_begin(D, F, ctx->st));
   CK(launch_sort(D, ctx->st));
+  CK(launch_lf_plan(D, ctx->st));
   for (int s = 0; s < D.nmax; ++s)
     for (int c2 : ctx->c2s) {
       if (D.flow) {

@@ -122,6 +122,13 @@ struct Dev {                    // pointers carved from the workspace
   int *primes;                  // NPRIMES
   int lf_target;                // work groups per leapfrog launch and resident group per compute unit
   int lf_grid;                  // grid of a leapfrog launch
+  // leapfrog work plan, written once per iteration from the active counts:
+  int4 *lf_post;                // [nmax][B] (first item, splits per tile, tiles with one more, tiles)
+  int4 *lf_items;               // [group][nmax][lf_grid] (posterior, tile, split | S << 16, first item of tile)
+  int *lf_count;                // [group][nmax] items of a launch
+  int ngroups;                  // feature-tile groups (one leapfrog launch each per step)
+  int group_c2[MAX_C2];         // C2 of group g
+  int c2_group[MAX_C2 + 1];     // group of C2
   // flow preconditioner (precond FLOW, one posterior)
   int flow;
   float *fz, *fz0, *fgz;        // latent position, pre-move latent, latent gradient [Jcap][DS]
@@ -150,7 +157,6 @@ hipError_t launch_pack_one(const Dev &D, const void *X, const float *y, int x_dt
                            const HostPost &P, hipStream_t st);
 hipError_t launch_pack_bf16(const Dev &D, const void *X, const float *y, int x_dtype,
                             const HostPost &P, hipStream_t st);
-// uint4 per lane and 32-row tile in the BF16 packing: [A: 2 KC | B: C2 | y: 2] (+1 if even)
 // Resident leapfrog work groups (8 waves each) per compute unit.  The FP32
 // kernel for up to 8 feature tiles is built for two (at most 128 VGPRs, LDS at
 // most 80 KB); wider FP32 problems and the BF16 kernel (about 170 VGPRs at
@@ -159,6 +165,7 @@ __host__ __device__ constexpr int lf_groups_per_cu(bool bf16, int c2) {
   return (!bf16 && c2 <= 8) ? 2 : 1;
 }
 
+// uint4 per lane and 32-row tile in the BF16 packing: [A: 2 KC | B: C2 | y: 2] (+1 if even)
 __host__ __device__ constexpr int bf16_lane_stride(int c2) {
   return ((2 * ((c2 + 1) / 2) + c2 + 2) % 2 == 0) ? 2 * ((c2 + 1) / 2) + c2 + 3
                                                    : 2 * ((c2 + 1) / 2) + c2 + 2;
@@ -174,6 +181,9 @@ hipError_t launch_mass(const Dev &D, int write_minv, hipStream_t st);
 hipError_t launch_gather(const Dev &D, int *anc_out, hipStream_t st);
 hipError_t launch_setup(const Dev &D, const float *momenta, int init_mode, hipStream_t st);
 hipError_t launch_sort(const Dev &D, hipStream_t st);
+// Work plan of every leapfrog launch of the iteration (after the sort, or the
+// initial active counts).
+hipError_t launch_lf_plan(const Dev &D, hipStream_t st);
 hipError_t launch_leapfrog(const Dev &D, int c2, int step, int zero_eps, hipStream_t st);
 hipError_t launch_lf_partial(const Dev &D, int c2, int step, int zero_eps, hipStream_t st);
 // mode 0: full step; 1: zero step size (gradient at theta, state rewritten);

@@ -297,101 +297,121 @@ struct Plan {
 
 constexpr int LF_MAX_SPLIT = 64;
 
-// Deterministic plan of a leapfrog launch at step s, computed identically by
-// every work group from the active counts.  About lf_target times the resident
-// work groups per compute unit items (one wave of resident work groups on 256
-// compute units) are spread over the active tiles in proportion
-// to their data tiles; within a posterior the tiles get split counts that
-// differ by at most one, so items carry nearly equal work.  Items are
-// enumerated posterior by posterior, tile by tile, split by split.
-struct PostPlan {
-  int T, base, extra, first;  // active tiles, splits per tile (>= 1), tiles with one more, first item
-};
+// Plan of the leapfrog launches at step s, written once per iteration by
+// k_lf_plan from the active counts (one work group per step and feature-tile
+// group).  About lf_target times the resident work groups per compute unit
+// items (one wave of resident work groups on 256 compute units) are spread
+// over the active tiles in proportion to their data tiles; within a posterior
+// the tiles get split counts that differ by at most one, so items carry nearly
+// equal work.  Items are enumerated posterior by posterior, tile by tile, split
+// by split.  Per posterior the table lf_post holds (first item, splits per
+// tile, tiles with one more split, active tiles); per launch lf_items holds
+// each item's (posterior, tile, split | S << 16, first item of its tile).
 
 // data tiles of a posterior in the leapfrog kernels: 16-row tiles (FP32) or
 // 32-row tiles (BF16)
 __device__ __forceinline__ int lf_units(const Dev &D, const Post &P) { return D.bf16 ? P.NT2 : P.NT; }
 
-__device__ bool lf_post_plan(const Dev &D, int c2, int s, int bq, PostPlan &out) {
-  long long U = 0;
-  for (int b = 0; b < D.B; ++b) {
-    const Post &P = D.posts[b];
-    if (P.C2 != c2) continue;
-    U += (long long)((D.active[b * (D.nmax + 1) + s] + TJ - 1) / TJ) * lf_units(D, P);
-  }
-  if (U == 0) return false;
-  int first = 0;
-  for (int b = 0; b < D.B; ++b) {
-    const Post &P = D.posts[b];
-    if (P.C2 != c2) continue;
-    const int T = (D.active[b * (D.nmax + 1) + s] + TJ - 1) / TJ;
-    int items = 0, base = 0, extra = 0;
-    if (T > 0) {
-      const int NU = lf_units(D, P);
-      // this posterior's share of the launch's items
-      long long G = ((long long)D.lf_target * lf_groups_per_cu(D.bf16, c2) * T * NU) / U;
-      if (G < T) G = T;
-      const long long cap = (long long)T * (NU < LF_MAX_SPLIT ? NU : LF_MAX_SPLIT);
-      if (G > cap) G = cap;
-      base = (int)(G / T);
-      extra = (int)(G % T);
-      items = (int)G;
-    }
-    if (b == bq) {
-      out.T = T;
-      out.base = base;
-      out.extra = extra;
-      out.first = first;
-      return T > 0;
-    }
-    first += items;
-  }
-  return false;
-}
+constexpr int PLAN_THREADS = 256;
 
-__device__ __forceinline__ int tile_first_item(const PostPlan &q, int tile) {
-  return q.first + tile * q.base + (tile < q.extra ? tile : q.extra);
-}
-
-__device__ bool lf_plan(const Dev &D, int c2, int s, int wid, Plan &pl) {
+__global__ __launch_bounds__(PLAN_THREADS) void k_lf_plan(Dev D) {
+  __shared__ long long red[PLAN_THREADS];
+  __shared__ int scan[PLAN_THREADS];
+  const int s = blockIdx.x, g = blockIdx.y, c2 = D.group_c2[g], tid = threadIdx.x;
+  const int *act = D.active + s;
+  const int stride = D.nmax + 1;
+  // U: data tiles times active particle tiles over the group's posteriors
+  long long u = 0;
+  for (int b = tid; b < D.B; b += PLAN_THREADS) {
+    const Post &P = D.posts[b];
+    if (P.C2 == c2) u += (long long)((act[b * stride] + TJ - 1) / TJ) * lf_units(D, P);
+  }
+  red[tid] = u;
+  __syncthreads();
+  for (int h = PLAN_THREADS / 2; h > 0; h >>= 1) {
+    if (tid < h) red[tid] += red[tid + h];
+    __syncthreads();
+  }
+  const long long U = red[0];
+  const long long share = (long long)D.lf_target * lf_groups_per_cu(D.bf16, c2);
+  // per posterior: item count, splits per tile; exclusive prefix of the counts
+  int run = 0;
+  for (int b0 = 0; b0 < D.B; b0 += PLAN_THREADS) {
+    const int b = b0 + tid;
+    int T = 0, items = 0, base = 0, extra = 0;
+    bool mine = false;
+    if (b < D.B) {
+      const Post &P = D.posts[b];
+      mine = P.C2 == c2;
+      if (mine) T = (act[b * stride] + TJ - 1) / TJ;
+      if (T > 0 && U > 0) {
+        const int NU = lf_units(D, P);
+        long long G = (share * T * NU) / U;  // this posterior's share of the items
+        if (G < T) G = T;
+        const long long cap = (long long)T * (NU < LF_MAX_SPLIT ? NU : LF_MAX_SPLIT);
+        if (G > cap) G = cap;
+        base = (int)(G / T);
+        extra = (int)(G % T);
+        items = (int)G;
+      } else {
+        T = 0;
+      }
+    }
+    __syncthreads();  // scan[] of the previous chunk has been read
+    scan[tid] = items;
+    __syncthreads();
+    for (int h = 1; h < PLAN_THREADS; h <<= 1) {
+      const int v = tid >= h ? scan[tid - h] : 0;
+      __syncthreads();
+      scan[tid] += v;
+      __syncthreads();
+    }
+    if (mine) D.lf_post[(long long)s * D.B + b] = make_int4(run + scan[tid] - items, base, extra, T);
+    run += scan[PLAN_THREADS - 1];
+  }
+  if (tid == 0) D.lf_count[g * D.nmax + s] = run < D.lf_grid ? run : D.lf_grid;
+  __syncthreads();  // lf_post of this block is visible to the whole block
+  int4 *it = D.lf_items + ((long long)g * D.nmax + s) * D.lf_grid;
   for (int b = 0; b < D.B; ++b) {
     if (D.posts[b].C2 != c2) continue;
-    PostPlan q;
-    if (!lf_post_plan(D, c2, s, b, q)) continue;
-    const int items = q.T * q.base + q.extra;
-    if (wid >= q.first + items) continue;
-    if (wid < q.first) return false;
-    const int w = wid - q.first;
-    const int big = q.extra * (q.base + 1);
-    int tile, split, S;
-    if (w < big) {
-      tile = w / (q.base + 1);
-      split = w % (q.base + 1);
-      S = q.base + 1;
-    } else {
-      tile = q.extra + (w - big) / q.base;
-      split = (w - big) % q.base;
-      S = q.base;
+    const int4 q = D.lf_post[(long long)s * D.B + b];
+    if (q.w == 0) continue;
+    const int items = q.w * q.y + q.z, big = q.z * (q.y + 1);
+    for (int w = tid; w < items; w += PLAN_THREADS) {
+      int tile, split, S;
+      if (w < big) {
+        tile = w / (q.y + 1);
+        split = w % (q.y + 1);
+        S = q.y + 1;
+      } else {
+        tile = q.z + (w - big) / q.y;
+        split = (w - big) % q.y;
+        S = q.y;
+      }
+      const int wid = q.x + w;
+      if (wid < D.lf_grid)
+        it[wid] = make_int4(b, tile, split | (S << 16), q.x + tile * q.y + (tile < q.z ? tile : q.z));
     }
-    pl.b = b;
-    pl.tile = tile;
-    pl.split = split;
-    pl.S = S;
-    pl.wbase = q.first + tile * q.base + (tile < q.extra ? tile : q.extra);
-    return true;
   }
-  return false;
 }
 
-// Plan entry of a given (posterior, tile): its split count and first item.
-__device__ bool lf_plan_tile(const Dev &D, int c2, int s, int bq, int tile, Plan &pl) {
-  PostPlan q;
-  if (!lf_post_plan(D, c2, s, bq, q) || tile >= q.T) return false;
-  pl.b = bq;
-  pl.tile = tile;
-  pl.split = 0;
-  pl.S = q.base + (tile < q.extra ? 1 : 0);
-  pl.wbase = tile_first_item(q, tile);
+hipError_t launch_lf_plan(const Dev &D, hipStream_t st) {
+  hipLaunchKernelGGL(k_lf_plan, dim3(D.nmax, D.ngroups), dim3(PLAN_THREADS), 0, st, D);
+  return hipGetLastError();
+}
+
+// Item of this work group in a leapfrog launch (false: nothing to do).
+__device__ __forceinline__ bool lf_item(const Dev &D, int c2, int s, int wid, Plan &pl) {
+  const int g = D.c2_group[c2];
+  const long long slot = (long long)g * D.nmax + s;
+  const int cnt = D.lf_count[slot];
+  const int4 e = D.lf_items[slot * D.lf_grid + wid];
+  if (wid >= cnt) return false;
+  pl.b = e.x;
+  pl.tile = e.y;
+  pl.split = e.z & 0xffff;
+  pl.S = e.z >> 16;
+  pl.wbase = e.w;
   return true;
 }
 
@@ -448,7 +468,7 @@ __global__ __launch_bounds__(WG, 2 * lf_groups_per_cu(false, C2)) void k_lf_part
   __shared__ Plan spl;
   if (threadIdx.x == 0) {
     Plan pl;
-    if (!lf_plan(D, C2, s, blockIdx.x, pl)) pl.b = -1;
+    if (!lf_item(D, C2, s, blockIdx.x, pl)) pl.b = -1;
     spl = pl;
   }
   __syncthreads();
@@ -590,7 +610,7 @@ __global__ __launch_bounds__(WG) void k_lf_partial_bf16(Dev D, int s, int zero_e
   __shared__ Plan spl;
   if (threadIdx.x == 0) {
     Plan pl;
-    if (!lf_plan(D, C2, s, blockIdx.x, pl)) pl.b = -1;
+    if (!lf_item(D, C2, s, blockIdx.x, pl)) pl.b = -1;
     spl = pl;
   }
   __syncthreads();
@@ -674,10 +694,10 @@ __global__ __launch_bounds__(WG) void k_lf_partial_bf16(Dev D, int s, int zero_e
 }
 
 // grid: (B * tiles per posterior, slices of 256 float4 of a tile's 128 x d
-// gradient block); one float4 per thread.  Every thread evaluates the tile's
-// plan itself (uniform loads, no barrier), then issues the row index, the
-// partials (eight splits per round) and the state loads together, so the
-// kernel costs a few memory latencies whatever the split count.
+// gradient block); one float4 per thread.  Every thread reads the tile's plan
+// itself (uniform loads, no barrier), then issues the row index, the partials
+// (eight splits per round) and the state loads together, so the kernel costs
+// a few memory latencies whatever the split count.
 constexpr int RED_THREADS = 256;
 constexpr int RED_ROUND = 8;
 
@@ -686,10 +706,13 @@ __global__ __launch_bounds__(RED_THREADS) void k_lf_reduce(Dev D, int c2, int s,
   const int b = blockIdx.x / ntile, tile = blockIdx.x % ntile;
   const int dq = 4 * c2;  // float4 per particle row
   const int idx = blockIdx.y * RED_THREADS + threadIdx.x;
-  if (D.posts[b].C2 != c2 || idx >= TJ * dq) return;
-  Plan pl;
-  if (!lf_plan_tile(D, c2, s, b, tile, pl)) return;
+  if (idx >= TJ * dq) return;
   const Post P = D.posts[b];
+  const int4 q = D.lf_post[(long long)s * D.B + b];
+  if (P.C2 != c2 || tile >= q.w) return;
+  Plan pl;
+  pl.S = q.y + (tile < q.z ? 1 : 0);
+  pl.wbase = q.x + tile * q.y + (tile < q.z ? tile : q.z);
   const int slot = idx / dq, k4 = idx - slot * dq;
   const int j = D.perm[P.row0 + tile * TJ + slot];
   const float4 *g0p = reinterpret_cast<const float4 *>(D.gpart + (long long)pl.wbase * TJ * D.DS);
