@@ -50,6 +50,7 @@ namespace {
 struct Layout {
   int B = 0, J = 0, Jcap = 0, DS = 0, nmax = 0;
   int lf_target = 0, lf_grid = 0, ll_smax = 0, ll_nitems = 0, col_chunks = 0;
+  int gpart_slots = 0, goff[MAX_C2] = {};
   std::vector<HostPost> hp;
   std::vector<Post> posts;
   std::vector<int4> items;
@@ -201,10 +202,8 @@ void plan(const smc_problem *pr, const smc_params *pa, Layout &L) {
   L.lf_target = 256;
   const int ntile = L.Jcap / TJ;
   L.lf_grid = L.lf_target * lf_groups_per_cu(bf16, 1) + B * ntile;
-  // log-likelihood pass: every tile, static splits
-  long long U = 0;
-  for (int b = 0; b < B; ++b) U += (long long)ntile * L.hp[b].NT;
-  const long long chunk = std::max(1LL, (U + L.lf_target - 1) / L.lf_target);
+  // log-likelihood pass: every tile, static splits, about lf_target items per
+  // launch (one launch per feature-tile group)
   L.items.clear();
   L.ll_smax = 1;
   // items grouped by feature-tile count C2: one launch per group covers
@@ -217,6 +216,10 @@ void plan(const smc_problem *pr, const smc_params *pa, Layout &L) {
   }
   for (auto &g : L.groups) {
     g.y = (int)L.items.size();
+    long long U = 0;
+    for (int b = 0; b < B; ++b)
+      if (L.hp[b].C2 == g.x) U += (long long)ntile * L.hp[b].NT;
+    const long long chunk = std::max(1LL, (U + L.lf_target - 1) / L.lf_target);
     for (int b = 0; b < B; ++b) {
       if (L.hp[b].C2 != g.x) continue;
       long long S = (L.hp[b].NT + chunk - 1) / chunk;
@@ -262,7 +265,16 @@ void plan(const smc_problem *pr, const smc_params *pa, Layout &L) {
   L.o_anc = take(c, rows * 4);
   L.o_acc = take(c, rows * 4);
   L.o_cdf = take(c, rows * 8);
-  L.o_gpart = take(c, (size_t)L.lf_grid * TJ * L.DS * sizeof(float));
+  // partial gradients: each feature-tile group owns the slots of its largest
+  // launch, so one reduction per step serves every group
+  L.gpart_slots = 0;
+  for (size_t g = 0; g < L.groups.size(); ++g) {
+    int Bg = 0;
+    for (int b = 0; b < B; ++b) Bg += L.hp[b].C2 == L.groups[g].x;
+    L.goff[g] = L.gpart_slots;
+    L.gpart_slots += L.lf_target * lf_groups_per_cu(bf16, L.groups[g].x) + Bg * ntile;
+  }
+  L.o_gpart = take(c, (size_t)L.gpart_slots * TJ * L.DS * sizeof(float));
   L.o_tilecnt = take(c, (size_t)B * ntile * 4);
   L.o_llpart = take(c, (size_t)L.ll_smax * rows * sizeof(float2));
   L.o_items = take(c, (size_t)L.ll_nitems * sizeof(int4));
@@ -434,12 +446,13 @@ smc_status smc_init(const smc_problem *prob, const smc_params *par, void *worksp
   for (int g = 0; g < D.ngroups; ++g) {
     D.group_c2[g] = L.groups[g].x;
     D.c2_group[L.groups[g].x] = g;
+    D.lf_goff[g] = L.goff[g];
   }
   D.anc = (int *)(w + L.o_anc);
   D.accepted = (int *)(w + L.o_acc);
   D.cdf = (unsigned long long *)(w + L.o_cdf);
   D.gpart = (float *)(w + L.o_gpart);
-  D.gpart_slots = L.lf_grid;
+  D.gpart_slots = L.gpart_slots;
   D.tilecnt = (int *)(w + L.o_tilecnt);
   D.llpart = (float2 *)(w + L.o_llpart);
   D.ll_smax = L.ll_smax;
@@ -526,7 +539,8 @@ smc_status smc_init(const smc_problem *prob, const smc_params *par, void *worksp
   }
   CKI(launch_init_theta(D, theta0, ctx->st));
   CKI(launch_lf_plan(D, ctx->st));
-  for (int c2 : ctx->c2s) CKI(launch_leapfrog(D, c2, 0, 1, ctx->st));
+  for (int c2 : ctx->c2s) CKI(launch_lf_partial(D, c2, 0, 1, ctx->st));
+  CKI(launch_lf_reduce(D, 0, 1, ctx->st));
   for (const int3 &g : ctx->ll_groups) CKI(launch_loglik(D, g.x, g.y, g.z, ctx->st));
   CKI(launch_init_weights(D, ctx->st));
   CKI(launch_ess(D, 0, ctx->st));
@@ -583,7 +597,7 @@ smc_status enqueue_step(smc_ctx *ctx, const smc_inject *inject) {
   if (D.flow) CK(launch_flow_begin(D, F, ctx->st));
   CK(launch_sort(D, ctx->st));
   CK(launch_lf_plan(D, ctx->st));
-  for (int s = 0; s < D.nmax; ++s)
+  for (int s = 0; s < D.nmax; ++s) {
     for (int c2 : ctx->c2s) {
       if (D.flow) {
         CK(timed_begin(ctx, 3, ei));
@@ -593,15 +607,17 @@ smc_status enqueue_step(smc_ctx *ctx, const smc_inject *inject) {
       CK(timed_begin(ctx, 0, ei));
       CK(launch_lf_partial(D, c2, s, D.flow ? 1 : 0, ctx->st));
       CK(timed_end(ctx, ei));
-      CK(timed_begin(ctx, 2, ei));
-      CK(launch_lf_reduce(D, c2, s, D.flow ? 2 : 0, ctx->st));
-      CK(timed_end(ctx, ei));
-      if (D.flow) {
-        CK(timed_begin(ctx, 3, ei));
-        CK(launch_flow_kick(D, F, s, ctx->st));
-        CK(timed_end(ctx, ei));
-      }
     }
+    // one reduction for all groups (disjoint partial slots)
+    CK(timed_begin(ctx, 2, ei));
+    CK(launch_lf_reduce(D, s, D.flow ? 2 : 0, ctx->st));
+    CK(timed_end(ctx, ei));
+    if (D.flow) {
+      CK(timed_begin(ctx, 3, ei));
+      CK(launch_flow_kick(D, F, s, ctx->st));
+      CK(timed_end(ctx, ei));
+    }
+  }
   for (const int3 &g : ctx->ll_groups) {
     CK(timed_begin(ctx, 1, ei));
     CK(launch_loglik(D, g.x, g.y, g.z, ctx->st));

@@ -129,6 +129,7 @@ struct Dev {                    // pointers carved from the workspace
   int ngroups;                  // feature-tile groups (one leapfrog launch each per step)
   int group_c2[MAX_C2];         // C2 of group g
   int c2_group[MAX_C2 + 1];     // group of C2
+  int lf_goff[MAX_C2];          // first partial-gradient slot of group g (groups own disjoint slots)
   // flow preconditioner (precond FLOW, one posterior)
   int flow;
   float *fz, *fz0, *fgz;        // latent position, pre-move latent, latent gradient [Jcap][DS]
@@ -184,11 +185,10 @@ hipError_t launch_sort(const Dev &D, hipStream_t st);
 // Work plan of every leapfrog launch of the iteration (after the sort, or the
 // initial active counts).
 hipError_t launch_lf_plan(const Dev &D, hipStream_t st);
-hipError_t launch_leapfrog(const Dev &D, int c2, int step, int zero_eps, hipStream_t st);
 hipError_t launch_lf_partial(const Dev &D, int c2, int step, int zero_eps, hipStream_t st);
 // mode 0: full step; 1: zero step size (gradient at theta, state rewritten);
 // 2: gradient only (theta given by the caller, p untouched)
-hipError_t launch_lf_reduce(const Dev &D, int c2, int step, int mode, hipStream_t st);
+hipError_t launch_lf_reduce(const Dev &D, int step, int mode, hipStream_t st);
 hipError_t launch_loglik(const Dev &D, int c2, int first, int count, hipStream_t st);
 hipError_t launch_weights(const Dev &D, const double *mh_u, int init_mode, hipStream_t st);
 hipError_t launch_chees(const Dev &D, hipStream_t st);

@@ -548,8 +548,8 @@ __global__ __launch_bounds__(WG, 2 * lf_groups_per_cu(false, C2)) void k_lf_part
     cur ^= 1;
   }
 
-  // partial gradient of this split: gpart[work item][slot][k]
-  float *gp = D.gpart + (long long)blockIdx.x * TJ * D.DS;
+  // partial gradient of this split: gpart[group's first slot + work item][slot][k]
+  float *gp = D.gpart + (long long)(D.lf_goff[D.c2_group[C2]] + blockIdx.x) * TJ * D.DS;
 #pragma unroll
   for (int sb = 0; sb < SUB; ++sb)
 #pragma unroll
@@ -683,7 +683,7 @@ __global__ __launch_bounds__(WG) void k_lf_partial_bf16(Dev D, int s, int zero_e
     cur ^= 1;
   }
 
-  float *gp = D.gpart + (long long)blockIdx.x * TJ * D.DS;
+  float *gp = D.gpart + (long long)(D.lf_goff[D.c2_group[C2]] + blockIdx.x) * TJ * D.DS;
 #pragma unroll
   for (int ct = 0; ct < C2; ++ct)
 #pragma unroll
@@ -701,18 +701,17 @@ __global__ __launch_bounds__(WG) void k_lf_partial_bf16(Dev D, int s, int zero_e
 constexpr int RED_THREADS = 256;
 constexpr int RED_ROUND = 8;
 
-__global__ __launch_bounds__(RED_THREADS) void k_lf_reduce(Dev D, int c2, int s, int zero_eps) {
+__global__ __launch_bounds__(RED_THREADS) void k_lf_reduce(Dev D, int s, int zero_eps) {
   const int ntile = D.Jcap / TJ;
   const int b = blockIdx.x / ntile, tile = blockIdx.x % ntile;
-  const int dq = 4 * c2;  // float4 per particle row
-  const int idx = blockIdx.y * RED_THREADS + threadIdx.x;
-  if (idx >= TJ * dq) return;
   const Post P = D.posts[b];
   const int4 q = D.lf_post[(long long)s * D.B + b];
-  if (P.C2 != c2 || tile >= q.w) return;
+  const int dq = 4 * P.C2;  // float4 per particle row
+  const int idx = blockIdx.y * RED_THREADS + threadIdx.x;
+  if (idx >= TJ * dq || tile >= q.w) return;
   Plan pl;
   pl.S = q.y + (tile < q.z ? 1 : 0);
-  pl.wbase = q.x + tile * q.y + (tile < q.z ? tile : q.z);
+  pl.wbase = D.lf_goff[D.c2_group[P.C2]] + q.x + tile * q.y + (tile < q.z ? tile : q.z);
   const int slot = idx / dq, k4 = idx - slot * dq;
   const int j = D.perm[P.row0 + tile * TJ + slot];
   const float4 *g0p = reinterpret_cast<const float4 *>(D.gpart + (long long)pl.wbase * TJ * D.DS);
@@ -775,19 +774,16 @@ static hipError_t launch_lf_c2(const Dev &D, int step, int zero_eps, hipStream_t
   return hipGetLastError();
 }
 
-hipError_t launch_lf_reduce(const Dev &D, int c2, int step, int zero_eps, hipStream_t st) {
-  // TJ * 4 c2 float4 per tile
-  const int slices = (TJ * 4 * c2 + RED_THREADS - 1) / RED_THREADS;
+hipError_t launch_lf_reduce(const Dev &D, int step, int zero_eps, hipStream_t st) {
+  // TJ * 4 C2 float4 per tile, for the widest group
+  int c2max = 1;
+  for (int g = 0; g < D.ngroups; ++g) c2max = D.group_c2[g] > c2max ? D.group_c2[g] : c2max;
+  const int slices = (TJ * 4 * c2max + RED_THREADS - 1) / RED_THREADS;
   hipLaunchKernelGGL(k_lf_reduce, dim3(D.B * (D.Jcap / TJ), slices), dim3(RED_THREADS), 0, st, D,
-                     c2, step, zero_eps);
+                     step, zero_eps);
   return hipGetLastError();
 }
 
-hipError_t launch_leapfrog(const Dev &D, int c2, int step, int zero_eps, hipStream_t st) {
-  hipError_t e = launch_lf_partial(D, c2, step, zero_eps, st);
-  if (e != hipSuccess) return e;
-  return launch_lf_reduce(D, c2, step, zero_eps, st);
-}
 
 hipError_t launch_lf_partial(const Dev &D, int c2, int step, int zero_eps, hipStream_t st) {
   switch (c2) {
