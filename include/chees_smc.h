@@ -48,10 +48,26 @@ typedef enum {
 
 /* data type of X */
 enum { SMC_F32 = 0, SMC_BF16 = 1 };
-/* jitter schemes of Sec. III-B-1 */
-enum { SMC_JITTER_HALTON1D = 0, /* 1-d Halton, base 2, index (k-1) J + j      */
-       SMC_JITTER_NONE = 1,     /* h = 1                                       */
-       SMC_JITTER_HALTONND = 2  /* h_jk = phi_{P_k}(j), P_k the k-th prime     */ };
+/* Jitter schemes of Sec. III-B-1: h_jk for particle j = 1..J at iteration
+ * k = 1, 2, ...; phi_b is the radical inverse in base b (eq. halton), P_k the
+ * k-th prime (the library holds the first 1024; later iterations reuse P_1024),
+ * K = smc_params.num_iterations, and k' = K - ((k - 1) mod K) the reversed
+ * column order of the inverse schemes (K + 1 - k for k <= K).  The uniform
+ * draws u_jk are word 0 of Philox4x32-10 block (0, particle, k, 6); the
+ * shuffle pi_k of the equidistant schemes is a 4-round Feistel network on the
+ * smallest even bit width covering J, round r keyed by Philox block
+ * (R, 4 b + r, k, 7) word 0 (b the posterior), walked until it lands in
+ * [0, J). */
+enum { SMC_JITTER_HALTON1D = 0,     /* phi_2((k-1) J + j)                          */
+       SMC_JITTER_NONE = 1,         /* h = 1                                       */
+       SMC_JITTER_HALTONND = 2,     /* phi_{P_k}(j)                                */
+       SMC_JITTER_UNIFORM = 3,      /* u_jk                                        */
+       SMC_JITTER_HALTONND_INV = 4, /* phi_{P_k'}(j)                               */
+       SMC_JITTER_PRIMES = 5,       /* j sqrt(P_k) mod 1 (eq. primes)              */
+       SMC_JITTER_PRIMES_INV = 6,   /* j sqrt(P_k') mod 1                          */
+       SMC_JITTER_GOLDEN = 7,       /* ((j-1) K + k) (sqrt 5 - 1)/2 mod 1          */
+       SMC_JITTER_EQUIDISTANT = 8,  /* (pi_k(j-1) + 1) / J                         */
+       SMC_JITTER_EQUIDISTANT_OFFSET = 9 /* (pi_k(j-1) + 1) / J + 0.1 u_jk        */ };
 /* resampling schemes (Sec. III) */
 enum { SMC_RESAMPLE_SYSTEMATIC = 0, SMC_RESAMPLE_MULTINOMIAL = 1 };
 /* arithmetic of the trajectory gradients */
@@ -108,6 +124,9 @@ typedef struct {
    * warm-started) and their learning rate */
   int32_t flow_layers, flow_width, flow_train_steps;
   double flow_lr;
+  /* K, the columns of the jitter matrix: required (1..1024) by the inverse
+   * schemes, and (>= 1) by the golden-ratio scheme; ignored otherwise */
+  int32_t num_iterations;
 } smc_params;
 
 /* Host-supplied randomness for one smc_step (all fields nullable, DEVICE

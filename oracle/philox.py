@@ -31,6 +31,8 @@ STREAM_MOMENTUM = 2  # momenta of each trajectory
 STREAM_MH = 3        # Metropolis-Hastings uniforms
 STREAM_RESAMPLE = 4  # resampling uniform(s)
 STREAM_FLOW = 5      # initial weights of the flow preconditioner
+STREAM_JITTER = 6    # uniform jitter draws (uniform and offset-equidistant schemes)
+STREAM_SHUFFLE = 7   # round functions of the equidistant schemes' shuffle
 
 
 def philox4x32_10(counter, key):

@@ -261,6 +261,93 @@ def halton_nd(k, J):
     return np.array([radical_inverse(j, b) for j in range(1, J + 1)])
 
 
+def reversed_column(k, K):
+    """Column of iteration k under the inverse schemes: the J x K matrix is
+    taken in reverse order of k (Sec. III-B-1, "sorted in reverse order of
+    k").  Reading: column K + 1 - k for k <= K; a run longer than K starts
+    over from column K (K - ((k - 1) mod K))."""
+    return K - (k - 1) % K
+
+
+def halton_nd_inverse(k, K, J):
+    """N-d inverse Halton: the N-d Halton matrix with its columns reversed."""
+    return halton_nd(reversed_column(k, K), J)
+
+
+def primes_nd(k, J):
+    """N-d primes jitter (eq. primes): h_jk = j sqrt(P_k) mod 1, j = 1..J, in
+    binary64 (one correctly rounded square root, one product, exact fraction).
+    """
+    r = math.sqrt(float(nth_prime(k)))
+    x = np.arange(1, J + 1, dtype=np.float64) * r
+    return x - np.floor(x)
+
+
+def primes_nd_inverse(k, K, J):
+    """N-d inverse primes: the N-d primes matrix with its columns reversed."""
+    return primes_nd(reversed_column(k, K), J)
+
+
+def golden_1d(k, K, J):
+    """1-d golden-ratio jitter: h_jk = ((j - 1) K + k) (sqrt 5 - 1) / 2 mod 1,
+    j = 1..J, in binary64."""
+    g = (math.sqrt(5.0) - 1.0) / 2.0
+    idx = np.arange(J, dtype=np.float64) * float(K) + float(k)
+    x = idx * g
+    return x - np.floor(x)
+
+
+def uniform_jitter(seed, k, J, b=0):
+    """Uniform jitter h_jk ~ U(0, 1): the Philox uniform of particle
+    b J + j - 1 at iteration k on the jitter stream."""
+    return np.array([philox.uniform(seed, b * J + j, k, philox.STREAM_JITTER) for j in range(J)])
+
+
+def shuffle(seed, k, J, b=0):
+    """The shuffle of column k of the equidistant schemes ("shuffled K times").
+
+    Reading: a keyed pseudo-random permutation of {0, .., J-1}: a balanced
+    Feistel network (Luby and Rackoff) of 4 rounds on 2 h bits, h the smallest
+    half width with 4^h >= J, whose round r maps the right half R to word 0 of
+    Philox block (R, 4 b + r, k, STREAM_SHUFFLE) masked to h bits, restricted
+    to {0, .., J-1} by cycle walking (Black and Rogaway): apply the network
+    until the value falls below J.  Returns pi with pi[j] the new position of
+    particle j.
+    """
+    h = 1
+    while 4 ** h < J:
+        h += 1
+    mask = (1 << h) - 1
+    key = philox.seed_key(seed)
+
+    def net(x):
+        hi, lo = x >> h, x & mask
+        for r in range(4):
+            f = philox.philox4x32_10((lo, 4 * b + r, k, philox.STREAM_SHUFFLE), key)[0] & mask
+            hi, lo = lo, hi ^ f
+        return (hi << h) | lo
+
+    pi = np.empty(J, dtype=np.int64)
+    for j in range(J):
+        y = net(j)
+        while y >= J:
+            y = net(y)
+        pi[j] = y
+    return pi
+
+
+def equidistant(seed, k, J, b=0):
+    """Equidistant jitter: the J points h = i / J, i = 1..J, shuffled per
+    iteration: h_jk = (pi_k(j) + 1) / J."""
+    return (shuffle(seed, k, J, b) + 1).astype(np.float64) / float(J)
+
+
+def equidistant_offset(seed, k, J, b=0):
+    """Offset equidistant jitter: the equidistant value plus a U(0, 0.1) draw,
+    0.1 u with u the particle's uniform on the jitter stream."""
+    return equidistant(seed, k, J, b) + 0.1 * uniform_jitter(seed, k, J, b)
+
+
 def step_counts(h, L, eps, n_max):
     """Jittered length l_j = h_j L and n_j = min(max(ceil(l_j / eps), 1), n_max)
     (Alg. smc_ChEES: l_m = h_m L_{m-1}, ceil(l_m / eps) leapfrog steps).
@@ -471,7 +558,7 @@ DEFAULTS = dict(
     adam_lr=0.025, adam_b1=0.9, adam_b2=0.999, adam_eps=1e-8, avg_decay=0.9,
     adapt_step_size=False, target_accept=0.651, seed=0, prior_var=1.0, precision="f64",
     precond="none", flow_layers=4, flow_width=128, flow_train_steps=10, flow_lr=1e-3,
-    flow_init=None,
+    flow_init=None, num_iterations=0,
 )
 
 
@@ -562,6 +649,21 @@ class OracleSMC:
             return np.ones(self.J)
         if kind == "haltonNd":
             return halton_nd(k, self.J)
+        K, seed = self.P["num_iterations"], self.P["seed"]
+        if kind == "uniform":
+            return uniform_jitter(seed, k, self.J)
+        if kind == "haltonNd_inv":
+            return halton_nd_inverse(k, K, self.J)
+        if kind == "primes":
+            return primes_nd(k, self.J)
+        if kind == "primes_inv":
+            return primes_nd_inverse(k, K, self.J)
+        if kind == "golden":
+            return golden_1d(k, K, self.J)
+        if kind == "equidistant":
+            return equidistant(seed, k, self.J)
+        if kind == "equidistant_offset":
+            return equidistant_offset(seed, k, self.J)
         raise ValueError(kind)
 
     def step(self, momenta=None, mh_uniforms=None, resample_u=None):

@@ -16,7 +16,9 @@ SMC_OK, SMC_EINVAL, SMC_EDEVICE, SMC_EDEGENERATE, SMC_ESTATE, SMC_ENOMEM = 0, -1
 STATUS = {0: "SMC_OK", -1: "SMC_EINVAL", -2: "SMC_EDEVICE", -3: "SMC_EDEGENERATE",
           -4: "SMC_ESTATE", -5: "SMC_ENOMEM"}
 SMC_F32, SMC_BF16 = 0, 1
-JITTER = {"halton1d": 0, "none": 1, "haltonNd": 2}
+JITTER = {"halton1d": 0, "none": 1, "haltonNd": 2, "uniform": 3, "haltonNd_inv": 4,
+          "primes": 5, "primes_inv": 6, "golden": 7, "equidistant": 8,
+          "equidistant_offset": 9}
 RESAMPLING = {"systematic": 0, "multinomial": 1}
 PRECISION = {"f32": 0, "bf16": 1}
 PRECOND = {"none": 0, "diag": 1, "flow": 2}
@@ -50,7 +52,7 @@ class Params(ctypes.Structure):
                 ("adapt_step_size", ctypes.c_int32), ("target_accept", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("flow_layers", ctypes.c_int32),
                 ("flow_width", ctypes.c_int32), ("flow_train_steps", ctypes.c_int32),
-                ("flow_lr", ctypes.c_double)]
+                ("flow_lr", ctypes.c_double), ("num_iterations", ctypes.c_int32)]
 
 
 class Inject(ctypes.Structure):
@@ -159,7 +161,8 @@ DEFAULT_PARAMS = dict(max_leapfrog=64, num_warmup=10, jitter="halton1d", mh_acce
                       step_size=0.1, traj_length=5.0, ess_frac=0.5, adam_lr=0.025,
                       adam_b1=0.9, adam_b2=0.999, adam_eps=1e-8, avg_decay=0.9,
                       adapt_step_size=False, target_accept=0.651, seed=0,
-                      flow_layers=4, flow_width=128, flow_train_steps=10, flow_lr=1e-3)
+                      flow_layers=4, flow_width=128, flow_train_steps=10, flow_lr=1e-3,
+                      num_iterations=0)
 
 
 def make_params(num_particles, **kw):
@@ -174,7 +177,7 @@ def make_params(num_particles, **kw):
                   p["traj_length"], p["ess_frac"], p["adam_lr"], p["adam_b1"], p["adam_b2"],
                   p["adam_eps"], p["avg_decay"], int(bool(p["adapt_step_size"])),
                   p["target_accept"], p["seed"], p["flow_layers"], p["flow_width"],
-                  p["flow_train_steps"], p["flow_lr"])
+                  p["flow_train_steps"], p["flow_lr"], p["num_iterations"])
 
 
 def make_problem(Xs, ys, prior_var=1.0):

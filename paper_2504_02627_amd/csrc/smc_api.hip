@@ -23,6 +23,7 @@ struct smc_ctx {
   std::vector<int3> ll_groups; // (C2, first item, count) of the log-likelihood pass
   std::vector<int4> ll_items;
   std::vector<int> primes;
+  std::vector<double> sqrtp;   // sqrt of the primes (binary64, correctly rounded)
   std::vector<float> minv;
   int stepped = 0;             // a step ran since the last adaptation
   int steps = 0;
@@ -61,7 +62,7 @@ struct Layout {
   size_t o_logpi, o_logpi_t, o_logw, o_h, o_l, o_H0, o_dH, o_alpha, o_ca, o_cg;
   size_t o_n, o_perm, o_active, o_anc, o_acc, o_cdf, o_gpart, o_tilecnt, o_llpart;
   size_t o_lf_post = 0, o_lf_items = 0, o_lf_count = 0;
-  size_t o_items, o_colpart, o_means, o_minv, o_primes;
+  size_t o_items, o_colpart, o_means, o_minv, o_primes, o_sqrtp = 0;
   FlowNet F;
   size_t o_fz = 0, o_fz0 = 0, o_fgz = 0, o_fld0 = 0, o_fld1 = 0, o_fm = 0, o_fL = 0, o_fAf = 0,
          o_fAb = 0, o_fAi = 0, o_fcov = 0, o_fLd = 0, o_fLi = 0, o_fbase = 0;
@@ -132,7 +133,12 @@ const char *check(const smc_problem *pr, const smc_params *pa) {
   if (pa->num_particles < 1 || pa->num_particles > 65536) return "num_particles in [1, 65536]";
   if (pa->max_leapfrog < 1 || pa->max_leapfrog > MAX_NMAX) return "max_leapfrog in [1, 4096]";
   if (pa->num_warmup < 1) return "num_warmup must be >= 1";
-  if (pa->jitter < 0 || pa->jitter > 2) return "jitter";
+  if (pa->jitter < SMC_JITTER_HALTON1D || pa->jitter > SMC_JITTER_EQUIDISTANT_OFFSET) return "jitter";
+  if ((pa->jitter == SMC_JITTER_HALTONND_INV || pa->jitter == SMC_JITTER_PRIMES_INV) &&
+      (pa->num_iterations < 1 || pa->num_iterations > NPRIMES))
+    return "the inverse jitter schemes need num_iterations in [1, 1024]";
+  if (pa->jitter == SMC_JITTER_GOLDEN && pa->num_iterations < 1)
+    return "the golden-ratio jitter needs num_iterations >= 1";
   if (pa->resampling < 0 || pa->resampling > 1) return "resampling";
   if (pa->precision != SMC_PRECISION_F32 && pa->precision != SMC_PRECISION_BF16) return "precision";
   if (pa->precond < 0 || pa->precond > 2) return "precond";
@@ -282,6 +288,7 @@ void plan(const smc_problem *pr, const smc_params *pa, Layout &L) {
   L.o_means = take(c, (size_t)B * 2 * L.DS * 8);
   L.o_minv = take(c, (size_t)B * L.DS * 4);
   L.o_primes = take(c, NPRIMES * 4);
+  L.o_sqrtp = take(c, NPRIMES * 8);
   if (pa->precond == SMC_PRECOND_FLOW) {
     flow_net(pr->dims[0], pa->flow_layers, pa->flow_width, L.F);
     L.F.ntrain = pa->flow_train_steps;
@@ -401,6 +408,8 @@ smc_status smc_init(const smc_problem *prob, const smc_params *par, void *worksp
   D.DS = L.DS;
   D.nmax = L.nmax;
   D.jitter = par->jitter;
+  D.jit_K = par->num_iterations;
+  D.golden = (std::sqrt(5.0) - 1.0) / 2.0;
   D.mh = par->mh_accept ? 1 : 0;
   D.resampling = par->resampling;
   D.precond = par->precond;
@@ -463,6 +472,7 @@ smc_status smc_init(const smc_problem *prob, const smc_params *par, void *worksp
   D.means = (double *)(w + L.o_means);
   D.minv = (float *)(w + L.o_minv);
   D.primes = (int *)(w + L.o_primes);
+  D.sqrtp = (double *)(w + L.o_sqrtp);
   D.lf_target = L.lf_target;
   D.lf_grid = L.lf_grid;
   D.flow = par->precond == SMC_PRECOND_FLOW ? 1 : 0;
@@ -499,6 +509,8 @@ smc_status smc_init(const smc_problem *prob, const smc_params *par, void *worksp
   ctx->ll_groups = L.groups;
   for (const int3 &g : L.groups) ctx->c2s.push_back(g.x);
   ctx->primes = first_primes(NPRIMES);
+  ctx->sqrtp.resize(NPRIMES);
+  for (int i = 0; i < NPRIMES; ++i) ctx->sqrtp[i] = std::sqrt((double)ctx->primes[i]);
   ctx->minv.assign((size_t)L.B * L.DS, 1.0f);
   ctx->ps_host.resize(L.B);
   for (PState &s : ctx->ps_host) {
@@ -528,6 +540,8 @@ smc_status smc_init(const smc_problem *prob, const smc_params *par, void *worksp
   CKI(hipMemcpyAsync(D.ps, ctx->ps_host.data(), L.B * sizeof(PState), hipMemcpyHostToDevice,
                      ctx->st));
   CKI(hipMemcpyAsync(D.primes, ctx->primes.data(), NPRIMES * sizeof(int), hipMemcpyHostToDevice,
+                     ctx->st));
+  CKI(hipMemcpyAsync(D.sqrtp, ctx->sqrtp.data(), NPRIMES * sizeof(double), hipMemcpyHostToDevice,
                      ctx->st));
   CKI(hipMemcpyAsync(D.minv, ctx->minv.data(), ctx->minv.size() * sizeof(float),
                      hipMemcpyHostToDevice, ctx->st));

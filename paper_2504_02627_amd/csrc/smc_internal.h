@@ -21,7 +21,7 @@ constexpr int NPRIMES = 1024;       // primes table for N-d Halton
 
 // Philox stream ids (counter word 3)
 constexpr uint32_t STREAM_INIT = 1, STREAM_MOMENTUM = 2, STREAM_MH = 3, STREAM_RESAMPLE = 4,
-                   STREAM_FLOW = 5;
+                   STREAM_FLOW = 5, STREAM_JITTER = 6, STREAM_SHUFFLE = 7;
 
 // Flow preconditioner: affine couplings with a two-hidden-layer conditioner
 // of width FH; FP particles per wave in the flow kernels.
@@ -120,6 +120,9 @@ struct Dev {                    // pointers carved from the workspace
   double *means;                // [B][2][DS]
   float *minv;                  // [B][DS] inverse mass diagonal
   int *primes;                  // NPRIMES
+  double *sqrtp;                // NPRIMES: sqrt(P_k), correctly rounded (host)
+  double golden;                // (sqrt 5 - 1) / 2 in binary64 (host)
+  int jit_K;                    // K, columns of the jitter matrix
   int lf_target;                // work groups per leapfrog launch and resident group per compute unit
   int lf_grid;                  // grid of a leapfrog launch
   // leapfrog work plan, written once per iteration from the active counts:

@@ -1166,6 +1166,64 @@ __device__ __forceinline__ double radical_inverse2(unsigned long long i) {
   return (double)r / (double)(1ull << m);
 }
 
+// Shuffle of the equidistant jitter schemes: a 4-round Feistel network on
+// 2 half bits (Luby and Rackoff), round r's function word 0 of the Philox
+// block (R, 4 b + r, k, STREAM_SHUFFLE) masked to half bits.  It permutes
+// [0, 2^(2 half)); cycle walking (Black and Rogaway) restricts it to [0, J):
+// the walk from x < J ends because x's cycle returns to x.
+__device__ uint32_t feistel(const Dev &D, uint32_t x, int half, uint32_t b, uint32_t k) {
+  const uint32_t mask = (1u << half) - 1u;
+  uint32_t lo = x & mask, hi = x >> half;
+  for (uint32_t r = 0; r < 4; ++r) {
+    const uint32_t f = philox_at(D.seed, lo, 4 * b + r, k, STREAM_SHUFFLE).x & mask;
+    const uint32_t t = hi ^ f;
+    hi = lo;
+    lo = t;
+  }
+  return (hi << half) | lo;
+}
+
+__device__ uint32_t shuffle_index(const Dev &D, uint32_t x, uint32_t b, uint32_t k) {
+  int half = 1;
+  while ((1ull << (2 * half)) < (unsigned long long)D.J) ++half;
+  uint32_t y = feistel(D, x, half, b, k);
+  while (y >= (uint32_t)D.J) y = feistel(D, y, half, b, k);
+  return y;
+}
+
+// Jitter h_jk of Sec. III-B-1 for particle j (0-based) of posterior b at
+// iteration k (1-based); the schemes and readings are listed with the
+// SMC_JITTER_* constants of the C interface.
+__device__ double jitter_h(const Dev &D, int b, int j, int k) {
+  const unsigned long long jj = (unsigned long long)j + 1;  // 1-based particle
+  const int K = D.jit_K;
+  const int krev = K > 0 ? K - (k - 1) % K : k;               // reversed column
+  const uint32_t particle = (uint32_t)(b * D.J + j);
+  switch (D.jitter) {
+    case 1: return 1.0;
+    case 2: return radical_inverse(jj, (unsigned long long)D.primes[min(k, NPRIMES) - 1]);
+    case 3: return u01(philox_at(D.seed, 0, particle, (uint32_t)k, STREAM_JITTER).x);
+    case 4: return radical_inverse(jj, (unsigned long long)D.primes[krev - 1]);
+    case 5:
+    case 6: {
+      const double x = (double)jj * D.sqrtp[(D.jitter == 5 ? min(k, NPRIMES) : krev) - 1];
+      return x - floor(x);
+    }
+    case 7: {
+      const double x = (double)((unsigned long long)j * K + k) * D.golden;
+      return x - floor(x);
+    }
+    case 8:
+    case 9: {
+      const uint32_t y = shuffle_index(D, (uint32_t)j, (uint32_t)b, (uint32_t)k);
+      double h = (double)(y + 1) / (double)D.J;
+      if (D.jitter == 9) h += 0.1 * u01(philox_at(D.seed, 0, particle, (uint32_t)k, STREAM_JITTER).x);
+      return h;
+    }
+    default: return radical_inverse2((unsigned long long)(k - 1) * D.J + jj);
+  }
+}
+
 __global__ __launch_bounds__(256) void k_setup(Dev D, const float *__restrict__ momenta,
                                                int init_mode) {
   const int lane = threadIdx.x & 63;
@@ -1225,13 +1283,7 @@ __global__ __launch_bounds__(256) void k_setup(Dev D, const float *__restrict__ 
   }
   const double K0 = 0.5 * wave_sum(kin);
   if (lane == 0) {
-    double h;
-    if (D.jitter == 1)
-      h = 1.0;
-    else if (D.jitter == 2)
-      h = radical_inverse((unsigned long long)(j + 1), (unsigned long long)D.primes[min(k, NPRIMES) - 1]);
-    else
-      h = radical_inverse2((unsigned long long)(k - 1) * D.J + (unsigned long long)(j + 1));
+    const double h = jitter_h(D, b, j, k);
     const double L = S.L, eps = S.eps;
     const double l = h * L;
     double nn = ceil(l / eps);

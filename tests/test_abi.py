@@ -41,7 +41,7 @@ def test_library_exports_every_declared_symbol():
 def test_struct_sizes_match_c_layout():
     from paper_2504_02627_amd import chees
     # natural alignment: these sizes follow from the field lists of the header
-    assert ctypes.sizeof(chees.Params) == 4 * 8 + 8 * 8 + 4 + 4 + 8 + 8 + 3 * 4 + 4 + 8
+    assert ctypes.sizeof(chees.Params) == 4 * 8 + 8 * 8 + 4 + 4 + 8 + 8 + 3 * 4 + 4 + 8 + 4 + 4
     assert ctypes.sizeof(chees.Stats) == 8 * 8 + 4 + 4 + 8
     assert ctypes.sizeof(chees.Inject) == 3 * 8
 

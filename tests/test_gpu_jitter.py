@@ -1,0 +1,81 @@
+"""Jitter generators of Sec. III-B-1 on the device against the oracle's
+definitions: h_jk bit-exact for every scheme over several iterations
+(including iterations past K for the schemes that take K), the step counts
+n_j that follow from them, and per-posterior streams of a batched context.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import smc as O
+from paper_2504_02627_amd import synth
+from tests._gpu_common import log, to_dev
+
+pytestmark = pytest.mark.gpu
+
+SCHEMES = ["halton1d", "none", "haltonNd", "uniform", "haltonNd_inv", "primes", "primes_inv",
+           "golden", "equidistant", "equidistant_offset"]
+
+
+def _oracle_h(kind, seed, k, K, J, b=0):
+    if kind == "halton1d":
+        return O.halton_1d(k, J)
+    if kind == "none":
+        return np.ones(J)
+    if kind == "haltonNd":
+        return O.halton_nd(k, J)
+    if kind == "uniform":
+        return O.uniform_jitter(seed, k, J, b)
+    if kind == "haltonNd_inv":
+        return O.halton_nd_inverse(k, K, J)
+    if kind == "primes":
+        return O.primes_nd(k, J)
+    if kind == "primes_inv":
+        return O.primes_nd_inverse(k, K, J)
+    if kind == "golden":
+        return O.golden_1d(k, K, J)
+    if kind == "equidistant":
+        return O.equidistant(seed, k, J, b)
+    return O.equidistant_offset(seed, k, J, b)
+
+
+@pytest.mark.parametrize("kind", SCHEMES)
+def test_jitter_bit_exact_over_iterations(kind):
+    from paper_2504_02627_amd import chees
+    N, d, J, K, seed = 200, 5, 300, 2, 77   # J not a power of two, beyond one tile
+    log(f"[jitter] scheme={kind} J={J} K={K}")
+    X, y, _ = synth.logistic_iid(N, d, 3)
+    eps = synth.default_step_size(N, d)
+    s = chees.Sampler(to_dev(X), to_dev(y), J, step_size=eps, traj_length=eps * 20,
+                      max_leapfrog=64, num_warmup=10, seed=seed, jitter=kind, num_iterations=K)
+    for k in range(1, 5):                    # k = 3, 4 run past K
+        st = s.step()
+        s.adapt()
+        tr = s.trace()
+        h = tr["h"].cpu().numpy()[:J]
+        n = tr["n"].cpu().numpy()[:J]
+        ref = _oracle_h(kind, seed, k, K, J)
+        np.testing.assert_array_equal(h, ref)
+        _, nref = O.step_counts(ref, st["L"], st["eps"], 64)
+        np.testing.assert_array_equal(n, nref)
+    if kind in ("equidistant", "equidistant_offset"):
+        base = O.equidistant(seed, 4, J)
+        np.testing.assert_array_equal(np.sort(base), np.arange(1, J + 1) / J)
+
+
+@pytest.mark.parametrize("kind", ["uniform", "equidistant", "equidistant_offset"])
+def test_jitter_streams_per_posterior(kind):
+    from paper_2504_02627_amd import chees
+    J, seed = 130, 5
+    data = [synth.logistic_iid(120, 4, 1), synth.logistic_iid(90, 7, 2)]
+    Xs = [to_dev(X) for X, _, _ in data]
+    ys = [to_dev(y) for _, y, _ in data]
+    log(f"[jitter] batched scheme={kind} J={J}")
+    s = chees.Sampler(Xs, ys, J, step_size=0.05, traj_length=1.0, max_leapfrog=32,
+                      num_warmup=5, seed=seed, jitter=kind)
+    s.step()
+    tr = s.trace()
+    jc = tr["jcap"]
+    h = tr["h"].cpu().numpy()
+    for b in range(2):
+        np.testing.assert_array_equal(h[b * jc:b * jc + J], _oracle_h(kind, seed, 1, 0, J, b))

@@ -32,7 +32,8 @@ def _sampler(X, y, J, theta0=None, **kw):
 
 
 def _one_iteration(N, d, J, seed, mh=False, jitter="halton1d", resampling="systematic",
-                   nmax=64, eps=None, L=None, prior_var=1.0, inject=True, precond="none"):
+                   nmax=64, eps=None, L=None, prior_var=1.0, inject=True, precond="none",
+                   num_iterations=0):
     log(f"[parity] N={N} d={d} J={J} seed={seed} mh={mh} jitter={jitter} resampling={resampling} nmax={nmax}")
     X, y, _ = synth.logistic_iid(N, d, seed)
     rng = np.random.default_rng(seed + 7)
@@ -40,7 +41,8 @@ def _one_iteration(N, d, J, seed, mh=False, jitter="halton1d", resampling="syste
     eps = eps if eps is not None else synth.default_step_size(N, d)
     L = L if L is not None else eps * nmax / 2
     params = dict(step_size=eps, traj_length=L, max_leapfrog=nmax, num_warmup=5, seed=seed,
-                  mh_accept=mh, jitter=jitter, resampling=resampling, precond=precond)
+                  mh_accept=mh, jitter=jitter, resampling=resampling, precond=precond,
+                  num_iterations=num_iterations)
     s = _sampler(X, y, J, theta0=theta0, prior_var=prior_var, **params)
     o = oracle_for(X, y, J, theta0, prior_var=prior_var, **params)
     if inject:
@@ -168,9 +170,10 @@ def test_mh_mode(mh):
     np.testing.assert_array_equal(logw.cpu().numpy(), o.logw)
 
 
-@pytest.mark.parametrize("jitter", ["none", "haltonNd"])
+@pytest.mark.parametrize("jitter", ["none", "haltonNd", "uniform", "haltonNd_inv", "primes",
+                                    "primes_inv", "golden", "equidistant", "equidistant_offset"])
 def test_other_jitters(jitter):
-    X, y, s, o, st, ost = _one_iteration(200, 5, 256, 31, jitter=jitter)
+    X, y, s, o, st, ost = _one_iteration(200, 5, 256, 31, jitter=jitter, num_iterations=7)
     _compare_iteration(s, o, st, ost, 256, 5)
 
 
