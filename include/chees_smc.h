@@ -82,14 +82,25 @@ enum { SMC_PRECOND_NONE = 0,  /* unit mass, the paper's M = I                   
                                  latent space on log pi(T(z)) + log|det J_T(z)|
                                  (one posterior per context)                    */ };
 
+/* Target densities.  LOGISTIC: the Bayesian logistic regression of Sec. IV
+ * (X, y, prior_var).  GAUSSIAN and BANANA: the synthetic targets of Sec. IV,
+ * one posterior per context, FP32 trajectories, no flow preconditioner. */
+enum { SMC_TARGET_LOGISTIC = 0,
+       SMC_TARGET_GAUSSIAN = 1,  /* log pi = log N(theta; mean, precision^{-1}) + log_const */
+       SMC_TARGET_BANANA = 2     /* d = 2: log pi = log N(theta_1; 0, s1^2)
+                                    + log N(theta_2; b (theta_1^2 - c), 1) + log_const */ };
+
 typedef struct smc_ctx smc_ctx;
 
 /* The posterior: pi(theta) = p(y | X, theta) q0(theta), q0 = N(0, prior_var I)
  * (Sec. II problem statement; Sec. IV model).  num_posteriors independent
  * problems may share one context (batched form); they are sampled with the
- * same parameters and independent particle populations. */
+ * same parameters and independent particle populations.  For the synthetic
+ * targets pi is the target density itself and q0 = N(0, prior_var I) is only
+ * the initial distribution (Sec. IV: N(0, I)); n_rows, X and y are unused
+ * (may be NULL). */
 typedef struct {
-  int32_t num_posteriors;     /* B >= 1                                         */
+  int32_t num_posteriors;     /* B >= 1 (1 for the synthetic targets)           */
   const int32_t *n_rows;      /* host [B]: N_b >= 1 data rows                    */
   const int32_t *dims;        /* host [B]: d_b in [1, 208] features             */
   const void *const *X;       /* host [B] of DEVICE pointers: row-major N_b x d_b,
@@ -97,6 +108,14 @@ typedef struct {
   const float *const *y;      /* host [B] of DEVICE pointers: N_b labels in {0,1} */
   int32_t x_dtype;            /* SMC_F32 or SMC_BF16                            */
   double prior_var;           /* q0 variance (the paper's N(0, I): 1.0)         */
+  int32_t target;             /* SMC_TARGET_*                                   */
+  const float *mean;          /* GAUSSIAN: DEVICE d, the mean mu                 */
+  const float *precision;     /* GAUSSIAN: DEVICE d x d row-major Sigma^{-1},
+                                 symmetric positive definite (checked by a
+                                 Cholesky factorisation at smc_init)            */
+  double log_const;           /* GAUSSIAN, BANANA: added to the normalised log
+                                 density, so the evidence is exp(log_const)     */
+  double banana_s1, banana_b, banana_c; /* BANANA: s1 > 0, b, c (Sec. IV: 10, 0.03, 100) */
 } smc_problem;
 
 typedef struct {

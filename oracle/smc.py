@@ -108,11 +108,19 @@ class Gaussian:
     pi is exactly exp(log_scale).
     """
 
-    def __init__(self, mu, cov, log_scale=0.0):
+    def __init__(self, mu, cov=None, log_scale=0.0, prec=None):
+        """Either the covariance or the precision P = Sigma^{-1} (the same
+        density; given P, log det Sigma = -log det P)."""
         self.mu = np.asarray(mu, dtype=np.float64)
-        self.cov = np.atleast_2d(np.asarray(cov, dtype=np.float64))
-        self.prec = np.linalg.inv(self.cov)
-        sign, logdet = np.linalg.slogdet(self.cov)
+        if prec is not None:
+            self.prec = np.atleast_2d(np.asarray(prec, dtype=np.float64))
+            self.cov = np.linalg.inv(self.prec)
+            sign, logdet_p = np.linalg.slogdet(self.prec)
+            logdet = -logdet_p
+        else:
+            self.cov = np.atleast_2d(np.asarray(cov, dtype=np.float64))
+            self.prec = np.linalg.inv(self.cov)
+            sign, logdet = np.linalg.slogdet(self.cov)
         assert sign > 0
         self.dim = self.mu.shape[0]
         self.log_norm = -0.5 * (self.dim * LOG_2PI + logdet) + log_scale

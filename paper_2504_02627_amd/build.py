@@ -7,7 +7,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libchees_smc.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("smc_kernels.hip", "flow_kernels.hip", "smc_api.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("smc_kernels.hip", "flow_kernels.hip", "target_kernels.hip", "smc_api.hip")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -22,6 +22,7 @@ JITTER = {"halton1d": 0, "none": 1, "haltonNd": 2, "uniform": 3, "haltonNd_inv":
 RESAMPLING = {"systematic": 0, "multinomial": 1}
 PRECISION = {"f32": 0, "bf16": 1}
 PRECOND = {"none": 0, "diag": 1, "flow": 2}
+TARGET = {"logistic": 0, "gaussian": 1, "banana": 2}
 
 
 class SmcError(RuntimeError):
@@ -37,7 +38,14 @@ class Problem(ctypes.Structure):
                 ("X", ctypes.POINTER(ctypes.c_void_p)),
                 ("y", ctypes.POINTER(ctypes.c_void_p)),
                 ("x_dtype", ctypes.c_int32),
-                ("prior_var", ctypes.c_double)]
+                ("prior_var", ctypes.c_double),
+                ("target", ctypes.c_int32),
+                ("mean", ctypes.c_void_p),
+                ("precision", ctypes.c_void_p),
+                ("log_const", ctypes.c_double),
+                ("banana_s1", ctypes.c_double),
+                ("banana_b", ctypes.c_double),
+                ("banana_c", ctypes.c_double)]
 
 
 class Params(ctypes.Structure):
@@ -201,21 +209,54 @@ def make_problem(Xs, ys, prior_var=1.0):
     return prob, keep
 
 
+def make_target_problem(kind, dim, mean=None, precision=None, log_const=0.0,
+                        banana=(10.0, 0.03, 100.0), prior_var=1.0):
+    """Problem for a synthetic target: "gaussian" (device float32 mean [d] and
+    precision [d, d]) or "banana" (d = 2; s1, b, c)."""
+    keep = dict(d=(ctypes.c_int32 * 1)(int(dim)))
+    prob = Problem(1, None, keep["d"], None, None, SMC_F32, prior_var)
+    prob.target = TARGET[kind]
+    prob.log_const = float(log_const)
+    if kind == "gaussian":
+        for t, shape in ((mean, (dim,)), (precision, (dim, dim))):
+            if t is None or not t.is_cuda or tuple(t.shape) != shape or not t.is_contiguous() \
+                    or t.dtype != _torch().float32:
+                raise ValueError("gaussian target: float32 contiguous device mean [d] and precision [d, d]")
+        keep["mean"], keep["precision"] = mean, precision
+        prob.mean, prob.precision = mean.data_ptr(), precision.data_ptr()
+    elif kind == "banana":
+        prob.banana_s1, prob.banana_b, prob.banana_c = (float(v) for v in banana)
+    else:
+        raise ValueError(kind)
+    return prob, keep
+
+
 class Sampler:
     """One SMC/ChEES-HMC sampler context over B posteriors (include/chees_smc.h)."""
 
-    def __init__(self, Xs, ys, num_particles, prior_var=1.0, theta0=None, stream=None, **params):
+    def __init__(self, Xs, ys, num_particles, prior_var=1.0, theta0=None, stream=None,
+                 target=None, **params):
+        """target: None (logistic regression on Xs, ys) or a dict with "kind"
+        ("gaussian" / "banana"), "dim" and the arguments of make_target_problem;
+        Xs and ys are then unused."""
         torch = _torch()
-        if not isinstance(Xs, (list, tuple)):
-            Xs, ys = [Xs], [ys]
         self.lib = load()
-        self.Xs, self.ys = list(Xs), list(ys)
-        self.B = len(Xs)
         self.J = int(num_particles)
-        self.dims = [int(X.shape[1]) for X in Xs]
-        self.device = Xs[0].device
         self.stream = stream
-        self.prob, self._keep = make_problem(self.Xs, self.ys, prior_var)
+        if target is None:
+            if not isinstance(Xs, (list, tuple)):
+                Xs, ys = [Xs], [ys]
+            self.Xs, self.ys = list(Xs), list(ys)
+            self.B = len(Xs)
+            self.dims = [int(X.shape[1]) for X in Xs]
+            self.device = Xs[0].device
+            self.prob, self._keep = make_problem(self.Xs, self.ys, prior_var)
+        else:
+            t = dict(target)
+            kind, dim = t.pop("kind"), int(t.pop("dim"))
+            self.Xs, self.ys, self.B, self.dims = [], [], 1, [dim]
+            self.device = t["mean"].device if kind == "gaussian" else torch.device("cuda:0")
+            self.prob, self._keep = make_target_problem(kind, dim, prior_var=prior_var, **t)
         self.params = make_params(self.J, **params)
         nbytes = self.lib.smc_workspace_bytes(ctypes.byref(self.prob), ctypes.byref(self.params))
         if nbytes == 0:

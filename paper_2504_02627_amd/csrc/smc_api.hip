@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <string>
 #include <vector>
 
@@ -62,6 +63,7 @@ struct Layout {
   size_t o_logpi, o_logpi_t, o_logw, o_h, o_l, o_H0, o_dH, o_alpha, o_ca, o_cg;
   size_t o_n, o_perm, o_active, o_anc, o_acc, o_cdf, o_gpart, o_tilecnt, o_llpart;
   size_t o_lf_post = 0, o_lf_items = 0, o_lf_count = 0;
+  size_t o_tmean = 0, o_tprec = 0;
   size_t o_items, o_colpart, o_means, o_minv, o_primes, o_sqrtp = 0;
   FlowNet F;
   size_t o_fz = 0, o_fz0 = 0, o_fgz = 0, o_fld0 = 0, o_fld1 = 0, o_fm = 0, o_fL = 0, o_fAf = 0,
@@ -122,13 +124,29 @@ size_t take(size_t &cur, size_t bytes) {
 const char *check(const smc_problem *pr, const smc_params *pa) {
   if (!pr || !pa) return "null problem or params";
   if (pr->num_posteriors < 1) return "num_posteriors must be >= 1";
-  if (!pr->n_rows || !pr->dims || !pr->X || !pr->y) return "null problem arrays";
-  for (int b = 0; b < pr->num_posteriors; ++b) {
-    if (pr->n_rows[b] < 1) return "n_rows must be >= 1";
-    if (pr->dims[b] < 1 || pr->dims[b] > 16 * MAX_C2) return "dims must be in [1, 208]";
-    if (!pr->X[b] || !pr->y[b]) return "null X or y";
+  if (pr->target < SMC_TARGET_LOGISTIC || pr->target > SMC_TARGET_BANANA) return "target";
+  if (!pr->dims) return "null problem arrays";
+  if (pr->target == SMC_TARGET_LOGISTIC) {
+    if (!pr->n_rows || !pr->X || !pr->y) return "null problem arrays";
+    for (int b = 0; b < pr->num_posteriors; ++b) {
+      if (pr->n_rows[b] < 1) return "n_rows must be >= 1";
+      if (pr->dims[b] < 1 || pr->dims[b] > 16 * MAX_C2) return "dims must be in [1, 208]";
+      if (!pr->X[b] || !pr->y[b]) return "null X or y";
+    }
+    if (pr->x_dtype != SMC_F32 && pr->x_dtype != SMC_BF16) return "x_dtype";
+  } else {
+    if (pr->num_posteriors != 1) return "a synthetic target takes one posterior";
+    if (pr->dims[0] < 1 || pr->dims[0] > 16 * MAX_C2) return "dims must be in [1, 208]";
+    if (pa && (pa->precond == SMC_PRECOND_FLOW || pa->precision != SMC_PRECISION_F32))
+      return "synthetic targets run FP32 trajectories without the flow preconditioner";
+    if (!std::isfinite(pr->log_const)) return "log_const must be finite";
+    if (pr->target == SMC_TARGET_GAUSSIAN && (!pr->mean || !pr->precision))
+      return "the Gaussian target needs mean and precision";
+    if (pr->target == SMC_TARGET_BANANA &&
+        (pr->dims[0] != 2 || !(pr->banana_s1 > 0.0) || !std::isfinite(pr->banana_b) ||
+         !std::isfinite(pr->banana_c)))
+      return "the banana target needs d = 2, s1 > 0 and finite b, c";
   }
-  if (pr->x_dtype != SMC_F32 && pr->x_dtype != SMC_BF16) return "x_dtype";
   if (!(pr->prior_var > 0.0)) return "prior_var must be > 0";
   if (pa->num_particles < 1 || pa->num_particles > 65536) return "num_particles in [1, 65536]";
   if (pa->max_leapfrog < 1 || pa->max_leapfrog > MAX_NMAX) return "max_leapfrog in [1, 4096]";
@@ -172,7 +190,7 @@ void plan(const smc_problem *pr, const smc_params *pa, Layout &L) {
   L.posts.resize(B);
   for (int b = 0; b < B; ++b) {
     HostPost &h = L.hp[b];
-    h.N = pr->n_rows[b];
+    h.N = pr->target == SMC_TARGET_LOGISTIC ? pr->n_rows[b] : 0;  // no data for a synthetic target
     h.d = pr->dims[b];
     h.C2 = (h.d + 15) / 16;
     h.C1 = 4 * h.C2;
@@ -287,6 +305,8 @@ void plan(const smc_problem *pr, const smc_params *pa, Layout &L) {
   L.o_colpart = take(c, (size_t)B * L.col_chunks * 2 * L.DS * 8);
   L.o_means = take(c, (size_t)B * 2 * L.DS * 8);
   L.o_minv = take(c, (size_t)B * L.DS * 4);
+  L.o_tmean = take(c, (size_t)L.DS * 4);
+  L.o_tprec = take(c, pr->target == SMC_TARGET_GAUSSIAN ? (size_t)L.DS * L.DS * 4 : 4);
   L.o_primes = take(c, NPRIMES * 4);
   L.o_sqrtp = take(c, NPRIMES * 8);
   if (pa->precond == SMC_PRECOND_FLOW) {
@@ -471,6 +491,13 @@ smc_status smc_init(const smc_problem *prob, const smc_params *par, void *worksp
   D.col_chunks = L.col_chunks;
   D.means = (double *)(w + L.o_means);
   D.minv = (float *)(w + L.o_minv);
+  D.tmean = (float *)(w + L.o_tmean);
+  D.tprec = (float *)(w + L.o_tprec);
+  D.target = prob->target;
+  D.bs1 = prob->banana_s1;
+  D.bb = prob->banana_b;
+  D.bc = prob->banana_c;
+  D.tconst = prob->log_const;
   D.primes = (int *)(w + L.o_primes);
   D.sqrtp = (double *)(w + L.o_sqrtp);
   D.lf_target = L.lf_target;
@@ -547,15 +574,49 @@ smc_status smc_init(const smc_problem *prob, const smc_params *par, void *worksp
                      hipMemcpyHostToDevice, ctx->st));
   CKI(hipMemcpyAsync(D.ll_items, ctx->ll_items.data(), ctx->ll_items.size() * sizeof(int4),
                      hipMemcpyHostToDevice, ctx->st));
-  for (int b = 0; b < L.B; ++b) {
-    CKI(launch_pack_one(D, prob->X[b], prob->y[b], prob->x_dtype, L.hp[b], ctx->st));
-    if (D.bf16) CKI(launch_pack_bf16(D, prob->X[b], prob->y[b], prob->x_dtype, L.hp[b], ctx->st));
+  if (D.target == SMC_TARGET_GAUSSIAN) {
+    // log N(theta; mu, P^{-1}) = 1/2 log det P - d/2 log 2 pi - 1/2 q: log det P
+    // from a binary64 Cholesky factorisation of the FP32 precision
+    const int d = L.hp[0].d;
+    std::vector<float> P((size_t)d * d);
+    CKI(hipMemcpyAsync(P.data(), prob->precision, P.size() * sizeof(float), hipMemcpyDeviceToHost,
+                       ctx->st));
+    CKI(hipStreamSynchronize(ctx->st));
+    std::vector<double> Lc((size_t)d * d, 0.0);
+    double logdet = 0.0;
+    for (int i = 0; i < d; ++i)
+      for (int j = 0; j <= i; ++j) {
+        double v = P[(size_t)i * d + j];
+        for (int k = 0; k < j; ++k) v -= Lc[(size_t)i * d + k] * Lc[(size_t)j * d + k];
+        if (i == j) {
+          if (!(v > 0.0)) {
+            ctx->err = "the Gaussian precision is not positive definite";
+            return fail(SMC_EINVAL);
+          }
+          Lc[(size_t)i * d + i] = std::sqrt(v);
+          logdet += 2.0 * std::log(Lc[(size_t)i * d + i]);
+        } else {
+          Lc[(size_t)i * d + j] = v / Lc[(size_t)j * d + j];
+        }
+      }
+    D.tconst = prob->log_const + 0.5 * logdet - 0.5 * d * std::log(2.0 * M_PI);
+    CKI(launch_target_pack(D, prob->mean, prob->precision, d, ctx->st));
   }
+  if (!D.target)
+    for (int b = 0; b < L.B; ++b) {
+      CKI(launch_pack_one(D, prob->X[b], prob->y[b], prob->x_dtype, L.hp[b], ctx->st));
+      if (D.bf16) CKI(launch_pack_bf16(D, prob->X[b], prob->y[b], prob->x_dtype, L.hp[b], ctx->st));
+    }
   CKI(launch_init_theta(D, theta0, ctx->st));
-  CKI(launch_lf_plan(D, ctx->st));
-  for (int c2 : ctx->c2s) CKI(launch_lf_partial(D, c2, 0, 1, ctx->st));
-  CKI(launch_lf_reduce(D, 0, 1, ctx->st));
-  for (const int3 &g : ctx->ll_groups) CKI(launch_loglik(D, g.x, g.y, g.z, ctx->st));
+  if (D.target) {
+    CKI(launch_target_step(D, 0, 1, ctx->st));
+    CKI(launch_target_energy(D, ctx->st));
+  } else {
+    CKI(launch_lf_plan(D, ctx->st));
+    for (int c2 : ctx->c2s) CKI(launch_lf_partial(D, c2, 0, 1, ctx->st));
+    CKI(launch_lf_reduce(D, 0, 1, ctx->st));
+    for (const int3 &g : ctx->ll_groups) CKI(launch_loglik(D, g.x, g.y, g.z, ctx->st));
+  }
   CKI(launch_init_weights(D, ctx->st));
   CKI(launch_ess(D, 0, ctx->st));
   if (D.flow) CKI(launch_flow_init(D, ctx->F, ctx->st));
@@ -610,8 +671,20 @@ smc_status enqueue_step(smc_ctx *ctx, const smc_inject *inject) {
   CK(launch_setup(D, inject ? inject->momenta : nullptr, 0, ctx->st));
   if (D.flow) CK(launch_flow_begin(D, F, ctx->st));
   CK(launch_sort(D, ctx->st));
-  CK(launch_lf_plan(D, ctx->st));
-  for (int s = 0; s < D.nmax; ++s) {
+  if (D.target) {
+    // synthetic target: one fused drift / gradient / kick launch per step
+    for (int s = 0; s < D.nmax; ++s) {
+      CK(timed_begin(ctx, 0, ei));
+      CK(launch_target_step(D, s, 0, ctx->st));
+      CK(timed_end(ctx, ei));
+    }
+    CK(timed_begin(ctx, 1, ei));
+    CK(launch_target_energy(D, ctx->st));
+    CK(timed_end(ctx, ei));
+  } else {
+    CK(launch_lf_plan(D, ctx->st));
+  }
+  for (int s = 0; s < (D.target ? 0 : D.nmax); ++s) {
     for (int c2 : ctx->c2s) {
       if (D.flow) {
         CK(timed_begin(ctx, 3, ei));
@@ -632,7 +705,7 @@ smc_status enqueue_step(smc_ctx *ctx, const smc_inject *inject) {
       CK(timed_end(ctx, ei));
     }
   }
-  for (const int3 &g : ctx->ll_groups) {
+  for (const int3 &g : (D.target ? std::vector<int3>() : ctx->ll_groups)) {
     CK(timed_begin(ctx, 1, ei));
     CK(launch_loglik(D, g.x, g.y, g.z, ctx->st));
     CK(timed_end(ctx, ei));

@@ -123,6 +123,11 @@ struct Dev {                    // pointers carved from the workspace
   double *sqrtp;                // NPRIMES: sqrt(P_k), correctly rounded (host)
   double golden;                // (sqrt 5 - 1) / 2 in binary64 (host)
   int jit_K;                    // K, columns of the jitter matrix
+  // synthetic targets (SMC_TARGET_GAUSSIAN / BANANA; 0 = logistic regression)
+  int target;
+  float *tmean, *tprec;         // Gaussian: mean [DS], precision [DS][DS] (zero padded)
+  double tconst;                // constant of log pi (normalisation + log_const)
+  double bs1, bb, bc;           // banana parameters
   int lf_target;                // work groups per leapfrog launch and resident group per compute unit
   int lf_grid;                  // grid of a leapfrog launch
   // leapfrog work plan, written once per iteration from the active counts:
@@ -188,6 +193,12 @@ hipError_t launch_sort(const Dev &D, hipStream_t st);
 // Work plan of every leapfrog launch of the iteration (after the sort, or the
 // initial active counts).
 hipError_t launch_lf_plan(const Dev &D, hipStream_t st);
+// Synthetic targets (target_kernels.hip): one leapfrog step (or the gradient
+// at theta_t), log pi(theta_t) into logpi_t, and the Gaussian's parameters.
+hipError_t launch_target_step(const Dev &D, int step, int grad_only, hipStream_t st);
+hipError_t launch_target_energy(const Dev &D, hipStream_t st);
+hipError_t launch_target_pack(const Dev &D, const float *mean, const float *prec, int d,
+                              hipStream_t st);
 hipError_t launch_lf_partial(const Dev &D, int c2, int step, int zero_eps, hipStream_t st);
 // mode 0: full step; 1: zero step size (gradient at theta, state rewritten);
 // 2: gradient only (theta given by the caller, p untouched)

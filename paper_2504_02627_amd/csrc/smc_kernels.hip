@@ -987,6 +987,16 @@ __global__ __launch_bounds__(256) void k_init_weights(Dev D) {
     }
     return;
   }
+  if (D.target) {
+    // log w = log pi - log q0 - log J, q0 = N(0, prior_var I) the initial draw
+    const double logq0 = row_log_prior(D, P, th, lane);
+    if (lane == 0) {
+      const double lp = D.logpi_t[row];
+      D.logpi[row] = lp;
+      D.logw[row] = lp - logq0 - log((double)D.J);
+    }
+    return;
+  }
   const double ll = row_loglik(D, P, row);
   const double lp = row_log_prior(D, P, th, lane);
   if (lane == 0) {
@@ -1392,8 +1402,9 @@ __global__ __launch_bounds__(256) void k_weights(Dev D, const double *__restrict
   const PState &S = D.ps[b];
   const float *th = D.theta_t + row * D.DS;
   const float *mv = D.minv + (long long)b * D.DS;
-  const double ll = row_loglik(D, P, row);
-  const double lp = row_log_prior(D, P, th, lane);
+  // synthetic targets: log pi(theta') was evaluated by the target's energy pass
+  const double ll = D.target ? 0.0 : row_loglik(D, P, row);
+  const double lp = D.target ? D.logpi_t[row] : row_log_prior(D, P, th, lane);
   const double K1 = row_kinetic(D, P, D.p_t + row * D.DS, mv, lane);
   if (lane != 0) return;
   const double logpi1 = ll + lp;

@@ -79,3 +79,36 @@ def default_step_size(N, d):
     """A Fisher-scale starting step size d^(-1/4) / sqrt(1 + N/4) (the logistic
     curvature is at most N/4 per unit-variance feature)."""
     return float(d) ** -0.25 / np.sqrt(1.0 + N / 4.0)
+
+
+# ---------------------------------------------------------------------------
+# Synthetic targets of Sec. IV (parameters only; the densities themselves are
+# evaluated by the device library and by the oracle, each on its own).
+# ---------------------------------------------------------------------------
+
+def gaussian5():
+    """Sec. IV Gaussian, D = 5: mu = [-4, -2, 0, 2, 4], Sigma = diag(1, 1.5, 2,
+    2.5, 3).  Returns float32 (mu, precision) and the float64 covariance."""
+    mu = np.array([-4.0, -2.0, 0.0, 2.0, 4.0])
+    var = np.array([1.0, 1.5, 2.0, 2.5, 3.0])
+    return mu.astype(np.float32), np.diag(1.0 / var).astype(np.float32), np.diag(var)
+
+
+def ill_conditioned_gaussian(d=100, seed=14):
+    """Sec. IV ill-conditioned Gaussian: Sigma = Q diag(lambda) Q^T with Q
+    Haar-distributed on O(d) (QR of a Gaussian matrix with the signs of R's
+    diagonal folded into Q) and lambda_i ~ Gamma(shape 0.5, scale 1); mu = 0.
+    The default seed gives condition number 1.27e5 (the paper quotes about
+    1.3e5).  Returns float32 (mu, precision) and the float64 covariance."""
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((d, d))
+    Q, R = np.linalg.qr(A)
+    Q = Q * np.sign(np.diag(R))
+    lam = rng.gamma(0.5, 1.0, size=d)
+    cov = (Q * lam) @ Q.T
+    prec = (Q / lam) @ Q.T
+    prec = 0.5 * (prec + prec.T)
+    return np.zeros(d, dtype=np.float32), prec.astype(np.float32), 0.5 * (cov + cov.T)
+
+
+BANANA = (10.0, 0.03, 100.0)  # Sec. IV Rosenbrock: s1, b, c
