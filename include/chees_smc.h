@@ -70,6 +70,16 @@ enum { SMC_JITTER_HALTON1D = 0,     /* phi_2((k-1) J + j)                       
        SMC_JITTER_EQUIDISTANT_OFFSET = 9 /* (pi_k(j-1) + 1) / J + 0.1 u_jk        */ };
 /* resampling schemes (Sec. III) */
 enum { SMC_RESAMPLE_SYSTEMATIC = 0, SMC_RESAMPLE_MULTINOMIAL = 1 };
+/* step-size adaptation during warm-up */
+enum { SMC_ADAPT_EPS_NONE = 0,
+       SMC_ADAPT_EPS_ADAM = 1,           /* Adam on log eps toward a harmonic-mean
+                                            acceptance of target_accept          */
+       SMC_ADAPT_EPS_DUAL_AVERAGING = 2  /* Nesterov dual averaging of log eps
+                                            (Hoffman and Gelman 2014: gamma 0.05,
+                                            t0 10, kappa 0.75, mu = log 10 eps_0)
+                                            on the mean alpha of the particles;
+                                            eps <- the averaged iterate at the end
+                                            of warm-up                          */ };
 /* arithmetic of the trajectory gradients */
 enum { SMC_PRECISION_F32 = 0, SMC_PRECISION_BF16 = 1 };
 /* preconditioning of the trajectories (none of them changes the target: the
@@ -83,12 +93,17 @@ enum { SMC_PRECOND_NONE = 0,  /* unit mass, the paper's M = I                   
                                  (one posterior per context)                    */ };
 
 /* Target densities.  LOGISTIC: the Bayesian logistic regression of Sec. IV
- * (X, y, prior_var).  GAUSSIAN and BANANA: the synthetic targets of Sec. IV,
- * one posterior per context, FP32 trajectories, no flow preconditioner. */
+ * (X, y, prior_var).  GAUSSIAN and BANANA: the synthetic targets of Sec. IV;
+ * FUNNEL: the funnel the paper names as future work (Sec. VI).  The synthetic
+ * targets take one posterior per context, FP32 trajectories and no flow
+ * preconditioner. */
 enum { SMC_TARGET_LOGISTIC = 0,
        SMC_TARGET_GAUSSIAN = 1,  /* log pi = log N(theta; mean, precision^{-1}) + log_const */
-       SMC_TARGET_BANANA = 2     /* d = 2: log pi = log N(theta_1; 0, s1^2)
-                                    + log N(theta_2; b (theta_1^2 - c), 1) + log_const */ };
+       SMC_TARGET_BANANA = 2,    /* d = 2: log pi = log N(theta_1; 0, s1^2)
+                                    + log N(theta_2; b (theta_1^2 - c), 1) + log_const */
+       SMC_TARGET_FUNNEL = 3     /* Neal's funnel, d >= 2, theta = (v, x_1..x_{d-1}):
+                                    log pi = log N(v; 0, funnel_scale^2)
+                                    + sum_i log N(x_i; 0, e^v) + log_const       */ };
 
 typedef struct smc_ctx smc_ctx;
 
@@ -116,6 +131,7 @@ typedef struct {
   double log_const;           /* GAUSSIAN, BANANA: added to the normalised log
                                  density, so the evidence is exp(log_const)     */
   double banana_s1, banana_b, banana_c; /* BANANA: s1 > 0, b, c (Sec. IV: 10, 0.03, 100) */
+  double funnel_scale;        /* FUNNEL: standard deviation of v (Neal: 3)      */
 } smc_problem;
 
 typedef struct {
@@ -134,9 +150,12 @@ typedef struct {
   double ess_frac;            /* resample iff J_eff < ess_frac J (paper: 0.5)   */
   double adam_lr, adam_b1, adam_b2, adam_eps; /* Adam on log L (ascent)         */
   double avg_decay;           /* Lbar <- avg_decay Lbar + (1 - avg_decay) L (0.9) */
-  int32_t adapt_step_size;    /* 1: Adam on log eps toward target_accept during
-                                 warm-up (not in the paper, whose eps is fixed) */
-  double target_accept;       /* harmonic-mean acceptance target (e.g. 0.651)   */
+  int32_t adapt_step_size;    /* SMC_ADAPT_EPS_*: step-size adaptation during
+                                 warm-up (the paper keeps eps fixed and names
+                                 dual averaging as future work)                 */
+  double target_accept;       /* acceptance target (ADAM: harmonic mean of
+                                 alpha, e.g. 0.651; DUAL_AVERAGING: mean alpha,
+                                 e.g. 0.65)                                     */
   uint64_t seed;              /* key of the Philox4x32-10 streams               */
   /* SMC_PRECOND_FLOW only: coupling layers (1..8), conditioner width (128),
    * Adam steps of the weighted maximum-likelihood fit per iteration (>= 0,

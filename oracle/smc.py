@@ -155,6 +155,27 @@ class Banana:
         return logp, g
 
 
+class Funnel:
+    """Neal's funnel (named as future work in Sec. VI), d >= 2,
+    theta = (v, x_1..x_{d-1}): v ~ N(0, scale^2), x_i | v ~ N(0, e^v)."""
+
+    def __init__(self, dim, scale=3.0, log_scale=0.0):
+        self.dim, self.scale, self.log_scale = int(dim), float(scale), float(log_scale)
+
+    def log_and_grad(self, theta):
+        theta = np.atleast_2d(theta)
+        v, x = theta[:, 0], theta[:, 1:]
+        n = self.dim - 1
+        x2 = np.sum(x * x, axis=1)
+        ev = np.exp(-v)
+        logp = (-0.5 * (v / self.scale) ** 2 - math.log(self.scale) - 0.5 * LOG_2PI
+                - 0.5 * ev * x2 - 0.5 * n * v - 0.5 * n * LOG_2PI + self.log_scale)
+        g = np.empty_like(theta)
+        g[:, 0] = -v / self.scale ** 2 - 0.5 * n + 0.5 * ev * x2
+        g[:, 1:] = -x * ev[:, None]
+        return logp, g
+
+
 # ===========================================================================
 # Hamiltonian dynamics (Sec. II-A)
 # ===========================================================================
@@ -637,6 +658,8 @@ class OracleSMC:
         self.Lbar = 0.0
         self.adam_L = Adam(P["adam_lr"], P["adam_b1"], P["adam_b2"], P["adam_eps"])
         self.adam_eps = Adam(P["adam_lr"], P["adam_b1"], P["adam_b2"], P["adam_eps"])
+        self.da_hbar, self.da_logbar = 0.0, 0.0      # dual averaging state
+        self.da_mu = math.log(10.0 * self.eps)
         self.k = 0
         self.grad_evals = J  # the gradient at theta_0
         self.last = None
@@ -784,9 +807,14 @@ class OracleSMC:
         m < M_w: Adam ascent on log L with g_hat (skipped if sum alpha = 0),
                  then Lbar <- 0.9 Lbar + 0.1 L;
         m = M_w: L <- Lbar.
-        Optional (adapt_step_size): Adam on log eps toward a harmonic-mean
-        acceptance of target_accept during warm-up (not in the paper, whose
-        step size is fixed; named there as future work)."""
+        Optional step-size adaptation during warm-up (not in the paper, whose
+        step size is fixed; dual averaging is named there as future work):
+          adapt_step_size True / "adam": Adam on log eps toward a harmonic-mean
+            acceptance of target_accept;
+          "dual_averaging": Nesterov dual averaging as Hoffman and Gelman
+            (2014) apply it to log eps (gamma 0.05, t0 10, kappa 0.75,
+            mu = log(10 eps_0)), driven by the mean alpha of the particles at
+            adaptation iteration m = k; eps <- exp(log eps_bar) at m = M_w."""
         P = self.P
         if self.last is None:
             raise RuntimeError("adapt before step")
@@ -795,11 +823,23 @@ class OracleSMC:
             if self.last["sum_alpha"] > 0:
                 self.L = math.exp(self.adam_L.ascend(math.log(self.L), self.last["ghat"]))
             self.Lbar = P["avg_decay"] * self.Lbar + (1.0 - P["avg_decay"]) * self.L
-            if P["adapt_step_size"]:
+            mode = P["adapt_step_size"]
+            if mode is True or mode == "adam" or mode == 1:
                 hm = harmonic_mean(self.last["alpha"])
                 self.eps = math.exp(self.adam_eps.ascend(math.log(self.eps), hm - P["target_accept"]))
+            elif mode == "dual_averaging" or mode == 2:
+                m = float(k)
+                abar = float(np.mean(self.last["alpha"]))
+                w = 1.0 / (m + 10.0)
+                self.da_hbar = (1.0 - w) * self.da_hbar + w * (P["target_accept"] - abar)
+                log_eps = self.da_mu - math.sqrt(m) / 0.05 * self.da_hbar
+                mk = m ** -0.75
+                self.da_logbar = mk * log_eps + (1.0 - mk) * self.da_logbar
+                self.eps = math.exp(log_eps)
         elif k == Mw:
             self.L = self.Lbar
+            if P["adapt_step_size"] == "dual_averaging" or P["adapt_step_size"] == 2:
+                self.eps = math.exp(self.da_logbar)
         return dict(L=self.L, eps=self.eps, Lbar=self.Lbar)
 
     def set_state(self, theta, logw, logpi=None):

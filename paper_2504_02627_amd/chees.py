@@ -22,7 +22,8 @@ JITTER = {"halton1d": 0, "none": 1, "haltonNd": 2, "uniform": 3, "haltonNd_inv":
 RESAMPLING = {"systematic": 0, "multinomial": 1}
 PRECISION = {"f32": 0, "bf16": 1}
 PRECOND = {"none": 0, "diag": 1, "flow": 2}
-TARGET = {"logistic": 0, "gaussian": 1, "banana": 2}
+TARGET = {"logistic": 0, "gaussian": 1, "banana": 2, "funnel": 3}
+ADAPT_EPS = {False: 0, True: 1, "none": 0, "adam": 1, "dual_averaging": 2}
 
 
 class SmcError(RuntimeError):
@@ -45,7 +46,8 @@ class Problem(ctypes.Structure):
                 ("log_const", ctypes.c_double),
                 ("banana_s1", ctypes.c_double),
                 ("banana_b", ctypes.c_double),
-                ("banana_c", ctypes.c_double)]
+                ("banana_c", ctypes.c_double),
+                ("funnel_scale", ctypes.c_double)]
 
 
 class Params(ctypes.Structure):
@@ -183,7 +185,7 @@ def make_params(num_particles, **kw):
                   int(bool(p["mh_accept"])), RESAMPLING[p["resampling"]],
                   PRECISION[p["precision"]], PRECOND[p["precond"]], p["step_size"],
                   p["traj_length"], p["ess_frac"], p["adam_lr"], p["adam_b1"], p["adam_b2"],
-                  p["adam_eps"], p["avg_decay"], int(bool(p["adapt_step_size"])),
+                  p["adam_eps"], p["avg_decay"], ADAPT_EPS[p["adapt_step_size"]],
                   p["target_accept"], p["seed"], p["flow_layers"], p["flow_width"],
                   p["flow_train_steps"], p["flow_lr"], p["num_iterations"])
 
@@ -210,9 +212,10 @@ def make_problem(Xs, ys, prior_var=1.0):
 
 
 def make_target_problem(kind, dim, mean=None, precision=None, log_const=0.0,
-                        banana=(10.0, 0.03, 100.0), prior_var=1.0):
+                        banana=(10.0, 0.03, 100.0), funnel_scale=3.0, prior_var=1.0):
     """Problem for a synthetic target: "gaussian" (device float32 mean [d] and
-    precision [d, d]) or "banana" (d = 2; s1, b, c)."""
+    precision [d, d]), "banana" (d = 2; s1, b, c) or "funnel" (d >= 2; the
+    standard deviation of v)."""
     keep = dict(d=(ctypes.c_int32 * 1)(int(dim)))
     prob = Problem(1, None, keep["d"], None, None, SMC_F32, prior_var)
     prob.target = TARGET[kind]
@@ -226,6 +229,8 @@ def make_target_problem(kind, dim, mean=None, precision=None, log_const=0.0,
         prob.mean, prob.precision = mean.data_ptr(), precision.data_ptr()
     elif kind == "banana":
         prob.banana_s1, prob.banana_b, prob.banana_c = (float(v) for v in banana)
+    elif kind == "funnel":
+        prob.funnel_scale = float(funnel_scale)
     else:
         raise ValueError(kind)
     return prob, keep

@@ -124,7 +124,7 @@ size_t take(size_t &cur, size_t bytes) {
 const char *check(const smc_problem *pr, const smc_params *pa) {
   if (!pr || !pa) return "null problem or params";
   if (pr->num_posteriors < 1) return "num_posteriors must be >= 1";
-  if (pr->target < SMC_TARGET_LOGISTIC || pr->target > SMC_TARGET_BANANA) return "target";
+  if (pr->target < SMC_TARGET_LOGISTIC || pr->target > SMC_TARGET_FUNNEL) return "target";
   if (!pr->dims) return "null problem arrays";
   if (pr->target == SMC_TARGET_LOGISTIC) {
     if (!pr->n_rows || !pr->X || !pr->y) return "null problem arrays";
@@ -146,6 +146,9 @@ const char *check(const smc_problem *pr, const smc_params *pa) {
         (pr->dims[0] != 2 || !(pr->banana_s1 > 0.0) || !std::isfinite(pr->banana_b) ||
          !std::isfinite(pr->banana_c)))
       return "the banana target needs d = 2, s1 > 0 and finite b, c";
+    if (pr->target == SMC_TARGET_FUNNEL &&
+        (pr->dims[0] < 2 || !(pr->funnel_scale > 0.0) || !std::isfinite(pr->funnel_scale)))
+      return "the funnel target needs d >= 2 and funnel_scale > 0";
   }
   if (!(pr->prior_var > 0.0)) return "prior_var must be > 0";
   if (pa->num_particles < 1 || pa->num_particles > 65536) return "num_particles in [1, 65536]";
@@ -174,6 +177,8 @@ const char *check(const smc_problem *pr, const smc_params *pa) {
       !(pa->adam_b2 >= 0.0 && pa->adam_b2 < 1.0) || !(pa->adam_eps > 0.0))
     return "Adam hyperparameters";
   if (!(pa->avg_decay >= 0.0 && pa->avg_decay <= 1.0)) return "avg_decay in [0, 1]";
+  if (pa->adapt_step_size < SMC_ADAPT_EPS_NONE || pa->adapt_step_size > SMC_ADAPT_EPS_DUAL_AVERAGING)
+    return "adapt_step_size";
   return nullptr;
 }
 
@@ -441,7 +446,7 @@ smc_status smc_init(const smc_problem *prob, const smc_params *par, void *worksp
   D.adam_eps = par->adam_eps;
   D.avg_decay = par->avg_decay;
   D.target_accept = par->target_accept;
-  D.adapt_eps = par->adapt_step_size ? 1 : 0;
+  D.adapt_eps = par->adapt_step_size;
   D.num_warmup = par->num_warmup;
   D.seed = par->seed;
   D.posts = (Post *)(w + L.o_posts);
@@ -497,6 +502,7 @@ smc_status smc_init(const smc_problem *prob, const smc_params *par, void *worksp
   D.bs1 = prob->banana_s1;
   D.bb = prob->banana_b;
   D.bc = prob->banana_c;
+  D.fsv = prob->funnel_scale;
   D.tconst = prob->log_const;
   D.primes = (int *)(w + L.o_primes);
   D.sqrtp = (double *)(w + L.o_sqrtp);
@@ -544,6 +550,7 @@ smc_status smc_init(const smc_problem *prob, const smc_params *par, void *worksp
     memset(&s, 0, sizeof(s));
     s.L = par->traj_length;
     s.eps = par->step_size;
+    s.da_mu = std::log(10.0 * par->step_size);
     s.adapted_k = 0;
   }
 

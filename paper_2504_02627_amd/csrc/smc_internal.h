@@ -85,6 +85,7 @@ struct PState {
   int pad0;
   double L_used, eps_used;      // parameters used by this step
   double ghat, sum_alpha, chees, sum_alpha_all, sum_inv_alpha;
+  double da_hbar, da_logbar, da_mu;  // dual averaging of log eps: H_bar, log eps_bar, mu
   long long grad_evals_step;
   long long tot_grad_evals, tot_resamples, tot_iters;
   double tot_ess;
@@ -128,6 +129,7 @@ struct Dev {                    // pointers carved from the workspace
   float *tmean, *tprec;         // Gaussian: mean [DS], precision [DS][DS] (zero padded)
   double tconst;                // constant of log pi (normalisation + log_const)
   double bs1, bb, bc;           // banana parameters
+  double fsv;                   // funnel: standard deviation of v
   int lf_target;                // work groups per leapfrog launch and resident group per compute unit
   int lf_grid;                  // grid of a leapfrog launch
   // leapfrog work plan, written once per iteration from the active counts:

@@ -1706,13 +1706,24 @@ __global__ void k_adapt(Dev D) {
       S.L = exp(adam_ascend(log(S.L), S.ghat, S.am, S.av, S.at, D.adam_lr, D.adam_b1, D.adam_b2,
                             D.adam_eps));
     S.Lbar = D.avg_decay * S.Lbar + (1.0 - D.avg_decay) * S.L;
-    if (D.adapt_eps) {
+    if (D.adapt_eps == 1) {
       const double hm = (double)D.J / S.sum_inv_alpha;
       S.eps = exp(adam_ascend(log(S.eps), hm - D.target_accept, S.em, S.ev, S.et, D.adam_lr,
                               D.adam_b1, D.adam_b2, D.adam_eps));
+    } else if (D.adapt_eps == 2) {
+      // dual averaging (Hoffman and Gelman 2014, with gamma 0.05, t0 10,
+      // kappa 0.75) at adaptation iteration m = k on the mean acceptance
+      const double m = (double)k, w = 1.0 / (m + 10.0);
+      const double abar = S.sum_alpha_all / (double)D.J;
+      S.da_hbar = (1.0 - w) * S.da_hbar + w * (D.target_accept - abar);
+      const double le = S.da_mu - sqrt(m) / 0.05 * S.da_hbar;
+      const double mk = pow(m, -0.75);
+      S.da_logbar = mk * le + (1.0 - mk) * S.da_logbar;
+      S.eps = exp(le);
     }
   } else if (k == D.num_warmup) {
     S.L = S.Lbar;
+    if (D.adapt_eps == 2) S.eps = exp(S.da_logbar);
   }
   S.adapted_k = k;
 }

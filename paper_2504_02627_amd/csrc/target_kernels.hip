@@ -1,6 +1,7 @@
-// Synthetic targets of Sec. IV on the device: the Gaussian (dense precision,
-// the D = 5 and the ill-conditioned D = 100 examples) and the Rosenbrock
-// (banana) density.  One posterior per context; rows are the particles of
+// Synthetic targets on the device: those of Sec. IV -- the Gaussian (dense
+// precision, the D = 5 and the ill-conditioned D = 100 examples) and the
+// Rosenbrock (banana) density -- and Neal's funnel, which Sec. VI names as
+// future work.  One posterior per context; rows are the particles of
 // posterior 0 in the trajectory buffers.
 //
 // A leapfrog step (eqs. LF_p1/2, LF_theta, LF_p; gradient cached between
@@ -105,8 +106,42 @@ __global__ __launch_bounds__(256) void k_banana_step(Dev D, int s, int grad_only
   }
 }
 
+// ---------------------------------------------------------------------------
+// Funnel step: one thread per particle, theta = (v, x_1..x_{d-1}).
+//   grad_v = -v / sv^2 - (d - 1)/2 + e^{-v} |x|^2 / 2,  grad_x = -x e^{-v}.
+// The drift is written first (theta', p + h g in the state rows), then the
+// gradient at theta' and the kick read them back.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_funnel_step(Dev D, int s, int grad_only) {
+  const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= D.active[s]) return;
+  const int row = D.perm[slot];
+  const int d = D.posts[0].d;
+  const float eps = grad_only ? 0.f : (float)D.ps[0].eps;
+  const float he = 0.5f * eps;
+  float *th = D.theta_t + (long long)row * D.DS, *p = D.p_t + (long long)row * D.DS,
+        *g = D.grad_t + (long long)row * D.DS;
+  float x2 = 0.f;
+  for (int k = 0; k < d; ++k) {
+    const float ph = fmaf(he, g[k], p[k]);
+    const float t1 = fmaf(eps * D.minv[k], ph, th[k]);
+    th[k] = t1;
+    p[k] = ph;
+    if (k > 0) x2 = fmaf(t1, t1, x2);
+  }
+  const float v = th[0], ev = __expf(-v), sv2 = (float)(D.fsv * D.fsv);
+  for (int k = 0; k < d; ++k) {
+    const float gk = k == 0 ? -v / sv2 - 0.5f * (float)(d - 1) + 0.5f * ev * x2 : -th[k] * ev;
+    g[k] = gk;
+    p[k] = fmaf(he, gk, p[k]);
+  }
+}
+
 hipError_t launch_target_step(const Dev &D, int step, int grad_only, hipStream_t st) {
-  if (D.target == SMC_TARGET_GAUSSIAN) {
+  if (D.target == SMC_TARGET_FUNNEL) {
+    hipLaunchKernelGGL(k_funnel_step, dim3((D.Jcap + 255) / 256), dim3(256), 0, st, D, step,
+                       grad_only);
+  } else if (D.target == SMC_TARGET_GAUSSIAN) {
     const int threads = 64 * (D.DS / 16);
     const size_t lds = (size_t)3 * GT * (D.DS + 1) * sizeof(float);
     hipLaunchKernelGGL(k_gauss_step, dim3(D.Jcap / GT), dim3(threads), lds, st, D, step, grad_only);
@@ -123,7 +158,8 @@ hipError_t launch_target_step(const Dev &D, int step, int grad_only, hipStream_t
 //   Gaussian: tconst - 1/2 (theta - mu)^T P (theta - mu), tconst = log_const
 //             + 1/2 log det P - d/2 log 2 pi (host, Cholesky in binary64);
 //   banana:   log N(theta_1; 0, s1^2) + log N(theta_2; b (theta_1^2 - c), 1)
-//             + log_const.
+//             + log_const;
+//   funnel:   log N(v; 0, sv^2) + sum_i log N(x_i; 0, e^v) + log_const.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_target_energy(Dev D) {
   const int lane = threadIdx.x & 63;
@@ -142,6 +178,17 @@ __global__ __launch_bounds__(256) void k_target_energy(Dev D) {
     }
     q = wave_sum(q);
     if (lane == 0) D.logpi_t[j] = D.tconst - 0.5 * q;
+  } else if (D.target == SMC_TARGET_FUNNEL) {
+    // log N(v; 0, sv^2) + sum_i log N(x_i; 0, e^v)
+    const double v = th[0];
+    double x2 = 0.0;
+    for (int k = 1 + lane; k < d; k += 64) x2 += (double)th[k] * (double)th[k];
+    x2 = wave_sum(x2);
+    if (lane == 0) {
+      const double z = v / D.fsv;
+      D.logpi_t[j] = D.tconst - 0.5 * z * z - log(D.fsv) - 0.5 * exp(-v) * x2 -
+                     0.5 * (d - 1) * v - 0.5 * d * 1.8378770664093454836;  // log 2 pi
+    }
   } else if (lane == 0) {
     const double t1 = th[0], t2 = th[1];
     const double r = t2 - D.bb * (t1 * t1 - D.bc);

@@ -112,3 +112,4 @@ def ill_conditioned_gaussian(d=100, seed=14):
 
 
 BANANA = (10.0, 0.03, 100.0)  # Sec. IV Rosenbrock: s1, b, c
+FUNNEL = (10, 3.0)            # Neal's funnel: dimension, standard deviation of v

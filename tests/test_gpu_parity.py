@@ -149,6 +149,29 @@ def test_step_size_adaptation_parity():
     assert a["L"] == pytest.approx(o2.L, rel=1e-13)
 
 
+def test_dual_averaging_parity():
+    # dual averaging of log eps during warm-up and the freeze at M_w, fed with
+    # the device's own acceptance probabilities
+    N, d, J, Mw = 200, 5, 256, 4
+    X, y, _ = synth.logistic_iid(N, d, 13)
+    theta0 = (np.random.default_rng(4).standard_normal((J, d)) * 0.3).astype(np.float32)
+    eps = synth.default_step_size(N, d)
+    params = dict(step_size=eps, traj_length=eps * 16, max_leapfrog=64, num_warmup=Mw, seed=6,
+                  adapt_step_size="dual_averaging", target_accept=0.65)
+    s = _sampler(X, y, J, theta0=theta0, **params)
+    o = oracle_for(X, y, J, theta0, **params)
+    for k in range(1, Mw + 2):
+        st = s.step()
+        al = s.trace()["alpha"].cpu().numpy()[:J]
+        a = s.adapt()
+        o.k = k
+        o.last = dict(sum_alpha=float(al.sum()), ghat=st["chees_grad"], alpha=al)
+        o.adapt()
+        log(f"  k={k} eps device {a['eps']:.6e} oracle {o.eps:.6e}")
+        assert a["eps"] == pytest.approx(o.eps, rel=1e-12)
+        assert a["L"] == pytest.approx(o.L, rel=1e-12)
+
+
 @pytest.mark.parametrize("mh", [True])
 def test_mh_mode(mh):
     N, d, J = 300, 8, 256

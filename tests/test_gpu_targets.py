@@ -1,5 +1,6 @@
-"""Synthetic targets of Sec. IV on the device (Gaussian D = 5, ill-conditioned
-Gaussian D = 100, banana D = 2) against the oracle's densities.
+"""Synthetic targets on the device (Sec. IV: Gaussian D = 5, ill-conditioned
+Gaussian D = 100, banana D = 2; Sec. VI: Neal's funnel D = 10) against the
+oracle's densities.
 
 Bars: the initial weights and one iteration from the same injected inputs
 (jitter and step counts bit-exact; theta', p' within the FP32 trajectory
@@ -31,6 +32,9 @@ def _target(kind):
     elif kind == "illcond":
         mu, P, _ = synth.ill_conditioned_gaussian()
         eps = 0.001
+    elif kind == "funnel":
+        d, sv = synth.FUNNEL
+        return (dict(kind="funnel", dim=d, funnel_scale=sv), O.Funnel(d, sv), 0.05)
     else:
         s1, b, c = synth.BANANA
         return (dict(kind="banana", dim=2, banana=synth.BANANA), O.Banana(s1, b, c), 0.01)
@@ -52,7 +56,7 @@ def _pair(kind, J, seed, nmax=64, **kw):
     return s, o, rng, d
 
 
-@pytest.mark.parametrize("kind", ["gauss5", "illcond", "banana"])
+@pytest.mark.parametrize("kind", ["gauss5", "illcond", "banana", "funnel"])
 def test_initial_weights(kind):
     J = 300
     log(f"[targets] init {kind} J={J}")
@@ -62,7 +66,8 @@ def test_initial_weights(kind):
     np.testing.assert_allclose(logw.cpu().numpy(), o.logw, rtol=1e-9, atol=1e-9)
 
 
-@pytest.mark.parametrize("kind,traj_tol", [("gauss5", 1e-5), ("illcond", 1e-4), ("banana", 1e-5)])
+@pytest.mark.parametrize("kind,traj_tol", [("gauss5", 1e-5), ("illcond", 1e-4), ("banana", 1e-5),
+                                           ("funnel", 1e-5)])
 def test_one_iteration(kind, traj_tol):
     J = 300
     log(f"[targets] one iteration {kind} J={J}")
