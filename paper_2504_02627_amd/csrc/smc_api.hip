@@ -53,6 +53,7 @@ struct Layout {
   int B = 0, J = 0, Jcap = 0, DS = 0, nmax = 0;
   int lf_target = 0, lf_grid = 0, ll_smax = 0, ll_nitems = 0, col_chunks = 0;
   int gpart_slots = 0, goff[MAX_C2] = {};
+  int nosplit = 0;
   std::vector<HostPost> hp;
   std::vector<Post> posts;
   std::vector<int4> items;
@@ -61,7 +62,7 @@ struct Layout {
   // byte offsets
   size_t o_posts, o_ps, o_xab, o_xbf, o_theta, o_grad, o_theta_t, o_p_t, o_grad_t;
   size_t o_logpi, o_logpi_t, o_logw, o_h, o_l, o_H0, o_dH, o_alpha, o_ca, o_cg;
-  size_t o_n, o_perm, o_active, o_anc, o_acc, o_cdf, o_gpart, o_tilecnt, o_llpart;
+  size_t o_n, o_perm, o_active, o_anc, o_acc, o_cdf, o_gpart, o_llpart;
   size_t o_lf_post = 0, o_lf_items = 0, o_lf_count = 0;
   size_t o_tmean = 0, o_tprec = 0;
   size_t o_items, o_colpart, o_means, o_minv, o_primes, o_sqrtp = 0;
@@ -230,6 +231,11 @@ void plan(const smc_problem *pr, const smc_params *pa, Layout &L) {
   // feature-tile group already gets its own launch)
   L.lf_target = 256;
   const int ntile = L.Jcap / TJ;
+  // small data sets (at most 32 data tiles per posterior): one item per
+  // particle tile holds the whole gradient and finishes the step, with no
+  // reduction launch
+  L.nosplit = 1;
+  for (int b = 0; b < B; ++b) L.nosplit &= (bf16 ? L.hp[b].NT2 : L.hp[b].NT) <= 32;
   L.lf_grid = L.lf_target * lf_groups_per_cu(bf16, 1) + B * ntile;
   // log-likelihood pass: every tile, static splits, about lf_target items per
   // launch (one launch per feature-tile group)
@@ -304,7 +310,6 @@ void plan(const smc_problem *pr, const smc_params *pa, Layout &L) {
     L.gpart_slots += L.lf_target * lf_groups_per_cu(bf16, L.groups[g].x) + Bg * ntile;
   }
   L.o_gpart = take(c, (size_t)L.gpart_slots * TJ * L.DS * sizeof(float));
-  L.o_tilecnt = take(c, (size_t)B * ntile * 4);
   L.o_llpart = take(c, (size_t)L.ll_smax * rows * sizeof(float2));
   L.o_items = take(c, (size_t)L.ll_nitems * sizeof(int4));
   L.o_colpart = take(c, (size_t)B * L.col_chunks * 2 * L.DS * 8);
@@ -487,7 +492,7 @@ smc_status smc_init(const smc_problem *prob, const smc_params *par, void *worksp
   D.cdf = (unsigned long long *)(w + L.o_cdf);
   D.gpart = (float *)(w + L.o_gpart);
   D.gpart_slots = L.gpart_slots;
-  D.tilecnt = (int *)(w + L.o_tilecnt);
+  D.lf_nosplit = L.nosplit;
   D.llpart = (float2 *)(w + L.o_llpart);
   D.ll_smax = L.ll_smax;
   D.ll_items = (int4 *)(w + L.o_items);
@@ -621,7 +626,7 @@ smc_status smc_init(const smc_problem *prob, const smc_params *par, void *worksp
   } else {
     CKI(launch_lf_plan(D, ctx->st));
     for (int c2 : ctx->c2s) CKI(launch_lf_partial(D, c2, 0, 1, ctx->st));
-    CKI(launch_lf_reduce(D, 0, 1, ctx->st));
+    if (!D.lf_nosplit) CKI(launch_lf_reduce(D, 0, 1, ctx->st));
     for (const int3 &g : ctx->ll_groups) CKI(launch_loglik(D, g.x, g.y, g.z, ctx->st));
   }
   CKI(launch_init_weights(D, ctx->st));
@@ -699,13 +704,16 @@ smc_status enqueue_step(smc_ctx *ctx, const smc_inject *inject) {
         CK(timed_end(ctx, ei));
       }
       CK(timed_begin(ctx, 0, ei));
-      CK(launch_lf_partial(D, c2, s, D.flow ? 1 : 0, ctx->st));
+      CK(launch_lf_partial(D, c2, s, D.flow ? 2 : 0, ctx->st));
       CK(timed_end(ctx, ei));
     }
-    // one reduction for all groups (disjoint partial slots)
-    CK(timed_begin(ctx, 2, ei));
-    CK(launch_lf_reduce(D, s, D.flow ? 2 : 0, ctx->st));
-    CK(timed_end(ctx, ei));
+    // one reduction for all groups (disjoint partial slots), unless every tile
+    // is one item that finished its own step
+    if (!D.lf_nosplit) {
+      CK(timed_begin(ctx, 2, ei));
+      CK(launch_lf_reduce(D, s, D.flow ? 2 : 0, ctx->st));
+      CK(timed_end(ctx, ei));
+    }
     if (D.flow) {
       CK(timed_begin(ctx, 3, ei));
       CK(launch_flow_kick(D, F, s, ctx->st));

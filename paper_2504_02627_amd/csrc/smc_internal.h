@@ -111,7 +111,6 @@ struct Dev {                    // pointers carved from the workspace
   unsigned long long *cdf;
   float *gpart;                 // split partial gradients, [wg][TJ][DS]
   int gpart_slots;              // number of [TJ][DS] slots
-  int *tilecnt;                 // arrival counters per (posterior, tile)
   float2 *llpart;               // log-likelihood partials [split][row]
   int ll_smax;
   int4 *ll_items;               // (posterior, tile, split, -) work items of the log-lik pass
@@ -132,6 +131,7 @@ struct Dev {                    // pointers carved from the workspace
   double fsv;                   // funnel: standard deviation of v
   int lf_target;                // work groups per leapfrog launch and resident group per compute unit
   int lf_grid;                  // grid of a leapfrog launch
+  int lf_nosplit;               // one split per tile: the leapfrog launch finishes each step
   // leapfrog work plan, written once per iteration from the active counts:
   int4 *lf_post;                // [nmax][B] (first item, splits per tile, tiles with one more, tiles)
   int4 *lf_items;               // [group][nmax][lf_grid] (posterior, tile, split | S << 16, first item of tile)

@@ -347,7 +347,7 @@ __global__ __launch_bounds__(PLAN_THREADS) void k_lf_plan(Dev D) {
       if (T > 0 && U > 0) {
         const int NU = lf_units(D, P);
         long long G = (share * T * NU) / U;  // this posterior's share of the items
-        if (G < T) G = T;
+        if (G < T || D.lf_nosplit) G = T;
         const long long cap = (long long)T * (NU < LF_MAX_SPLIT ? NU : LF_MAX_SPLIT);
         if (G > cap) G = cap;
         base = (int)(G / T);
@@ -460,7 +460,30 @@ __device__ __forceinline__ void stage_issue(float4 *xs, const float4 *__restrict
   }
 }
 
-template <int C2>
+// End of a leapfrog step for one (particle row, feature) with the full
+// likelihood gradient G: the arithmetic of the split reduction.
+__device__ __forceinline__ void lf_finish(const Dev &D, long long row, int k, float G, float eps,
+                                          float he, const float *minv, int mode) {
+  const long long e = row * D.DS + k;
+  const float inv_pv = (float)(1.0 / D.prior_var);
+  const float t0 = D.theta_t[e];
+  if (mode == 2) {  // gradient only: theta' was written by the caller
+    D.grad_t[e] = G - t0 * inv_pv;
+    return;
+  }
+  const float ph = fmaf(he, D.grad_t[e], D.p_t[e]);
+  const float th1 = fmaf(eps * minv[k], ph, t0);
+  const float gn = G - th1 * inv_pv;
+  D.theta_t[e] = th1;
+  D.p_t[e] = fmaf(he, gn, ph);
+  D.grad_t[e] = gn;
+}
+
+// FIN: the plan has one split per tile (small data sets), so the item holds
+// its particles' whole likelihood gradient and finishes the step itself
+// (prior, second half kick, or the gradient only for zero_eps = 2), exactly as
+// the split reduction does; no reduction launch follows.
+template <int C2, bool FIN>
 __global__ __launch_bounds__(WG, 2 * lf_groups_per_cu(false, C2)) void k_lf_partial(Dev D, int s, int zero_eps) {
   constexpr int K1 = 4 * C2;
   using TL = Tiles<C2>;
@@ -548,6 +571,20 @@ __global__ __launch_bounds__(WG, 2 * lf_groups_per_cu(false, C2)) void k_lf_part
     cur ^= 1;
   }
 
+  if constexpr (FIN) {
+#pragma unroll
+    for (int sb = 0; sb < SUB; ++sb)
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int slot = (wave * SUB + sb) * 16 + 4 * kq + rr;
+        const long long row = P.row0 + perm[pl.tile * TJ + slot];
+        if (D.n[row] <= s) continue;
+#pragma unroll
+        for (int ct = 0; ct < C2; ++ct)
+          lf_finish(D, row, 16 * ct + (lane & 15), gacc[sb][ct][rr], eps, he, minv, zero_eps);
+      }
+    return;
+  }
   // partial gradient of this split: gpart[group's first slot + work item][slot][k]
   float *gp = D.gpart + (long long)(D.lf_goff[D.c2_group[C2]] + blockIdx.x) * TJ * D.DS;
 #pragma unroll
@@ -588,21 +625,55 @@ struct TilesBF {
   static constexpr int NINST = STAGE / 64;
 };
 
+
+// Register-staged prefetch of the BF16 tile loop.  A stage (two 32-row
+// tiles, 2 TILE uint4, contiguous in the packing) is loaded by all 512
+// threads with consecutive 16-byte global loads into registers while the
+// waves compute on the other LDS buffer, then written to LDS after the
+// compute.  (Direct global-to-LDS loads would save the registers, but the
+// compiler must assume such a load may alias any LDS read and waits for it
+// before the first operand read, so the prefetch would never overlap.)
 template <int C2>
-__device__ __forceinline__ void stage_issue_bf(uint4 *xs, const uint4 *__restrict__ xbf, int t,
-                                               int t1, int wave, int lane) {
+struct StageRegs {
+  static constexpr int N = 2 * TilesBF<C2>::TILE;           // uint4 per stage
+  static constexpr int K = (N + WG - 1) / WG;               // uint4 per thread
+  // one vector value (not an array) so that it lives in registers
+  typedef unsigned int vec __attribute__((ext_vector_type(4 * K)));
+  vec v;
+};
+
+// The loads are unconditional (indices clamped to the split's last tile and
+// to the stage), so no branch separates a load from its use and the compiler
+// keeps them all in flight; only the LDS stores are guarded.  Requires t < t1.
+template <int C2>
+__device__ __forceinline__ void stage_load_bf(StageRegs<C2> &r, const uint4 *__restrict__ xbf, int t,
+                                              int t1, int tid) {
   using TL = TilesBF<C2>;
-  const uint4 *src = xbf + (long long)t * TL::TILE + lane;
 #pragma unroll
-  for (int k = 0; k < (TL::NINST + WAVES - 1) / WAVES; ++k) {
-    const int m = wave + k * WAVES;
-    if (m < TL::NINST && t + m / TL::LSTR < t1)
-      __builtin_amdgcn_global_load_lds((const void *)(src + 64 * m), (lds_void *)(xs + 64 * m), 16,
-                                       0, 0);
+  for (int k = 0; k < StageRegs<C2>::K; ++k) {
+    const int idx = min(tid + k * WG, StageRegs<C2>::N - 1);
+    const int tile = min(t + idx / TL::TILE, t1 - 1);
+    const uint4 u = xbf[(long long)tile * TL::TILE + idx % TL::TILE];
+    r.v[4 * k + 0] = u.x;
+    r.v[4 * k + 1] = u.y;
+    r.v[4 * k + 2] = u.z;
+    r.v[4 * k + 3] = u.w;
   }
 }
 
 template <int C2>
+__device__ __forceinline__ void stage_store_bf(uint4 *xs, const StageRegs<C2> &r, int t, int t1,
+                                               int tid) {
+  using TL = TilesBF<C2>;
+#pragma unroll
+  for (int k = 0; k < StageRegs<C2>::K; ++k) {
+    const int idx = tid + k * WG;
+    if (idx < StageRegs<C2>::N && t + idx / TL::TILE < t1)
+      xs[idx] = make_uint4(r.v[4 * k + 0], r.v[4 * k + 1], r.v[4 * k + 2], r.v[4 * k + 3]);
+  }
+}
+
+template <int C2, bool FIN>
 __global__ __launch_bounds__(WG) void k_lf_partial_bf16(Dev D, int s, int zero_eps) {
   using TL = TilesBF<C2>;
   constexpr int KC = TL::KC;
@@ -648,13 +719,16 @@ __global__ __launch_bounds__(WG) void k_lf_partial_bf16(Dev D, int s, int zero_e
   const int t0 = (int)((long long)pl.split * P.NT2 / pl.S);
   const int t1 = (int)((long long)(pl.split + 1) * P.NT2 / pl.S);
   const uint4 *xbf = D.xbf + P.xbf;
-  stage_issue_bf<C2>(xs[0], xbf, t0, t1, wave, lane);
-  __builtin_amdgcn_s_waitcnt(0);
+  StageRegs<C2> pre;
+  if (t0 < t1) {
+    stage_load_bf<C2>(pre, xbf, t0, t1, tid);
+    stage_store_bf<C2>(xs[0], pre, t0, t1, tid);
+  }
   __syncthreads();
   int cur = 0;
   for (int t = t0; t < t1; t += 2) {
     const bool more = t + 2 < t1;
-    if (more) stage_issue_bf<C2>(xs[cur ^ 1], xbf, t + 2, t1, wave, lane);
+    if (more) stage_load_bf<C2>(pre, xbf, t + 2, t1, tid);  // in flight during the compute
     const int ntt = (t + 1 < t1) ? 2 : 1;
     for (int tt = 0; tt < ntt; ++tt) {
       const uint4 *xl = xs[cur] + tt * TL::TILE + lane * TL::LSTR;
@@ -678,11 +752,23 @@ __global__ __launch_bounds__(WG) void k_lf_partial_bf16(Dev D, int s, int zero_e
       for (int ct = 0; ct < C2; ++ct)
         gacc[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ra, as_v8bf(xl[2 * KC + ct]), gacc[ct], 0, 0, 0);
     }
-    __builtin_amdgcn_s_waitcnt(0);
+    // the other buffer was released by the barrier that ended the previous stage
+    if (more) stage_store_bf<C2>(xs[cur ^ 1], pre, t + 2, t1, tid);
     __syncthreads();
     cur ^= 1;
   }
 
+  if constexpr (FIN) {
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      const long long row = P.row0 + perm[pl.tile * TJ + wave * 16 + 4 * g + rr];
+      if (D.n[row] <= s) continue;
+#pragma unroll
+      for (int ct = 0; ct < C2; ++ct)
+        lf_finish(D, row, 16 * ct + (lane & 15), gacc[ct][rr], eps, he, minv, zero_eps);
+    }
+    return;
+  }
   float *gp = D.gpart + (long long)(D.lf_goff[D.c2_group[C2]] + blockIdx.x) * TJ * D.DS;
 #pragma unroll
   for (int ct = 0; ct < C2; ++ct)
@@ -702,20 +788,20 @@ constexpr int RED_THREADS = 256;
 constexpr int RED_ROUND = 8;
 
 __global__ __launch_bounds__(RED_THREADS) void k_lf_reduce(Dev D, int s, int zero_eps) {
-  const int ntile = D.Jcap / TJ;
+  const int tj = TJ, ntile = D.Jcap / tj;
   const int b = blockIdx.x / ntile, tile = blockIdx.x % ntile;
   const Post P = D.posts[b];
   const int4 q = D.lf_post[(long long)s * D.B + b];
   const int dq = 4 * P.C2;  // float4 per particle row
   const int idx = blockIdx.y * RED_THREADS + threadIdx.x;
-  if (idx >= TJ * dq || tile >= q.w) return;
+  if (idx >= tj * dq || tile >= q.w) return;
   Plan pl;
   pl.S = q.y + (tile < q.z ? 1 : 0);
   pl.wbase = D.lf_goff[D.c2_group[P.C2]] + q.x + tile * q.y + (tile < q.z ? tile : q.z);
   const int slot = idx / dq, k4 = idx - slot * dq;
-  const int j = D.perm[P.row0 + tile * TJ + slot];
-  const float4 *g0p = reinterpret_cast<const float4 *>(D.gpart + (long long)pl.wbase * TJ * D.DS);
-  const long long sstride = (long long)TJ * D.DS / 4;  // float4 between splits
+  const int j = D.perm[P.row0 + tile * tj + slot];
+  const float4 *g0p = reinterpret_cast<const float4 *>(D.gpart + (long long)pl.wbase * tj * D.DS);
+  const long long sstride = (long long)tj * D.DS / 4;  // float4 between splits
   const long long o4 = (long long)slot * D.DS / 4 + k4;
   // ordered sum over the splits: ((p0 + p1) + p2) + ...
   float4 G = g0p[o4];
@@ -767,10 +853,18 @@ __global__ __launch_bounds__(RED_THREADS) void k_lf_reduce(Dev D, int s, int zer
 
 template <int C2>
 static hipError_t launch_lf_c2(const Dev &D, int step, int zero_eps, hipStream_t st) {
-  if (D.bf16)
-    hipLaunchKernelGGL(k_lf_partial_bf16<C2>, dim3(D.lf_grid), dim3(WG), 0, st, D, step, zero_eps);
+  if (D.bf16 && D.lf_nosplit)
+    hipLaunchKernelGGL((k_lf_partial_bf16<C2, true>), dim3(D.lf_grid), dim3(WG), 0, st, D, step,
+                       zero_eps);
+  else if (D.bf16)
+    hipLaunchKernelGGL((k_lf_partial_bf16<C2, false>), dim3(D.lf_grid), dim3(WG), 0, st, D, step,
+                       zero_eps);
+  else if (D.lf_nosplit)
+    hipLaunchKernelGGL((k_lf_partial<C2, true>), dim3(D.lf_grid), dim3(WG), 0, st, D, step,
+                       zero_eps);
   else
-    hipLaunchKernelGGL(k_lf_partial<C2>, dim3(D.lf_grid), dim3(WG), 0, st, D, step, zero_eps);
+    hipLaunchKernelGGL((k_lf_partial<C2, false>), dim3(D.lf_grid), dim3(WG), 0, st, D, step,
+                       zero_eps);
   return hipGetLastError();
 }
 
