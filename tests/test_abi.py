@@ -44,6 +44,9 @@ def test_struct_sizes_match_c_layout():
     assert ctypes.sizeof(chees.Params) == 4 * 8 + 8 * 8 + 4 + 4 + 8 + 8 + 3 * 4 + 4 + 8 + 4 + 4
     assert ctypes.sizeof(chees.Stats) == 8 * 8 + 4 + 4 + 8
     assert ctypes.sizeof(chees.Inject) == 3 * 8
+    # num_posteriors (+pad), n_rows, dims, X, y, x_dtype (+pad), prior_var,
+    # target (+pad), mean, precision, log_const, banana s1/b/c, funnel_scale
+    assert ctypes.sizeof(chees.Problem) == 8 + 4 * 8 + 8 + 8 + 8 + 2 * 8 + 8 + 3 * 8 + 8
 
 
 def test_workspace_query_validates_without_gpu():
