@@ -237,8 +237,8 @@ void plan(const smc_problem *pr, const smc_params *pa, Layout &L) {
   L.nosplit = 1;
   for (int b = 0; b < B; ++b) L.nosplit &= (bf16 ? L.hp[b].NT2 : L.hp[b].NT) <= 32;
   L.lf_grid = L.lf_target * lf_groups_per_cu(bf16, 1) + B * ntile;
-  // log-likelihood pass: every tile, static splits, about lf_target items per
-  // launch (one launch per feature-tile group)
+  // log-likelihood pass: every tile, static splits, one launch per
+  // feature-tile group of about lf_target items per resident work group slot
   L.items.clear();
   L.ll_smax = 1;
   // items grouped by feature-tile count C2: one launch per group covers
@@ -254,7 +254,10 @@ void plan(const smc_problem *pr, const smc_params *pa, Layout &L) {
     long long U = 0;
     for (int b = 0; b < B; ++b)
       if (L.hp[b].C2 == g.x) U += (long long)ntile * L.hp[b].NT;
-    const long long chunk = std::max(1LL, (U + L.lf_target - 1) / L.lf_target);
+    // two resident log-likelihood work groups per compute unit while the
+    // staging buffers fit twice in LDS (C2 <= 9), so twice the items
+    const long long items = (long long)L.lf_target * (g.x <= 9 ? 2 : 1);
+    const long long chunk = std::max(1LL, (U + items - 1) / items);
     for (int b = 0; b < B; ++b) {
       if (L.hp[b].C2 != g.x) continue;
       long long S = (L.hp[b].NT + chunk - 1) / chunk;
