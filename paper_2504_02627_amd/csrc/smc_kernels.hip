@@ -505,6 +505,12 @@ __global__ __launch_bounds__(WG, 2 * lf_groups_per_cu(false, C2)) void k_lf_part
   const float *minv = D.minv + (long long)pl.b * D.DS;
   const int *perm = D.perm + P.row0;
 
+  // the first stage of data tiles is in flight while theta' is formed
+  const int t0 = (int)((long long)pl.split * P.NT / pl.S);
+  const int t1 = (int)((long long)(pl.split + 1) * P.NT / pl.S);
+  const float4 *xab = reinterpret_cast<const float4 *>(D.xab + P.xab);
+  stage_issue<C2>(xs[0], xab, t0, t1, wave, lane);
+
   // theta' of this wave's particles in the B-operand layout of GEMM1
   float th[SUB][K1];
 #pragma unroll
@@ -527,10 +533,6 @@ __global__ __launch_bounds__(WG, 2 * lf_groups_per_cu(false, C2)) void k_lf_part
 #pragma unroll
     for (int ct = 0; ct < C2; ++ct) gacc[sb][ct] = v4f{0.f, 0.f, 0.f, 0.f};
 
-  const int t0 = (int)((long long)pl.split * P.NT / pl.S);
-  const int t1 = (int)((long long)(pl.split + 1) * P.NT / pl.S);
-  const float4 *xab = reinterpret_cast<const float4 *>(D.xab + P.xab);
-  stage_issue<C2>(xs[0], xab, t0, t1, wave, lane);
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   int cur = 0;
@@ -695,6 +697,13 @@ __global__ __launch_bounds__(WG) void k_lf_partial_bf16(Dev D, int s, int zero_e
   const float *minv = D.minv + (long long)pl.b * D.DS;
   const int *perm = D.perm + P.row0;
 
+  // the first stage of data tiles is in flight while theta' is formed
+  const int t0 = (int)((long long)pl.split * P.NT2 / pl.S);
+  const int t1 = (int)((long long)(pl.split + 1) * P.NT2 / pl.S);
+  const uint4 *xbf = D.xbf + P.xbf;
+  StageRegs<C2> pre;
+  if (t0 < t1) stage_load_bf<C2>(pre, xbf, t0, t1, tid);
+
   // theta' (bfloat16, B operand of GEMM1): chunk c holds features 32c + 8g + e
   v8bf thb[KC];
   {
@@ -716,14 +725,7 @@ __global__ __launch_bounds__(WG) void k_lf_partial_bf16(Dev D, int s, int zero_e
 #pragma unroll
   for (int ct = 0; ct < C2; ++ct) gacc[ct] = v4f{0.f, 0.f, 0.f, 0.f};
 
-  const int t0 = (int)((long long)pl.split * P.NT2 / pl.S);
-  const int t1 = (int)((long long)(pl.split + 1) * P.NT2 / pl.S);
-  const uint4 *xbf = D.xbf + P.xbf;
-  StageRegs<C2> pre;
-  if (t0 < t1) {
-    stage_load_bf<C2>(pre, xbf, t0, t1, tid);
-    stage_store_bf<C2>(xs[0], pre, t0, t1, tid);
-  }
+  if (t0 < t1) stage_store_bf<C2>(xs[0], pre, t0, t1, tid);
   __syncthreads();
   int cur = 0;
   for (int t = t0; t < t1; t += 2) {
@@ -933,6 +935,11 @@ __global__ __launch_bounds__(WG) void k_loglik(Dev D, int first) {
   const int b = it.x, tile = it.y, split = it.z;
   const Post P = D.posts[b];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, kq = lane >> 4;
+  const int S = P.ll_splits;
+  const int t0 = (int)((long long)split * P.NT / S);
+  const int t1 = (int)((long long)(split + 1) * P.NT / S);
+  const float4 *xab = reinterpret_cast<const float4 *>(D.xab + P.xab);
+  stage_issue<C2>(xs[0], xab, t0, t1, wave, lane);  // in flight with the theta loads
   float th[SUB][K1];
 #pragma unroll
   for (int sb = 0; sb < SUB; ++sb) {
@@ -944,11 +951,6 @@ __global__ __launch_bounds__(WG) void k_loglik(Dev D, int first) {
   Neu acc[SUB];
 #pragma unroll
   for (int sb = 0; sb < SUB; ++sb) acc[sb] = Neu{0.f, 0.f};
-  const int S = P.ll_splits;
-  const int t0 = (int)((long long)split * P.NT / S);
-  const int t1 = (int)((long long)(split + 1) * P.NT / S);
-  const float4 *xab = reinterpret_cast<const float4 *>(D.xab + P.xab);
-  stage_issue<C2>(xs[0], xab, t0, t1, wave, lane);
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   int cur = 0;
