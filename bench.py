@@ -288,8 +288,7 @@ def other_workloads(args):
     forms = {
         "unit_mass": dict(step_size=e0, traj_length=e0 * 32),
         "diagonal_mass": dict(step_size=0.05, traj_length=1.6, precond="diag"),
-        "flow_base_only": dict(step_size=0.3, traj_length=2.4, precond="flow", flow_layers=4,
-                               flow_train_steps=0),
+        "flow_base_only": dict(step_size=0.3, traj_length=2.4, precond="flow", flow_layers=0),
         "flow_4x128_trained": dict(step_size=0.3, traj_length=2.4, precond="flow", flow_layers=4,
                                    flow_train_steps=10, flow_lr=2e-5),
     }

@@ -157,7 +157,8 @@ typedef struct {
                                  alpha, e.g. 0.651; DUAL_AVERAGING: mean alpha,
                                  e.g. 0.65)                                     */
   uint64_t seed;              /* key of the Philox4x32-10 streams               */
-  /* SMC_PRECOND_FLOW only: coupling layers (1..8), conditioner width (128),
+  /* SMC_PRECOND_FLOW only: coupling layers (0..8; 0 = the base map alone,
+   * a dense mass from the weighted covariance), conditioner width (128),
    * Adam steps of the weighted maximum-likelihood fit per iteration (>= 0,
    * warm-started) and their learning rate */
   int32_t flow_layers, flow_width, flow_train_steps;

@@ -735,7 +735,7 @@ class OracleSMC:
             W = normalise(self.logw)
             # reading: no fit on a resampled iteration (a resampled population
             # holds duplicates, onto which a maximum-likelihood fit collapses)
-            for _ in range(0 if resampled else P["flow_train_steps"]):
+            for _ in range(0 if resampled or P["flow_layers"] == 0 else P["flow_train_steps"]):
                 _, g_ = flow.objective_and_grad(self.flow_ps, base, self.theta, W)
                 self.flow_ps = self.flow_adam.ascend(self.flow_ps, g_)
             self.flow_base = base

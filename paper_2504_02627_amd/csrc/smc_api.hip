@@ -76,7 +76,9 @@ struct Layout {
 // Layer table of the flow: even layers transform the first floor(d/2)
 // coordinates given the rest, odd layers the rest given the first ones.
 bool flow_net(int d, int layers, int width, FlowNet &F) {
-  if (d < 2 || d > 16 * MAX_C2 || layers < 1 || layers > FMAXL || width != FH) return false;
+  // layers = 0: the base map alone (theta = m + L u, a dense mass from the
+  // weighted covariance)
+  if (d < 2 || d > 16 * MAX_C2 || layers < 0 || layers > FMAXL || width != FH) return false;
   memset(&F, 0, sizeof(F));
   F.L = layers;
   F.d = d;
@@ -168,7 +170,7 @@ const char *check(const smc_problem *pr, const smc_params *pa) {
     FlowNet F;
     if (pr->num_posteriors != 1) return "the flow preconditioner takes one posterior";
     if (!flow_net(pr->dims[0], pa->flow_layers, pa->flow_width, F))
-      return "flow: d >= 2, flow_layers in [1, 8], flow_width 128";
+      return "flow: d >= 2, flow_layers in [0, 8], flow_width 128";
     if (pa->flow_train_steps < 0 || pa->flow_train_steps > 100000) return "flow_train_steps";
     if (!(pa->flow_lr >= 0.0)) return "flow_lr >= 0";
   }
@@ -324,7 +326,7 @@ void plan(const smc_problem *pr, const smc_params *pa, Layout &L) {
   L.o_sqrtp = take(c, NPRIMES * 8);
   if (pa->precond == SMC_PRECOND_FLOW) {
     flow_net(pr->dims[0], pa->flow_layers, pa->flow_width, L.F);
-    L.F.ntrain = pa->flow_train_steps;
+    L.F.ntrain = L.F.L > 0 ? pa->flow_train_steps : 0;  // nothing to fit without couplings
     L.F.lr = (float)pa->flow_lr;
     const size_t np = (size_t)L.F.nparams;
     L.o_fz = take(c, st);
@@ -350,7 +352,7 @@ void plan(const smc_problem *pr, const smc_params *pa, Layout &L) {
     L.o_fgrad = take(c, (size_t)FKSPLIT * np * 4);
     L.o_fadm = take(c, np * 4);
     L.o_fadv = take(c, np * 4);
-    L.o_ftape = take(c, rows * L.F.L * std::max(L.F.tape_stride, L.F.train_stride) * 4);
+    L.o_ftape = take(c, rows * std::max(L.F.L, 1) * std::max(L.F.tape_stride, L.F.train_stride) * 4);
     L.o_fstate = take(c, 256);
   }
   L.total = (c + 255) & ~(size_t)255;

@@ -77,8 +77,9 @@ def _blocks_close(dev, ref, d, what, rtol=1e-4):
     assert worst <= rtol
 
 
-@pytest.mark.parametrize("N,d,J,seed", [(500, 12, 256, 5), (800, 37, 130, 6)])
-def test_flow_iteration_parity(N, d, J, seed):
+@pytest.mark.parametrize("N,d,J,seed,layers", [(500, 12, 256, 5, LAYERS), (800, 37, 130, 6, LAYERS),
+                                               (500, 12, 256, 7, 0)])
+def test_flow_iteration_parity(N, d, J, seed, layers):
     """Two iterations with one Adam step each (the fit is warm-started), no
     resampling, so that the weighted objective sees the population's own
     weights.  Adam normalises each coordinate of the gradient, so coordinates
@@ -88,8 +89,9 @@ def test_flow_iteration_parity(N, d, J, seed):
     same parameters and population) and through the Adam update applied to the
     device's gradient."""
     lr = 1e-2
-    X, y, theta0, params, s, t, rng = _setup(N, d, J, seed, 1, lr, ess_frac=0.0)
-    log(f"[flow] N={N} d={d} J={J} seed={seed}")
+    X, y, theta0, params, s, t, rng = _setup(N, d, J, seed, 1, lr, ess_frac=0.0,
+                                             flow_layers=layers)
+    log(f"[flow] N={N} d={d} J={J} seed={seed} layers={layers}")
     P0 = s.flow()[0].cpu().numpy().astype(np.float64)
     ad = F.FlowAdam(lr)
     th_prev = theta0.astype(np.float64)
@@ -107,16 +109,19 @@ def test_flow_iteration_parity(N, d, J, seed):
         np.testing.assert_allclose(m_dev, ref.m, rtol=1e-6, atol=1e-7)
         np.testing.assert_allclose(L_dev, ref.L, rtol=1e-5, atol=1e-6 * np.abs(ref.L).max())
         base = F.Base(m_dev, L_dev)
-        W = O.normalise(lw_prev)
-        _, g = F.objective_and_grad(F.unflatten(Pprev, d, LAYERS, 128)[0], base, th0, W)
-        _blocks_close(g_dev, F.flatten(g), d, f"iteration {k}: fit gradient")
-        P_exp = F.flatten(ad.ascend(F.unflatten(Pprev, d, LAYERS, 128)[0],
-                                    F.unflatten(g_dev, d, LAYERS, 128)[0]))
-        dP = np.abs(prm - P_exp)
-        log(f"  iteration {k}: Adam update max |dP| {dP.max():.2e}")
-        assert np.all(dP <= 1e-6 * (np.abs(P_exp) + lr))
+        if layers:
+            W = O.normalise(lw_prev)
+            _, g = F.objective_and_grad(F.unflatten(Pprev, d, layers, 128)[0], base, th0, W)
+            _blocks_close(g_dev, F.flatten(g), d, f"iteration {k}: fit gradient")
+            P_exp = F.flatten(ad.ascend(F.unflatten(Pprev, d, layers, 128)[0],
+                                        F.unflatten(g_dev, d, layers, 128)[0]))
+            dP = np.abs(prm - P_exp)
+            log(f"  iteration {k}: Adam update max |dP| {dP.max():.2e}")
+            assert np.all(dP <= 1e-6 * (np.abs(P_exp) + lr))
+        else:
+            assert prm.size == 0   # the base map alone: no parameters to fit
         # moves with the device's trained couplings, BF16-rounded
-        psb = F.bf16_params(F.unflatten(prm, d, LAYERS, 128)[0])
+        psb = F.bf16_params(F.unflatten(prm, d, layers, 128)[0])
         z0, ldi = F.inverse(psb, base, th0)
         z0_dev = tr["latent0"].cpu().numpy()[:J, :d].astype(np.float64)
         ez0 = rel_rows(z0_dev, z0)
