@@ -377,6 +377,85 @@ def equidistant_offset(seed, k, J, b=0):
     return equidistant(seed, k, J, b) + 0.1 * uniform_jitter(seed, k, J, b)
 
 
+# --- Sobol (eq. sobol) ---------------------------------------------------------
+
+def joe_kuo_rows(dims):
+    """The first `dims` rows of Joe and Kuo's direction-number table, as the
+    scipy package ships it (the generator the paper names for its Sobol
+    schemes): for each dimension the primitive polynomial as a bit mask with
+    its leading and constant terms (1 for the first dimension) and the
+    initial direction integers m_1..m_s (zero beyond the degree s)."""
+    import os
+    import scipy.stats
+    z = np.load(os.path.join(os.path.dirname(scipy.stats.__file__), "_sobol_direction_numbers.npz"))
+    return [(int(p), [int(v) for v in row]) for p, row in zip(z["poly"][:dims], z["vinit"][:dims])]
+
+
+def sobol_direction_integers(poly, minit, nbits):
+    """m_1..m_nbits of one dimension (Bratley and Fox; Joe and Kuo).
+
+    For the primitive polynomial x^s + a_1 x^(s-1) + .. + a_(s-1) x + 1 the
+    integers after the s given ones follow
+        m_i = 2 a_1 m_(i-1) ^ 4 a_2 m_(i-2) ^ .. ^ 2^(s-1) a_(s-1) m_(i-s+1)
+              ^ 2^s m_(i-s) ^ m_(i-s)            (^ is bitwise xor),
+    and the direction number nu_i is m_i / 2^i.  A polynomial of degree 0
+    (the first dimension) has m_i = 1 for all i: the van der Corput sequence.
+    """
+    s = poly.bit_length() - 1
+    if s == 0:
+        return [1] * nbits
+    m = list(minit[:s])
+    for i in range(s, nbits):          # m[i] is m_(i+1)
+        v = m[i - s] ^ (m[i - s] << s)
+        for t in range(1, s):
+            if (poly >> (s - t)) & 1:  # a_t
+                v ^= m[i - t] << t
+        m.append(v)
+    return m
+
+
+def sobol_point(m, i, nbits):
+    """x_i of one Sobol dimension (eq. sobol): the xor of the direction
+    numbers nu_b over the binary digits b of i, as an exact binary fraction.
+
+    Reading: eq. sobol writes the digits of i itself; the scipy generator the
+    paper uses takes the digits of the Gray code i ^ (i >> 1), which lists
+    the same points in each block of 2^m in another order.  The Gray-code
+    digits are used, so that the sequence is the one the paper ran."""
+    g = i ^ (i >> 1)
+    x, b = 0, 0
+    while g:
+        if g & 1:
+            x ^= m[b] << (nbits - 1 - b)
+        g >>= 1
+        b += 1
+    return x / 2 ** nbits
+
+
+def sobol_1d(k, J):
+    """1-d Sobol jitter: J*K numbers from the first Sobol dimension.
+
+    Reading: the printed definition points to eq. halton with k = 1, which
+    has no base; taken as the first dimension of eq. sobol (nu_b = 2^-b),
+    flattened like the 1-d Halton scheme, index (k-1) J + j, j = 1..J (the
+    point 0 of the sequence is never used)."""
+    m = [1] * 64
+    return np.array([sobol_point(m, (k - 1) * J + j, 64) for j in range(1, J + 1)])
+
+
+def sobol_nd(k, J, rows=None):
+    """N-d Sobol jitter (eq. sobol): h_jk = x_j of Sobol dimension k,
+    j = 1..J (the point 0 is skipped), direction numbers of Joe and Kuo."""
+    poly, minit = (rows or joe_kuo_rows(k))[k - 1]
+    m = sobol_direction_integers(poly, minit, 32)
+    return np.array([sobol_point(m, j, 32) for j in range(1, J + 1)])
+
+
+def sobol_nd_inverse(k, K, J, rows=None):
+    """Inverse N-d Sobol: the N-d Sobol matrix with its columns reversed."""
+    return sobol_nd(reversed_column(k, K), J, rows)
+
+
 def step_counts(h, L, eps, n_max):
     """Jittered length l_j = h_j L and n_j = min(max(ceil(l_j / eps), 1), n_max)
     (Alg. smc_ChEES: l_m = h_m L_{m-1}, ceil(l_m / eps) leapfrog steps).
@@ -695,6 +774,12 @@ class OracleSMC:
             return equidistant(seed, k, self.J)
         if kind == "equidistant_offset":
             return equidistant_offset(seed, k, self.J)
+        if kind == "sobol1d":
+            return sobol_1d(k, self.J)
+        if kind == "sobolNd":
+            return sobol_nd(k, self.J)
+        if kind == "sobolNd_inv":
+            return sobol_nd_inverse(k, K, self.J)
         raise ValueError(kind)
 
     def step(self, momenta=None, mh_uniforms=None, resample_u=None):

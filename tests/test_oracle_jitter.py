@@ -176,3 +176,65 @@ def test_sampler_uses_scheme(kind):
     o2 = O.OracleSMC(t, J, theta0=np.zeros((J, 3)), jitter="halton1d", seed=9,
                      step_size=0.05, traj_length=0.5, max_leapfrog=16, num_warmup=2)
     assert not np.array_equal(h, o2.jitter(2))
+
+
+# --- Sobol ------------------------------------------------------------------------------
+
+def test_sobol_first_dimension_by_hand():
+    # nu_b = 2^-b: x_i is the base-2 radical inverse of the Gray code of i;
+    # Gray codes of 1..8 are 1, 3, 2, 6, 7, 5, 4, 12
+    np.testing.assert_array_equal(O.sobol_1d(1, 8), [1 / 2, 3 / 4, 1 / 4, 3 / 8, 7 / 8, 5 / 8,
+                                                     1 / 8, 3 / 16])
+    # iteration 2 of J = 4 continues the sequence at index 5
+    np.testing.assert_array_equal(O.sobol_1d(2, 4), [7 / 8, 5 / 8, 1 / 8, 3 / 16])
+
+
+def test_sobol_direction_integers_by_hand():
+    # x + 1 (mask 3), m_1 = 1: m_i = 2 m_(i-1) ^ m_(i-1) -> 1, 3, 5, 15, 17
+    assert O.sobol_direction_integers(3, [1], 5) == [1, 3, 5, 15, 17]
+    # x^2 + x + 1 (mask 7), m = 1, 3: m_3 = 2 m_2 ^ 4 m_1 ^ m_1 = 6 ^ 4 ^ 1 = 3,
+    # m_4 = 2 m_3 ^ 4 m_2 ^ m_2 = 6 ^ 12 ^ 3 = 9
+    assert O.sobol_direction_integers(7, [1, 3], 4) == [1, 3, 3, 9]
+    rows = O.joe_kuo_rows(3)
+    assert rows[1][0] == 3 and rows[2][0] == 7 and rows[2][1][:2] == [1, 3]
+    # dimension 2: nu = 1/2, 3/4, 5/8; points by hand
+    np.testing.assert_array_equal(O.sobol_nd(2, 4, rows), [1 / 2, 1 / 4, 3 / 4, 3 / 8])
+    # dimension 3: nu = 1/2, 3/4, 3/8
+    np.testing.assert_array_equal(O.sobol_nd(3, 4, rows), [1 / 2, 1 / 4, 3 / 4, 5 / 8])
+
+
+def test_sobol_matches_scipy():
+    # the library generator the paper names, unscrambled, 32-bit: its points
+    # 1..2^10 - 1 in every one of the first 200 dimensions, and its first
+    # dimension continued past one block
+    K = 200
+    rows = O.joe_kuo_rows(K)
+    ref = stats.qmc.Sobol(d=K, scramble=False, bits=32).random_base2(10)[1:]
+    for k in (1, 2, 3, 4, 17, 64, 123, 200):
+        np.testing.assert_array_equal(O.sobol_nd(k, 1023, rows), ref[:, k - 1])
+    g = stats.qmc.Sobol(d=1, scramble=False, bits=32)
+    g.fast_forward(1 + 2 * 300)                    # iteration 3 of J = 300
+    np.testing.assert_array_equal(O.sobol_1d(3, 300), g.random(300)[:, 0])
+
+
+def test_sobol_every_dimension_is_a_net():
+    # any valid direction numbers (m_i odd, m_i < 2^i) make the first 2^m
+    # points of each dimension, the point 0 included, hit every cell of width
+    # 2^-m once; dimensions 1 and 2 together form a (0, m, 2)-net
+    m = 8
+    rows = O.joe_kuo_rows(60)
+    for k in range(1, 61):
+        x = np.concatenate([[0.0], O.sobol_nd(k, 2 ** m - 1, rows)])
+        assert sorted((x * 2 ** m).astype(int).tolist()) == list(range(2 ** m))
+    x1 = np.concatenate([[0.0], O.sobol_nd(1, 2 ** m - 1, rows)])
+    x2 = np.concatenate([[0.0], O.sobol_nd(2, 2 ** m - 1, rows)])
+    for a in range(m + 1):                         # boxes 2^-a x 2^-(m-a)
+        cells = set(zip((x1 * 2 ** a).astype(int).tolist(), (x2 * 2 ** (m - a)).astype(int).tolist()))
+        assert len(cells) == 2 ** m
+
+
+def test_sobol_inverse_reverses_columns():
+    rows = O.joe_kuo_rows(5)
+    np.testing.assert_array_equal(O.sobol_nd_inverse(1, 5, 40, rows), O.sobol_nd(5, 40, rows))
+    np.testing.assert_array_equal(O.sobol_nd_inverse(5, 5, 40, rows), O.sobol_nd(1, 40, rows))
+    np.testing.assert_array_equal(O.sobol_nd_inverse(6, 5, 40, rows), O.sobol_nd(5, 40, rows))
