@@ -67,7 +67,16 @@ enum { SMC_JITTER_HALTON1D = 0,     /* phi_2((k-1) J + j)                       
        SMC_JITTER_PRIMES_INV = 6,   /* j sqrt(P_k') mod 1                          */
        SMC_JITTER_GOLDEN = 7,       /* ((j-1) K + k) (sqrt 5 - 1)/2 mod 1          */
        SMC_JITTER_EQUIDISTANT = 8,  /* (pi_k(j-1) + 1) / J                         */
-       SMC_JITTER_EQUIDISTANT_OFFSET = 9 /* (pi_k(j-1) + 1) / J + 0.1 u_jk        */ };
+       SMC_JITTER_EQUIDISTANT_OFFSET = 9, /* (pi_k(j-1) + 1) / J + 0.1 u_jk       */
+       SMC_JITTER_SOBOL1D = 10,     /* x^(1)((k-1) J + j)                          */
+       SMC_JITTER_SOBOLND = 11,     /* x^(k)(j), k beyond sobol_dims: the last one  */
+       SMC_JITTER_SOBOLND_INV = 12  /* x^(k')(j)                                   */ };
+/* Sobol schemes (eq. sobol): x^(k)(i) is point i of Sobol dimension k, the
+ * xor of its direction numbers nu_b = m_b / 2^b over the binary digits b of
+ * the Gray code i ^ (i >> 1) (the order of scipy's generator, which the paper
+ * uses), point 0 never used.  Dimension 1 has nu_b = 2^-b (the base-2 van der
+ * Corput sequence) and needs no table; the N-d schemes take the direction
+ * integers from smc_params.sobol_table. */
 /* resampling schemes (Sec. III) */
 enum { SMC_RESAMPLE_SYSTEMATIC = 0, SMC_RESAMPLE_MULTINOMIAL = 1 };
 /* step-size adaptation during warm-up */
@@ -164,8 +173,20 @@ typedef struct {
   int32_t flow_layers, flow_width, flow_train_steps;
   double flow_lr;
   /* K, the columns of the jitter matrix: required (1..1024) by the inverse
-   * schemes, and (>= 1) by the golden-ratio scheme; ignored otherwise */
+   * Halton and primes schemes, (1..sobol_dims) by the inverse Sobol scheme,
+   * and (>= 1) by the golden-ratio scheme; ignored otherwise */
   int32_t num_iterations;
+  /* SMC_JITTER_SOBOLND(_INV) only (NULL and 0 otherwise): HOST array of
+   * sobol_dims (1..21201) rows of 19 words, row k - 1 for dimension k: the
+   * primitive polynomial x^s + a_1 x^(s-1) + .. + a_(s-1) x + 1 as the bit
+   * mask with bit s set for x^s, bit s - t for a_t and bit 0 for the constant
+   * term (the mask 1, s = 0, means the first dimension's nu_b = 2^-b), then
+   * the initial direction integers m_1..m_s (odd, m_i < 2^i; s <= 18; the
+   * words past s are ignored).  This is the layout of Joe and Kuo's table as
+   * scipy ships it.  Read during smc_init only; a malformed row is
+   * SMC_EINVAL. */
+  const uint32_t *sobol_table;
+  int32_t sobol_dims;
 } smc_params;
 
 /* Host-supplied randomness for one smc_step (all fields nullable, DEVICE

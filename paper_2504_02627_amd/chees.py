@@ -18,7 +18,7 @@ STATUS = {0: "SMC_OK", -1: "SMC_EINVAL", -2: "SMC_EDEVICE", -3: "SMC_EDEGENERATE
 SMC_F32, SMC_BF16 = 0, 1
 JITTER = {"halton1d": 0, "none": 1, "haltonNd": 2, "uniform": 3, "haltonNd_inv": 4,
           "primes": 5, "primes_inv": 6, "golden": 7, "equidistant": 8,
-          "equidistant_offset": 9}
+          "equidistant_offset": 9, "sobol1d": 10, "sobolNd": 11, "sobolNd_inv": 12}
 RESAMPLING = {"systematic": 0, "multinomial": 1}
 PRECISION = {"f32": 0, "bf16": 1}
 PRECOND = {"none": 0, "diag": 1, "flow": 2}
@@ -62,7 +62,8 @@ class Params(ctypes.Structure):
                 ("adapt_step_size", ctypes.c_int32), ("target_accept", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("flow_layers", ctypes.c_int32),
                 ("flow_width", ctypes.c_int32), ("flow_train_steps", ctypes.c_int32),
-                ("flow_lr", ctypes.c_double), ("num_iterations", ctypes.c_int32)]
+                ("flow_lr", ctypes.c_double), ("num_iterations", ctypes.c_int32),
+                ("sobol_table", ctypes.c_void_p), ("sobol_dims", ctypes.c_int32)]
 
 
 class Inject(ctypes.Structure):
@@ -172,7 +173,26 @@ DEFAULT_PARAMS = dict(max_leapfrog=64, num_warmup=10, jitter="halton1d", mh_acce
                       adam_b1=0.9, adam_b2=0.999, adam_eps=1e-8, avg_decay=0.9,
                       adapt_step_size=False, target_accept=0.651, seed=0,
                       flow_layers=4, flow_width=128, flow_train_steps=10, flow_lr=1e-3,
-                      num_iterations=0)
+                      num_iterations=0, sobol_dims=0)
+
+
+SOBOL_MAX_DIMS = 21201
+
+
+def sobol_table(dims):
+    """The first `dims` rows of Joe and Kuo's Sobol direction-number table in
+    the layout smc_params.sobol_table takes (polynomial mask, m_1..m_18 per
+    row), read from the copy the scipy package ships (a numpy archive of
+    integers, loaded without pickle)."""
+    import numpy as np
+    import scipy.stats
+    path = os.path.join(os.path.dirname(scipy.stats.__file__), "_sobol_direction_numbers.npz")
+    with np.load(path) as z:
+        poly, vinit = z["poly"][:dims], z["vinit"][:dims]
+    tab = np.zeros((dims, 19), dtype=np.uint32)
+    tab[:, 0] = poly
+    tab[:, 1:] = vinit
+    return np.ascontiguousarray(tab)
 
 
 def make_params(num_particles, **kw):
@@ -181,13 +201,21 @@ def make_params(num_particles, **kw):
     if unknown:
         raise TypeError(f"unknown parameters {sorted(unknown)}")
     p.update(kw)
-    return Params(num_particles, p["max_leapfrog"], p["num_warmup"], JITTER[p["jitter"]],
-                  int(bool(p["mh_accept"])), RESAMPLING[p["resampling"]],
-                  PRECISION[p["precision"]], PRECOND[p["precond"]], p["step_size"],
-                  p["traj_length"], p["ess_frac"], p["adam_lr"], p["adam_b1"], p["adam_b2"],
-                  p["adam_eps"], p["avg_decay"], ADAPT_EPS[p["adapt_step_size"]],
-                  p["target_accept"], p["seed"], p["flow_layers"], p["flow_width"],
-                  p["flow_train_steps"], p["flow_lr"], p["num_iterations"])
+    par = Params(num_particles, p["max_leapfrog"], p["num_warmup"], JITTER[p["jitter"]],
+                 int(bool(p["mh_accept"])), RESAMPLING[p["resampling"]],
+                 PRECISION[p["precision"]], PRECOND[p["precond"]], p["step_size"],
+                 p["traj_length"], p["ess_frac"], p["adam_lr"], p["adam_b1"], p["adam_b2"],
+                 p["adam_eps"], p["avg_decay"], ADAPT_EPS[p["adapt_step_size"]],
+                 p["target_accept"], p["seed"], p["flow_layers"], p["flow_width"],
+                 p["flow_train_steps"], p["flow_lr"], p["num_iterations"])
+    if p["jitter"] in ("sobolNd", "sobolNd_inv"):
+        # one dimension per iteration: sobol_dims if given, else K of them
+        # (1024 when K is not given either)
+        dims = int(p["sobol_dims"]) or min(max(int(p["num_iterations"]), 1024), SOBOL_MAX_DIMS)
+        par._sobol = sobol_table(dims)      # kept alive with the struct
+        par.sobol_table = par._sobol.ctypes.data
+        par.sobol_dims = dims
+    return par
 
 
 def make_problem(Xs, ys, prior_var=1.0):

@@ -25,6 +25,7 @@ struct smc_ctx {
   std::vector<int4> ll_items;
   std::vector<int> primes;
   std::vector<double> sqrtp;   // sqrt of the primes (binary64, correctly rounded)
+  std::vector<uint32_t> sobol; // direction numbers of the N-d Sobol schemes
   std::vector<float> minv;
   int stepped = 0;             // a step ran since the last adaptation
   int steps = 0;
@@ -65,7 +66,7 @@ struct Layout {
   size_t o_n, o_perm, o_active, o_anc, o_acc, o_cdf, o_gpart, o_llpart;
   size_t o_lf_post = 0, o_lf_items = 0, o_lf_count = 0;
   size_t o_tmean = 0, o_tprec = 0;
-  size_t o_items, o_colpart, o_means, o_minv, o_primes, o_sqrtp = 0;
+  size_t o_items, o_colpart, o_means, o_minv, o_primes, o_sqrtp = 0, o_sobol = 0;
   FlowNet F;
   size_t o_fz = 0, o_fz0 = 0, o_fgz = 0, o_fld0 = 0, o_fld1 = 0, o_fm = 0, o_fL = 0, o_fAf = 0,
          o_fAb = 0, o_fAi = 0, o_fcov = 0, o_fLd = 0, o_fLi = 0, o_fbase = 0;
@@ -124,6 +125,41 @@ size_t take(size_t &cur, size_t bytes) {
   return o;
 }
 
+// Direction numbers of the Sobol dimensions (Bratley and Fox; Joe and Kuo)
+// from the table rows (polynomial mask, m_1..m_18): for the primitive
+// polynomial x^s + a_1 x^(s-1) + .. + a_(s-1) x + 1 the direction integers
+// after the s given ones follow
+//   m_i = 2 a_1 m_(i-1) ^ .. ^ 2^(s-1) a_(s-1) m_(i-s+1) ^ 2^s m_(i-s) ^ m_(i-s),
+// and V[b] = m_(b+1) 2^(31-b) is nu_(b+1) in 32-bit fixed point.  The mask 1
+// (s = 0) gives m_i = 1.  Returns false for a malformed row (even mask, degree
+// above 18, an m_i even or not below 2^i); V may be NULL (validation only).
+bool sobol_directions(const uint32_t *tab, int dims, uint32_t *V) {
+  for (int r = 0; r < dims; ++r) {
+    const uint32_t *row = tab + (size_t)r * (1 + SOBOL_MAXDEG);
+    const uint32_t poly = row[0];
+    if (!(poly & 1u)) return false;
+    const int s = 31 - __builtin_clz(poly);
+    if (s > SOBOL_MAXDEG) return false;
+    uint64_t m[32];
+    for (int i = 0; i < 32; ++i) {
+      if (s == 0) {
+        m[i] = 1;
+      } else if (i < s) {
+        m[i] = row[1 + i];
+        if (!(m[i] & 1u) || m[i] >= (2ull << i)) return false;
+      } else {
+        uint64_t v = m[i - s] ^ (m[i - s] << s);
+        for (int t = 1; t < s; ++t)
+          if ((poly >> (s - t)) & 1u) v ^= m[i - t] << t;
+        m[i] = v;
+      }
+    }
+    if (V)
+      for (int b = 0; b < 32; ++b) V[(size_t)r * 32 + b] = (uint32_t)(m[b] << (31 - b));
+  }
+  return true;
+}
+
 const char *check(const smc_problem *pr, const smc_params *pa) {
   if (!pr || !pa) return "null problem or params";
   if (pr->num_posteriors < 1) return "num_posteriors must be >= 1";
@@ -157,7 +193,16 @@ const char *check(const smc_problem *pr, const smc_params *pa) {
   if (pa->num_particles < 1 || pa->num_particles > 65536) return "num_particles in [1, 65536]";
   if (pa->max_leapfrog < 1 || pa->max_leapfrog > MAX_NMAX) return "max_leapfrog in [1, 4096]";
   if (pa->num_warmup < 1) return "num_warmup must be >= 1";
-  if (pa->jitter < SMC_JITTER_HALTON1D || pa->jitter > SMC_JITTER_EQUIDISTANT_OFFSET) return "jitter";
+  if (pa->jitter < SMC_JITTER_HALTON1D || pa->jitter > SMC_JITTER_SOBOLND_INV) return "jitter";
+  if (pa->jitter == SMC_JITTER_SOBOLND || pa->jitter == SMC_JITTER_SOBOLND_INV) {
+    if (!pa->sobol_table || pa->sobol_dims < 1 || pa->sobol_dims > SOBOL_MAXDIM)
+      return "the N-d Sobol schemes need sobol_table with sobol_dims in [1, 21201]";
+    if (!sobol_directions(pa->sobol_table, pa->sobol_dims, nullptr))
+      return "sobol_table: a row with a bad polynomial or direction integers";
+    if (pa->jitter == SMC_JITTER_SOBOLND_INV &&
+        (pa->num_iterations < 1 || pa->num_iterations > pa->sobol_dims))
+      return "the inverse Sobol scheme needs num_iterations in [1, sobol_dims]";
+  }
   if ((pa->jitter == SMC_JITTER_HALTONND_INV || pa->jitter == SMC_JITTER_PRIMES_INV) &&
       (pa->num_iterations < 1 || pa->num_iterations > NPRIMES))
     return "the inverse jitter schemes need num_iterations in [1, 1024]";
@@ -324,6 +369,8 @@ void plan(const smc_problem *pr, const smc_params *pa, Layout &L) {
   L.o_tprec = take(c, pr->target == SMC_TARGET_GAUSSIAN ? (size_t)L.DS * L.DS * 4 : 4);
   L.o_primes = take(c, NPRIMES * 4);
   L.o_sqrtp = take(c, NPRIMES * 8);
+  const bool sobol = pa->jitter == SMC_JITTER_SOBOLND || pa->jitter == SMC_JITTER_SOBOLND_INV;
+  L.o_sobol = take(c, sobol ? (size_t)pa->sobol_dims * 32 * 4 : 4);
   if (pa->precond == SMC_PRECOND_FLOW) {
     flow_net(pr->dims[0], pa->flow_layers, pa->flow_width, L.F);
     L.F.ntrain = L.F.L > 0 ? pa->flow_train_steps : 0;  // nothing to fit without couplings
@@ -516,6 +563,10 @@ smc_status smc_init(const smc_problem *prob, const smc_params *par, void *worksp
   D.tconst = prob->log_const;
   D.primes = (int *)(w + L.o_primes);
   D.sqrtp = (double *)(w + L.o_sqrtp);
+  D.sobol = (uint32_t *)(w + L.o_sobol);
+  D.sobol_dims =
+      (par->jitter == SMC_JITTER_SOBOLND || par->jitter == SMC_JITTER_SOBOLND_INV) ? par->sobol_dims
+                                                                                    : 0;
   D.lf_target = L.lf_target;
   D.lf_grid = L.lf_grid;
   D.flow = par->precond == SMC_PRECOND_FLOW ? 1 : 0;
@@ -587,6 +638,12 @@ smc_status smc_init(const smc_problem *prob, const smc_params *par, void *worksp
                      ctx->st));
   CKI(hipMemcpyAsync(D.sqrtp, ctx->sqrtp.data(), NPRIMES * sizeof(double), hipMemcpyHostToDevice,
                      ctx->st));
+  if (D.sobol_dims > 0) {
+    ctx->sobol.resize((size_t)D.sobol_dims * 32);
+    sobol_directions(par->sobol_table, D.sobol_dims, ctx->sobol.data());
+    CKI(hipMemcpyAsync(D.sobol, ctx->sobol.data(), ctx->sobol.size() * sizeof(uint32_t),
+                       hipMemcpyHostToDevice, ctx->st));
+  }
   CKI(hipMemcpyAsync(D.minv, ctx->minv.data(), ctx->minv.size() * sizeof(float),
                      hipMemcpyHostToDevice, ctx->st));
   CKI(hipMemcpyAsync(D.ll_items, ctx->ll_items.data(), ctx->ll_items.size() * sizeof(int4),

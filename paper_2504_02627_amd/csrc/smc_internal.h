@@ -18,6 +18,8 @@ constexpr int MAX_C2 = 13;          // d <= 16 * 13 = 208
 constexpr int MAX_NMAX = 4096;      // cap on max_leapfrog
 constexpr int QUANT_BITS = 40;      // fixed-point resolution of resampling weights
 constexpr int NPRIMES = 1024;       // primes table for N-d Halton
+constexpr int SOBOL_MAXDIM = 21201; // rows of Joe and Kuo's table
+constexpr int SOBOL_MAXDEG = 18;    // its largest polynomial degree
 
 // Philox stream ids (counter word 3)
 constexpr uint32_t STREAM_INIT = 1, STREAM_MOMENTUM = 2, STREAM_MH = 3, STREAM_RESAMPLE = 4,
@@ -123,6 +125,8 @@ struct Dev {                    // pointers carved from the workspace
   double *sqrtp;                // NPRIMES: sqrt(P_k), correctly rounded (host)
   double golden;                // (sqrt 5 - 1) / 2 in binary64 (host)
   int jit_K;                    // K, columns of the jitter matrix
+  uint32_t *sobol;              // [sobol_dims][32] direction numbers nu_b 2^32 (host)
+  int sobol_dims;
   // synthetic targets (SMC_TARGET_GAUSSIAN / BANANA; 0 = logistic regression)
   int target;
   float *tmean, *tprec;         // Gaussian: mean [DS], precision [DS][DS] (zero padded)

@@ -1326,6 +1326,20 @@ __device__ double jitter_h(const Dev &D, int b, int j, int k) {
       if (D.jitter == 9) h += 0.1 * u01(philox_at(D.seed, 0, particle, (uint32_t)k, STREAM_JITTER).x);
       return h;
     }
+    case 10: {
+      // first Sobol dimension, nu_b = 2^-b: the bit reversal of the Gray code
+      const unsigned long long i = (unsigned long long)(k - 1) * D.J + jj;
+      return (double)__builtin_bitreverse64(i ^ (i >> 1)) * 0x1p-64;
+    }
+    case 11:
+    case 12: {
+      const int dim = D.jitter == 11 ? min(k, D.sobol_dims) : krev;
+      const uint32_t *V = D.sobol + (size_t)(dim - 1) * 32;
+      uint32_t g = (uint32_t)(jj ^ (jj >> 1)), x = 0;
+      for (int b = 0; g; ++b, g >>= 1)
+        if (g & 1u) x ^= V[b];
+      return (double)x * 0x1p-32;
+    }
     default: return radical_inverse2((unsigned long long)(k - 1) * D.J + jj);
   }
 }

@@ -29,7 +29,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(HERE))
 
 SCHEMES = ["none", "uniform", "haltonNd", "haltonNd_inv", "halton1d", "primes", "primes_inv",
-           "golden", "equidistant", "equidistant_offset"]
+           "golden", "equidistant", "equidistant_offset", "sobol1d", "sobolNd", "sobolNd_inv"]
 TARGETS = ["gaussian", "illcond", "banana"]
 STEP = {"gaussian": 0.1, "illcond": 0.001, "banana": 0.01}
 

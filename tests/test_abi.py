@@ -41,7 +41,9 @@ def test_library_exports_every_declared_symbol():
 def test_struct_sizes_match_c_layout():
     from paper_2504_02627_amd import chees
     # natural alignment: these sizes follow from the field lists of the header
-    assert ctypes.sizeof(chees.Params) == 4 * 8 + 8 * 8 + 4 + 4 + 8 + 8 + 3 * 4 + 4 + 8 + 4 + 4
+    # ... flow_lr, num_iterations (+pad), sobol_table, sobol_dims (+pad)
+    assert ctypes.sizeof(chees.Params) == (4 * 8 + 8 * 8 + 4 + 4 + 8 + 8 + 3 * 4 + 4 + 8 + 4 + 4
+                                           + 8 + 4 + 4)
     assert ctypes.sizeof(chees.Stats) == 8 * 8 + 4 + 4 + 8
     assert ctypes.sizeof(chees.Inject) == 3 * 8
     # num_posteriors (+pad), n_rows, dims, X, y, x_dtype (+pad), prior_var,
@@ -84,3 +86,33 @@ def test_flow_parameter_count_matches_the_oracle_layout():
     assert lib.smc_flow_param_count(1, 4, 128) == 0
     assert lib.smc_flow_param_count(100, 9, 128) == 0
     assert lib.smc_flow_param_count(100, 4, 64) == 0
+
+
+def test_sobol_table_is_validated_without_gpu():
+    from paper_2504_02627_amd import chees
+    lib = _lib()
+    n = (ctypes.c_int32 * 1)(200)
+    d = (ctypes.c_int32 * 1)(5)
+    X = (ctypes.c_void_p * 1)(0x1000)
+    y = (ctypes.c_void_p * 1)(0x2000)
+    prob = chees.Problem(1, n, d, X, y, chees.SMC_F32, 1.0)
+    par = chees.make_params(256, jitter="sobolNd", num_iterations=50)
+    assert par.sobol_dims == 1024 and lib.smc_workspace_bytes(ctypes.byref(prob), ctypes.byref(par)) > 0
+    tab = par._sobol
+    assert tab[1, 0] == 3 and tab[2, 0] == 7 and list(tab[2, 1:3]) == [1, 3]
+    tab[2, 2] = 2                                      # m_2 even: not a direction integer
+    assert lib.smc_workspace_bytes(ctypes.byref(prob), ctypes.byref(par)) == 0
+    tab[2, 2] = 5                                      # m_2 >= 2^2
+    assert lib.smc_workspace_bytes(ctypes.byref(prob), ctypes.byref(par)) == 0
+    tab[2, 2] = 3
+    tab[4, 0] = 6                                      # polynomial without constant term
+    assert lib.smc_workspace_bytes(ctypes.byref(prob), ctypes.byref(par)) == 0
+    inv = chees.make_params(256, jitter="sobolNd_inv", num_iterations=50)
+    assert lib.smc_workspace_bytes(ctypes.byref(prob), ctypes.byref(inv)) > 0
+    inv.num_iterations = 2000                          # more columns than table rows
+    assert lib.smc_workspace_bytes(ctypes.byref(prob), ctypes.byref(inv)) == 0
+    inv.num_iterations = 50
+    inv.sobol_table = None
+    assert lib.smc_workspace_bytes(ctypes.byref(prob), ctypes.byref(inv)) == 0
+    assert lib.smc_workspace_bytes(ctypes.byref(prob), ctypes.byref(
+        chees.make_params(256, jitter="sobol1d"))) > 0

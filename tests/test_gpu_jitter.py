@@ -1,7 +1,9 @@
 """Jitter generators of Sec. III-B-1 on the device against the oracle's
 definitions: h_jk bit-exact for every scheme over several iterations
 (including iterations past K for the schemes that take K), the step counts
-n_j that follow from them, and per-posterior streams of a batched context.
+n_j that follow from them, per-posterior streams of a batched context, and
+the Sobol schemes at the largest particle count and past the table's
+dimensions.
 """
 
 import numpy as np
@@ -14,7 +16,7 @@ from tests._gpu_common import log, to_dev
 pytestmark = pytest.mark.gpu
 
 SCHEMES = ["halton1d", "none", "haltonNd", "uniform", "haltonNd_inv", "primes", "primes_inv",
-           "golden", "equidistant", "equidistant_offset"]
+           "golden", "equidistant", "equidistant_offset", "sobol1d", "sobolNd", "sobolNd_inv"]
 
 
 def _oracle_h(kind, seed, k, K, J, b=0):
@@ -36,6 +38,12 @@ def _oracle_h(kind, seed, k, K, J, b=0):
         return O.golden_1d(k, K, J)
     if kind == "equidistant":
         return O.equidistant(seed, k, J, b)
+    if kind == "sobol1d":
+        return O.sobol_1d(k, J)
+    if kind == "sobolNd":
+        return O.sobol_nd(k, J)
+    if kind == "sobolNd_inv":
+        return O.sobol_nd_inverse(k, K, J)
     return O.equidistant_offset(seed, k, J, b)
 
 
@@ -79,3 +87,20 @@ def test_jitter_streams_per_posterior(kind):
     h = tr["h"].cpu().numpy()
     for b in range(2):
         np.testing.assert_array_equal(h[b * jc:b * jc + J], _oracle_h(kind, seed, 1, 0, J, b))
+
+
+def test_sobol_at_full_particle_count_and_past_the_table():
+    # J = 65536 (every Gray-code bit up to 2^16), and a table of 3 dimensions
+    # for 5 iterations: iterations 4 and 5 reuse dimension 3
+    from paper_2504_02627_amd import chees
+    J = 65536
+    X, y, _ = synth.logistic_iid(64, 3, 4)
+    log(f"[jitter] sobolNd J={J} table of 3 dimensions")
+    s = chees.Sampler(to_dev(X), to_dev(y), J, step_size=0.05, traj_length=0.5,
+                      max_leapfrog=16, num_warmup=3, seed=2, jitter="sobolNd", sobol_dims=3)
+    rows = O.joe_kuo_rows(3)
+    for k in range(1, 6):
+        s.step()
+        s.adapt()
+        h = s.trace()["h"].cpu().numpy()[:J]
+        np.testing.assert_array_equal(h, O.sobol_nd(min(k, 3), J, rows))

@@ -194,7 +194,8 @@ def test_mh_mode(mh):
 
 
 @pytest.mark.parametrize("jitter", ["none", "haltonNd", "uniform", "haltonNd_inv", "primes",
-                                    "primes_inv", "golden", "equidistant", "equidistant_offset"])
+                                    "primes_inv", "golden", "equidistant", "equidistant_offset",
+                                    "sobol1d", "sobolNd", "sobolNd_inv"])
 def test_other_jitters(jitter):
     X, y, s, o, st, ost = _one_iteration(200, 5, 256, 31, jitter=jitter, num_iterations=7)
     _compare_iteration(s, o, st, ost, 256, 5)
