@@ -2,6 +2,7 @@
 // order of kernel launches for each ABI call (include/chees_smc.h).
 #include <math.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -55,6 +56,8 @@ struct Layout {
   int lf_target = 0, lf_grid = 0, ll_smax = 0, ll_nitems = 0, col_chunks = 0;
   int gpart_slots = 0, goff[MAX_C2] = {};
   int nosplit = 0;
+  int traj = 0;
+  size_t traj_lds = 0;
   std::vector<HostPost> hp;
   std::vector<Post> posts;
   std::vector<int4> items;
@@ -283,6 +286,18 @@ void plan(const smc_problem *pr, const smc_params *pa, Layout &L) {
   // reduction launch
   L.nosplit = 1;
   for (int b = 0; b < B; ++b) L.nosplit &= (bf16 ? L.hp[b].NT2 : L.hp[b].NT) <= 32;
+  // whole trajectories in one launch when one posterior's packed data tiles
+  // fit in a work group's LDS (unless CHEES_SMC_PER_STEP=1 asks for the
+  // per-step launches)
+  L.traj = 0;
+  if (B == 1 && pr->target == SMC_TARGET_LOGISTIC && pa->precond != SMC_PRECOND_FLOW &&
+      L.hp[0].C2 <= 2) {
+    const int c2 = L.hp[0].C2;
+    L.traj_lds = traj_lds_bytes(c2, L.hp[0].NT);
+    const size_t fixed = (size_t)TRAJ_WAVES * 16 * (16 * c2 + 1) * sizeof(float);
+    const char *env = getenv("CHEES_SMC_PER_STEP");
+    L.traj = L.traj_lds + fixed <= TRAJ_LDS_MAX && !(env && env[0] == '1');
+  }
   L.lf_grid = L.lf_target * lf_groups_per_cu(bf16, 1) + B * ntile;
   // log-likelihood pass: every tile, static splits, one launch per
   // feature-tile group of about lf_target items per resident work group slot
@@ -545,6 +560,8 @@ smc_status smc_init(const smc_problem *prob, const smc_params *par, void *worksp
   D.gpart = (float *)(w + L.o_gpart);
   D.gpart_slots = L.gpart_slots;
   D.lf_nosplit = L.nosplit;
+  D.traj = L.traj;
+  D.traj_lds = L.traj_lds;
   D.llpart = (float2 *)(w + L.o_llpart);
   D.ll_smax = L.ll_smax;
   D.ll_items = (int4 *)(w + L.o_items);
@@ -755,10 +772,14 @@ smc_status enqueue_step(smc_ctx *ctx, const smc_inject *inject) {
     CK(timed_begin(ctx, 1, ei));
     CK(launch_target_energy(D, ctx->st));
     CK(timed_end(ctx, ei));
+  } else if (D.traj) {
+    CK(timed_begin(ctx, 0, ei));
+    CK(launch_traj(D, ctx->c2s[0], ctx->st));
+    CK(timed_end(ctx, ei));
   } else {
     CK(launch_lf_plan(D, ctx->st));
   }
-  for (int s = 0; s < (D.target ? 0 : D.nmax); ++s) {
+  for (int s = 0; s < (D.target || D.traj ? 0 : D.nmax); ++s) {
     for (int c2 : ctx->c2s) {
       if (D.flow) {
         CK(timed_begin(ctx, 3, ei));

@@ -14,6 +14,9 @@ constexpr int WAVES = 8;
 constexpr int SUB = 1;
 constexpr int TJ = WAVES * SUB * 16;
 constexpr int WG = 64 * WAVES;
+// waves per work group of the whole-trajectory kernel (16 particles each)
+constexpr int TRAJ_WAVES = 4;
+constexpr size_t TRAJ_LDS_MAX = 65536;  // LDS of one work group
 constexpr int MAX_C2 = 13;          // d <= 16 * 13 = 208
 constexpr int MAX_NMAX = 4096;      // cap on max_leapfrog
 constexpr int QUANT_BITS = 40;      // fixed-point resolution of resampling weights
@@ -136,6 +139,8 @@ struct Dev {                    // pointers carved from the workspace
   int lf_target;                // work groups per leapfrog launch and resident group per compute unit
   int lf_grid;                  // grid of a leapfrog launch
   int lf_nosplit;               // one split per tile: the leapfrog launch finishes each step
+  int traj;                     // whole trajectories in one launch (k_traj), 0 = per step
+  size_t traj_lds;              // its dynamic LDS: every packed data tile
   // leapfrog work plan, written once per iteration from the active counts:
   int4 *lf_post;                // [nmax][B] (first item, splits per tile, tiles with one more, tiles)
   int4 *lf_items;               // [group][nmax][lf_grid] (posterior, tile, split | S << 16, first item of tile)
@@ -206,6 +211,8 @@ hipError_t launch_target_energy(const Dev &D, hipStream_t st);
 hipError_t launch_target_pack(const Dev &D, const float *mean, const float *prec, int d,
                               hipStream_t st);
 hipError_t launch_lf_partial(const Dev &D, int c2, int step, int zero_eps, hipStream_t st);
+size_t traj_lds_bytes(int c2, int nt);
+hipError_t launch_traj(const Dev &D, int c2, hipStream_t st);
 // mode 0: full step; 1: zero step size (gradient at theta, state rewritten);
 // 2: gradient only (theta given by the caller, p untouched)
 hipError_t launch_lf_reduce(const Dev &D, int step, int mode, hipStream_t st);

@@ -601,6 +601,166 @@ __global__ __launch_bounds__(WG, 2 * lf_groups_per_cu(false, C2)) void k_lf_part
 }
 
 // ---------------------------------------------------------------------------
+// Whole trajectories in one launch, for one posterior whose packed data tiles
+// fit in LDS (small N d).  Each wave owns 16 sorted particle slots and runs
+// their leapfrog steps s < n_j back to back with theta, p and the gradient in
+// registers, in the output layout of GEMM2 (particle 4 (lane / 16) + r,
+// feature 16 ct + lane % 16).  Per step: drift; theta' moved into the
+// B-operand layout of GEMM1 through a per-wave LDS tile; GEMM1 -> sigmoid ->
+// GEMM2 over every data tile; prior; second half kick; a particle past its
+// n_j keeps its state.  Arithmetic and summation order are those of the
+// one-split step kernel (k_lf_partial with FIN), so the trajectories agree
+// with it exactly; only the launches per step and the state round trips
+// through HBM are gone.
+// BF: the precision form's operands, theta', X and R rounded to bfloat16
+// (nearest even), on the FP32 MFMA: the products are exact and accumulate in
+// FP32, as on the BF16 MFMA.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float bf16_val(float x) { return (float)(__bf16)x; }
+
+template <int C2, bool BF>
+__global__ __launch_bounds__(64 * TRAJ_WAVES) void k_traj(Dev D) {
+  using TL = Tiles<C2>;
+  constexpr int K1 = 4 * C2, FS = 16 * C2 + 1;
+  extern __shared__ float4 xall[];                // every data tile of the posterior
+  __shared__ float tb[TRAJ_WAVES][16 * FS];        // per-wave theta' transpose
+  const Post P = D.posts[0];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, kq = lane >> 4, col = lane & 15;
+
+  const float4 *xab = reinterpret_cast<const float4 *>(D.xab + P.xab);
+  const int nx = P.NT * TL::TILE;
+  for (int e = tid; e < nx; e += 64 * TRAJ_WAVES) {
+    float4 v = xab[e];
+    if constexpr (BF) {
+      v.x = bf16_val(v.x);  // labels and the 1/2 padding are exact in bfloat16
+      v.y = bf16_val(v.y);
+      v.z = bf16_val(v.z);
+      v.w = bf16_val(v.w);
+    }
+    xall[e] = v;
+  }
+
+  const float eps = (float)D.ps[0].eps, he = 0.5f * eps;
+  const float inv_pv = (float)(1.0 / D.prior_var);
+  const int *perm = D.perm + P.row0;
+  const int base = blockIdx.x * (16 * TRAJ_WAVES) + wave * 16;
+  long long row[4];
+  int nn[4];
+  float th[C2][4], pp[C2][4], gg[C2][4], em[C2];
+#pragma unroll
+  for (int ct = 0; ct < C2; ++ct) em[ct] = eps * D.minv[16 * ct + col];
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr) {
+    row[rr] = P.row0 + perm[base + 4 * kq + rr];
+    nn[rr] = D.n[row[rr]];
+#pragma unroll
+    for (int ct = 0; ct < C2; ++ct) {
+      const long long e = row[rr] * D.DS + 16 * ct + col;
+      th[ct][rr] = D.theta_t[e];
+      pp[ct][rr] = D.p_t[e];
+      gg[ct][rr] = D.grad_t[e];
+    }
+  }
+  // steps of this wave: the largest n_j of its 16 particles
+  int nw = D.n[P.row0 + perm[base + col]];
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) nw = max(nw, __shfl_xor(nw, o));
+  nw = __builtin_amdgcn_readfirstlane(nw);
+  __syncthreads();
+
+  float *T = tb[wave];
+  for (int s = 0; s < nw; ++s) {
+    float ph[C2][4], t1[C2][4];
+#pragma unroll
+    for (int ct = 0; ct < C2; ++ct)
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        ph[ct][rr] = fmaf(he, gg[ct][rr], pp[ct][rr]);
+        t1[ct][rr] = fmaf(em[ct], ph[ct][rr], th[ct][rr]);
+        T[(4 * kq + rr) * FS + 16 * ct + col] = t1[ct][rr];
+      }
+    __builtin_amdgcn_wave_barrier();
+    float tB[K1];
+#pragma unroll
+    for (int c = 0; c < K1; ++c) {
+      tB[c] = T[col * FS + kq * K1 + c];
+      if constexpr (BF) tB[c] = bf16_val(tB[c]);
+    }
+    v4f gacc[C2];
+#pragma unroll
+    for (int ct = 0; ct < C2; ++ct) gacc[ct] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < P.NT; ++t) {
+      const float4 *xl = xall + t * TL::TILE + lane * TL::LSTR;
+      const float4 y4 = xl[2 * C2];
+      const float ya[4] = {y4.x, y4.y, y4.z, y4.w};
+      v4f z = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int q = 0; q < C2; ++q) {
+        const float4 a = xl[q];
+        z = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, tB[4 * q + 0], z, 0, 0, 0);
+        z = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, tB[4 * q + 1], z, 0, 0, 0);
+        z = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, tB[4 * q + 2], z, 0, 0, 0);
+        z = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, tB[4 * q + 3], z, 0, 0, 0);
+      }
+      float r[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        r[i] = ya[i] - sigmoidf_fast(z[i]);
+        if constexpr (BF) r[i] = bf16_val(r[i]);
+      }
+#pragma unroll
+      for (int ct = 0; ct < C2; ++ct) {
+        const float4 bb = xl[C2 + ct];
+        gacc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(r[0], bb.x, gacc[ct], 0, 0, 0);
+        gacc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(r[1], bb.y, gacc[ct], 0, 0, 0);
+        gacc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(r[2], bb.z, gacc[ct], 0, 0, 0);
+        gacc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(r[3], bb.w, gacc[ct], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int ct = 0; ct < C2; ++ct)
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const float gn = gacc[ct][rr] - t1[ct][rr] * inv_pv;
+        const bool on = s < nn[rr];
+        th[ct][rr] = on ? t1[ct][rr] : th[ct][rr];
+        pp[ct][rr] = on ? fmaf(he, gn, ph[ct][rr]) : pp[ct][rr];
+        gg[ct][rr] = on ? gn : gg[ct][rr];
+      }
+    __builtin_amdgcn_wave_barrier();
+  }
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr) {
+    if (nn[rr] <= 0) continue;
+#pragma unroll
+    for (int ct = 0; ct < C2; ++ct) {
+      const long long e = row[rr] * D.DS + 16 * ct + col;
+      D.theta_t[e] = th[ct][rr];
+      D.p_t[e] = pp[ct][rr];
+      D.grad_t[e] = gg[ct][rr];
+    }
+  }
+}
+
+size_t traj_lds_bytes(int c2, int nt) { return (size_t)nt * 64 * (2 * c2 + 1) * 16; }
+
+hipError_t launch_traj(const Dev &D, int c2, hipStream_t st) {
+  const dim3 grid(D.Jcap / (16 * TRAJ_WAVES)), block(64 * TRAJ_WAVES);
+  const size_t lds = D.traj_lds;
+  if (c2 == 1 && D.bf16)
+    hipLaunchKernelGGL((k_traj<1, true>), grid, block, lds, st, D);
+  else if (c2 == 1)
+    hipLaunchKernelGGL((k_traj<1, false>), grid, block, lds, st, D);
+  else if (c2 == 2 && D.bf16)
+    hipLaunchKernelGGL((k_traj<2, true>), grid, block, lds, st, D);
+  else if (c2 == 2)
+    hipLaunchKernelGGL((k_traj<2, false>), grid, block, lds, st, D);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Fused leapfrog step with BF16 trajectory gradients (precision form):
 // theta' and X in bfloat16 on v_mfma_f32_16x16x32_bf16 with FP32
 // accumulation; the residual R is rounded to bfloat16 as the A operand of the

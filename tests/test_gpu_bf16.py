@@ -80,8 +80,10 @@ def test_bf16_initial_gradient_interval(N, d, J):
     assert np.all(excess <= 0)
 
 
-def test_bf16_energies_exact_at_device_end_points():
-    N, d, J = 400, 12, 256
+@pytest.mark.parametrize("N,d,J", [(400, 12, 256), (200, 5, 256), (150, 24, 130)])
+def test_bf16_energies_exact_at_device_end_points(N, d, J):
+    # the two small cases run whole trajectories in one launch
+    log(f"[bf16 energies] N={N} d={d} J={J}")
     X, y, theta0, params, s, t, rng = _setup(N, d, J, 12)
     xi = rng.standard_normal((J, d)).astype(np.float32)
     u0 = rng.random(1)

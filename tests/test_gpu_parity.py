@@ -103,7 +103,8 @@ def _compare_iteration(s, o, st, ost, J, d):
     (17, 1, 1, 3),          # one particle, one feature
     (1, 3, 5, 4),           # one data row
     (500, 208, 130, 5),     # widest supported d
-    (333, 16, 129, 6),
+    (333, 16, 129, 6),      # per-step launches (data tiles beyond one work group's LDS)
+    (150, 24, 200, 7),      # two feature tiles, whole trajectories in one launch
 ])
 def test_one_iteration(N, d, J, seed):
     X, y, s, o, st, ost = _one_iteration(N, d, J, seed)
