@@ -241,6 +241,11 @@ typedef struct {
   const float *latent0, *latent, *latent_grad, *logdet0, *logdet;
   int32_t dpad;         /* row stride (floats) of p_final and theta_prop       */
   int32_t jcap;         /* particle rows per posterior (J padded)              */
+  const int32_t *order; /* per posterior, the jcap rows (index within the
+                           posterior) sorted by n_j, longest first, index
+                           order within equal n_j: the order in which the
+                           trajectory kernels group particles               */
+  const int32_t *active; /* per posterior, n_max + 1 counts: #{j: n_j > s}  */
 } smc_trace;
 
 /* Workspace size for a problem and parameters; 0 if they are invalid. */

@@ -104,7 +104,8 @@ class Trace(ctypes.Structure):
                 ("minv", ctypes.c_void_p), ("latent0", ctypes.c_void_p),
                 ("latent", ctypes.c_void_p), ("latent_grad", ctypes.c_void_p),
                 ("logdet0", ctypes.c_void_p), ("logdet", ctypes.c_void_p),
-                ("dpad", ctypes.c_int32), ("jcap", ctypes.c_int32)]
+                ("dpad", ctypes.c_int32), ("jcap", ctypes.c_int32),
+                ("order", ctypes.c_void_p), ("active", ctypes.c_void_p)]
 
 
 _LIB = None
@@ -395,6 +396,8 @@ class Sampler:
             theta_prop=view(t.theta_prop, rows * t.dpad, torch.float32, 4).view(rows, t.dpad),
             grad=view(t.grad, rows * t.dpad, torch.float32, 4).view(rows, t.dpad),
             minv=view(t.minv, self.B * t.dpad, torch.float32, 4).view(self.B, t.dpad),
+            order=view(t.order, rows, torch.int32, 4),
+            active=view(t.active, self.B * (self.params.max_leapfrog + 1), torch.int32, 4),
             jcap=t.jcap, dpad=t.dpad)
         if t.latent:
             res.update(

@@ -961,6 +961,8 @@ smc_status smc_get_trace(smc_ctx *ctx, smc_trace *t) {
   t->logdet = ctx->D.flow ? ctx->D.fld1 : nullptr;
   t->dpad = ctx->D.DS;
   t->jcap = ctx->D.Jcap;
+  t->order = ctx->D.perm;
+  t->active = ctx->D.active;
   return SMC_OK;
 }
 

@@ -1647,8 +1647,83 @@ __global__ __launch_bounds__(1024) void k_sort(Dev D) {
   }
 }
 
+// The same stable counting sort without barriers between the waves while
+// placing, for n_max < SORT_FAST_BINS: wave w owns the particle segment
+// [w seg, (w + 1) seg) (seg a multiple of 64); per-wave bin counts give each
+// wave its own cursor per bin (bin start + the counts of the waves before
+// it), and each wave then places its segment chunk by chunk in index order.
+// The placement equals that of k_sort.
+constexpr int SORT_FAST_BINS = 257;
+constexpr int SORT_WAVES = 16;
+
+__global__ __launch_bounds__(64 * SORT_WAVES) void k_sort_seg(Dev D) {
+  __shared__ int hw[SORT_WAVES][SORT_FAST_BINS];  // counts, then cursors
+  const int b = blockIdx.x, row0 = b * D.Jcap, nb = D.nmax + 1;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int seg = ((D.Jcap + 64 * SORT_WAVES - 1) / (64 * SORT_WAVES)) * 64;
+  const int j0 = wave * seg, j1 = min(D.Jcap, j0 + seg);
+  for (int i = threadIdx.x; i < SORT_WAVES * SORT_FAST_BINS; i += blockDim.x) (&hw[0][0])[i] = 0;
+  __syncthreads();
+  for (int j = j0 + lane; j < j1; j += 64) atomicAdd(&hw[wave][D.n[row0 + j]], 1);
+  __syncthreads();
+  // bins longest first (index t holds n = n_max - t): inclusive scan of the
+  // bin totals, then the cursor of wave w in bin n is
+  // start(n) + sum_{w' < w} count(w', n)
+  __shared__ int ts[SORT_FAST_BINS];
+  __shared__ double shr[SORT_WAVES];
+  const int t = threadIdx.x;
+  int tot = 0;
+  if (t < nb) {
+    for (int w = 0; w < SORT_WAVES; ++w) tot += hw[w][D.nmax - t];
+    ts[t] = tot;
+  }
+  __syncthreads();
+  for (int off = 1; off < nb; off <<= 1) {
+    const int v = (t < nb && t >= off) ? ts[t - off] : 0;
+    __syncthreads();
+    if (t < nb) ts[t] += v;
+    __syncthreads();
+  }
+  int *act = D.active + b * nb;
+  if (t < nb) {
+    const int n = D.nmax - t;
+    int pos = ts[t] - tot;  // particles with n_j > n
+    if (n < D.nmax) act[n] = pos;
+    for (int w = 0; w < SORT_WAVES; ++w) {
+      const int c = hw[w][n];
+      hw[w][n] = pos;
+      pos += c;
+    }
+  }
+  if (t == 0) act[D.nmax] = 0;
+  const double ev = block_reduce(t < nb ? (double)(D.nmax - t) * tot : 0.0, shr, OpAdd());
+  if (t == 0) D.ps[b].grad_evals_step = (long long)ev;  // exact: below 2^53
+  __syncthreads();
+  const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  for (int c0 = j0; c0 < j1; c0 += 64) {
+    const int j = c0 + lane;
+    const int n = j < j1 ? D.n[row0 + j] : -1;
+    unsigned long long left = __ballot(1), peers = 0;
+    while (left) {
+      const int v = __shfl(n, __ffsll((long long)left) - 1);
+      const unsigned long long m = __ballot(n == v);
+      if (n == v) peers = m;
+      left &= ~m;
+    }
+    const int rank = __popcll(peers & below);
+    const int base = n >= 0 ? hw[wave][n] : 0;
+    __builtin_amdgcn_wave_barrier();
+    if (n >= 0 && rank == 0) hw[wave][n] = base + __popcll(peers);
+    __builtin_amdgcn_wave_barrier();
+    if (n >= 0) D.perm[row0 + base + rank] = j;
+  }
+}
+
 hipError_t launch_sort(const Dev &D, hipStream_t st) {
-  hipLaunchKernelGGL(k_sort, dim3(D.B), dim3(1024), 2 * (D.nmax + 1) * sizeof(int), st, D);
+  if (D.nmax < SORT_FAST_BINS)
+    hipLaunchKernelGGL(k_sort_seg, dim3(D.B), dim3(64 * SORT_WAVES), 0, st, D);
+  else
+    hipLaunchKernelGGL(k_sort, dim3(D.B), dim3(1024), 2 * (D.nmax + 1) * sizeof(int), st, D);
   return hipGetLastError();
 }
 
@@ -1784,10 +1859,8 @@ __global__ __launch_bounds__(1024) void k_chees_reduce(Dev D) {
   __shared__ double sh[16];
   const int b = blockIdx.x;
   const long long r0 = (long long)b * D.Jcap;
-  const int chunk = (D.J + blockDim.x - 1) / blockDim.x;
-  const int j0 = min(D.J, (int)threadIdx.x * chunk), j1 = min(D.J, j0 + chunk);
   double sag = 0, sa = 0, sa2 = 0, sinv = 0;
-  for (int j = j0; j < j1; ++j) {
+  for (int j = threadIdx.x; j < D.J; j += blockDim.x) {  // coalesced, fixed order
     const double al = D.alpha[r0 + j], a = D.ca[r0 + j];
     sag += al * D.cg[r0 + j];
     sa += al;
@@ -1910,17 +1983,17 @@ __global__ __launch_bounds__(1024) void k_ess(Dev D, int count) {
   __shared__ double sh[16];
   const int b = blockIdx.x;
   const double *lw = D.logw + (long long)b * D.Jcap;
-  const int chunk = (D.J + blockDim.x - 1) / blockDim.x;
-  const int j0 = min(D.J, (int)threadIdx.x * chunk), j1 = min(D.J, j0 + chunk);
+  // strided over the threads (coalesced); a fixed order, so the sums are the
+  // same on every run
   double m = -INFINITY;
-  for (int j = j0; j < j1; ++j) {
+  for (int j = threadIdx.x; j < D.J; j += blockDim.x) {
     const double v = lw[j];
     if (v == v && v > m) m = v;
   }
   m = block_reduce(m, sh, OpMax());
   double s = 0.0, s2 = 0.0;
   if (m > -INFINITY)
-    for (int j = j0; j < j1; ++j) {
+    for (int j = threadIdx.x; j < D.J; j += blockDim.x) {
       const double v = lw[j];
       if (v == v && v > -INFINITY) {
         const double e = exp(v - m);

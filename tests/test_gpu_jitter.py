@@ -104,3 +104,33 @@ def test_sobol_at_full_particle_count_and_past_the_table():
         s.adapt()
         h = s.trace()["h"].cpu().numpy()[:J]
         np.testing.assert_array_equal(h, O.sobol_nd(min(k, 3), J, rows))
+
+
+@pytest.mark.parametrize("J,nmax,B", [(300, 64, 1), (16384, 64, 1), (1000, 300, 1), (130, 32, 2)])
+def test_particle_order_is_a_stable_sort_by_steps(J, nmax, B):
+    # the order in which the trajectory kernels take the particles: every row
+    # once, n_j non-increasing, index order within equal n_j; active counts
+    # #{j: n_j > s}.  n_max = 300 takes the single-group sort, the others the
+    # segmented one.
+    from paper_2504_02627_amd import chees
+    log(f"[order] J={J} nmax={nmax} B={B}")
+    data = [synth.logistic_iid(120, 4, 1 + b) for b in range(B)]
+    Xs = [to_dev(X) for X, _, _ in data]
+    ys = [to_dev(y) for _, y, _ in data]
+    s = chees.Sampler(Xs, ys, J, step_size=0.05, traj_length=0.05 * nmax / 2, max_leapfrog=nmax,
+                      num_warmup=5, seed=9, jitter="uniform")
+    for _ in range(2):
+        st = s.step()
+        s.adapt()
+        tr = s.trace()
+        jc = tr["jcap"]
+        n_all = tr["n"].cpu().numpy()
+        order = tr["order"].cpu().numpy()
+        act = tr["active"].cpu().numpy().reshape(B, nmax + 1)
+        for b in range(B):
+            n = n_all[b * jc:(b + 1) * jc]
+            o = order[b * jc:(b + 1) * jc]
+            ref = np.array(sorted(range(jc), key=lambda j: (-n[j], j)))
+            np.testing.assert_array_equal(o, ref)
+            np.testing.assert_array_equal(act[b], [(n > k).sum() for k in range(nmax)] + [0])
+        assert st["grad_evals"] == int(n_all[:jc].sum())
