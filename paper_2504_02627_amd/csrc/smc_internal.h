@@ -16,6 +16,8 @@ constexpr int TJ = WAVES * SUB * 16;
 constexpr int WG = 64 * WAVES;
 // waves per work group of the whole-trajectory kernel (16 particles each)
 constexpr int TRAJ_WAVES = 4;
+// blocks per posterior of the FP64 population reductions (ESS, ChEES sums)
+constexpr int RED_G = 32;
 constexpr size_t TRAJ_LDS_MAX = 65536;  // LDS of one work group
 constexpr int MAX_C2 = 13;          // d <= 16 * 13 = 208
 constexpr int MAX_NMAX = 4096;      // cap on max_leapfrog
@@ -114,6 +116,8 @@ struct Dev {                    // pointers carved from the workspace
   double *h, *l, *H0, *dH, *alpha, *ca, *cg;
   int *n, *perm, *active, *anc, *accepted;
   unsigned long long *cdf;
+  double *red_part;             // [B][RED_G][4] per-block partial sums of the reductions
+  int *red_cnt;                 // [B][2] blocks done (ESS, ChEES); zero between launches
   float *gpart;                 // split partial gradients, [wg][TJ][DS]
   int gpart_slots;              // number of [TJ][DS] slots
   float2 *llpart;               // log-likelihood partials [split][row]

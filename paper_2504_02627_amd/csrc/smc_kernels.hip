@@ -31,6 +31,34 @@ __device__ T block_reduce(T v, T *sh, Op op) {
   return r;
 }
 
+// Blocks of the reductions over a population: g of G blocks takes rows
+// g T + i, g T + i + G T, ...  (T threads); the block that finishes last
+// (a device-scope counter, reset by that block) combines the G partials in
+// block order, so the result is the same on every run.
+constexpr int RED_T = 256;
+
+inline int red_grid(int J) {
+  const int g = (J + 2 * RED_T - 1) / (2 * RED_T);
+  return g < 1 ? 1 : (g > RED_G ? RED_G : g);
+}
+
+// Called by every thread of the block; true in the block that counted last,
+// whose threads then see the partials every block wrote before counting.
+__device__ __forceinline__ bool red_last(int *cnt, int G) {
+  __shared__ int last;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    last = atomicAdd(cnt, 1) == G - 1;
+    if (last) {
+      *cnt = 0;  // every block has counted: ready for the next launch
+      __threadfence();
+    }
+  }
+  __syncthreads();
+  return last;
+}
+
 struct OpAdd {
   template <typename T>
   __device__ T operator()(T a, T b) const { return a + b; }
@@ -1193,8 +1221,47 @@ hipError_t launch_loglik(const Dev &D, int c2, int first, int count, hipStream_t
 }
 
 // ---------------------------------------------------------------------------
-// Per-row helpers: one wave per particle row.
+// Per-row helpers: LPR lanes of a wave per particle row (a power of two up
+// to 64; sums over a row's lanes by a butterfly inside its lane group).
 // ---------------------------------------------------------------------------
+template <int LPR>
+__device__ __forceinline__ double seg_sum(double v) {
+#pragma unroll
+  for (int o = LPR / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Lanes per row for a row stride of DS floats: about four columns a lane.
+__host__ __device__ constexpr int row_lanes(int DS) {
+  return DS <= 16 ? 4 : DS <= 32 ? 8 : DS <= 64 ? 16 : DS <= 128 ? 32 : 64;
+}
+
+// Launch of a row kernel templated on LPR: 256 threads, 256 / LPR rows each.
+#define LAUNCH_ROWS(KERNEL, DS, ROWS, STREAM, ...)                                          \
+  do {                                                                                      \
+    const long long rows_ = (ROWS);                                                         \
+    switch (row_lanes(DS)) {                                                                \
+      case 4:                                                                               \
+        hipLaunchKernelGGL(KERNEL<4>, dim3((unsigned)((rows_ + 63) / 64)), dim3(256), 0,     \
+                           STREAM, __VA_ARGS__);                                            \
+        break;                                                                              \
+      case 8:                                                                               \
+        hipLaunchKernelGGL(KERNEL<8>, dim3((unsigned)((rows_ + 31) / 32)), dim3(256), 0,     \
+                           STREAM, __VA_ARGS__);                                            \
+        break;                                                                              \
+      case 16:                                                                              \
+        hipLaunchKernelGGL(KERNEL<16>, dim3((unsigned)((rows_ + 15) / 16)), dim3(256), 0,    \
+                           STREAM, __VA_ARGS__);                                            \
+        break;                                                                              \
+      case 32:                                                                              \
+        hipLaunchKernelGGL(KERNEL<32>, dim3((unsigned)((rows_ + 7) / 8)), dim3(256), 0,      \
+                           STREAM, __VA_ARGS__);                                            \
+        break;                                                                              \
+      default:                                                                              \
+        hipLaunchKernelGGL(KERNEL<64>, dim3((unsigned)((rows_ + 3) / 4)), dim3(256), 0,      \
+                           STREAM, __VA_ARGS__);                                            \
+    }                                                                                       \
+  } while (0)
 __device__ __forceinline__ double row_loglik(const Dev &D, const Post &P, long long row) {
   double ll = 0.0;
   for (int sp = 0; sp < P.ll_splits; ++sp) {
@@ -1205,20 +1272,22 @@ __device__ __forceinline__ double row_loglik(const Dev &D, const Post &P, long l
 }
 
 // log q0(theta) = -|theta|^2 / (2 prior_var) - d/2 log(2 pi prior_var), FP64.
+template <int LPR>
 __device__ __forceinline__ double row_log_prior(const Dev &D, const Post &P, const float *th,
                                                 int lane) {
   double sq = 0.0;
-  for (int c = lane; c < P.d; c += 64) sq += (double)th[c] * (double)th[c];
-  sq = wave_sum(sq);
+  for (int c = lane; c < P.d; c += LPR) sq += (double)th[c] * (double)th[c];
+  sq = seg_sum<LPR>(sq);
   return -0.5 * sq / D.prior_var - 0.5 * P.d * log(2.0 * 3.141592653589793 * D.prior_var);
 }
 
 // 1/2 p^T M^{-1} p, FP64 (kinetic energy, Sec. II-A).
+template <int LPR>
 __device__ __forceinline__ double row_kinetic(const Dev &D, const Post &P, const float *p,
                                               const float *mv, int lane) {
   double k = 0.0;
-  for (int c = lane; c < P.d; c += 64) k += (double)mv[c] * (double)p[c] * (double)p[c];
-  return 0.5 * wave_sum(k);
+  for (int c = lane; c < P.d; c += LPR) k += (double)mv[c] * (double)p[c] * (double)p[c];
+  return 0.5 * seg_sum<LPR>(k);
 }
 
 // ---------------------------------------------------------------------------
@@ -1245,7 +1314,7 @@ __global__ __launch_bounds__(256) void k_init_weights(Dev D) {
   }
   if (D.target) {
     // log w = log pi - log q0 - log J, q0 = N(0, prior_var I) the initial draw
-    const double logq0 = row_log_prior(D, P, th, lane);
+    const double logq0 = row_log_prior<64>(D, P, th, lane);
     if (lane == 0) {
       const double lp = D.logpi_t[row];
       D.logpi[row] = lp;
@@ -1254,7 +1323,7 @@ __global__ __launch_bounds__(256) void k_init_weights(Dev D) {
     return;
   }
   const double ll = row_loglik(D, P, row);
-  const double lp = row_log_prior(D, P, th, lane);
+  const double lp = row_log_prior<64>(D, P, th, lane);
   if (lane == 0) {
     D.logpi[row] = ll + lp;
     D.logw[row] = ll - log((double)D.J);
@@ -1504,10 +1573,11 @@ __device__ double jitter_h(const Dev &D, int b, int j, int k) {
   }
 }
 
+template <int LPR>
 __global__ __launch_bounds__(256) void k_setup(Dev D, const float *__restrict__ momenta,
                                                int init_mode) {
-  const int lane = threadIdx.x & 63;
-  const long long row = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x % LPR;  // lane within the row's group
+  const long long row = (long long)blockIdx.x * (256 / LPR) + threadIdx.x / LPR;
   if (row >= (long long)D.B * D.Jcap) return;
   const int b = (int)(row / D.Jcap), j = (int)(row % D.Jcap);
   PState &S = D.ps[b];
@@ -1523,13 +1593,13 @@ __global__ __launch_bounds__(256) void k_setup(Dev D, const float *__restrict__ 
   }
   const int resampled = S.resampled;
   if (resampled) {
-    for (int c = lane; c < D.DS; c += 64) {
+    for (int c = lane; c < D.DS; c += LPR) {
       D.theta[o + c] = D.theta_t[o + c];
       D.grad[o + c] = D.grad_t[o + c];
     }
     if (lane == 0) D.logpi[row] = D.logpi_t[row];
   } else if (init_mode != 2) {
-    for (int c = lane; c < D.DS; c += 64) {
+    for (int c = lane; c < D.DS; c += LPR) {
       D.theta_t[o + c] = D.theta[o + c];
       D.grad_t[o + c] = D.grad[o + c];
     }
@@ -1540,7 +1610,7 @@ __global__ __launch_bounds__(256) void k_setup(Dev D, const float *__restrict__ 
   // momenta: lane q covers columns 4q .. 4q+3 (one Philox block); the kinetic
   // energy is accumulated from the values written
   double kin = 0.0;
-  for (int q = lane; q * 4 < D.DS; q += 64) {
+  for (int q = lane; q * 4 < D.DS; q += LPR) {
     double xi[4] = {0, 0, 0, 0};
     if (4 * q < P.d) {
       if (momenta) {
@@ -1561,7 +1631,7 @@ __global__ __launch_bounds__(256) void k_setup(Dev D, const float *__restrict__ 
       D.p_t[o + c] = pv;
     }
   }
-  const double K0 = 0.5 * wave_sum(kin);
+  const double K0 = 0.5 * seg_sum<LPR>(kin);
   if (lane == 0) {
     const double h = jitter_h(D, b, j, k);
     const double L = S.L, eps = S.eps;
@@ -1581,9 +1651,7 @@ __global__ __launch_bounds__(256) void k_setup(Dev D, const float *__restrict__ 
 }
 
 hipError_t launch_setup(const Dev &D, const float *momenta, int init_mode, hipStream_t st) {
-  const long long rows = (long long)D.B * D.Jcap;
-  hipLaunchKernelGGL(k_setup, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st, D, momenta,
-                     init_mode);
+  LAUNCH_ROWS(k_setup, D.DS, (long long)D.B * D.Jcap, st, D, momenta, init_mode);
   return hipGetLastError();
 }
 
@@ -1655,6 +1723,21 @@ __global__ __launch_bounds__(1024) void k_sort(Dev D) {
 // The placement equals that of k_sort.
 constexpr int SORT_FAST_BINS = 257;
 constexpr int SORT_WAVES = 16;
+constexpr int SORT_BATCH = 16;  // 64-particle chunks per batch of key loads
+
+// Lanes of the wave holding the same 9-bit key as this lane: the
+// intersection over the key's bits of the ballot of that bit (or of its
+// complement), nine ballots whatever the number of distinct keys.
+__device__ __forceinline__ unsigned long long peers9(int v) {
+  unsigned long long peers = ~0ull;
+#pragma unroll
+  for (int bit = 0; bit < 9; ++bit) {
+    const bool on = (v >> bit) & 1;
+    const unsigned long long m = __ballot(on);
+    peers &= on ? m : ~m;
+  }
+  return peers;
+}
 
 __global__ __launch_bounds__(64 * SORT_WAVES) void k_sort_seg(Dev D) {
   __shared__ int hw[SORT_WAVES][SORT_FAST_BINS];  // counts, then cursors
@@ -1662,9 +1745,28 @@ __global__ __launch_bounds__(64 * SORT_WAVES) void k_sort_seg(Dev D) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int seg = ((D.Jcap + 64 * SORT_WAVES - 1) / (64 * SORT_WAVES)) * 64;
   const int j0 = wave * seg, j1 = min(D.Jcap, j0 + seg);
+  const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
   for (int i = threadIdx.x; i < SORT_WAVES * SORT_FAST_BINS; i += blockDim.x) (&hw[0][0])[i] = 0;
   __syncthreads();
-  for (int j = j0 + lane; j < j1; j += 64) atomicAdd(&hw[wave][D.n[row0 + j]], 1);
+  // per-wave counts: the lowest lane of each key adds its peer count
+  // (the keys' leaders are distinct lanes, and hw[wave] is this wave's own)
+  // keys of SORT_BATCH chunks at a time, so that their loads are in flight
+  // together
+  for (int c0 = j0; c0 < j1; c0 += 64 * SORT_BATCH) {
+    int nv[SORT_BATCH];
+#pragma unroll
+    for (int u = 0; u < SORT_BATCH; ++u) {
+      const int j = c0 + 64 * u + lane;
+      nv[u] = j < j1 ? D.n[row0 + j] : 511;  // 511: no particle (n_max < 257)
+    }
+#pragma unroll
+    for (int u = 0; u < SORT_BATCH; ++u) {
+      const int n = nv[u];
+      const unsigned long long peers = peers9(n);
+      if (n != 511 && !(peers & below)) hw[wave][n] += __popcll(peers);
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
   __syncthreads();
   // bins longest first (index t holds n = n_max - t): inclusive scan of the
   // bin totals, then the cursor of wave w in bin n is
@@ -1699,23 +1801,24 @@ __global__ __launch_bounds__(64 * SORT_WAVES) void k_sort_seg(Dev D) {
   const double ev = block_reduce(t < nb ? (double)(D.nmax - t) * tot : 0.0, shr, OpAdd());
   if (t == 0) D.ps[b].grad_evals_step = (long long)ev;  // exact: below 2^53
   __syncthreads();
-  const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
-  for (int c0 = j0; c0 < j1; c0 += 64) {
-    const int j = c0 + lane;
-    const int n = j < j1 ? D.n[row0 + j] : -1;
-    unsigned long long left = __ballot(1), peers = 0;
-    while (left) {
-      const int v = __shfl(n, __ffsll((long long)left) - 1);
-      const unsigned long long m = __ballot(n == v);
-      if (n == v) peers = m;
-      left &= ~m;
+  for (int c0 = j0; c0 < j1; c0 += 64 * SORT_BATCH) {
+    int nv[SORT_BATCH];
+#pragma unroll
+    for (int u = 0; u < SORT_BATCH; ++u) {
+      const int j = c0 + 64 * u + lane;
+      nv[u] = j < j1 ? D.n[row0 + j] : 511;
     }
-    const int rank = __popcll(peers & below);
-    const int base = n >= 0 ? hw[wave][n] : 0;
-    __builtin_amdgcn_wave_barrier();
-    if (n >= 0 && rank == 0) hw[wave][n] = base + __popcll(peers);
-    __builtin_amdgcn_wave_barrier();
-    if (n >= 0) D.perm[row0 + base + rank] = j;
+#pragma unroll
+    for (int u = 0; u < SORT_BATCH; ++u) {
+      const int n = nv[u];
+      const unsigned long long peers = peers9(n);
+      const int rank = __popcll(peers & below);
+      const int base = n != 511 ? hw[wave][n] : 0;
+      __builtin_amdgcn_wave_barrier();
+      if (n != 511 && rank == 0) hw[wave][n] = base + __popcll(peers);
+      __builtin_amdgcn_wave_barrier();
+      if (n != 511) D.perm[row0 + base + rank] = c0 + 64 * u + lane;
+    }
   }
 }
 
@@ -1737,9 +1840,10 @@ hipError_t launch_sort(const Dev &D, hipStream_t st) {
 //   MH mode: accept iff u < alpha (eq. mh_ratio_rn), weight unchanged.
 // One wave per row.
 // ---------------------------------------------------------------------------
+template <int LPR>
 __global__ __launch_bounds__(256) void k_weights(Dev D, const double *__restrict__ mh_u) {
-  const int lane = threadIdx.x & 63;
-  const long long row = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x % LPR;  // lane within the row's group
+  const long long row = (long long)blockIdx.x * (256 / LPR) + threadIdx.x / LPR;
   if (row >= (long long)D.B * D.Jcap) return;
   const int b = (int)(row / D.Jcap), j = (int)(row % D.Jcap);
   if (j >= D.J) return;
@@ -1749,8 +1853,8 @@ __global__ __launch_bounds__(256) void k_weights(Dev D, const double *__restrict
   const float *mv = D.minv + (long long)b * D.DS;
   // synthetic targets: log pi(theta') was evaluated by the target's energy pass
   const double ll = D.target ? 0.0 : row_loglik(D, P, row);
-  const double lp = D.target ? D.logpi_t[row] : row_log_prior(D, P, th, lane);
-  const double K1 = row_kinetic(D, P, D.p_t + row * D.DS, mv, lane);
+  const double lp = D.target ? D.logpi_t[row] : row_log_prior<LPR>(D, P, th, lane);
+  const double K1 = row_kinetic<LPR>(D, P, D.p_t + row * D.DS, mv, lane);
   if (lane != 0) return;
   const double logpi1 = ll + lp;
   double dh = (-logpi1 + K1) - D.H0[row];
@@ -1773,8 +1877,7 @@ __global__ __launch_bounds__(256) void k_weights(Dev D, const double *__restrict
 
 hipError_t launch_weights(const Dev &D, const double *mh_u, int init_mode, hipStream_t st) {
   (void)init_mode;
-  const long long rows = (long long)D.B * D.Jcap;
-  hipLaunchKernelGGL(k_weights, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st, D, mh_u);
+  LAUNCH_ROWS(k_weights, D.DS, (long long)D.B * D.Jcap, st, D, mh_u);
   return hipGetLastError();
 }
 
@@ -1798,7 +1901,8 @@ __global__ __launch_bounds__(256) void k_colsum(Dev D) {
     const int c = cg * 64 + cl;
     double s0 = 0.0, s1 = 0.0;
     if (c < D.DS)
-      for (int r = r0 + rl; r < r1; r += 4) {
+#pragma unroll 8
+      for (int r = r0 + rl; r < r1; r += 4) {  // unrolled: the loads overlap, the sum order stays
         const long long o = ((long long)b * D.Jcap + r) * D.DS + c;
         s0 += (double)(D.flow ? D.fz0 : D.theta)[o];
         s1 += (double)(D.flow ? D.fz : D.theta_t)[o];
@@ -1820,15 +1924,17 @@ __global__ void k_colmean(Dev D) {
   for (int c = threadIdx.x; c < 2 * D.DS; c += blockDim.x) {
     const int which = c / D.DS, col = c % D.DS;
     double s = 0.0;
+#pragma unroll 8
     for (int ch = 0; ch < D.col_chunks; ++ch)
       s += D.colpart[(((long long)b * D.col_chunks + ch) * 2 + which) * D.DS + col];
     D.means[((long long)b * 2 + which) * D.DS + col] = s / D.J;
   }
 }
 
+template <int LPR>
 __global__ __launch_bounds__(256) void k_chees_row(Dev D) {
-  const int lane = threadIdx.x & 63;
-  const long long row = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x % LPR;  // lane within the row's group
+  const long long row = (long long)blockIdx.x * (256 / LPR) + threadIdx.x / LPR;
   if (row >= (long long)D.B * D.Jcap) return;
   const int b = (int)(row / D.Jcap), j = (int)(row % D.Jcap);
   if (j >= D.J) return;
@@ -1838,16 +1944,16 @@ __global__ __launch_bounds__(256) void k_chees_row(Dev D) {
   const float *mv = D.minv + (long long)b * D.DS;
   const long long o = row * D.DS;
   double an = 0.0, ao = 0.0, dt = 0.0;
-  for (int c = lane; c < P.d; c += 64) {
+  for (int c = lane; c < P.d; c += LPR) {
     const double cn = (double)(D.flow ? D.fz : D.theta_t)[o + c] - mn[c];
     const double co = (double)(D.flow ? D.fz0 : D.theta)[o + c] - mo[c];
     an += cn * cn;
     ao += co * co;
     dt += cn * (double)mv[c] * (double)D.p_t[o + c];
   }
-  an = wave_sum(an);
-  ao = wave_sum(ao);
-  dt = wave_sum(dt);
+  an = seg_sum<LPR>(an);
+  ao = seg_sum<LPR>(ao);
+  dt = seg_sum<LPR>(dt);
   if (lane == 0) {
     const double a = an - ao;
     D.ca[row] = a;
@@ -1855,12 +1961,13 @@ __global__ __launch_bounds__(256) void k_chees_row(Dev D) {
   }
 }
 
-__global__ __launch_bounds__(1024) void k_chees_reduce(Dev D) {
-  __shared__ double sh[16];
-  const int b = blockIdx.x;
+__global__ __launch_bounds__(RED_T) void k_chees_reduce(Dev D) {
+  __shared__ double sh[RED_T / 64];
+  const int b = blockIdx.y, g = blockIdx.x, G = gridDim.x;
   const long long r0 = (long long)b * D.Jcap;
   double sag = 0, sa = 0, sa2 = 0, sinv = 0;
-  for (int j = threadIdx.x; j < D.J; j += blockDim.x) {  // coalesced, fixed order
+#pragma unroll 4
+  for (int j = g * RED_T + threadIdx.x; j < D.J; j += G * RED_T) {
     const double al = D.alpha[r0 + j], a = D.ca[r0 + j];
     sag += al * D.cg[r0 + j];
     sa += al;
@@ -1871,22 +1978,34 @@ __global__ __launch_bounds__(1024) void k_chees_reduce(Dev D) {
   sa = block_reduce(sa, sh, OpAdd());
   sa2 = block_reduce(sa2, sh, OpAdd());
   sinv = block_reduce(sinv, sh, OpAdd());
+  double *part = D.red_part + (long long)b * RED_G * 4;
   if (threadIdx.x == 0) {
-    PState &S = D.ps[b];
-    S.sum_alpha = sa;
-    S.ghat = sa > 0.0 ? sag / sa : 0.0;
-    S.chees = 0.25 * sa2 / D.J;
-    S.sum_alpha_all = sa;
-    S.sum_inv_alpha = sinv;
+    part[4 * g] = sag;
+    part[4 * g + 1] = sa;
+    part[4 * g + 2] = sa2;
+    part[4 * g + 3] = sinv;
   }
+  if (!red_last(D.red_cnt + 2 * b + 1, G)) return;
+  const bool own = threadIdx.x < G;  // thread g takes partial g (fixed order)
+  sag = block_reduce(own ? part[4 * threadIdx.x] : 0.0, sh, OpAdd());
+  sa = block_reduce(own ? part[4 * threadIdx.x + 1] : 0.0, sh, OpAdd());
+  sa2 = block_reduce(own ? part[4 * threadIdx.x + 2] : 0.0, sh, OpAdd());
+  sinv = block_reduce(own ? part[4 * threadIdx.x + 3] : 0.0, sh, OpAdd());
+  if (threadIdx.x != 0) return;
+  PState &S = D.ps[b];
+  S.sum_alpha = sa;
+  S.ghat = sa > 0.0 ? sag / sa : 0.0;
+  S.chees = 0.25 * sa2 / D.J;
+  S.sum_alpha_all = sa;
+  S.sum_inv_alpha = sinv;
 }
 
 hipError_t launch_chees(const Dev &D, hipStream_t st) {
   const long long rows = (long long)D.B * D.Jcap;
   hipLaunchKernelGGL(k_colsum, dim3(D.col_chunks, D.B), dim3(256), 0, st, D);
   hipLaunchKernelGGL(k_colmean, dim3(D.B), dim3(256), 0, st, D);
-  hipLaunchKernelGGL(k_chees_row, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st, D);
-  hipLaunchKernelGGL(k_chees_reduce, dim3(D.B), dim3(1024), 0, st, D);
+  LAUNCH_ROWS(k_chees_row, D.DS, rows, st, D);
+  hipLaunchKernelGGL(k_chees_reduce, dim3(red_grid(D.J), D.B), dim3(RED_T), 0, st, D);
   return hipGetLastError();
 }
 
@@ -1979,21 +2098,22 @@ hipError_t launch_commit(const Dev &D, hipStream_t st) {
 //   m = max log w, S = sum e^{log w - m}, S2 = sum e^{2(log w - m)},
 //   J_eff = S^2 / S2; resample next iff J_eff < ess_frac J.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_ess(Dev D, int count) {
-  __shared__ double sh[16];
-  const int b = blockIdx.x;
+__global__ __launch_bounds__(RED_T) void k_ess(Dev D, int count) {
+  __shared__ double sh[RED_T / 64];
+  const int b = blockIdx.y, g = blockIdx.x, G = gridDim.x;
   const double *lw = D.logw + (long long)b * D.Jcap;
-  // strided over the threads (coalesced); a fixed order, so the sums are the
-  // same on every run
+  const int j0 = g * RED_T + threadIdx.x, js = G * RED_T;
   double m = -INFINITY;
-  for (int j = threadIdx.x; j < D.J; j += blockDim.x) {
+#pragma unroll 4
+  for (int j = j0; j < D.J; j += js) {
     const double v = lw[j];
     if (v == v && v > m) m = v;
   }
   m = block_reduce(m, sh, OpMax());
   double s = 0.0, s2 = 0.0;
   if (m > -INFINITY)
-    for (int j = threadIdx.x; j < D.J; j += blockDim.x) {
+#pragma unroll 4
+    for (int j = j0; j < D.J; j += js) {
       const double v = lw[j];
       if (v == v && v > -INFINITY) {
         const double e = exp(v - m);
@@ -2003,24 +2123,42 @@ __global__ __launch_bounds__(1024) void k_ess(Dev D, int count) {
     }
   s = block_reduce(s, sh, OpAdd());
   s2 = block_reduce(s2, sh, OpAdd());
+  double *part = D.red_part + (long long)b * RED_G * 4;
   if (threadIdx.x == 0) {
-    PState &S = D.ps[b];
-    S.m = m;
-    S.S = s;
-    S.S2 = s2;
-    S.ess = s > 0.0 ? s * s / s2 : 0.0;
-    S.degenerate = !(s > 0.0);
-    S.flag_resample = S.ess < D.ess_frac * D.J;
-    if (count) {
-      S.tot_iters += 1;
-      S.tot_ess += S.ess;
-      S.tot_grad_evals += S.grad_evals_step;
-    }
+    part[4 * g] = m;
+    part[4 * g + 1] = s;
+    part[4 * g + 2] = s2;
+  }
+  if (!red_last(D.red_cnt + 2 * b, G)) return;
+  // m = max m_g, S = sum S_g e^{m_g - m}, S2 = sum S2_g e^{2 (m_g - m)}:
+  // thread g takes partial g (fixed reduction order)
+  const double mg = threadIdx.x < G ? part[4 * threadIdx.x] : -INFINITY;
+  const double M = block_reduce(mg, sh, OpMax());
+  double sg = 0.0, s2g = 0.0;
+  if (M > -INFINITY && mg > -INFINITY) {
+    const double f = exp(mg - M);
+    sg = part[4 * threadIdx.x + 1] * f;
+    s2g = part[4 * threadIdx.x + 2] * f * f;
+  }
+  const double S = block_reduce(sg, sh, OpAdd());
+  const double S2 = block_reduce(s2g, sh, OpAdd());
+  if (threadIdx.x != 0) return;
+  PState &St = D.ps[b];
+  St.m = M;
+  St.S = S;
+  St.S2 = S2;
+  St.ess = S > 0.0 ? S * S / S2 : 0.0;
+  St.degenerate = !(S > 0.0);
+  St.flag_resample = St.ess < D.ess_frac * D.J;
+  if (count) {
+    St.tot_iters += 1;
+    St.tot_ess += St.ess;
+    St.tot_grad_evals += St.grad_evals_step;
   }
 }
 
 hipError_t launch_ess(const Dev &D, int count, hipStream_t st) {
-  hipLaunchKernelGGL(k_ess, dim3(D.B), dim3(1024), 0, st, D, count);
+  hipLaunchKernelGGL(k_ess, dim3(red_grid(D.J), D.B), dim3(RED_T), 0, st, D, count);
   return hipGetLastError();
 }
 
