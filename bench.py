@@ -277,8 +277,19 @@ def other_workloads(args):
         prec: run_workload(Xd if prec == "f32" else Xd.to(torch.bfloat16), yd, 16384,
                            dict(p, precision=prec), 20, 10)
         for prec in ("f32", "bf16")}
+    # the same with one leapfrog launch per step instead of whole trajectories
+    os.environ["CHEES_SMC_PER_STEP"] = "1"
+    try:
+        out["small_model_J16384"]["f32_per_step_launches"] = run_workload(
+            Xd, yd, 16384, dict(p, precision="f32"), 20, 10)
+    finally:
+        del os.environ["CHEES_SMC_PER_STEP"]
     out["small_model_J16384"]["workload"] = ("logistic N=200, d=5, J=16384, 20 iterations; bf16: "
-                                             "X stored in bfloat16")
+                                             "X stored in bfloat16; whole trajectories in one "
+                                             "launch unless named per-step")
+    # the small model at J = 256 (latency-bound: 16 waves)
+    out["small_model_J256"] = run_workload(Xd, yd, 256, dict(p, precision="f32"), 20, 10)
+    out["small_model_J256"]["workload"] = "logistic N=200, d=5, J=256, 20 iterations, FP32"
     print("[bench] small model done", file=sys.stderr, flush=True)
     # flow preconditioner on the Toeplitz model: N = 5000, d = 100, J = 4096
     X, y, _ = synth.toeplitz_logistic()
