@@ -15,6 +15,8 @@
 
 using namespace smc;
 
+constexpr int MAX_SIDE = 3;  // side streams: four lanes of group launches in all
+
 struct smc_ctx {
   Dev D;
   hipStream_t st = nullptr;
@@ -41,11 +43,20 @@ struct smc_ctx {
   hipStream_t cap_st = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
+  // side streams on which the launches of several feature-tile groups run
+  // side by side (created at smc_init when there is more than one group)
+  hipStream_t side[MAX_SIDE] = {};
+  hipEvent_t fork_ev = nullptr, join_ev[MAX_SIDE] = {};
   ~smc_ctx() {
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (graph) (void)hipGraphDestroy(graph);
     if (cap_st) (void)hipStreamDestroy(cap_st);
+    for (int i = 0; i < MAX_SIDE; ++i) {
+      if (side[i]) (void)hipStreamDestroy(side[i]);
+      if (join_ev[i]) (void)hipEventDestroy(join_ev[i]);
+    }
+    if (fork_ev) (void)hipEventDestroy(fork_ev);
   }
 };
 
@@ -652,6 +663,13 @@ smc_status smc_init(const smc_problem *prob, const smc_params *par, void *worksp
     }                                                                                \
   } while (0)
   CKI(fill_i32((int *)w, (long long)(L.total / 4), 0, ctx->st));
+  if (ctx->c2s.size() > 1) {  // side streams for the group launches, default priority
+    for (int i = 0; i < MAX_SIDE; ++i) {
+      CKI(hipStreamCreateWithFlags(&ctx->side[i], hipStreamNonBlocking));
+      CKI(hipEventCreateWithFlags(&ctx->join_ev[i], hipEventDisableTiming));
+    }
+    CKI(hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming));
+  }
   CKI(hipMemcpyAsync(D.posts, ctx->posts.data(), L.B * sizeof(Post), hipMemcpyHostToDevice,
                      ctx->st));
   CKI(hipMemcpyAsync(D.ps, ctx->ps_host.data(), L.B * sizeof(PState), hipMemcpyHostToDevice,
@@ -743,6 +761,33 @@ hipError_t timed_end(smc_ctx *ctx, size_t idx) {
   if (!ctx->timing) return hipSuccess;
   return hipEventRecord(ctx->ev_pool[idx + 1], ctx->st);
 }
+// Launches fn(g, stream) for the feature-tile groups g = 0 .. n-1.  With one
+// group, or with per-launch timing (events on the context's stream), in order
+// on the context's stream; otherwise group g on lane g mod 4, lane 0 the
+// context's stream and lanes 1..3 side streams forked from it and joined
+// back into it afterwards (graph edges under capture).  The groups write
+// disjoint memory, so the results do not depend on how they overlap.
+extern "C++" template <typename Fn>
+hipError_t for_groups(smc_ctx *ctx, int n, Fn fn) {
+  if (n == 1 || ctx->timing || !ctx->fork_ev) {
+    for (int g = 0; g < n; ++g) {
+      const hipError_t e = fn(g, ctx->st);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+  const int lanes = std::min(n, MAX_SIDE + 1);
+  hipError_t e = hipEventRecord(ctx->fork_ev, ctx->st);
+  for (int i = 1; i < lanes && e == hipSuccess; ++i)
+    e = hipStreamWaitEvent(ctx->side[i - 1], ctx->fork_ev, 0);
+  for (int g = 0; g < n && e == hipSuccess; ++g)
+    e = fn(g, g % lanes == 0 ? ctx->st : ctx->side[g % lanes - 1]);
+  for (int i = 1; i < lanes && e == hipSuccess; ++i) {
+    e = hipEventRecord(ctx->join_ev[i - 1], ctx->side[i - 1]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(ctx->st, ctx->join_ev[i - 1], 0);
+  }
+  return e;
+}
 }  // namespace
 
 namespace {
@@ -785,16 +830,17 @@ smc_status enqueue_step(smc_ctx *ctx, const smc_inject *inject) {
     CK(launch_lf_plan(D, ctx->st));
   }
   for (int s = 0; s < (D.target || D.traj ? 0 : D.nmax); ++s) {
-    for (int c2 : ctx->c2s) {
-      if (D.flow) {
-        CK(timed_begin(ctx, 3, ei));
-        CK(launch_flow_drift(D, F, s, ctx->st));
-        CK(timed_end(ctx, ei));
-      }
-      CK(timed_begin(ctx, 0, ei));
-      CK(launch_lf_partial(D, c2, s, D.flow ? 2 : 0, ctx->st));
+    if (D.flow) {  // one posterior, one group
+      CK(timed_begin(ctx, 3, ei));
+      CK(launch_flow_drift(D, F, s, ctx->st));
       CK(timed_end(ctx, ei));
     }
+    CK(for_groups(ctx, (int)ctx->c2s.size(), [&](int g, hipStream_t stream) {
+      hipError_t e = timed_begin(ctx, 0, ei);
+      if (e == hipSuccess) e = launch_lf_partial(D, ctx->c2s[g], s, D.flow ? 2 : 0, stream);
+      if (e == hipSuccess) e = timed_end(ctx, ei);
+      return e;
+    }));
     // one reduction for all groups (disjoint partial slots), unless every tile
     // is one item that finished its own step
     if (!D.lf_nosplit) {
@@ -808,11 +854,14 @@ smc_status enqueue_step(smc_ctx *ctx, const smc_inject *inject) {
       CK(timed_end(ctx, ei));
     }
   }
-  for (const int3 &g : (D.target ? std::vector<int3>() : ctx->ll_groups)) {
-    CK(timed_begin(ctx, 1, ei));
-    CK(launch_loglik(D, g.x, g.y, g.z, ctx->st));
-    CK(timed_end(ctx, ei));
-  }
+  if (!D.target)
+    CK(for_groups(ctx, (int)ctx->ll_groups.size(), [&](int i, hipStream_t stream) {
+      const int3 &g = ctx->ll_groups[i];
+      hipError_t e = timed_begin(ctx, 1, ei);
+      if (e == hipSuccess) e = launch_loglik(D, g.x, g.y, g.z, stream);
+      if (e == hipSuccess) e = timed_end(ctx, ei);
+      return e;
+    }));
   CK(launch_weights(D, inject ? inject->mh_uniforms : nullptr, 0, ctx->st));
   CK(launch_chees(D, ctx->st));
   CK(launch_commit(D, ctx->st));
