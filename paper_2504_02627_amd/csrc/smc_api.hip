@@ -829,7 +829,22 @@ smc_status enqueue_step(smc_ctx *ctx, const smc_inject *inject) {
   } else {
     CK(launch_lf_plan(D, ctx->st));
   }
-  for (int s = 0; s < (D.target || D.traj ? 0 : D.nmax); ++s) {
+  const bool lanes = ctx->c2s.size() > 1 && !ctx->timing && ctx->fork_ev && !D.target &&
+                     !D.traj && !D.flow;
+  if (lanes) {
+    // several feature-tile groups: each group's trajectories (step launches
+    // and its own reductions) run on a stream lane of their own, joined once
+    // after the last step
+    CK(for_groups(ctx, (int)ctx->c2s.size(), [&](int g, hipStream_t stream) {
+      hipError_t e = hipSuccess;
+      for (int s = 0; s < D.nmax && e == hipSuccess; ++s) {
+        e = launch_lf_partial(D, ctx->c2s[g], s, 0, stream);
+        if (e == hipSuccess && !D.lf_nosplit) e = launch_lf_reduce(D, s, 0, stream, ctx->c2s[g]);
+      }
+      return e;
+    }));
+  }
+  for (int s = 0; s < (D.target || D.traj || lanes ? 0 : D.nmax); ++s) {
     if (D.flow) {  // one posterior, one group
       CK(timed_begin(ctx, 3, ei));
       CK(launch_flow_drift(D, F, s, ctx->st));

@@ -219,7 +219,8 @@ size_t traj_lds_bytes(int c2, int nt);
 hipError_t launch_traj(const Dev &D, int c2, hipStream_t st);
 // mode 0: full step; 1: zero step size (gradient at theta, state rewritten);
 // 2: gradient only (theta given by the caller, p untouched)
-hipError_t launch_lf_reduce(const Dev &D, int step, int mode, hipStream_t st);
+// c2only > 0: only the posteriors of that feature-tile group
+hipError_t launch_lf_reduce(const Dev &D, int step, int mode, hipStream_t st, int c2only = 0);
 hipError_t launch_loglik(const Dev &D, int c2, int first, int count, hipStream_t st);
 hipError_t launch_weights(const Dev &D, const double *mh_u, int init_mode, hipStream_t st);
 hipError_t launch_chees(const Dev &D, hipStream_t st);

@@ -977,10 +977,11 @@ __global__ __launch_bounds__(WG) void k_lf_partial_bf16(Dev D, int s, int zero_e
 constexpr int RED_THREADS = 256;
 constexpr int RED_ROUND = 8;
 
-__global__ __launch_bounds__(RED_THREADS) void k_lf_reduce(Dev D, int s, int zero_eps) {
+__global__ __launch_bounds__(RED_THREADS) void k_lf_reduce(Dev D, int s, int zero_eps, int c2only) {
   const int tj = TJ, ntile = D.Jcap / tj;
   const int b = blockIdx.x / ntile, tile = blockIdx.x % ntile;
   const Post P = D.posts[b];
+  if (c2only && P.C2 != c2only) return;  // another group's posterior
   const int4 q = D.lf_post[(long long)s * D.B + b];
   const int dq = 4 * P.C2;  // float4 per particle row
   const int idx = blockIdx.y * RED_THREADS + threadIdx.x;
@@ -1058,13 +1059,14 @@ static hipError_t launch_lf_c2(const Dev &D, int step, int zero_eps, hipStream_t
   return hipGetLastError();
 }
 
-hipError_t launch_lf_reduce(const Dev &D, int step, int zero_eps, hipStream_t st) {
-  // TJ * 4 C2 float4 per tile, for the widest group
-  int c2max = 1;
-  for (int g = 0; g < D.ngroups; ++g) c2max = D.group_c2[g] > c2max ? D.group_c2[g] : c2max;
+hipError_t launch_lf_reduce(const Dev &D, int step, int zero_eps, hipStream_t st, int c2only) {
+  // TJ * 4 C2 float4 per tile, for the widest group (or the one group)
+  int c2max = c2only;
+  for (int g = 0; g < D.ngroups && !c2only; ++g)
+    c2max = D.group_c2[g] > c2max ? D.group_c2[g] : c2max;
   const int slices = (TJ * 4 * c2max + RED_THREADS - 1) / RED_THREADS;
   hipLaunchKernelGGL(k_lf_reduce, dim3(D.B * (D.Jcap / TJ), slices), dim3(RED_THREADS), 0, st, D,
-                     step, zero_eps);
+                     step, zero_eps, c2only);
   return hipGetLastError();
 }
 
