@@ -47,6 +47,7 @@ struct smc_ctx {
   // side by side (created at smc_init when there is more than one group)
   hipStream_t side[MAX_SIDE] = {};
   hipEvent_t fork_ev = nullptr, join_ev[MAX_SIDE] = {};
+  std::vector<int> group_lane;  // lane of each group: largest work first to the least loaded
   ~smc_ctx() {
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     if (gexec) (void)hipGraphExecDestroy(gexec);
@@ -635,6 +636,24 @@ smc_status smc_init(const smc_problem *prob, const smc_params *par, void *worksp
   ctx->ll_items = L.items;
   ctx->ll_groups = L.groups;
   for (const int3 &g : L.groups) ctx->c2s.push_back(g.x);
+  {
+    // lanes of the groups: work ~ sum over the group's posteriors of data
+    // tiles x feature tiles; largest first onto the least loaded lane
+    const int ng = (int)ctx->c2s.size();
+    std::vector<double> work(ng, 0.0), load(MAX_SIDE + 1, 0.0);
+    for (const HostPost &h : L.hp)
+      for (int g = 0; g < ng; ++g)
+        if (ctx->c2s[g] == h.C2) work[g] += (double)h.NT * h.C2;
+    std::vector<int> idx(ng);
+    for (int g = 0; g < ng; ++g) idx[g] = g;
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return work[a] > work[b]; });
+    ctx->group_lane.assign(ng, 0);
+    for (int g : idx) {
+      const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      ctx->group_lane[g] = l;
+      load[l] += work[g];
+    }
+  }
   ctx->primes = first_primes(NPRIMES);
   ctx->sqrtp.resize(NPRIMES);
   for (int i = 0; i < NPRIMES; ++i) ctx->sqrtp[i] = std::sqrt((double)ctx->primes[i]);
@@ -780,8 +799,10 @@ hipError_t for_groups(smc_ctx *ctx, int n, Fn fn) {
   hipError_t e = hipEventRecord(ctx->fork_ev, ctx->st);
   for (int i = 1; i < lanes && e == hipSuccess; ++i)
     e = hipStreamWaitEvent(ctx->side[i - 1], ctx->fork_ev, 0);
-  for (int g = 0; g < n && e == hipSuccess; ++g)
-    e = fn(g, g % lanes == 0 ? ctx->st : ctx->side[g % lanes - 1]);
+  for (int g = 0; g < n && e == hipSuccess; ++g) {
+    const int l = (int)ctx->group_lane.size() == n ? ctx->group_lane[g] % lanes : g % lanes;
+    e = fn(g, l == 0 ? ctx->st : ctx->side[l - 1]);
+  }
   for (int i = 1; i < lanes && e == hipSuccess; ++i) {
     e = hipEventRecord(ctx->join_ev[i - 1], ctx->side[i - 1]);
     if (e == hipSuccess) e = hipStreamWaitEvent(ctx->st, ctx->join_ev[i - 1], 0);
