@@ -636,38 +636,48 @@ __global__ __launch_bounds__(WG, 2 * lf_groups_per_cu(false, C2)) void k_lf_part
 // feature 16 ct + lane % 16).  Per step: drift; theta' moved into the
 // B-operand layout of GEMM1 through a per-wave LDS tile; GEMM1 -> sigmoid ->
 // GEMM2 over every data tile; prior; second half kick; a particle past its
-// n_j keeps its state.  Arithmetic and summation order are those of the
-// one-split step kernel (k_lf_partial with FIN), so the trajectories agree
-// with it exactly; only the launches per step and the state round trips
-// through HBM are gone.
+// n_j keeps its state.  The arithmetic is that of the one-split step kernel
+// (k_lf_partial with FIN) except GEMM1's K order: the features are
+// interleaved over the lane groups so that the MFMAs on the padding of d to
+// 16 C2 are skipped (d = 5: 2 of 4), which changes the order of Z's sum only.
 // BF: the precision form's operands, theta', X and R rounded to bfloat16
 // (nearest even), on the FP32 MFMA: the products are exact and accumulate in
 // FP32, as on the BF16 MFMA.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float bf16_val(float x) { return (float)(__bf16)x; }
 
-template <int C2, bool BF>
-__global__ __launch_bounds__(64 * TRAJ_WAVES) void k_traj(Dev D) {
+// GEMM1 of one data tile in the whole-trajectory kernel, K interleaved over
+// the lane groups (MFMA m takes features 4m .. 4m + 3, lane group kq feature
+// 4m + kq), issuing only the RL MFMAs of the last group that reach a real
+// feature (ceil(d/4) - 4 (C2 - 1)); the rest would multiply zero padding.
+template <int C2, int RL>
+__device__ __forceinline__ v4f traj_gemm1(const float4 *xl, const float *tB) {
+  v4f z = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int q = 0; q < C2 - 1; ++q) {
+    const float4 a = xl[q];
+    z = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, tB[4 * q + 0], z, 0, 0, 0);
+    z = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, tB[4 * q + 1], z, 0, 0, 0);
+    z = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, tB[4 * q + 2], z, 0, 0, 0);
+    z = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, tB[4 * q + 3], z, 0, 0, 0);
+  }
+  const float4 a = xl[C2 - 1];
+  const float *tq = tB + 4 * (C2 - 1);
+  z = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, tq[0], z, 0, 0, 0);
+  if constexpr (RL > 1) z = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, tq[1], z, 0, 0, 0);
+  if constexpr (RL > 2) z = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, tq[2], z, 0, 0, 0);
+  if constexpr (RL > 3) z = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, tq[3], z, 0, 0, 0);
+  return z;
+}
+
+// The leapfrog steps of one wave's 16 particles (k_traj below), with RL
+// GEMM1 MFMAs in the last operand group.
+template <int C2, bool BF, int RL>
+__device__ __forceinline__ void traj_steps(const Dev &D, const Post &P, const float4 *xall,
+                                           float *T) {
   using TL = Tiles<C2>;
   constexpr int K1 = 4 * C2, FS = 16 * C2 + 1;
-  extern __shared__ float4 xall[];                // every data tile of the posterior
-  __shared__ float tb[TRAJ_WAVES][16 * FS];        // per-wave theta' transpose
-  const Post P = D.posts[0];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, kq = lane >> 4, col = lane & 15;
-
-  const float4 *xab = reinterpret_cast<const float4 *>(D.xab + P.xab);
-  const int nx = P.NT * TL::TILE;
-  for (int e = tid; e < nx; e += 64 * TRAJ_WAVES) {
-    float4 v = xab[e];
-    if constexpr (BF) {
-      v.x = bf16_val(v.x);  // labels and the 1/2 padding are exact in bfloat16
-      v.y = bf16_val(v.y);
-      v.z = bf16_val(v.z);
-      v.w = bf16_val(v.w);
-    }
-    xall[e] = v;
-  }
-
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, kq = lane >> 4, col = lane & 15;
   const float eps = (float)D.ps[0].eps, he = 0.5f * eps;
   const float inv_pv = (float)(1.0 / D.prior_var);
   const int *perm = D.perm + P.row0;
@@ -694,9 +704,8 @@ __global__ __launch_bounds__(64 * TRAJ_WAVES) void k_traj(Dev D) {
 #pragma unroll
   for (int o = 8; o > 0; o >>= 1) nw = max(nw, __shfl_xor(nw, o));
   nw = __builtin_amdgcn_readfirstlane(nw);
-  __syncthreads();
+  __syncthreads();  // the data tiles are in LDS
 
-  float *T = tb[wave];
   for (int s = 0; s < nw; ++s) {
     float ph[C2][4], t1[C2][4];
 #pragma unroll
@@ -708,10 +717,10 @@ __global__ __launch_bounds__(64 * TRAJ_WAVES) void k_traj(Dev D) {
         T[(4 * kq + rr) * FS + 16 * ct + col] = t1[ct][rr];
       }
     __builtin_amdgcn_wave_barrier();
-    float tB[K1];
+    float tB[K1];  // tB[c] is feature 4c + kq
 #pragma unroll
     for (int c = 0; c < K1; ++c) {
-      tB[c] = T[col * FS + kq * K1 + c];
+      tB[c] = T[col * FS + 4 * c + kq];
       if constexpr (BF) tB[c] = bf16_val(tB[c]);
     }
     v4f gacc[C2];
@@ -721,15 +730,7 @@ __global__ __launch_bounds__(64 * TRAJ_WAVES) void k_traj(Dev D) {
       const float4 *xl = xall + t * TL::TILE + lane * TL::LSTR;
       const float4 y4 = xl[2 * C2];
       const float ya[4] = {y4.x, y4.y, y4.z, y4.w};
-      v4f z = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int q = 0; q < C2; ++q) {
-        const float4 a = xl[q];
-        z = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, tB[4 * q + 0], z, 0, 0, 0);
-        z = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, tB[4 * q + 1], z, 0, 0, 0);
-        z = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, tB[4 * q + 2], z, 0, 0, 0);
-        z = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, tB[4 * q + 3], z, 0, 0, 0);
-      }
+      const v4f z = traj_gemm1<C2, RL>(xl, tB);
       float r[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
@@ -767,6 +768,48 @@ __global__ __launch_bounds__(64 * TRAJ_WAVES) void k_traj(Dev D) {
       D.p_t[e] = pp[ct][rr];
       D.grad_t[e] = gg[ct][rr];
     }
+  }
+}
+
+template <int C2, bool BF>
+__global__ __launch_bounds__(64 * TRAJ_WAVES) void k_traj(Dev D) {
+  using TL = Tiles<C2>;
+  constexpr int K1 = 4 * C2, LF = 4 * TL::LSTR, FS = 16 * C2 + 1;
+  extern __shared__ float4 xall[];                // every data tile of the posterior
+  __shared__ float tb[TRAJ_WAVES][16 * FS];        // per-wave theta' transpose
+  const Post P = D.posts[0];
+  const int tid = threadIdx.x;
+  // the packed tiles into LDS; the GEMM1 operands re-ordered on the way to
+  // the interleaved K order (slot c of lane (n, kq) <- feature 4c + kq, which
+  // the packing holds in lane (n, f / K1), slot f mod K1)
+  const float *xf = D.xab + P.xab;
+  const int nx = P.NT * TL::TILE;
+  for (int e = tid; e < nx; e += 64 * TRAJ_WAVES) {
+    const int t = e / TL::TILE, r = e - t * TL::TILE;
+    const int ln = r / TL::LSTR, q = r - ln * TL::LSTR;
+    float v[4];
+    if (q < C2) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int f = 4 * (4 * q + i) + (ln >> 4);
+        v[i] = xf[((long long)t * 64 + (ln & 15) + 16 * (f / K1)) * LF + f % K1];
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) v[i] = xf[((long long)t * 64 + ln) * LF + 4 * q + i];
+    }
+    if constexpr (BF) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) v[i] = bf16_val(v[i]);  // labels, 1/2 padding exact
+    }
+    xall[e] = make_float4(v[0], v[1], v[2], v[3]);
+  }
+  float *T = tb[threadIdx.x >> 6];
+  switch ((P.d + 3) / 4 - 4 * (C2 - 1)) {
+    case 1: traj_steps<C2, BF, 1>(D, P, xall, T); break;
+    case 2: traj_steps<C2, BF, 2>(D, P, xall, T); break;
+    case 3: traj_steps<C2, BF, 3>(D, P, xall, T); break;
+    default: traj_steps<C2, BF, 4>(D, P, xall, T);
   }
 }
 

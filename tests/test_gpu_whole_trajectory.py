@@ -2,12 +2,14 @@
 a work group's LDS) against the per-step launches (CHEES_SMC_PER_STEP=1) on
 identical inputs, and the launch counts that show which path ran.
 
-Bars: FP32 trajectories, energies and log-weights of the two paths agree to
-1e-6 relative (the arithmetic and its order are the same; the bar leaves room
-for a different contraction of one multiply-add); the precision form's
-trajectories of the two paths (FP32 MFMA on bfloat16 operands vs the BF16
-MFMA; each within 5e-3 of the BF16-emulating oracle) agree to 1e-2.  Parity against the oracle for
-this path is covered by the small cases of test_gpu_parity.py and
+Bars: FP32 trajectories of the two paths agree to 1e-5 relative, Delta H and
+the log-weights to 1e-5 (|H0| + |H1|), the parity bars against the oracle
+(the arithmetic is the same but for the order of GEMM1's K sum: the
+one-launch kernel interleaves the features over the lane groups to skip the
+MFMAs on the padding); the precision form's trajectories of the two paths
+(FP32 MFMA on bfloat16 operands vs the BF16 MFMA; each within 5e-3 of the
+BF16-emulating oracle) agree to 1e-2.  Parity against the oracle for this
+path is covered by the small cases of test_gpu_parity.py and
 test_gpu_bf16.py, which take it by default.
 """
 
@@ -43,11 +45,11 @@ def _run(N, d, J, seed, per_step, monkeypatch, precision="f32", steps=2):
         st = s.step(momenta=to_dev(xi), resample_u=to_dev(u))
         s.adapt()
         tr = s.trace()
-        _, logw, _ = s.state()
+        _, logw, logpi = s.state()
         out.append(dict(st=st, th=tr["theta_prop"].cpu().numpy()[:J, :d].astype(np.float64),
                         p=tr["p_final"].cpu().numpy()[:J, :d].astype(np.float64),
                         dh=tr["dH"].cpu().numpy()[:J], n=tr["n"].cpu().numpy()[:J],
-                        logw=logw.cpu().numpy()))
+                        logw=logw.cpu().numpy()[:J], lp=logpi.cpu().numpy()[:J]))
     torch.cuda.synchronize()
     launches = s.timing()["leapfrog_launches"]
     s.close()
@@ -65,10 +67,14 @@ def test_whole_trajectory_matches_per_step(N, d, J, monkeypatch):
         np.testing.assert_array_equal(x["n"], y_["n"])
         et, ep = rel_rows(x["th"], y_["th"]), rel_rows(x["p"], y_["p"])
         log(f"  theta rel {et:.1e}  p rel {ep:.1e}")
-        assert et <= 1e-6 and ep <= 1e-6
-        scale = np.abs(x["dh"]) + 1.0
-        assert np.all(np.abs(x["dh"] - y_["dh"]) <= 1e-6 * scale)
-        np.testing.assert_allclose(x["logw"], y_["logw"], rtol=1e-6, atol=1e-6)
+        assert et <= 1e-5 and ep <= 1e-5
+        # Delta H cancels two energies of size |log pi|: the parity bar
+        # 1e-5 (|H0| + |H1|), with |H0| + |H1| >= 2 |log pi(theta')| - |Delta H|
+        scale = np.maximum(2 * np.abs(x["lp"]) - np.abs(x["dh"]), 1.0)
+        err = np.abs(x["dh"] - y_["dh"])
+        log(f"  max |dH_a - dH_b| / scale {np.max(err / scale):.1e}")
+        assert np.all(err <= 1e-5 * scale)
+        assert np.all(np.abs(x["logw"] - y_["logw"]) <= 1e-5 * scale)
 
 
 @pytest.mark.parametrize("N,d,J", [(200, 5, 256), (150, 24, 130)])
