@@ -82,3 +82,44 @@ def test_full_size_sampled_particles(precision):
         L, eps = ad["L"], ad["eps"]
         theta_prev = s.state()[0].cpu().numpy().astype(np.float64)
     s.close()
+
+
+def test_max_particles_sampled():
+    # the largest particle count the boundary accepts, J = 65536, on the
+    # split path (N = 2000, d = 40: 125 data tiles, three feature tiles):
+    # jitter and step counts for every particle, trajectories and Delta H for
+    # a sample integrated by the oracle one by one
+    from paper_2504_02627_amd import chees
+    Jm, Nm, Dm = 65536, 2000, 40
+    X, y, _ = synth.logistic_iid(Nm, Dm, 31)
+    target = O.LogisticRegression(X.astype(np.float64), y.astype(np.float64))
+    eps = synth.default_step_size(Nm, Dm)
+    params = dict(step_size=eps, traj_length=eps * 16, max_leapfrog=32, num_warmup=5, seed=5)
+    rng = np.random.default_rng(77)
+    theta0 = (0.3 * rng.standard_normal((Jm, Dm))).astype(np.float32)
+    log(f"[fullsize] max particles J={Jm} N={Nm} d={Dm}")
+    s = chees.Sampler(to_dev(X), to_dev(y), Jm, theta0=to_dev(theta0), **params)
+    xi = rng.standard_normal((Jm, Dm)).astype(np.float32)
+    st = s.step(momenta=to_dev(xi), resample_u=to_dev(np.array([0.37])))
+    tr = s.trace()
+    h = tr["h"].cpu().numpy()[:Jm]
+    n = tr["n"].cpu().numpy()[:Jm]
+    np.testing.assert_array_equal(h, O.halton_1d(1, Jm))
+    np.testing.assert_array_equal(n, O.step_counts(h, params["traj_length"], eps, 32)[1])
+    assert st["grad_evals"] == int(n.sum())
+    # the prior draw's weights are degenerate: the step resamples first
+    anc = tr["ancestors"].cpu().numpy()[:Jm] if st["resampled"] else np.arange(Jm)
+    sample = np.unique(np.concatenate([np.linspace(0, Jm - 1, 16).astype(int),
+                                       rng.integers(0, Jm, 8)]))
+    th_b = theta0[anc[sample]].astype(np.float64)
+    p0 = xi[sample].astype(np.float64)
+    lp0, g0 = target.log_and_grad(th_b)
+    th1o, p1o, _, lp1o, _ = O.leapfrog(target, th_b, p0, g0, eps, n[sample])
+    th1 = tr["theta_prop"].cpu().numpy()[sample, :Dm].astype(np.float64)
+    p1 = tr["p_final"].cpu().numpy()[sample, :Dm].astype(np.float64)
+    et, ep = rel_rows(th1, th1o), rel_rows(p1, p1o)
+    H0, H1 = O.hamiltonian(lp0, p0), O.hamiltonian(lp1o, p1o)
+    edh = np.abs(tr["dH"].cpu().numpy()[sample] - (H1 - H0))
+    log(f"  traj rel err theta {et:.2e} p {ep:.2e}; max |dH err| {edh.max():.2e}")
+    assert et <= 1e-5 and ep <= 1e-5
+    assert np.all(edh <= 1e-5 * (np.abs(H0) + np.abs(H1)))
