@@ -79,7 +79,7 @@ struct Layout {
   size_t o_posts, o_ps, o_xab, o_xbf, o_theta, o_grad, o_theta_t, o_p_t, o_grad_t;
   size_t o_logpi, o_logpi_t, o_logw, o_h, o_l, o_H0, o_dH, o_alpha, o_ca, o_cg;
   size_t o_n, o_perm, o_active, o_anc, o_acc, o_cdf, o_gpart, o_llpart;
-  size_t o_redp = 0, o_redc = 0;
+  size_t o_redp = 0, o_redc = 0, o_sortc = 0;
   size_t o_lf_post = 0, o_lf_items = 0, o_lf_count = 0;
   size_t o_tmean = 0, o_tprec = 0;
   size_t o_items, o_colpart, o_means, o_minv, o_primes, o_sqrtp = 0, o_sobol = 0;
@@ -380,6 +380,7 @@ void plan(const smc_problem *pr, const smc_params *pa, Layout &L) {
   L.o_cdf = take(c, rows * 8);
   L.o_redp = take(c, (size_t)B * RED_G * 4 * sizeof(double));
   L.o_redc = take(c, (size_t)B * 2 * sizeof(int));
+  L.o_sortc = take(c, (size_t)B * ((L.Jcap + 1023) / 1024) * 256 * sizeof(int));
   // partial gradients: each feature-tile group owns the slots of its largest
   // launch, so one reduction per step serves every group
   L.gpart_slots = 0;
@@ -574,6 +575,8 @@ smc_status smc_init(const smc_problem *prob, const smc_params *par, void *worksp
   D.cdf = (unsigned long long *)(w + L.o_cdf);
   D.red_part = (double *)(w + L.o_redp);
   D.red_cnt = (int *)(w + L.o_redc);
+  D.sort_cnt = (int *)(w + L.o_sortc);
+  D.sort_chunks = (L.Jcap + 1023) / 1024;
   D.gpart = (float *)(w + L.o_gpart);
   D.gpart_slots = L.gpart_slots;
   D.lf_nosplit = L.nosplit;

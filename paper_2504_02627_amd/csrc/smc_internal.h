@@ -118,6 +118,8 @@ struct Dev {                    // pointers carved from the workspace
   unsigned long long *cdf;
   double *red_part;             // [B][RED_G][4] per-block partial sums of the reductions
   int *red_cnt;                 // [B][2] blocks done (ESS, ChEES); zero between launches
+  int *sort_cnt;                // [B][sort_chunks][256] bin counts of the sort's work groups
+  int sort_chunks;              // ceil(Jcap / 1024)
   float *gpart;                 // split partial gradients, [wg][TJ][DS]
   int gpart_slots;              // number of [TJ][DS] slots
   float2 *llpart;               // log-likelihood partials [split][row]

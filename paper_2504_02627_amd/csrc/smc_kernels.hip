@@ -1760,15 +1760,17 @@ __global__ __launch_bounds__(1024) void k_sort(Dev D) {
   }
 }
 
-// The same stable counting sort without barriers between the waves while
-// placing, for n_max < SORT_FAST_BINS: wave w owns the particle segment
-// [w seg, (w + 1) seg) (seg a multiple of 64); per-wave bin counts give each
-// wave its own cursor per bin (bin start + the counts of the waves before
-// it), and each wave then places its segment chunk by chunk in index order.
-// The placement equals that of k_sort.
-constexpr int SORT_FAST_BINS = 257;
-constexpr int SORT_WAVES = 16;
-constexpr int SORT_BATCH = 16;  // 64-particle chunks per batch of key loads
+// The same stable counting sort over many work groups, for n_max < 256.
+// Work group c of a posterior owns the particles [1024 c, 1024 c + 1024),
+// its wave w the quarter [256 w, 256 w + 256) of those.  k_sort_count writes
+// each group's bin counts; k_sort_place, a later launch (so every count is
+// visible to it), gives each wave a cursor per bin: the bin's start (bins
+// longest first) + the counts of the groups before it + those of the waves
+// before it in its group; the wave then places its quarter in index order.
+// Inside a wave, keys are ranked by nine per-bit ballots.  The placement
+// equals that of k_sort.
+constexpr int SORT_BINS = 256;    // the multi-group sort takes n_max < 256
+constexpr int SORT_CHUNK = 1024;  // particles per work group: 4 waves x 256
 
 // Lanes of the wave holding the same 9-bit key as this lane: the
 // intersection over the key's bits of the ballot of that bit (or of its
@@ -1784,48 +1786,69 @@ __device__ __forceinline__ unsigned long long peers9(int v) {
   return peers;
 }
 
-__global__ __launch_bounds__(64 * SORT_WAVES) void k_sort_seg(Dev D) {
-  __shared__ int hw[SORT_WAVES][SORT_FAST_BINS];  // counts, then cursors
-  const int b = blockIdx.x, row0 = b * D.Jcap, nb = D.nmax + 1;
+// Keys of this wave's quarter of the group's particles [j0, j1): four
+// 64-particle chunks, 511 where there is no particle.
+__device__ __forceinline__ void sort_keys(const Dev &D, int row0, int j0, int j1, int (&nv)[4]) {
+  const int lane = threadIdx.x & 63, q0 = j0 + 256 * (threadIdx.x >> 6);
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int j = q0 + 64 * u + lane;
+    nv[u] = j < j1 ? D.n[row0 + j] : 511;
+  }
+}
+
+// Per-wave bin counts of the group's quarters into hw (zeroed here).  The
+// lowest lane of each key adds its peer count: the keys' leaders are
+// distinct lanes and hw[wave] is the wave's own row.
+__device__ __forceinline__ void sort_wave_counts(const int (&nv)[4], int (*hw)[SORT_BINS]) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int seg = ((D.Jcap + 64 * SORT_WAVES - 1) / (64 * SORT_WAVES)) * 64;
-  const int j0 = wave * seg, j1 = min(D.Jcap, j0 + seg);
   const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
-  for (int i = threadIdx.x; i < SORT_WAVES * SORT_FAST_BINS; i += blockDim.x) (&hw[0][0])[i] = 0;
+  for (int i = threadIdx.x; i < 4 * SORT_BINS; i += blockDim.x) (&hw[0][0])[i] = 0;
   __syncthreads();
-  // per-wave counts: the lowest lane of each key adds its peer count
-  // (the keys' leaders are distinct lanes, and hw[wave] is this wave's own)
-  // keys of SORT_BATCH chunks at a time, so that their loads are in flight
-  // together
-  for (int c0 = j0; c0 < j1; c0 += 64 * SORT_BATCH) {
-    int nv[SORT_BATCH];
 #pragma unroll
-    for (int u = 0; u < SORT_BATCH; ++u) {
-      const int j = c0 + 64 * u + lane;
-      nv[u] = j < j1 ? D.n[row0 + j] : 511;  // 511: no particle (n_max < 257)
-    }
-#pragma unroll
-    for (int u = 0; u < SORT_BATCH; ++u) {
-      const int n = nv[u];
-      const unsigned long long peers = peers9(n);
-      if (n != 511 && !(peers & below)) hw[wave][n] += __popcll(peers);
-      __builtin_amdgcn_wave_barrier();
-    }
+  for (int u = 0; u < 4; ++u) {
+    const unsigned long long peers = peers9(nv[u]);
+    if (nv[u] != 511 && !(peers & below)) hw[wave][nv[u]] += __popcll(peers);
+    __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
-  // bins longest first (index t holds n = n_max - t): inclusive scan of the
-  // bin totals, then the cursor of wave w in bin n is
-  // start(n) + sum_{w' < w} count(w', n)
-  __shared__ int ts[SORT_FAST_BINS];
-  __shared__ double shr[SORT_WAVES];
-  const int t = threadIdx.x;
-  int tot = 0;
+}
+
+__global__ __launch_bounds__(256) void k_sort_count(Dev D) {
+  __shared__ int hw[4][SORT_BINS];
+  const int b = blockIdx.y, c = blockIdx.x, nb = D.nmax + 1;
+  const int j0 = c * SORT_CHUNK, j1 = min(D.Jcap, j0 + SORT_CHUNK);
+  int nv[4];
+  sort_keys(D, b * D.Jcap, j0, j1, nv);
+  sort_wave_counts(nv, hw);
+  int *out = D.sort_cnt + ((long long)b * D.sort_chunks + c) * SORT_BINS;
+  for (int n = threadIdx.x; n < nb; n += blockDim.x) out[n] = hw[0][n] + hw[1][n] + hw[2][n] + hw[3][n];
+}
+
+__global__ __launch_bounds__(256) void k_sort_place(Dev D) {
+  __shared__ int hw[4][SORT_BINS];  // counts, then cursors
+  __shared__ int ts[SORT_BINS];
+  __shared__ double shr[4];
+  const int b = blockIdx.y, c = blockIdx.x, nb = D.nmax + 1, row0 = b * D.Jcap;
+  const int j0 = c * SORT_CHUNK, j1 = min(D.Jcap, j0 + SORT_CHUNK);
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  int nv[4];
+  sort_keys(D, row0, j0, j1, nv);
+  sort_wave_counts(nv, hw);
+  // index t holds bin n = n_max - t (longest first): its total over the
+  // groups, and the counts of the groups before this one
+  int tot = 0, bef = 0;
   if (t < nb) {
-    for (int w = 0; w < SORT_WAVES; ++w) tot += hw[w][D.nmax - t];
+    const int *cn = D.sort_cnt + (long long)b * D.sort_chunks * SORT_BINS + (D.nmax - t);
+    for (int cc = 0; cc < D.sort_chunks; ++cc) {
+      const int v = cn[(long long)cc * SORT_BINS];
+      tot += v;
+      bef += cc < c ? v : 0;
+    }
     ts[t] = tot;
   }
   __syncthreads();
-  for (int off = 1; off < nb; off <<= 1) {
+  for (int off = 1; off < nb; off <<= 1) {  // inclusive scan of the totals
     const int v = (t < nb && t >= off) ? ts[t - off] : 0;
     __syncthreads();
     if (t < nb) ts[t] += v;
@@ -1834,44 +1857,45 @@ __global__ __launch_bounds__(64 * SORT_WAVES) void k_sort_seg(Dev D) {
   int *act = D.active + b * nb;
   if (t < nb) {
     const int n = D.nmax - t;
-    int pos = ts[t] - tot;  // particles with n_j > n
-    if (n < D.nmax) act[n] = pos;
-    for (int w = 0; w < SORT_WAVES; ++w) {
-      const int c = hw[w][n];
+    const int start = ts[t] - tot;  // particles with n_j > n
+    if (c == 0 && n < D.nmax) act[n] = start;
+    int pos = start + bef;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      const int k = hw[w][n];
       hw[w][n] = pos;
-      pos += c;
+      pos += k;
     }
   }
-  if (t == 0) act[D.nmax] = 0;
-  const double ev = block_reduce(t < nb ? (double)(D.nmax - t) * tot : 0.0, shr, OpAdd());
-  if (t == 0) D.ps[b].grad_evals_step = (long long)ev;  // exact: below 2^53
+  if (c == 0) {  // uniform in the work group
+    if (t == 0) act[D.nmax] = 0;
+    const double ev = block_reduce(t < nb ? (double)(D.nmax - t) * tot : 0.0, shr, OpAdd());
+    if (t == 0) D.ps[b].grad_evals_step = (long long)ev;  // exact: below 2^53
+  }
   __syncthreads();
-  for (int c0 = j0; c0 < j1; c0 += 64 * SORT_BATCH) {
-    int nv[SORT_BATCH];
+  const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  const int q0 = j0 + 256 * wave;
 #pragma unroll
-    for (int u = 0; u < SORT_BATCH; ++u) {
-      const int j = c0 + 64 * u + lane;
-      nv[u] = j < j1 ? D.n[row0 + j] : 511;
-    }
-#pragma unroll
-    for (int u = 0; u < SORT_BATCH; ++u) {
-      const int n = nv[u];
-      const unsigned long long peers = peers9(n);
-      const int rank = __popcll(peers & below);
-      const int base = n != 511 ? hw[wave][n] : 0;
-      __builtin_amdgcn_wave_barrier();
-      if (n != 511 && rank == 0) hw[wave][n] = base + __popcll(peers);
-      __builtin_amdgcn_wave_barrier();
-      if (n != 511) D.perm[row0 + base + rank] = c0 + 64 * u + lane;
-    }
+  for (int u = 0; u < 4; ++u) {
+    const int n = nv[u];
+    const unsigned long long peers = peers9(n);
+    const int rank = __popcll(peers & below);
+    const int base = n != 511 ? hw[wave][n] : 0;
+    __builtin_amdgcn_wave_barrier();
+    if (n != 511 && rank == 0) hw[wave][n] = base + __popcll(peers);
+    __builtin_amdgcn_wave_barrier();
+    if (n != 511) D.perm[row0 + base + rank] = q0 + 64 * u + lane;
   }
 }
 
 hipError_t launch_sort(const Dev &D, hipStream_t st) {
-  if (D.nmax < SORT_FAST_BINS)
-    hipLaunchKernelGGL(k_sort_seg, dim3(D.B), dim3(64 * SORT_WAVES), 0, st, D);
-  else
+  if (D.nmax < SORT_BINS) {
+    const dim3 grid(D.sort_chunks, D.B);
+    hipLaunchKernelGGL(k_sort_count, grid, dim3(256), 0, st, D);
+    hipLaunchKernelGGL(k_sort_place, grid, dim3(256), 0, st, D);
+  } else {
     hipLaunchKernelGGL(k_sort, dim3(D.B), dim3(1024), 2 * (D.nmax + 1) * sizeof(int), st, D);
+  }
   return hipGetLastError();
 }
 

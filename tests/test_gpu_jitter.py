@@ -106,12 +106,13 @@ def test_sobol_at_full_particle_count_and_past_the_table():
         np.testing.assert_array_equal(h, O.sobol_nd(min(k, 3), J, rows))
 
 
-@pytest.mark.parametrize("J,nmax,B", [(300, 64, 1), (16384, 64, 1), (1000, 300, 1), (130, 32, 2)])
+@pytest.mark.parametrize("J,nmax,B", [(300, 64, 1), (16384, 64, 1), (65536, 255, 1), (1000, 300, 1),
+                                      (130, 32, 2), (3000, 64, 3)])
 def test_particle_order_is_a_stable_sort_by_steps(J, nmax, B):
     # the order in which the trajectory kernels take the particles: every row
     # once, n_j non-increasing, index order within equal n_j; active counts
     # #{j: n_j > s}.  n_max = 300 takes the single-group sort, the others the
-    # segmented one.
+    # multi-group one (up to 64 groups of 1024 particles).
     from paper_2504_02627_amd import chees
     log(f"[order] J={J} nmax={nmax} B={B}")
     data = [synth.logistic_iid(120, 4, 1 + b) for b in range(B)]
