@@ -257,7 +257,13 @@ size_t smc_workspace_bytes(const smc_problem *prob, const smc_params *par);
  * (eqs. init_sample, init_weights; the -log J makes sum_j w_j an evidence
  * estimate).  theta0: nullable DEVICE (B*J) x d_b FP32; NULL draws
  * theta_0 ~ q0 from Philox.  hip_stream: a hipStream_t (NULL = default).
- * Does not synchronise. */
+ * Does not synchronise.  Launch shapes chosen here: a single posterior whose
+ * packed data fits in one work group's LDS runs each iteration's
+ * trajectories in one launch (the environment variable CHEES_SMC_PER_STEP=1
+ * at smc_init keeps one launch per leapfrog step instead, for comparison);
+ * several feature-tile groups run side by side on three extra streams of
+ * default priority, created here and forked from and joined into
+ * hip_stream. */
 smc_status smc_init(const smc_problem *prob, const smc_params *par, void *workspace,
                     size_t workspace_bytes, void *hip_stream, const float *theta0,
                     smc_ctx **out);
