@@ -368,6 +368,23 @@ smc_status smc_get_timing(smc_ctx *ctx, smc_timing *out);
 /* Set the adapted parameters L and eps (stream-ordered; host values). */
 smc_status smc_set_params(smc_ctx *ctx, double L, double eps);
 
+/* Checkpoint and resume (not in the paper).  smc_save copies into HOST memory
+ * buf (at least smc_state_bytes bytes) the state after the last completed
+ * iteration: particles, gradients, log-densities and log-weights, the inverse
+ * mass, each posterior's scalars (L, eps and their Adam and dual-averaging
+ * moments, the moving average, the iteration counter k, the evidence
+ * accumulator, the totals) and, with the flow preconditioner, the couplings,
+ * their packed copies and Adam moments; it synchronises the stream and is
+ * SMC_ESTATE between smc_step and chees_adapt.  smc_load restores such an
+ * image into a context built from the same problem and parameters: the
+ * randomness is counter-based (Philox keyed by seed and k), so the run goes
+ * on bit-identically.  An image of another shape (B, J, row stride, n_max,
+ * flow size, precision) is SMC_EINVAL; the caller owns keeping the problem
+ * and the remaining parameters the same. */
+size_t smc_state_bytes(const smc_ctx *ctx);
+smc_status smc_save(smc_ctx *ctx, void *buf, size_t bytes);
+smc_status smc_load(smc_ctx *ctx, const void *buf, size_t bytes);
+
 void smc_destroy(smc_ctx *ctx);
 const char *smc_last_error(const smc_ctx *ctx);
 

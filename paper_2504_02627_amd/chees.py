@@ -141,6 +141,9 @@ def load():
             "smc_get_counters": (i32, [vp, P(Counters)]),
             "smc_set_params": (i32, [vp, dbl, dbl]),
             "smc_set_timing": (i32, [vp, i32]),
+            "smc_state_bytes": (ctypes.c_size_t, [vp]),
+            "smc_save": (i32, [vp, vp, ctypes.c_size_t]),
+            "smc_load": (i32, [vp, vp, ctypes.c_size_t]),
             "smc_get_timing": (i32, [vp, P(Timing)]),
             "smc_destroy": (None, [vp]),
             "smc_last_error": (ctypes.c_char_p, [vp]),
@@ -444,6 +447,18 @@ class Sampler:
         t = Timing()
         self._check(self.lib.smc_get_timing(self.ctx, ctypes.byref(t)), "smc_get_timing")
         return {k: getattr(t, k) for k, _ in t._fields_}
+
+    def save(self):
+        """Checkpoint of the state after the last completed iteration (bytes)."""
+        n = self.lib.smc_state_bytes(self.ctx)
+        buf = ctypes.create_string_buffer(n)
+        self._check(self.lib.smc_save(self.ctx, buf, n), "smc_save")
+        return buf.raw
+
+    def load(self, image):
+        """Restore a checkpoint from save() of a sampler built the same way."""
+        buf = ctypes.create_string_buffer(bytes(image), len(image))
+        self._check(self.lib.smc_load(self.ctx, buf, len(image)), "smc_load")
 
     def set_params(self, L, eps):
         self._check(self.lib.smc_set_params(self.ctx, float(L), float(eps)), "smc_set_params")

@@ -1148,6 +1148,117 @@ smc_status smc_set_flow(smc_ctx *ctx, const float *params) {
   return SMC_OK;
 }
 
+}  // extern "C"
+
+namespace {
+// Device arrays a checkpoint holds: what the next iteration reads (the
+// trajectory buffers, plans and partials are rebuilt by every step).
+std::vector<std::pair<void *, size_t>> state_pieces(const smc_ctx *ctx) {
+  const Dev &D = ctx->D;
+  const size_t rows = (size_t)D.B * D.Jcap;
+  std::vector<std::pair<void *, size_t>> v = {{D.ps, (size_t)D.B * sizeof(PState)},
+                                              {D.theta, rows * D.DS * sizeof(float)},
+                                              {D.grad, rows * D.DS * sizeof(float)},
+                                              {D.logpi, rows * sizeof(double)},
+                                              {D.logw, rows * sizeof(double)},
+                                              {D.minv, (size_t)D.B * D.DS * sizeof(float)}};
+  if (D.flow) {
+    const size_t np = (size_t)ctx->F.nparams * 4, npk = (size_t)ctx->F.npacked * 4;
+    v.push_back({D.fp, np});
+    v.push_back({D.fpk, npk});
+    v.push_back({D.fbk, npk});
+    v.push_back({D.fbias, np});
+    v.push_back({D.fadm, np});
+    v.push_back({D.fadv, np});
+    v.push_back({D.fstate, 256});
+  }
+  return v;
+}
+
+struct StateHeader {
+  char magic[8];
+  int32_t B, J, Jcap, DS, nmax, flow, nparams, bf16;
+  int64_t steps, bytes;
+};
+
+void state_header(const smc_ctx *ctx, StateHeader &h) {
+  memset(&h, 0, sizeof(h));
+  memcpy(h.magic, "CHEESMC1", 8);
+  h.B = ctx->D.B;
+  h.J = ctx->D.J;
+  h.Jcap = ctx->D.Jcap;
+  h.DS = ctx->D.DS;
+  h.nmax = ctx->D.nmax;
+  h.flow = ctx->D.flow;
+  h.nparams = ctx->D.flow ? ctx->F.nparams : 0;
+  h.bf16 = ctx->D.bf16;
+  h.steps = ctx->steps;
+  size_t bytes = sizeof(StateHeader);
+  for (const auto &p : state_pieces(ctx)) bytes += p.second;
+  h.bytes = (int64_t)bytes;
+}
+}  // namespace
+
+extern "C" {
+
+size_t smc_state_bytes(const smc_ctx *ctx) {
+  if (!ctx) return 0;
+  StateHeader h;
+  state_header(ctx, h);
+  return (size_t)h.bytes;
+}
+
+smc_status smc_save(smc_ctx *ctx, void *buf, size_t bytes) {
+  if (!ctx || !buf) return SMC_EINVAL;
+  if (ctx->stepped) {
+    ctx->err = "smc_save between smc_step and chees_adapt";
+    return SMC_ESTATE;
+  }
+  StateHeader h;
+  state_header(ctx, h);
+  if (bytes < (size_t)h.bytes) {
+    ctx->err = "smc_save: buffer smaller than smc_state_bytes";
+    return SMC_EINVAL;
+  }
+  char *out = (char *)buf;
+  memcpy(out, &h, sizeof(h));
+  size_t off = sizeof(h);
+  for (const auto &p : state_pieces(ctx)) {
+    CK(hipMemcpyAsync(out + off, p.first, p.second, hipMemcpyDeviceToHost, ctx->st));
+    off += p.second;
+  }
+  CK(hipStreamSynchronize(ctx->st));
+  return SMC_OK;
+}
+
+smc_status smc_load(smc_ctx *ctx, const void *buf, size_t bytes) {
+  if (!ctx || !buf) return SMC_EINVAL;
+  StateHeader mine, img;
+  state_header(ctx, mine);
+  if (bytes < sizeof(img)) {
+    ctx->err = "smc_load: image too short";
+    return SMC_EINVAL;
+  }
+  memcpy(&img, buf, sizeof(img));
+  if (memcmp(img.magic, mine.magic, 8) != 0 || img.B != mine.B || img.J != mine.J ||
+      img.Jcap != mine.Jcap || img.DS != mine.DS || img.nmax != mine.nmax ||
+      img.flow != mine.flow || img.nparams != mine.nparams || img.bf16 != mine.bf16 ||
+      img.bytes != mine.bytes || bytes < (size_t)img.bytes) {
+    ctx->err = "smc_load: the image was saved from a context of another shape";
+    return SMC_EINVAL;
+  }
+  const char *in = (const char *)buf;
+  size_t off = sizeof(img);
+  for (const auto &p : state_pieces(ctx)) {
+    CK(hipMemcpyAsync(p.first, in + off, p.second, hipMemcpyHostToDevice, ctx->st));
+    off += p.second;
+  }
+  CK(hipStreamSynchronize(ctx->st));
+  ctx->steps = img.steps;
+  ctx->stepped = 0;
+  return SMC_OK;
+}
+
 void smc_destroy(smc_ctx *ctx) { delete ctx; }
 
 const char *smc_last_error(const smc_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
