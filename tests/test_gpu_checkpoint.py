@@ -94,3 +94,25 @@ def test_load_refuses_another_shape_and_save_checks_call_order():
     assert len(a.save()) == len(image)
     a.close()
     b.close()
+
+
+def test_runner_logs_every_iteration_and_resumes(tmp_path):
+    # the command-line runner: one JSON record per iteration; a run split by
+    # a checkpoint logs what the uninterrupted run logs (wall time aside)
+    import json
+    from paper_2504_02627_amd import run
+    full, first, second = tmp_path / "full.jsonl", tmp_path / "a.jsonl", tmp_path / "b.jsonl"
+    ck = tmp_path / "state.bin"
+    common = ["--workload", "small", "--particles", "2048", "--iterations", "6"]
+    run.main(common + ["--jsonl", str(full)])
+    run.main(["--workload", "small", "--particles", "2048", "--iterations", "6", "--jsonl",
+              str(first), "--save", str(ck)])
+    recs = [json.loads(l) for l in open(full)]
+    assert [r["iteration"] for r in recs] == list(range(1, 7))
+    assert all(0 < r["ess"] <= 2048 and 1 <= r["n_max"] <= 64 for r in recs)
+    assert recs == [dict(r, wall_ms=x["wall_ms"]) for r, x in
+                    zip([json.loads(l) for l in open(first)], recs)]
+    # resume from the checkpoint for the same schedule: iterations 7.. of a 6 + 6 run
+    run.main(common + ["--jsonl", str(second), "--resume", str(ck)])
+    more = [json.loads(l) for l in open(second)]
+    assert [r["iteration"] for r in more] == list(range(7, 13))
