@@ -76,7 +76,7 @@ struct Layout {
   std::vector<int3> groups;  // (C2, first item, item count) of the log-likelihood pass
   size_t total = 0;
   // byte offsets
-  size_t o_posts, o_ps, o_xab, o_xbf, o_theta, o_grad, o_theta_t, o_p_t, o_grad_t;
+  size_t o_posts, o_ps, o_xab, o_xbf, o_theta, o_grad, o_theta_t, o_p_t, o_grad_t, o_theta_n;
   size_t o_logpi, o_logpi_t, o_logw, o_h, o_l, o_H0, o_dH, o_alpha, o_ca, o_cg;
   size_t o_n, o_perm, o_active, o_anc, o_acc, o_cdf, o_gpart, o_llpart;
   size_t o_redp = 0, o_redc = 0, o_sortc = 0;
@@ -357,6 +357,7 @@ void plan(const smc_problem *pr, const smc_params *pa, Layout &L) {
   L.o_theta = take(c, st);
   L.o_grad = take(c, st);
   L.o_theta_t = take(c, st);
+  L.o_theta_n = take(c, st);
   L.o_p_t = take(c, st);
   L.o_grad_t = take(c, st);
   L.o_logpi = take(c, rows * 8);
@@ -545,6 +546,7 @@ smc_status smc_init(const smc_problem *prob, const smc_params *par, void *worksp
   D.theta = (float *)(w + L.o_theta);
   D.grad = (float *)(w + L.o_grad);
   D.theta_t = (float *)(w + L.o_theta_t);
+  D.theta_n = (float *)(w + L.o_theta_n);
   D.p_t = (float *)(w + L.o_p_t);
   D.grad_t = (float *)(w + L.o_grad_t);
   D.logpi = (double *)(w + L.o_logpi);

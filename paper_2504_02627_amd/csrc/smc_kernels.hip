@@ -539,19 +539,27 @@ __global__ __launch_bounds__(WG, 2 * lf_groups_per_cu(false, C2)) void k_lf_part
   const float4 *xab = reinterpret_cast<const float4 *>(D.xab + P.xab);
   stage_issue<C2>(xs[0], xab, t0, t1, wave, lane);
 
-  // theta' of this wave's particles in the B-operand layout of GEMM1
+  // theta' of this wave's particles in the B-operand layout of GEMM1: after
+  // the first step of the split path the previous reduction has written it
+  // (the same arithmetic), so one array is read instead of three
   float th[SUB][K1];
+  const bool given = !FIN && s > 0 && !zero_eps;
 #pragma unroll
   for (int sb = 0; sb < SUB; ++sb) {
     const int slot = pl.tile * TJ + (wave * SUB + sb) * 16 + (lane & 15);
     const long long base = (long long)(P.row0 + perm[slot]) * D.DS + kq * K1;
+    if (given) {
 #pragma unroll
-    for (int c = 0; c < K1; ++c) {
-      const float t0 = D.theta_t[base + c], p0 = D.p_t[base + c], g0 = D.grad_t[base + c];
-      const float ph = fmaf(he, g0, p0);
-      // eps = 0 (gradient at the given theta): t0 + 0 * ph = t0 for finite ph;
-      // written without a select, which costs this kernel its schedule
-      th[sb][c] = fmaf(eps * minv[kq * K1 + c], ph, t0);
+      for (int c = 0; c < K1; ++c) th[sb][c] = D.theta_n[base + c];
+    } else {
+#pragma unroll
+      for (int c = 0; c < K1; ++c) {
+        const float t0 = D.theta_t[base + c], p0 = D.p_t[base + c], g0 = D.grad_t[base + c];
+        const float ph = fmaf(he, g0, p0);
+        // eps = 0 (gradient at the given theta): t0 + 0 * ph = t0 for finite
+        // ph; written without a select, which costs this kernel its schedule
+        th[sb][c] = fmaf(eps * minv[kq * K1 + c], ph, t0);
+      }
     }
   }
 
@@ -940,14 +948,19 @@ __global__ __launch_bounds__(WG) void k_lf_partial_bf16(Dev D, int s, int zero_e
   {
     const int slot = pl.tile * TJ + wave * 16 + (lane & 15);
     const long long base = (long long)(P.row0 + perm[slot]) * D.DS;
+    const bool given = !FIN && s > 0 && !zero_eps;  // written by the previous reduction
 #pragma unroll
     for (int c = 0; c < KC; ++c) {
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const int k = 32 * c + 8 * g + e;
-        const float t0 = D.theta_t[base + k], p0 = D.p_t[base + k], g0 = D.grad_t[base + k];
-        const float ph = fmaf(he, g0, p0);
-        thb[c][e] = (__bf16)fmaf(eps * minv[k], ph, t0);
+        if (given) {
+          thb[c][e] = (__bf16)D.theta_n[base + k];
+        } else {
+          const float t0 = D.theta_t[base + k], p0 = D.p_t[base + k], g0 = D.grad_t[base + k];
+          const float ph = fmaf(he, g0, p0);
+          thb[c][e] = (__bf16)fmaf(eps * minv[k], ph, t0);
+        }
       }
     }
   }
@@ -1083,6 +1096,15 @@ __global__ __launch_bounds__(RED_THREADS) void k_lf_reduce(Dev D, int s, int zer
   reinterpret_cast<float4 *>(D.theta_t)[e] = th1;
   reinterpret_cast<float4 *>(D.p_t)[e] = pn;
   reinterpret_cast<float4 *>(D.grad_t)[e] = gn;
+  if (!zero_eps) {
+    // theta' of the next step from the state just written, exactly as the
+    // leapfrog prologue would form it
+    float4 tn;
+#define LF_NEXT(c) tn.c = fmaf(eps * mv.c, fmaf(he, gn.c, pn.c), th1.c);
+    LF_NEXT(x) LF_NEXT(y) LF_NEXT(z) LF_NEXT(w)
+#undef LF_NEXT
+    reinterpret_cast<float4 *>(D.theta_n)[e] = tn;
+  }
 }
 
 template <int C2>
