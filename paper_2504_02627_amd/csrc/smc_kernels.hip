@@ -948,19 +948,16 @@ __global__ __launch_bounds__(WG) void k_lf_partial_bf16(Dev D, int s, int zero_e
   {
     const int slot = pl.tile * TJ + wave * 16 + (lane & 15);
     const long long base = (long long)(P.row0 + perm[slot]) * D.DS;
-    const bool given = !FIN && s > 0 && !zero_eps;  // written by the previous reduction
+    // (reading the reduction's theta' here instead measured slower: the
+    // loop's register allocation and schedule changed)
 #pragma unroll
     for (int c = 0; c < KC; ++c) {
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const int k = 32 * c + 8 * g + e;
-        if (given) {
-          thb[c][e] = (__bf16)D.theta_n[base + k];
-        } else {
-          const float t0 = D.theta_t[base + k], p0 = D.p_t[base + k], g0 = D.grad_t[base + k];
-          const float ph = fmaf(he, g0, p0);
-          thb[c][e] = (__bf16)fmaf(eps * minv[k], ph, t0);
-        }
+        const float t0 = D.theta_t[base + k], p0 = D.p_t[base + k], g0 = D.grad_t[base + k];
+        const float ph = fmaf(he, g0, p0);
+        thb[c][e] = (__bf16)fmaf(eps * minv[k], ph, t0);
       }
     }
   }
