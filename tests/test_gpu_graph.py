@@ -13,11 +13,15 @@ from tests._gpu_common import log, to_dev
 pytestmark = pytest.mark.gpu
 
 
+def _host(t):
+    ts = t if isinstance(t, (list, tuple)) else [t]
+    return np.concatenate([x.cpu().numpy().ravel() for x in ts])
+
+
 def _snap(s):
     theta, logw, logpi = s.state()
-    ts = theta if not isinstance(theta, list) else theta[0]
-    return (ts.cpu().numpy().copy(), logw.cpu().numpy().copy(), logpi.cpu().numpy().copy(),
-            s.counters()["grad_evals"], s.log_evidence())
+    return (_host(theta), _host(logw), _host(logpi), s.counters()["grad_evals"],
+            s.log_evidence())
 
 
 def _same(a, b):
@@ -55,6 +59,34 @@ def test_graph_replays_match_eager(precision, precond):
         graph.adapt()
         _same(_snap(eager), _snap(graph))
         log(f"  replay {rep}: {k} iterations identical; ESS {st['ess']:.1f}")
+    eager.close()
+    graph.close()
+
+
+@pytest.mark.parametrize("shapes,J", [([(200, 5)], 2048),                       # one launch per iteration
+                                      ([(300, 5), (800, 40), (500, 17), (1200, 70)], 256)])  # group lanes
+def test_graph_replays_match_eager_other_launch_shapes(shapes, J):
+    # whole trajectories in one launch, and a batched context whose feature-tile
+    # groups run on forked stream lanes (graph edges under capture)
+    import torch
+    from paper_2504_02627_amd import chees
+    data = [synth.logistic_iid(N, d, 50 + i) for i, (N, d) in enumerate(shapes)]
+    Xs = [to_dev(X) for X, _, _ in data]
+    ys = [to_dev(y) for _, y, _ in data]
+    eps = min(synth.default_step_size(N, d) for N, d in shapes)
+    kw = dict(step_size=eps, traj_length=eps * 20, max_leapfrog=40, num_warmup=4, seed=3,
+              adapt_step_size=True)
+    one = len(shapes) == 1
+    log(f"[graph] shapes={shapes} J={J}")
+    mk = lambda: chees.Sampler(Xs[0] if one else Xs, ys[0] if one else ys, J, **kw)
+    eager, graph = mk(), mk()
+    for k in (2, 3):
+        for _ in range(k):
+            eager.step(stats=False)
+            eager.adapt(stats=False)
+        graph.run(k)
+        torch.cuda.synchronize()
+        _same(_snap(eager), _snap(graph))
     eager.close()
     graph.close()
 
