@@ -193,10 +193,10 @@ __host__ __device__ constexpr int lf_groups_per_cu(bool bf16, int c2) {
   return (!bf16 && c2 <= 8) ? 2 : 1;
 }
 
-// uint4 per lane and 32-row tile in the BF16 packing: [A: 2 KC | B: C2 | y: 2] (+1 if even)
+// uint4 per lane and 32-row tile in the BF16 packing: [A: 2 KC | B: C2 | y: 1] (+1 if even)
 __host__ __device__ constexpr int bf16_lane_stride(int c2) {
-  return ((2 * ((c2 + 1) / 2) + c2 + 2) % 2 == 0) ? 2 * ((c2 + 1) / 2) + c2 + 3
-                                                   : 2 * ((c2 + 1) / 2) + c2 + 2;
+  return ((2 * ((c2 + 1) / 2) + c2 + 1) % 2 == 0) ? 2 * ((c2 + 1) / 2) + c2 + 2
+                                                   : 2 * ((c2 + 1) / 2) + c2 + 1;
 }
 hipError_t fill_f32(float *p, long long n, float v, hipStream_t st);
 hipError_t fill_i32(int *p, long long n, int v, hipStream_t st);

@@ -138,7 +138,9 @@ hipError_t launch_pack_one(const Dev &D, const void *X, const float *y, int x_dt
 //   B, feature tile ct < C2:          X[n_e][16ct + l%16], with n_e = 32T +
 //        4(l/16) + e for e < 4 and 32T + 16 + 4(l/16) + e - 4 for e >= 4 (the
 //        rows whose residuals the lane holds after GEMM1 on the two halves);
-//   y, half h: y[32T + 16h + 4(l/16) + i], i < 4 (1/2 beyond N);
+//   y: one slot of eight bfloat16 labels, element e = 4h + i holding
+//        y[32T + 16h + 4(l/16) + i] (1/2 beyond N; 0, 1 and 1/2 are exact), so
+//        the tile loop reads them with one 16-byte LDS read;
 //   a zero pad slot when the count is even (odd lane stride: no LDS bank
 //   conflicts).  Values are rounded to bfloat16 to nearest even.
 // ---------------------------------------------------------------------------
@@ -183,12 +185,13 @@ __global__ void k_pack_bf16(const T *__restrict__ X, const float *__restrict__ y
         v[e] = (n < N && k < d) ? to_bf16<T>(X[(long long)n * d + k]) : (uint16_t)0;
       }
       for (int q = 0; q < 4; ++q) w[q] = (uint32_t)v[2 * q] | ((uint32_t)v[2 * q + 1] << 16);
-    } else if (slot < 2 * KC + C2 + 2) {
-      const int h = slot - 2 * KC - C2;
-      for (int i = 0; i < 4; ++i) {
-        const int n = 32 * tl + 16 * h + 4 * g + i;
-        w[i] = __float_as_uint(n < N ? y[n] : 0.5f);
+    } else if (slot == 2 * KC + C2) {
+      uint16_t v[8];
+      for (int e = 0; e < 8; ++e) {
+        const int n = 32 * tl + 16 * (e >> 2) + 4 * g + (e & 3);
+        v[e] = bf16_rne(n < N ? y[n] : 0.5f);
       }
+      for (int q = 0; q < 4; ++q) w[q] = (uint32_t)v[2 * q] | ((uint32_t)v[2 * q + 1] << 16);
     }
     xbf[idx] = make_uint4(w[0], w[1], w[2], w[3]);
   }
@@ -981,16 +984,17 @@ __global__ __launch_bounds__(WG) void k_lf_partial_bf16(Dev D, int s, int zero_e
         z0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_v8bf(xl[c]), thb[c], z0, 0, 0, 0);
         z1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_v8bf(xl[KC + c]), thb[c], z1, 0, 0, 0);
       }
-      const uint4 yu0 = xl[2 * KC + C2], yu1 = xl[2 * KC + C2 + 1];
+      // the eight labels, bfloat16 pairs (exact) in one 16-byte read
+      const uint4 yu = xl[2 * KC + C2];
       v8bf ra;
-      ra[0] = (__bf16)(__uint_as_float(yu0.x) - sigmoidf_fast(z0[0]));
-      ra[1] = (__bf16)(__uint_as_float(yu0.y) - sigmoidf_fast(z0[1]));
-      ra[2] = (__bf16)(__uint_as_float(yu0.z) - sigmoidf_fast(z0[2]));
-      ra[3] = (__bf16)(__uint_as_float(yu0.w) - sigmoidf_fast(z0[3]));
-      ra[4] = (__bf16)(__uint_as_float(yu1.x) - sigmoidf_fast(z1[0]));
-      ra[5] = (__bf16)(__uint_as_float(yu1.y) - sigmoidf_fast(z1[1]));
-      ra[6] = (__bf16)(__uint_as_float(yu1.z) - sigmoidf_fast(z1[2]));
-      ra[7] = (__bf16)(__uint_as_float(yu1.w) - sigmoidf_fast(z1[3]));
+      ra[0] = (__bf16)(__uint_as_float(yu.x << 16) - sigmoidf_fast(z0[0]));
+      ra[1] = (__bf16)(__uint_as_float(yu.x & 0xffff0000u) - sigmoidf_fast(z0[1]));
+      ra[2] = (__bf16)(__uint_as_float(yu.y << 16) - sigmoidf_fast(z0[2]));
+      ra[3] = (__bf16)(__uint_as_float(yu.y & 0xffff0000u) - sigmoidf_fast(z0[3]));
+      ra[4] = (__bf16)(__uint_as_float(yu.z << 16) - sigmoidf_fast(z1[0]));
+      ra[5] = (__bf16)(__uint_as_float(yu.z & 0xffff0000u) - sigmoidf_fast(z1[1]));
+      ra[6] = (__bf16)(__uint_as_float(yu.w << 16) - sigmoidf_fast(z1[2]));
+      ra[7] = (__bf16)(__uint_as_float(yu.w & 0xffff0000u) - sigmoidf_fast(z1[3]));
 #pragma unroll
       for (int ct = 0; ct < C2; ++ct)
         gacc[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ra, as_v8bf(xl[2 * KC + ct]), gacc[ct], 0, 0, 0);
