@@ -337,8 +337,10 @@ def main():
     if args.gpus != 1 or world != 1:
         if int(os.environ.get("RANK", "0")) == 0:
             print(f"bench.py measures one GPU only: the sampler runs on a single MI355X "
-                  f"(asked for --gpus {args.gpus}, WORLD_SIZE {world}); see DESIGN.md for "
-                  f"how the path would shard.", file=sys.stderr)
+                  f"(asked for --gpus {args.gpus}, WORLD_SIZE {world}); particles would "
+                  f"shard across GPUs with a few FP64 all-reduces per iteration and a "
+                  f"particle exchange at resampling; only the single-GPU path is implemented.",
+                  file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
