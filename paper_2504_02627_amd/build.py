@@ -40,5 +40,32 @@ def build(verbose=False):
     return LIB
 
 
+def build_sanitized(out):
+    """The same library with the host code under AddressSanitizer and
+    UndefinedBehaviorSanitizer (device code unchanged), for CPU tests of the
+    validation and planning paths.  Load it with the ASan runtime preloaded
+    (sanitizer_runtime())."""
+    flags = [f for f in HIPCC_FLAGS if f != "-O3"] + [
+        "-O1", "-g",
+        "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+        "-Xarch_host", "-fno-omit-frame-pointer",
+    ]
+    cmd = [hipcc()] + flags + ["-I", os.path.join(ROOT, "include"),
+                               "-I", os.path.join(HERE, "csrc")] + SOURCES + ["-o", str(out)]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("hipcc failed:\n" + r.stdout + r.stderr)
+    return str(out)
+
+
+def sanitizer_runtime():
+    """Path of the compiler's AddressSanitizer runtime, or None."""
+    import glob
+    base = os.path.join(os.path.dirname(os.path.dirname(hipcc())) if os.path.isabs(hipcc())
+                        else "/opt/rocm", "llvm", "lib", "clang")
+    hits = sorted(glob.glob(os.path.join(base, "*", "lib", "linux", "libclang_rt.asan-x86_64.so")))
+    return hits[-1] if hits else None
+
+
 if __name__ == "__main__":
     print(build(verbose="-v" in sys.argv))
