@@ -1429,6 +1429,31 @@ __device__ int upper_search(const unsigned long long *C, int J, unsigned __int12
   return lo;
 }
 
+// The same search in two levels: idx[b] = C[min(J, (b + 1) s) - 1], the last
+// entry of each block of s entries (in LDS), is searched first, then the one
+// block of C whose last entry passes (C is non-decreasing, so the answer lies
+// in the first such block).  Requires C[J - 1] * scale > lhs_num.
+__device__ int upper_search2(const unsigned long long *C, const unsigned long long *idx, int J,
+                             int s, int nb, unsigned __int128 lhs_num, unsigned long long scale) {
+  int lo = 0, hi = nb - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if ((unsigned __int128)idx[mid] * scale > lhs_num)
+      hi = mid;
+    else
+      lo = mid + 1;
+  }
+  int jl = lo * s, jh = min(J, (lo + 1) * s) - 1;
+  while (jl < jh) {
+    const int mid = (jl + jh) >> 1;
+    if ((unsigned __int128)C[mid] * scale > lhs_num)
+      jh = mid;
+    else
+      jl = mid + 1;
+  }
+  return jl;
+}
+
 __device__ void quantise_scan(const double *lw, double m, int J, unsigned long long *cdf,
                               unsigned long long *sh) {
   // each thread takes a contiguous chunk; chunk sums are scanned in LDS
@@ -1487,22 +1512,28 @@ __global__ __launch_bounds__(1024) void k_begin_step(Dev D, int conditional, con
   unsigned long long *cdf = D.cdf + P.row0;
   quantise_scan(D.logw + P.row0, S.m, J, cdf, sh);
   const unsigned long long T = cdf[J - 1];
+  // search index in LDS (the scan buffer, free again): the last entry of
+  // every block of bs entries, at most 1024 blocks
+  const int bs = (J + 1023) / 1024, nb = (J + bs - 1) / bs;
+  for (int q = t; q < nb; q += blockDim.x) sh[q] = cdf[min(J, (q + 1) * bs) - 1];
+  __syncthreads();
   const int chunk = (J + blockDim.x - 1) / blockDim.x;
   const int i0 = min(J, t * chunk), i1 = min(J, i0 + chunk);
+  // every target below is < C[J - 1] * scale, so each search has an answer
   if (D.resampling == 0) {
     const double u0 = u ? u[b] : u01(philox_at(D.seed, 0, (uint32_t)b, (uint32_t)k, STREAM_RESAMPLE).x);
     const unsigned long long U = u_to_u32(u0);
     const unsigned long long scale = (unsigned long long)J << 32;
     for (int i = i0; i < i1; ++i) {
       const unsigned __int128 lhs = (unsigned __int128)(((unsigned long long)i << 32) + U) * T;
-      D.anc[P.row0 + i] = upper_search(cdf, J, lhs, scale);
+      D.anc[P.row0 + i] = upper_search2(cdf, sh, J, bs, nb, lhs, scale);
     }
   } else {
     for (int i = i0; i < i1; ++i) {
       const double ui = u ? u[(long long)b * J + i]
                           : u01(philox_at(D.seed, 0, (uint32_t)(b * J + i), (uint32_t)k, STREAM_RESAMPLE).x);
       const unsigned __int128 lhs = (unsigned __int128)u_to_u32(ui) * T;
-      D.anc[P.row0 + i] = upper_search(cdf, J, lhs, 4294967296ull);
+      D.anc[P.row0 + i] = upper_search2(cdf, sh, J, bs, nb, lhs, 4294967296ull);
     }
   }
   if (t == 0) {
