@@ -298,11 +298,12 @@ __global__ void k_flow_adam(Dev D, FlowNet F, int step, int update, const float 
 // theta - m -> x via L^-1, with u_c = x_q(c)) and log|det L|.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_flow_cov(Dev D, FlowNet F) {
-  // one 16 x 16 tile of C per block; 64 particles staged at a time
+  // one 16 x 16 tile of C and one of FCOV_CH particle chunks per block (its
+  // partial sum goes to its own slice); 64 particles staged at a time
   __shared__ double Xa[64][17], Xb[64][17];
   __shared__ double Wc[64];
   const int d = F.d, nt = (d + 15) / 16;
-  const int ta = blockIdx.x / nt, tb = blockIdx.x % nt;
+  const int ta = blockIdx.x / nt, tb = blockIdx.x % nt, ch = blockIdx.y;
   if (tb > ta) return;  // lower triangle of tiles
   const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
   const int c = 16 * ta + ty, k = 16 * tb + tx;
@@ -310,18 +311,20 @@ __global__ __launch_bounds__(256) void k_flow_cov(Dev D, FlowNet F) {
   const int rs = PS.resampled;
   const float *src = rs ? D.theta_t : D.theta;
   const double *mean = D.means;
+  const int per = ((D.J + FCOV_CH - 1) / FCOV_CH + 63) / 64 * 64;
+  const int jb = ch * per, je = min(D.J, jb + per);
   double acc = 0.0;
-  for (int j0 = 0; j0 < D.J; j0 += 64) {
+  for (int j0 = jb; j0 < je; j0 += 64) {
     for (int i = threadIdx.x; i < 64 * 16; i += 256) {
       const int jj = i >> 4, cc = i & 15, j = j0 + jj;
       const int ca = 16 * ta + cc, cb = 16 * tb + cc;
-      Xa[jj][cc] = (j < D.J && ca < d) ? (double)src[(long long)j * D.DS + ca] - mean[ca] : 0.0;
-      Xb[jj][cc] = (j < D.J && cb < d) ? (double)src[(long long)j * D.DS + cb] - mean[cb] : 0.0;
+      Xa[jj][cc] = (j < je && ca < d) ? (double)src[(long long)j * D.DS + ca] - mean[ca] : 0.0;
+      Xb[jj][cc] = (j < je && cb < d) ? (double)src[(long long)j * D.DS + cb] - mean[cb] : 0.0;
     }
     if (threadIdx.x < 64) {
       const int j = j0 + threadIdx.x;
       double w = 0.0;
-      if (j < D.J) {
+      if (j < je) {
         const double lw = D.logw[j];
         w = rs ? 1.0 / D.J : ((lw == lw && lw > -INFINITY) ? exp(lw - PS.m) / PS.S : 0.0);
       }
@@ -332,9 +335,17 @@ __global__ __launch_bounds__(256) void k_flow_cov(Dev D, FlowNet F) {
     __syncthreads();
   }
   if (c < d && k < d) {
-    D.fcov[(long long)c * d + k] = acc;
-    D.fcov[(long long)k * d + c] = acc;
+    double *out = D.fcov + (long long)ch * d * d;
+    out[(long long)c * d + k] = acc;
+    out[(long long)k * d + c] = acc;
   }
+}
+
+// C = sum of the chunk partials in chunk order, shrunk: n/(n+5) C + 1e-3 5/(n+5) I.
+__device__ __forceinline__ double flow_shrunk_cov(const Dev &D, int d, int i, double sc, double sh) {
+  double v = 0.0;
+  for (int ch = 0; ch < FCOV_CH; ++ch) v += D.fcov[(long long)ch * d * d + i];
+  return sc * v + ((i / d == i % d) ? sh : 0.0);
 }
 
 __global__ __launch_bounds__(256) void k_flow_chol(Dev D, FlowNet F) {
@@ -342,7 +353,7 @@ __global__ __launch_bounds__(256) void k_flow_chol(Dev D, FlowNet F) {
   double *A = D.fLd, *X = D.fLi;
   const double n = D.ps[0].ess_before;
   const double sc = n / (n + 5.0), sh = 1e-3 * (5.0 / (n + 5.0));
-  for (int i = tid; i < d * d; i += 256) A[i] = sc * D.fcov[i] + ((i / d == i % d) ? sh : 0.0);
+  for (int i = tid; i < d * d; i += 256) A[i] = flow_shrunk_cov(D, d, i, sc, sh);
   __syncthreads();
   // right-looking Cholesky, lower triangle in place
   for (int k = 0; k < d; ++k) {
@@ -381,6 +392,71 @@ __global__ __launch_bounds__(256) void k_flow_chol(Dev D, FlowNet F) {
     D.fAi[pk_index(xpos(c, d), k, K16)] = li;         // x_q(c) = (L^-1 (theta - m))_c
   }
   for (int c = tid; c < D.DS; c += 256) D.fm[c] = c < d ? (float)D.means[c] : 0.f;
+  if (tid == 0) {
+    double s = 0.0;
+    for (int c = 0; c < d; ++c) s += log(A[(long long)c * d + c]);
+    D.fbase[0] = (float)s;
+  }
+}
+
+// The same for d <= FCHOL_LDS in one 1024-thread work group with the matrix
+// in LDS.  Cholesky: right-looking, the same operations in the same order as
+// k_flow_chol (pivot k: scale column k by sqrt(C_kk), then the trailing
+// lower triangle loses the outer product of that column).  L^-1: by pivots
+// too, so that every pivot updates all later rows at once: pivot q finishes
+// row q of X = L^-1 (X_qj = acc_qj / L_qq, X_qq = 1 / L_qq), then every row
+// r > q takes acc_rj -= L_rq X_qj for j <= q.  Each X_ij thus comes from
+// delta_ij - sum_{q=j}^{i-1} L_iq X_qj summed in the same order as the
+// column-by-column form above; column q of L is staged before acc_rq
+// overwrites it.  Trailing updates run on a 32 x 32 thread grid.
+constexpr int FCHOL_LDS = 128;
+
+__global__ __launch_bounds__(1024) void k_flow_chol_lds(Dev D, FlowNet F) {
+  __shared__ double M[FCHOL_LDS * FCHOL_LDS];
+  __shared__ double Lc[2][FCHOL_LDS];
+  const int d = F.d, tid = threadIdx.x, nt = blockDim.x;
+  const int tr = tid >> 5, tc = tid & 31;
+  const double n = D.ps[0].ess_before;
+  const double sc = n / (n + 5.0), sh = 1e-3 * (5.0 / (n + 5.0));
+  for (int i = tid; i < d * d; i += nt) M[i] = flow_shrunk_cov(D, d, i, sc, sh);
+  __syncthreads();
+  for (int k = 0; k < d; ++k) {
+    const double lkk = sqrt(M[k * d + k]);
+    for (int i = k + 1 + tid; i < d; i += nt) M[i * d + k] /= lkk;
+    __syncthreads();
+    if (tid == 0) M[k * d + k] = lkk;  // not read by this phase
+    for (int i = k + 1 + tr; i < d; i += 32)
+      for (int j = k + 1 + tc; j <= i; j += 32) M[i * d + j] -= M[i * d + k] * M[j * d + k];
+    __syncthreads();
+  }
+  double *A = D.fLd;
+  for (int e = tid; e < d * d; e += nt) A[e] = M[e];
+  for (int r = tid; r < d; r += nt) Lc[0][r] = M[r * d];
+  __syncthreads();
+  for (int q = 0; q < d; ++q) {
+    const double *lc = Lc[q & 1];
+    for (int j = tid; j <= q; j += nt) M[q * d + j] = (j == q ? 1.0 : M[q * d + j]) / lc[q];
+    // column q + 1 of L (rows >= q + 1) is untouched so far
+    for (int r = q + 1 + tid; r < d; r += nt) Lc[(q + 1) & 1][r] = M[r * d + q + 1];
+    __syncthreads();
+    for (int r = q + 1 + tr; r < d; r += 32)
+      for (int j = tc; j <= q; j += 32) {
+        const double v = (j == q) ? 0.0 : M[r * d + j];
+        M[r * d + j] = v - lc[r] * M[q * d + j];
+      }
+    __syncthreads();
+  }
+  const int K16 = (d + 15) / 16 * 16;
+  for (int e = tid; e < d * d; e += nt) {
+    const int c = e / d, k = e % d;
+    const float l = k <= c ? (float)A[e] : 0.f;
+    const float li = k <= c ? (float)M[e] : 0.f;
+    D.fL[e] = l;
+    D.fAf[pk_index(c, xpos(k, d), K16)] = l;          // theta - m = L u, u_k = x_q(k)
+    D.fAb[pk_index(xpos(k, d), c, K16)] = l;          // cotangent of x: L^T g
+    D.fAi[pk_index(xpos(c, d), k, K16)] = li;         // x_q(c) = (L^-1 (theta - m))_c
+  }
+  for (int c = tid; c < D.DS; c += nt) D.fm[c] = c < d ? (float)D.means[c] : 0.f;
   if (tid == 0) {
     double s = 0.0;
     for (int c = 0; c < d; ++c) s += log(A[(long long)c * d + c]);
@@ -804,8 +880,11 @@ hipError_t launch_flow_publish(const Dev &D, const FlowNet &F, hipStream_t st) {
 
 hipError_t launch_flow_base(const Dev &D, const FlowNet &F, hipStream_t st) {
   const int nt = (F.d + 15) / 16;
-  hipLaunchKernelGGL(k_flow_cov, dim3(nt * nt), dim3(256), 0, st, D, F);
-  hipLaunchKernelGGL(k_flow_chol, dim3(1), dim3(256), 0, st, D, F);
+  hipLaunchKernelGGL(k_flow_cov, dim3(nt * nt, FCOV_CH), dim3(256), 0, st, D, F);
+  if (F.d <= FCHOL_LDS)
+    hipLaunchKernelGGL(k_flow_chol_lds, dim3(1), dim3(1024), 0, st, D, F);
+  else
+    hipLaunchKernelGGL(k_flow_chol, dim3(1), dim3(256), 0, st, D, F);
   return hipGetLastError();
 }
 

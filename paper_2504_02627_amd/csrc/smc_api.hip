@@ -420,7 +420,7 @@ void plan(const smc_problem *pr, const smc_params *pa, Layout &L) {
     L.o_fAf = take(c, d16 * d16 * 4);
     L.o_fAb = take(c, d16 * d16 * 4);
     L.o_fAi = take(c, d16 * d16 * 4);
-    L.o_fcov = take(c, dd * 8);
+    L.o_fcov = take(c, (size_t)FCOV_CH * dd * 8);
     L.o_fLd = take(c, dd * 8);
     L.o_fLi = take(c, dd * 8);
     L.o_fbase = take(c, 256);

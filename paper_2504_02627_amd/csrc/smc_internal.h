@@ -18,6 +18,8 @@ constexpr int WG = 64 * WAVES;
 constexpr int TRAJ_WAVES = 4;
 // blocks per posterior of the FP64 population reductions (ESS, ChEES sums)
 constexpr int RED_G = 32;
+// particle chunks of the flow's weighted covariance (partials summed in order)
+constexpr int FCOV_CH = 8;
 constexpr size_t TRAJ_LDS_MAX = 65536;  // LDS of one work group
 constexpr int MAX_C2 = 13;          // d <= 16 * 13 = 208
 constexpr int MAX_NMAX = 4096;      // cap on max_leapfrog
@@ -164,7 +166,8 @@ struct Dev {                    // pointers carved from the workspace
   float *fm;                    // base map theta = m + L u: m [DS]
   float *fL;                    // L, row-major d x d
   float *fAf, *fAb, *fAi;       // packed base products: L P^T, P L^T, P L^-1
-  double *fcov, *fLd, *fLi;     // weighted covariance, Cholesky factor, inverse (FP64)
+  double *fcov, *fLd, *fLi;     // weighted covariance [FCOV_CH][d][d] (partials over
+                                // particle chunks), Cholesky factor, inverse (FP64)
   float *fbase;                 // [0]: log|det L|
   float *fp;                    // FP32 parameters (flat)
   float *fpk, *fbk;             // packed weights (and transposes): FP32, bfloat16-rounded
