@@ -78,7 +78,10 @@ def _blocks_close(dev, ref, d, what, rtol=1e-4):
 
 
 @pytest.mark.parametrize("N,d,J,seed,layers", [(500, 12, 256, 5, LAYERS), (800, 37, 130, 6, LAYERS),
-                                               (500, 12, 256, 7, 0)])
+                                               (500, 12, 256, 7, 0),
+                                               # the base map's factorisation in LDS up to
+                                               # d = 128, in global memory above
+                                               (600, 128, 256, 8, 0), (600, 150, 200, 9, 0)])
 def test_flow_iteration_parity(N, d, J, seed, layers):
     """Two iterations with one Adam step each (the fit is warm-started), no
     resampling, so that the weighted objective sees the population's own
