@@ -74,6 +74,111 @@ struct BlockLDS {
 
 enum { ST_PLAIN = 0, ST_TANH = 1, ST_DTANH = 2, ST_ADD = 3 };
 
+// Epilogue of one 16-row output tile t (accumulator acc, tape quad axq, the
+// lane's four biases bq).
+__device__ __forceinline__ void mdense_out(int t, const v4f &acc, const float4 &axq,
+                                           const float *bq, int M, const float *bias, float *out,
+                                           int outs, int mode, float *tp, const float *ax, int pn,
+                                           int kq) {
+  const int u0 = 16 * t + 4 * kq;
+  const bool quad = u0 + 3 < M;
+  const float axv[4] = {axq.x, axq.y, axq.z, axq.w};
+  float vq[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int u = u0 + i;
+    vq[i] = 0.f;
+    if (u >= M) continue;
+    float v = acc[i];
+    if (bias) v += bq[i];
+    if (mode == ST_TANH) {
+      v = tanhf(v);
+    } else if (mode == ST_DTANH) {
+      const float h = quad ? axv[i] : ax[u];
+      v *= 1.f - h * h;
+    }
+    if (mode == ST_ADD)
+      out[pn * outs + u] += v;
+    else
+      out[pn * outs + u] = v;
+    vq[i] = v;
+  }
+  if (tp) {
+    if (quad) {
+      *reinterpret_cast<float4 *>(tp + u0) = make_float4(vq[0], vq[1], vq[2], vq[3]);
+    } else {
+      for (int i = 0; i < 4; ++i)
+        if (u0 + i < M) tp[u0 + i] = vq[i];
+    }
+  }
+}
+
+// NTL (1 or 2) output tiles t, t + NT / 64 of one wave in one pass: the
+// tiles' MFMA chains interleave and share the B operand read from LDS; each
+// tile's MFMAs run in the same order as alone.  A chunks are loaded four at a
+// time so that a group's loads are in flight together, and the biases and
+// the tape values of ST_DTANH before the MFMAs (at typical populations each
+// SIMD holds one wave, so latency, not the MFMAs, sets the pace).  The lane's outputs u0 .. u0 + 3
+// are consecutive in a tape row; tape rows and offsets are multiples of 4
+// floats, so whole quads move as single 16-byte accesses.
+template <int NTL>
+__device__ __forceinline__ void mdense_tiles(const float *Ap, int t, int M, int C16,
+                                             const float *bias, const float *ip0, float *out,
+                                             int outs, int mode, float *tp, const float *ax,
+                                             int pn, int kq, int lane) {
+  int tt[NTL];
+  float4 axq[NTL];
+  float bq[NTL][4];
+  v4f acc[NTL];
+  const float4 *ap[NTL];
+#pragma unroll
+  for (int g = 0; g < NTL; ++g) {
+    tt[g] = t + g * (NT / 64);
+    const int u0 = 16 * tt[g] + 4 * kq;
+    axq[g] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (ax && u0 + 3 < M) axq[g] = *reinterpret_cast<const float4 *>(ax + u0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) bq[g][i] = (bias && u0 + i < M) ? bias[u0 + i] : 0.f;
+    acc[g] = v4f{0.f, 0.f, 0.f, 0.f};
+    ap[g] = reinterpret_cast<const float4 *>(Ap) + (long long)tt[g] * C16 * 64 + lane;
+  }
+  int c = 0;
+  for (; c + 4 <= C16; c += 4) {
+    float4 a[NTL][4];
+#pragma unroll
+    for (int g = 0; g < NTL; ++g)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a[g][u] = ap[g][(c + u) * 64];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const float *ip = ip0 + 16 * (c + u);
+      const float b0 = ip[0], b1 = ip[4], b2 = ip[8], b3 = ip[12];
+#pragma unroll
+      for (int g = 0; g < NTL; ++g) {
+        acc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[g][u].x, b0, acc[g], 0, 0, 0);
+        acc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[g][u].y, b1, acc[g], 0, 0, 0);
+        acc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[g][u].z, b2, acc[g], 0, 0, 0);
+        acc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[g][u].w, b3, acc[g], 0, 0, 0);
+      }
+    }
+  }
+  for (; c < C16; ++c) {
+    const float *ip = ip0 + 16 * c;
+    const float b0 = ip[0], b1 = ip[4], b2 = ip[8], b3 = ip[12];
+#pragma unroll
+    for (int g = 0; g < NTL; ++g) {
+      const float4 a = ap[g][c * 64];
+      acc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b0, acc[g], 0, 0, 0);
+      acc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b1, acc[g], 0, 0, 0);
+      acc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b2, acc[g], 0, 0, 0);
+      acc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b3, acc[g], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int g = 0; g < NTL; ++g)
+    mdense_out(tt[g], acc[g], axq[g], bq[g], M, bias, out, outs, mode, tp, ax, pn, kq);
+}
+
 // One dense layer for the block's 16 particles:
 //   v[p][u] = sum_k A[u][k] in[p][k] (+ bias[u]),  u < M, k < K,
 // then out[p][u] = v (ST_PLAIN), tanh(v) (ST_TANH), v (1 - aux[u]^2)
@@ -88,35 +193,15 @@ __device__ void mdense(const float *Ap, int M, int K, const float *bias, const f
   const float *ip0 = in + pn * ins + kq;
   float *tp = (toff >= 0 && S.tw[pn]) ? S.tw[pn] + toff : nullptr;
   const float *ax = mode == ST_DTANH ? S.tr[pn] + aoff : nullptr;
-  for (int t = wave; t < T; t += NT / 64) {
-    v4f acc = {0.f, 0.f, 0.f, 0.f};
-    const float4 *ap = reinterpret_cast<const float4 *>(Ap) + (long long)t * C16 * 64 + lane;
-    for (int c = 0; c < C16; ++c) {
-      const float4 a = ap[c * 64];
-      const float *ip = ip0 + 16 * c;
-      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, ip[0], acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, ip[4], acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, ip[8], acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, ip[12], acc, 0, 0, 0);
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int u = 16 * t + 4 * kq + i;
-      if (u >= M) continue;
-      float v = acc[i];
-      if (bias) v += bias[u];
-      if (mode == ST_TANH) {
-        v = tanhf(v);
-      } else if (mode == ST_DTANH) {
-        const float h = ax[u];
-        v *= 1.f - h * h;
-      }
-      if (mode == ST_ADD)
-        out[pn * outs + u] += v;
-      else
-        out[pn * outs + u] = v;
-      if (tp) tp[u] = v;
-    }
+  constexpr int NW = NT / 64;
+  // two tiles per pass in the backward layers; the forward layers (tanh
+  // epilogue) measured faster one tile at a time
+  const bool pair = mode == ST_DTANH || mode == ST_ADD;
+  for (int t = wave; t < T; t += (pair ? 2 : 1) * NW) {
+    if (pair && t + NW < T)
+      mdense_tiles<2>(Ap, t, M, C16, bias, ip0, out, outs, mode, tp, ax, pn, kq, lane);
+    else
+      mdense_tiles<1>(Ap, t, M, C16, bias, ip0, out, outs, mode, tp, ax, pn, kq, lane);
   }
 }
 

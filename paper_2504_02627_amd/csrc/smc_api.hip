@@ -128,7 +128,7 @@ bool flow_net(int d, int layers, int width, FlowNet &F) {
     Y.qW3 = q, q += FH * c16(2 * Y.dt);
   }
   F.npacked = q;
-  F.half = (half + 1) / 2 * 2;
+  F.half = (half + 3) / 4 * 4;  // tape rows and offsets stay multiples of 4 floats
   F.tape_stride = 2 * FH + 2 * F.half;
   F.train_stride = 5 * F.half + 4 * FH;
   F.nparams = o;

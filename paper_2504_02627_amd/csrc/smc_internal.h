@@ -52,7 +52,7 @@ struct FlowLayerDesc {
 struct FlowNet {
   int L;                  // coupling layers
   int d;                  // dimension
-  int half;               // max(dt, dc) rounded up to even
+  int half;               // max(dt, dc) rounded up to a multiple of 4
   int tape_stride;        // floats per particle and layer of the move tape
   int train_stride;       // floats per particle and layer of the training record
   int nparams;            // length of the flat parameter vector
