@@ -698,8 +698,17 @@ __global__ __launch_bounds__(256) void k_flow_wgrad(Dev D, FlowNet F, float *par
   const float *base = D.ftape + (long long)l * F.train_stride;
   if (isbias) {
     for (int u = t; u < g.rows; u += blockDim.x) {
+      const float *q = base + g.off_delta + u;
       float s = 0.f;
-      for (int j = ja; j < jb; ++j) s += base[j * stride + g.off_delta + u];
+      int j = ja;
+      for (; j + 8 <= jb; j += 8) {  // eight loads in flight, summed in index order
+        float v[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = q[(j + e) * stride];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) s += v[e];
+      }
+      for (; j < jb; ++j) s += q[j * stride];
       out[g.ob + u] = s;
     }
     return;
@@ -707,29 +716,50 @@ __global__ __launch_bounds__(256) void k_flow_wgrad(Dev D, FlowNet F, float *par
   const int ntc = (g.cols + 63) / 64;
   const int u0 = (tile / ntc) * 64, k0 = (tile % ntc) * 64;
   const int ty = t >> 4, tx = t & 15;
-  float acc[4][4] = {};
-  for (int jj0 = ja; jj0 < jb; jj0 += 32) {
-    // 32 particles x 64 delta rows / 64 input columns
-    for (int idx = t; idx < 32 * 16; idx += 256) {
-      const int jj = idx >> 4, c4 = idx & 15;
-      const int j = jj0 + jj;
-      float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a;
+  // one round: 32 particles x 64 delta rows / 64 input columns, two float4
+  // pairs per thread (tape rows and offsets are multiples of 4 floats); the
+  // next round's loads are issued before this round's FMAs
+  auto fetch = [&](int j0, float4 *a, float4 *b) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int idx = t + 256 * q, jj = idx >> 4, c4 = idx & 15;
+      const int j = j0 + jj;
+      a[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+      b[q] = a[q];
       if (j < jb) {
         const float *r = base + j * stride;
         const int u = u0 + 4 * c4, k = k0 + 4 * c4;
-        float av[4], bv[4];
+        if (u + 3 < g.rows) {
+          a[q] = *reinterpret_cast<const float4 *>(r + g.off_delta + u);
+        } else {
+          float av[4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          av[e] = (u + e < g.rows) ? r[g.off_delta + u + e] : 0.f;
-          bv[e] = (k + e < g.cols) ? r[g.off_in + k + e] : 0.f;
+          for (int e = 0; e < 4; ++e) av[e] = (u + e < g.rows) ? r[g.off_delta + u + e] : 0.f;
+          a[q] = make_float4(av[0], av[1], av[2], av[3]);
         }
-        a = make_float4(av[0], av[1], av[2], av[3]);
-        b = make_float4(bv[0], bv[1], bv[2], bv[3]);
+        if (k + 3 < g.cols) {
+          b[q] = *reinterpret_cast<const float4 *>(r + g.off_in + k);
+        } else {
+          float bv[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) bv[e] = (k + e < g.cols) ? r[g.off_in + k + e] : 0.f;
+          b[q] = make_float4(bv[0], bv[1], bv[2], bv[3]);
+        }
       }
-      As[jj][c4] = a;
-      Bs[jj][c4] = b;
+    }
+  };
+  float acc[4][4] = {};
+  float4 pa[2], pb[2];
+  fetch(ja, pa, pb);
+  for (int jj0 = ja; jj0 < jb; jj0 += 32) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int idx = t + 256 * q;
+      As[idx >> 4][idx & 15] = pa[q];
+      Bs[idx >> 4][idx & 15] = pb[q];
     }
     __syncthreads();
+    if (jj0 + 32 < jb) fetch(jj0 + 32, pa, pb);
 #pragma unroll 4
     for (int jj = 0; jj < 32; ++jj) {
       const float4 a = As[jj][ty], b = Bs[jj][tx];
