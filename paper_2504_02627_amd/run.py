@@ -13,7 +13,10 @@ d = 100), toeplitz (N = 5000, d = 100, rows correlated 0.95^|i-j|), batched
 
 Usage: python -m paper_2504_02627_amd.run --workload small --iterations 50
            [--particles J] [--precision f32|bf16] [--jitter halton1d ...]
-           [--precond none|diag|flow] [--jsonl FILE] [--save FILE] [--resume FILE]
+           [--precond none|diag|flow] [--step-size EPS] [--traj-length L]
+           [--adapt-step-size none|adam|dual_averaging] [--flow-layers K]
+           [--flow-train-steps S] [--flow-lr LR] [--jsonl FILE] [--save FILE]
+           [--resume FILE]
 """
 
 import argparse
@@ -53,6 +56,14 @@ def main(argv=None):
     ap.add_argument("--jitter", default="halton1d")
     ap.add_argument("--precond", default="none", choices=["none", "diag", "flow"])
     ap.add_argument("--max-leapfrog", type=int, default=64)
+    ap.add_argument("--step-size", type=float, default=0.0,
+                    help="initial eps (default: the workload's conservative step size)")
+    ap.add_argument("--traj-length", type=float, default=0.0,
+                    help="initial L (default: eps * max_leapfrog / 2)")
+    ap.add_argument("--adapt-step-size", default="none", choices=["none", "adam", "dual_averaging"])
+    ap.add_argument("--flow-layers", type=int, default=4)
+    ap.add_argument("--flow-train-steps", type=int, default=10)
+    ap.add_argument("--flow-lr", type=float, default=1e-3)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--jsonl", default=None, help="write the per-iteration records here")
     ap.add_argument("--save", default=None, help="write a checkpoint of the final state")
@@ -64,15 +75,18 @@ def main(argv=None):
     dev = torch.device("cuda:0")
     Xs, ys = problem(a.workload)
     J = a.particles or DEFAULT_J[a.workload]
-    eps = min(synth.default_step_size(X.shape[0], X.shape[1]) for X in Xs)
+    eps = a.step_size or min(synth.default_step_size(X.shape[0], X.shape[1]) for X in Xs)
+    L = a.traj_length or eps * a.max_leapfrog / 2
     Xd = [torch.from_numpy(X).to(dev) for X in Xs]
     if a.precision == "bf16":
         Xd = [X.to(torch.bfloat16) for X in Xd]
     yd = [torch.from_numpy(y).to(dev) for y in ys]
     s = chees.Sampler(Xd if len(Xd) > 1 else Xd[0], yd if len(yd) > 1 else yd[0], J,
-                      step_size=eps, traj_length=eps * a.max_leapfrog / 2,
+                      step_size=eps, traj_length=L,
                       max_leapfrog=a.max_leapfrog, num_warmup=a.iterations // 2,
                       jitter=a.jitter, precision=a.precision, precond=a.precond,
+                      adapt_step_size=a.adapt_step_size, flow_layers=a.flow_layers,
+                      flow_train_steps=a.flow_train_steps, flow_lr=a.flow_lr,
                       num_iterations=a.iterations, seed=a.seed)
     if a.resume:
         with open(a.resume, "rb") as f:
