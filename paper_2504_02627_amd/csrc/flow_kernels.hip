@@ -13,7 +13,7 @@
 // few Adam steps on the weighted maximum-likelihood objective of the
 // population.
 //
-// A block of four waves carries 16 particles.  Every dense layer of the
+// A block of eight waves carries 16 particles.  Every dense layer of the
 // conditioners runs on v_mfma_f32_16x16x4f32 with a 16-unit tile of the
 // weight matrix as A (the waves take the tiles in turn) and the 16 particles'
 // activations, held in LDS, as B; the weights are pre-packed in the A-operand
@@ -36,7 +36,9 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 
 constexpr int MAXD = 16 * MAX_C2;  // largest dimension
 constexpr int PB = 16;             // particles per block
-constexpr int NT = 256;            // threads per block
+constexpr int NT = 512;            // threads per block: one wave per 16-row output tile of a
+                                   // 128-wide layer (J = 4096 gives one block per compute unit)
+constexpr int LPP = NT / PB;       // lanes per particle in the element-wise parts
 constexpr int XP = MAXD + 17;      // LDS pitch of state rows: a padded K chunk stays in the row
 constexpr int HP = FH + 1;         // LDS pitch of hidden rows
 constexpr int KSPLIT = FKSPLIT;
@@ -210,7 +212,7 @@ __device__ void mdense(const float *Ap, int M, int K, const float *bias, const f
 // returns the thread's partial sum of s (particle tid / 16).
 __device__ float forward_couplings(const FlowNet &F, const float *Ap, const float *bias,
                                    BlockLDS &S, int wave, int lane, int tid) {
-  const int p = tid >> 4, r = tid & 15;
+  const int p = tid / LPP, r = tid % LPP;
   float ldp = 0.f;
   for (int l = 0; l < F.L; ++l) {
     const FlowLayerDesc &Y = F.ly[l];
@@ -225,7 +227,7 @@ __device__ float forward_couplings(const FlowNet &F, const float *Ap, const floa
            -1, 0, wave, lane);
     __syncthreads();
     float *tp = S.tw[p] ? S.tw[p] + lo + 2 * FH : nullptr;
-    for (int f = r; f < Y.dt; f += 16) {
+    for (int f = r; f < Y.dt; f += LPP) {
       const float s = tanhf(S.ob[p][f]);
       const float t = S.ob[p][Y.dt + f];
       const float x = S.xs[p][Y.T0 + f];
@@ -246,12 +248,12 @@ __device__ float forward_couplings(const FlowNet &F, const float *Ap, const floa
 // cotangent of every s.  Bp: the transposed weights, packed.
 __device__ void vjp_couplings(const FlowNet &F, const float *Bp, BlockLDS &S, int wave, int lane,
                               int tid) {
-  const int p = tid >> 4, r = tid & 15;
+  const int p = tid / LPP, r = tid % LPP;
   for (int l = F.L - 1; l >= 0; --l) {
     const FlowLayerDesc &Y = F.ly[l];
     const int lo = l * F.tape_stride;
     const float *ts = S.tr[p] + lo + 2 * FH;
-    for (int f = r; f < Y.dt; f += 16) {
+    for (int f = r; f < Y.dt; f += LPP) {
       const float s = ts[f], xT = ts[F.half + f];
       const float gy = S.xs[p][Y.T0 + f];
       const float es = expf(s);
@@ -272,10 +274,11 @@ __device__ void vjp_couplings(const FlowNet &F, const float *Bp, BlockLDS &S, in
   }
 }
 
-// Sum of the 16 partials of a particle (lanes 16 p .. 16 p + 15 of a wave), fixed order.
-__device__ __forceinline__ float sum16(float v) {
+// Sum of the LPP partials of a particle (lanes LPP p .. LPP p + LPP - 1 of a
+// wave), fixed order.
+__device__ __forceinline__ float sum_lpp(float v) {
 #pragma unroll
-  for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, 16);
+  for (int o = LPP / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, LPP);
   return v;
 }
 
@@ -561,7 +564,7 @@ __global__ __launch_bounds__(NT) void k_flow_train(Dev D, FlowNet F) {
   if (D.ps[0].resampled) return;
   __shared__ BlockLDS S;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int p = tid >> 4, r = tid & 15;
+  const int p = tid / LPP, r = tid % LPP;
   const int j0 = blockIdx.x * PB;
   const PState &PS = D.ps[0];
   const int rs = PS.resampled;
@@ -597,7 +600,7 @@ __global__ __launch_bounds__(NT) void k_flow_train(Dev D, FlowNet F) {
     const FlowLayerDesc &Y = F.ly[l];
     const int lo = l * TS;
     if (S.tw[p])
-      for (int c = r; c < Y.dc; c += 16) S.tw[p][lo + c] = S.xs[p][Y.C0 + c];
+      for (int c = r; c < Y.dc; c += LPP) S.tw[p][lo + c] = S.xs[p][Y.C0 + c];
     mdense(D.fpk + Y.pW1, FH, Y.dc, W + Y.ob1, &S.xs[0][Y.C0], XP, &S.h1[0][0], HP, ST_TANH, S,
            lo + h, 0, wave, lane);
     __syncthreads();
@@ -607,7 +610,7 @@ __global__ __launch_bounds__(NT) void k_flow_train(Dev D, FlowNet F) {
     mdense(D.fpk + Y.pW3, 2 * Y.dt, FH, W + Y.ob3, &S.h2[0][0], HP, &S.ob[0][0], XP, ST_PLAIN, S,
            -1, 0, wave, lane);
     __syncthreads();
-    for (int f = r; f < Y.dt; f += 16) {
+    for (int f = r; f < Y.dt; f += LPP) {
       const float s = tanhf(S.ob[p][f]);
       const float t = S.ob[p][Y.dt + f];
       const float x = (S.xs[p][Y.T0 + f] - t) * expf(-s);
@@ -620,14 +623,14 @@ __global__ __launch_bounds__(NT) void k_flow_train(Dev D, FlowNet F) {
     __syncthreads();
   }
   // cotangent of z: -W_j z
-  for (int c = r; c < MAXD; c += 16) S.xs[p][c] = -S.wj[p] * S.xs[p][c];
+  for (int c = r; c < MAXD; c += LPP) S.xs[p][c] = -S.wj[p] * S.xs[p][c];
   __syncthreads();
   // reverse of the inverse order: layer 0 first
   for (int l = 0; l < F.L; ++l) {
     const FlowLayerDesc &Y = F.ly[l];
     const int lo = l * TS;
     const float *rr = S.tr[p] + lo;
-    for (int f = r; f < Y.dt; f += 16) {
+    for (int f = r; f < Y.dt; f += LPP) {
       const float s = rr[h + 2 * FH + f], xT = rr[2 * h + 2 * FH + f];
       const float gx = S.xs[p][Y.T0 + f];
       const float es = expf(-s);
@@ -789,7 +792,7 @@ __global__ __launch_bounds__(256) void k_flow_wgrad(Dev D, FlowNet F, float *par
 __global__ __launch_bounds__(NT) void k_flow_inverse(Dev D, FlowNet F) {
   __shared__ BlockLDS S;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int p = tid >> 4, r = tid & 15;
+  const int p = tid / LPP, r = tid % LPP;
   const int j0 = blockIdx.x * PB;
   if (tid < PB) {
     const int j = j0 + tid;
@@ -819,17 +822,17 @@ __global__ __launch_bounds__(NT) void k_flow_inverse(Dev D, FlowNet F) {
     mdense(D.fbk + Y.pW3, 2 * Y.dt, FH, D.fbias + Y.ob3, &S.h2[0][0], HP, &S.ob[0][0], XP,
            ST_PLAIN, S, -1, 0, wave, lane);
     __syncthreads();
-    for (int f = r; f < Y.dt; f += 16) {
+    for (int f = r; f < Y.dt; f += LPP) {
       const float s = tanhf(S.ob[p][f]);
       S.xs[p][Y.T0 + f] = (S.xs[p][Y.T0 + f] - S.ob[p][Y.dt + f]) * expf(-s);
       ldp -= s;
     }
     __syncthreads();
   }
-  const float ld0 = -sum16(ldp);   // log|det J_T(z0)|
+  const float ld0 = -sum_lpp(ldp);   // log|det J_T(z0)|
   const int j = S.rows[p];
   if (j >= 0) {
-    for (int c = r; c < D.DS; c += 16) {
+    for (int c = r; c < D.DS; c += LPP) {
       const float z = c < F.d ? S.xs[p][c] : 0.f;
       D.fz[(long long)j * D.DS + c] = z;
       D.fz0[(long long)j * D.DS + c] = z;
@@ -879,7 +882,7 @@ __device__ __forceinline__ bool move_rows(const Dev &D, const FlowNet &F, BlockL
 __global__ __launch_bounds__(NT) void k_flow_drift(Dev D, FlowNet F, int step, int init) {
   __shared__ BlockLDS S;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int p = tid >> 4, r = tid & 15;
+  const int p = tid / LPP, r = tid % LPP;
   if (!move_rows(D, F, S, step, init, tid)) return;
   const float eps = (float)D.ps[0].eps;
   const float he = 0.5f * eps;
@@ -904,11 +907,11 @@ __global__ __launch_bounds__(NT) void k_flow_drift(Dev D, FlowNet F, int step, i
   if (init) return;
   mdense(D.fAf, F.d, F.d, nullptr, &S.xs[0][0], XP, &S.ob[0][0], XP, ST_PLAIN, S, -1, 0, wave, lane);
   if (r == 0) ldp += D.fbase[0];
-  const float ld = sum16(ldp);
+  const float ld = sum_lpp(ldp);
   __syncthreads();
   const int j = S.rows[p];
   if (j >= 0) {
-    for (int c = r; c < D.DS; c += 16)
+    for (int c = r; c < D.DS; c += LPP)
       D.theta_t[(long long)j * D.DS + c] = c < F.d ? D.fm[c] + S.ob[p][c] : 0.f;
     if (r == 0) D.fld1[j] = ld;
   }
