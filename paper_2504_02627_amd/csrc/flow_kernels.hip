@@ -881,11 +881,10 @@ __device__ __forceinline__ bool move_rows(const Dev &D, const FlowNet &F, BlockL
 // (BF16 weights) with the move tape and log|det J_T(z)|.  The likelihood
 // gradient at theta follows (k_lf_partial / k_lf_reduce in gradient mode).
 // init: only the forward pass from z0, for the tape of the latent gradient.
-__global__ __launch_bounds__(NT) void k_flow_drift(Dev D, FlowNet F, int step, int init) {
-  __shared__ BlockLDS S;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+__device__ __forceinline__ void drift_body(const Dev &D, const FlowNet &F, BlockLDS &S, int init,
+                                           int tid) {
+  const int lane = tid & 63, wave = tid >> 6;
   const int p = tid / LPP, r = tid % LPP;
-  if (!move_rows(D, F, S, step, init, tid)) return;
   const float eps = (float)D.ps[0].eps;
   const float he = 0.5f * eps;
   for (int i = tid; i < PB * D.DS; i += NT) {
@@ -919,13 +918,18 @@ __global__ __launch_bounds__(NT) void k_flow_drift(Dev D, FlowNet F, int step, i
   }
 }
 
+__global__ __launch_bounds__(NT) void k_flow_drift(Dev D, FlowNet F, int step, int init) {
+  __shared__ BlockLDS S;
+  if (!move_rows(D, F, S, step, init, threadIdx.x)) return;
+  drift_body(D, F, S, init, threadIdx.x);
+}
+
 // Leapfrog step `step`, second half: g_z = J_T^T grad log pi(theta) +
 // grad log|det J_T| from the move tape; p += eps/2 g_z.  init: the latent
 // gradient at z0 from the cached gradient at theta0, no kick.
-__global__ __launch_bounds__(NT) void k_flow_kick(Dev D, FlowNet F, int step, int init) {
-  __shared__ BlockLDS S;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  if (!move_rows(D, F, S, step, init, tid)) return;
+__device__ __forceinline__ void kick_body(const Dev &D, const FlowNet &F, BlockLDS &S, int init,
+                                          int tid) {
+  const int lane = tid & 63, wave = tid >> 6;
   const float he = 0.5f * (float)D.ps[0].eps;
   for (int i = tid; i < PB * F.d; i += NT) {
     const int q = i / F.d, c = i % F.d;
@@ -947,6 +951,26 @@ __global__ __launch_bounds__(NT) void k_flow_kick(Dev D, FlowNet F, int step, in
     D.fgz[e] = g;
     if (!init) D.p_t[e] = fmaf(he, g, D.p_t[e]);
   }
+}
+
+__global__ __launch_bounds__(NT) void k_flow_kick(Dev D, FlowNet F, int step, int init) {
+  __shared__ BlockLDS S;
+  if (!move_rows(D, F, S, step, init, threadIdx.x)) return;
+  kick_body(D, F, S, init, threadIdx.x);
+}
+
+// The kick of step `step` and the drift of step `step + 1` in one launch (one
+// kernel boundary fewer per step).  Both work on the block's own particles
+// only: a particle moving at step + 1 moves at step too, and its p and g_z
+// pass from the kick to the drift through global memory within the block.
+__global__ __launch_bounds__(NT) void k_flow_kick_drift(Dev D, FlowNet F, int step) {
+  __shared__ BlockLDS S;
+  const int tid = threadIdx.x;
+  if (!move_rows(D, F, S, step, 0, tid)) return;
+  kick_body(D, F, S, 0, tid);
+  __syncthreads();  // the kick's LDS reads and global writes before the drift's set-up
+  if (!move_rows(D, F, S, step + 1, 0, tid)) return;
+  drift_body(D, F, S, 0, tid);
 }
 
 // New parameters from the caller: restart the Adam moments, and count Adam
@@ -1038,6 +1062,11 @@ hipError_t launch_flow_drift(const Dev &D, const FlowNet &F, int step, hipStream
 
 hipError_t launch_flow_kick(const Dev &D, const FlowNet &F, int step, hipStream_t st) {
   hipLaunchKernelGGL(k_flow_kick, dim3((D.J + PB - 1) / PB), dim3(NT), 0, st, D, F, step, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_flow_kick_drift(const Dev &D, const FlowNet &F, int step, hipStream_t st) {
+  hipLaunchKernelGGL(k_flow_kick_drift, dim3((D.J + PB - 1) / PB), dim3(NT), 0, st, D, F, step);
   return hipGetLastError();
 }
 

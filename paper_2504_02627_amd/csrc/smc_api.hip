@@ -871,7 +871,7 @@ smc_status enqueue_step(smc_ctx *ctx, const smc_inject *inject) {
     }));
   }
   for (int s = 0; s < (D.target || D.traj || lanes ? 0 : D.nmax); ++s) {
-    if (D.flow) {  // one posterior, one group
+    if (D.flow && s == 0) {  // one posterior, one group; later drifts join the kicks
       CK(timed_begin(ctx, 3, ei));
       CK(launch_flow_drift(D, F, s, ctx->st));
       CK(timed_end(ctx, ei));
@@ -891,7 +891,8 @@ smc_status enqueue_step(smc_ctx *ctx, const smc_inject *inject) {
     }
     if (D.flow) {
       CK(timed_begin(ctx, 3, ei));
-      CK(launch_flow_kick(D, F, s, ctx->st));
+      CK(s + 1 < D.nmax ? launch_flow_kick_drift(D, F, s, ctx->st)
+                        : launch_flow_kick(D, F, s, ctx->st));
       CK(timed_end(ctx, ei));
     }
   }

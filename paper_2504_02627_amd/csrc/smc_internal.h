@@ -247,6 +247,8 @@ hipError_t launch_flow_gradsum(const Dev &D, const FlowNet &F, float *out, hipSt
 hipError_t launch_flow_begin(const Dev &D, const FlowNet &F, hipStream_t st);
 hipError_t launch_flow_drift(const Dev &D, const FlowNet &F, int step, hipStream_t st);
 hipError_t launch_flow_kick(const Dev &D, const FlowNet &F, int step, hipStream_t st);
+// the kick of step `step` and the drift of step `step + 1` in one launch
+hipError_t launch_flow_kick_drift(const Dev &D, const FlowNet &F, int step, hipStream_t st);
 hipError_t launch_resample_indices(const double *w, int J, const double *u, int scheme,
                                    int *anc, unsigned long long *cdf, double *wmax, int *err,
                                    hipStream_t st);
