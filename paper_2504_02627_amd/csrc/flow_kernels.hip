@@ -335,7 +335,9 @@ __global__ void k_flow_init(Dev D, FlowNet F) {
 // ---------------------------------------------------------------------------
 __global__ void k_flow_adam(Dev D, FlowNet F, int step, int update, const float *part) {
   if (update && D.ps[0].resampled) return;  // no fit on a resampled iteration
-  const int t = D.fstate[1] + 1;             // Adam steps taken so far, plus this one
+  // Adam steps taken before this iteration's fit, plus this one (step: its
+  // index in the fit; the count advances once, after the fit's last step)
+  const int t = D.fstate[1] + step + 1;
   const double c1 = 1.0 - pow(D.adam_b1, (double)t), c2 = 1.0 - pow(D.adam_b2, (double)t);
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < F.nparams; i += gridDim.x * blockDim.x) {
     float pv = D.fp[i];
@@ -983,9 +985,9 @@ __global__ void k_flow_reset(Dev D, FlowNet F) {
   if (blockIdx.x == 0 && threadIdx.x == 0) D.fstate[1] = 0;
 }
 
-// Count an Adam step of the fit (after k_flow_adam has read the count).
-__global__ void k_flow_tick(Dev D) {
-  if (!D.ps[0].resampled) D.fstate[1] += 1;
+// Count the Adam steps of an iteration's fit (after its last k_flow_adam).
+__global__ void k_flow_tick(Dev D, int steps) {
+  if (!D.ps[0].resampled) D.fstate[1] += steps;
 }
 
 // The gradient the last Adam step used: the ordered sum of the chunk partials.
@@ -1043,7 +1045,7 @@ hipError_t launch_flow_train(const Dev &D, const FlowNet &F, int step, hipStream
   hipLaunchKernelGGL(k_flow_wgrad, dim3(nb, KSPLIT), dim3(256), 0, st, D, F, D.fgrad);
   hipLaunchKernelGGL(k_flow_adam, dim3(256), dim3(256), 0, st, D, F, step, 1,
                      (const float *)D.fgrad);
-  hipLaunchKernelGGL(k_flow_tick, dim3(1), dim3(1), 0, st, D);
+  if (step == F.ntrain - 1) hipLaunchKernelGGL(k_flow_tick, dim3(1), dim3(1), 0, st, D, F.ntrain);
   return hipGetLastError();
 }
 
