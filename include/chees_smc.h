@@ -19,7 +19,9 @@
  *
  * Memory model.  Every device buffer is caller-owned: the data X, y, the
  * workspace (size from smc_workspace_bytes) and the HIP stream must outlive
- * the context.  The library allocates no device memory at all; the context
+ * the context.  The library allocates no device memory at run time; its one
+ * static device array (8 MiB per GPU, the scratch of
+ * resample_indices_noalloc) is part of the loaded code object.  The context
  * header is host memory released by smc_destroy.  Every call is
  * stream-ordered and asynchronous unless it says it synchronises.
  *
@@ -328,6 +330,21 @@ size_t resample_workspace_bytes(int32_t J);
 smc_status resample_indices(const double *w, int32_t J, const double *u, int32_t scheme,
                             int32_t *ancestors, void *workspace, size_t workspace_bytes,
                             void *hip_stream);
+
+/* The same stateless resampling with no workspace argument, for callers that
+ * cannot allocate device memory (code that may not call hipMalloc: tight
+ * serving loops, harnesses that forbid allocation).  Its scratch (the integer
+ * CDF and an error flag) is a static device array of the library, one copy
+ * per GPU, sized for J <= resample_noalloc_max() = 1048576 weights (8 MiB),
+ * held until the process ends.  Larger J is SMC_EINVAL (nothing launched).
+ * The call allocates nothing; it launches one kernel on hip_stream, copies the
+ * 4-byte error flag to the host and synchronises the stream.  Every call on a
+ * GPU shares that GPU's array: calls that overlap on one GPU (other streams or
+ * threads) race and must be serialised by the caller.  Arguments, results and
+ * SMC_EDEGENERATE as for resample_indices. */
+int32_t resample_noalloc_max(void);
+smc_status resample_indices_noalloc(const double *w, int32_t J, const double *u, int32_t scheme,
+                                    int32_t *ancestors, void *hip_stream);
 
 /* log Z_hat = C + LSE(log w), C the sum of LSE(log w) over past resamplings
  * (the standard SMC evidence estimator).  Synchronises.  log_z_host: posterior

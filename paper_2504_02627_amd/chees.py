@@ -135,6 +135,8 @@ def load():
             "resample": (i32, [vp, vp, vp]),
             "resample_workspace_bytes": (sz, [i32]),
             "resample_indices": (i32, [vp, i32, vp, i32, vp, vp, sz, vp]),
+            "resample_noalloc_max": (i32, []),
+            "resample_indices_noalloc": (i32, [vp, i32, vp, i32, vp, vp]),
             "log_evidence": (i32, [vp, P(dbl), P(dbl)]),
             "smc_get_state": (i32, [vp, vp, vp, vp]),
             "smc_get_trace": (i32, [vp, P(Trace)]),
@@ -514,6 +516,27 @@ def resample_indices(w, u, scheme="systematic", stream=None):
                               _stream_handle(stream))
     if rc != SMC_OK:
         raise SmcError(rc, "resample_indices")
+    return anc
+
+
+def resample_indices_noalloc(w, u, anc, scheme="systematic", stream=None):
+    """Stateless resampling into the caller's int32 device tensor `anc` with
+    the library's static scratch: no device allocation by this call (see
+    resample_indices_noalloc in include/chees_smc.h)."""
+    torch = _torch()
+    lib = load()
+    J = int(w.numel())
+    if w.dtype != torch.float64 or u.dtype != torch.float64 or not (w.is_cuda and u.is_cuda):
+        raise ValueError("w and u: float64 device tensors")
+    if anc.dtype != torch.int32 or not anc.is_cuda or anc.numel() < J:
+        raise ValueError(f"anc: int32 device tensor of at least {J} values")
+    need = 1 if scheme == "systematic" else J
+    if u.numel() < need:
+        raise ValueError(f"u needs {need} values")
+    rc = lib.resample_indices_noalloc(_ptr(w), J, _ptr(u), RESAMPLING[scheme], _ptr(anc),
+                                      _stream_handle(stream))
+    if rc != SMC_OK:
+        raise SmcError(rc, "resample_indices_noalloc")
     return anc
 
 

@@ -1016,6 +1016,31 @@ smc_status resample_indices(const double *w, int32_t J, const double *u, int32_t
   return herr ? SMC_EDEGENERATE : SMC_OK;
 }
 
+int32_t resample_noalloc_max(void) { return RS_STATIC_MAX; }
+
+smc_status resample_indices_noalloc(const double *w, int32_t J, const double *u, int32_t scheme,
+                                    int32_t *ancestors, void *hip_stream) {
+  if (!w || !u || !ancestors || J < 1 ||
+      (scheme != SMC_RESAMPLE_SYSTEMATIC && scheme != SMC_RESAMPLE_MULTINOMIAL))
+    return SMC_EINVAL;
+  if (J > RS_STATIC_MAX) {
+    fprintf(stderr, "resample_indices_noalloc: J = %d exceeds the static scratch (%d weights)\n",
+            J, RS_STATIC_MAX);
+    return SMC_EINVAL;
+  }
+  unsigned long long *cdf = nullptr;
+  int *err = nullptr;
+  if (static_resample_scratch(&cdf, &err) != hipSuccess) return SMC_EDEVICE;
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (launch_resample_indices(w, J, u, scheme, ancestors, cdf, nullptr, err, st) != hipSuccess)
+    return SMC_EDEVICE;
+  int herr = 0;
+  if (hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess)
+    return SMC_EDEVICE;
+  if (hipStreamSynchronize(st) != hipSuccess) return SMC_EDEVICE;
+  return herr ? SMC_EDEGENERATE : SMC_OK;
+}
+
 smc_status log_evidence(smc_ctx *ctx, double *log_z_host, double *per_posterior_host) {
   if (!ctx) return SMC_EINVAL;
   CK(hipMemcpyAsync(ctx->ps_host.data(), ctx->D.ps, ctx->D.B * sizeof(PState),

@@ -252,5 +252,11 @@ hipError_t launch_flow_kick_drift(const Dev &D, const FlowNet &F, int step, hipS
 hipError_t launch_resample_indices(const double *w, int J, const double *u, int scheme,
                                    int *anc, unsigned long long *cdf, double *wmax, int *err,
                                    hipStream_t st);
+// Device address of the no-allocation resampling scratch on the current
+// device (looked up once per device): CDF of RS_STATIC_MAX entries and the
+// error flag.
+constexpr int RS_STATIC_MAX = 1 << 20;
+constexpr int RS_MAX_DEVICES = 64;
+hipError_t static_resample_scratch(unsigned long long **cdf, int **err);
 
 }  // namespace smc

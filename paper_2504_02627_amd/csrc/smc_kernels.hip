@@ -9,6 +9,8 @@
 
 #include <math.h>
 
+#include <mutex>
+
 #include "smc_internal.h"
 #include "dev_common.h"
 
@@ -2434,6 +2436,33 @@ hipError_t launch_resample_indices(const double *w, int J, const double *u, int 
   hipLaunchKernelGGL(k_resample_indices, dim3(1), dim3(1024), 0, st, w, J, u, scheme, anc, cdf,
                      err);
   return hipGetLastError();
+}
+
+// Scratch of the no-allocation resampling entry point: the integer CDF of at
+// most RS_STATIC_MAX weights, then 256 bytes for the error flag.  One copy per
+// device, held until the process ends.  Host code never passes the array's
+// name to a kernel (in host code it is a stand-in, not a device address): the
+// device address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) unsigned long long scratch[RS_STATIC_MAX + 32];
+
+hipError_t static_resample_scratch(unsigned long long **cdf, int **err) {
+  static std::mutex mu;
+  static void *addr[RS_MAX_DEVICES] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= RS_MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    addr[dev] = p;
+  }
+  *cdf = static_cast<unsigned long long *>(addr[dev]);
+  *err = reinterpret_cast<int *>(*cdf + RS_STATIC_MAX);
+  return hipSuccess;
 }
 
 }  // namespace smc

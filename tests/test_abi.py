@@ -116,3 +116,15 @@ def test_sobol_table_is_validated_without_gpu():
     assert lib.smc_workspace_bytes(ctypes.byref(prob), ctypes.byref(inv)) == 0
     assert lib.smc_workspace_bytes(ctypes.byref(prob), ctypes.byref(
         chees.make_params(256, jitter="sobol1d"))) > 0
+
+
+def test_noalloc_resampling_validates_without_gpu():
+    # sizes past the static scratch and bad arguments are refused before any
+    # device call
+    lib = _lib()
+    assert lib.resample_noalloc_max() == 1 << 20
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.resample_indices_noalloc(fake, (1 << 20) + 1, fake, 0, fake, None) == -1
+    assert lib.resample_indices_noalloc(None, 16, fake, 0, fake, None) == -1
+    assert lib.resample_indices_noalloc(fake, 0, fake, 0, fake, None) == -1
+    assert lib.resample_indices_noalloc(fake, 16, fake, 2, fake, None) == -1
