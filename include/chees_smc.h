@@ -189,6 +189,16 @@ typedef struct {
    * SMC_EINVAL. */
   const uint32_t *sobol_table;
   int32_t sobol_dims;
+  /* Launch tuning of the split leapfrog launches (0 = the library's
+   * default; neither changes the arithmetic except through the split count,
+   * which fixes the order of the partial-gradient sums):
+   *   lf_items: work items per resident work-group slot and step (1..4096;
+   *     default 256);
+   *   lf_split_cap: most data-row splits of one particle tile in one step
+   *     (1..64; default 64).
+   * paper_2504_02627_amd/autotune.py measures them per workload and caches
+   * the choice. */
+  int32_t lf_items, lf_split_cap;
 } smc_params;
 
 /* Host-supplied randomness for one smc_step (all fields nullable, DEVICE

@@ -63,7 +63,8 @@ class Params(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("flow_layers", ctypes.c_int32),
                 ("flow_width", ctypes.c_int32), ("flow_train_steps", ctypes.c_int32),
                 ("flow_lr", ctypes.c_double), ("num_iterations", ctypes.c_int32),
-                ("sobol_table", ctypes.c_void_p), ("sobol_dims", ctypes.c_int32)]
+                ("sobol_table", ctypes.c_void_p), ("sobol_dims", ctypes.c_int32),
+                ("lf_items", ctypes.c_int32), ("lf_split_cap", ctypes.c_int32)]
 
 
 class Inject(ctypes.Structure):
@@ -179,7 +180,7 @@ DEFAULT_PARAMS = dict(max_leapfrog=64, num_warmup=10, jitter="halton1d", mh_acce
                       adam_b1=0.9, adam_b2=0.999, adam_eps=1e-8, avg_decay=0.9,
                       adapt_step_size=False, target_accept=0.651, seed=0,
                       flow_layers=4, flow_width=128, flow_train_steps=10, flow_lr=1e-3,
-                      num_iterations=0, sobol_dims=0)
+                      num_iterations=0, sobol_dims=0, lf_items=0, lf_split_cap=0)
 
 
 SOBOL_MAX_DIMS = 21201
@@ -221,6 +222,7 @@ def make_params(num_particles, **kw):
         par._sobol = sobol_table(dims)      # kept alive with the struct
         par.sobol_table = par._sobol.ctypes.data
         par.sobol_dims = dims
+    par.lf_items, par.lf_split_cap = int(p["lf_items"]), int(p["lf_split_cap"])
     return par
 
 
@@ -274,10 +276,12 @@ class Sampler:
     """One SMC/ChEES-HMC sampler context over B posteriors (include/chees_smc.h)."""
 
     def __init__(self, Xs, ys, num_particles, prior_var=1.0, theta0=None, stream=None,
-                 target=None, **params):
+                 target=None, tune=None, **params):
         """target: None (logistic regression on Xs, ys) or a dict with "kind"
         ("gaussian" / "banana"), "dim" and the arguments of make_target_problem;
-        Xs and ys are then unused."""
+        Xs and ys are then unused.  tune="cache": take the launch setting
+        (lf_items, lf_split_cap) the autotuner stored for this workload, unless
+        given explicitly."""
         torch = _torch()
         self.lib = load()
         self.J = int(num_particles)
@@ -296,6 +300,14 @@ class Sampler:
             self.Xs, self.ys, self.B, self.dims = [], [], 1, [dim]
             self.device = t["mean"].device if kind == "gaussian" else torch.device("cuda:0")
             self.prob, self._keep = make_target_problem(kind, dim, prior_var=prior_var, **t)
+        if tune == "cache" and target is None:
+            from paper_2504_02627_amd import autotune
+            best = autotune.lookup(self.dims, [X.shape[0] for X in self.Xs], self.J,
+                                   params.get("precision", "f32"), params.get("max_leapfrog", 64))
+            params = dict(best, **params)
+        elif tune not in (None, "cache"):
+            raise ValueError("tune: None or 'cache'")
+        self.tuned = {k: params.get(k, 0) for k in ("lf_items", "lf_split_cap")}
         self.params = make_params(self.J, **params)
         nbytes = self.lib.smc_workspace_bytes(ctypes.byref(self.prob), ctypes.byref(self.params))
         if nbytes == 0:

@@ -69,6 +69,7 @@ struct Layout {
   int gpart_slots = 0, goff[MAX_C2] = {};
   int nosplit = 0;
   int traj = 0;
+  int split_cap = LF_MAX_SPLIT;
   size_t traj_lds = 0;
   std::vector<HostPost> hp;
   std::vector<Post> posts;
@@ -79,7 +80,7 @@ struct Layout {
   size_t o_posts, o_ps, o_xab, o_xbf, o_theta, o_grad, o_theta_t, o_p_t, o_grad_t, o_theta_n;
   size_t o_logpi, o_logpi_t, o_logw, o_h, o_l, o_H0, o_dH, o_alpha, o_ca, o_cg;
   size_t o_n, o_perm, o_active, o_anc, o_acc, o_cdf, o_gpart, o_llpart;
-  size_t o_redp = 0, o_redc = 0, o_sortc = 0;
+  size_t o_redp = 0, o_redc = 0, o_sortc = 0, o_status = 0;
   size_t o_lf_post = 0, o_lf_items = 0, o_lf_count = 0;
   size_t o_tmean = 0, o_tprec = 0;
   size_t o_items, o_colpart, o_means, o_minv, o_primes, o_sqrtp = 0, o_sobol = 0;
@@ -243,6 +244,8 @@ const char *check(const smc_problem *pr, const smc_params *pa) {
   if (!(pa->avg_decay >= 0.0 && pa->avg_decay <= 1.0)) return "avg_decay in [0, 1]";
   if (pa->adapt_step_size < SMC_ADAPT_EPS_NONE || pa->adapt_step_size > SMC_ADAPT_EPS_DUAL_AVERAGING)
     return "adapt_step_size";
+  if (pa->lf_items < 0 || pa->lf_items > 4096) return "lf_items in [0, 4096]";
+  if (pa->lf_split_cap < 0 || pa->lf_split_cap > LF_MAX_SPLIT) return "lf_split_cap in [0, 64]";
   return nullptr;
 }
 
@@ -292,7 +295,7 @@ void plan(const smc_problem *pr, const smc_params *pa, Layout &L) {
   // compute unit (256 CUs; two groups for the FP32 kernel up to d = 128)
   // (more items per launch for the batched form measured slower: each
   // feature-tile group already gets its own launch)
-  L.lf_target = 256;
+  L.lf_target = pa->lf_items > 0 ? pa->lf_items : 256;
   const int ntile = L.Jcap / TJ;
   // small data sets (at most 32 data tiles per posterior): one item per
   // particle tile holds the whole gradient and finishes the step, with no
@@ -312,6 +315,7 @@ void plan(const smc_problem *pr, const smc_params *pa, Layout &L) {
     L.traj = L.traj_lds + fixed <= TRAJ_LDS_MAX && !(env && env[0] == '1');
   }
   L.lf_grid = L.lf_target * lf_groups_per_cu(bf16, 1) + B * ntile;
+  L.split_cap = pa->lf_split_cap > 0 ? pa->lf_split_cap : LF_MAX_SPLIT;
   // log-likelihood pass: every tile, static splits, one launch per
   // feature-tile group of about lf_target items per resident work group slot
   L.items.clear();
@@ -381,6 +385,7 @@ void plan(const smc_problem *pr, const smc_params *pa, Layout &L) {
   L.o_cdf = take(c, rows * 8);
   L.o_redp = take(c, (size_t)B * RED_G * 4 * sizeof(double));
   L.o_redc = take(c, (size_t)B * 2 * sizeof(int));
+  L.o_status = take(c, 256);
   L.o_sortc = take(c, (size_t)B * ((L.Jcap + 1023) / 1024) * 256 * sizeof(int));
   // partial gradients: each feature-tile group owns the slots of its largest
   // launch, so one reduction per step serves every group
@@ -392,6 +397,7 @@ void plan(const smc_problem *pr, const smc_params *pa, Layout &L) {
     L.gpart_slots += L.lf_target * lf_groups_per_cu(bf16, L.groups[g].x) + Bg * ntile;
   }
   L.o_gpart = take(c, (size_t)L.gpart_slots * TJ * L.DS * sizeof(float));
+
   L.o_llpart = take(c, (size_t)L.ll_smax * rows * sizeof(float2));
   L.o_items = take(c, (size_t)L.ll_nitems * sizeof(int4));
   L.o_colpart = take(c, (size_t)B * L.col_chunks * 2 * L.DS * 8);
@@ -543,6 +549,7 @@ smc_status smc_init(const smc_problem *prob, const smc_params *par, void *worksp
   D.xab = (float *)(w + L.o_xab);
   D.xbf = (uint4 *)(w + L.o_xbf);
   D.bf16 = par->precision == SMC_PRECISION_BF16 ? 1 : 0;
+  D.status = (int *)(w + L.o_status);
   D.theta = (float *)(w + L.o_theta);
   D.grad = (float *)(w + L.o_grad);
   D.theta_t = (float *)(w + L.o_theta_t);
@@ -607,6 +614,7 @@ smc_status smc_init(const smc_problem *prob, const smc_params *par, void *worksp
       (par->jitter == SMC_JITTER_SOBOLND || par->jitter == SMC_JITTER_SOBOLND_INV) ? par->sobol_dims
                                                                                     : 0;
   D.lf_target = L.lf_target;
+  D.split_cap = L.split_cap;
   D.lf_grid = L.lf_grid;
   D.flow = par->precond == SMC_PRECOND_FLOW ? 1 : 0;
   if (D.flow) {
@@ -759,7 +767,13 @@ smc_status smc_init(const smc_problem *prob, const smc_params *par, void *worksp
   CKI(launch_ess(D, 0, ctx->st));
   if (D.flow) CKI(launch_flow_init(D, ctx->F, ctx->st));
   // the host copies above must stay alive until they have run
+  int status = 0;
+  CKI(hipMemcpyAsync(&status, D.status, sizeof(int), hipMemcpyDeviceToHost, ctx->st));
   CKI(hipStreamSynchronize(ctx->st));
+  if (status) {
+    ctx->err = "the BF16 precision form needs labels y in {0, 1}";
+    return fail(SMC_EINVAL);
+  }
   (void)rc;
   *out = ctx;
   return SMC_OK;

@@ -23,6 +23,7 @@ constexpr int FCOV_CH = 8;
 constexpr size_t TRAJ_LDS_MAX = 65536;  // LDS of one work group
 constexpr int MAX_C2 = 13;          // d <= 16 * 13 = 208
 constexpr int MAX_NMAX = 4096;      // cap on max_leapfrog
+constexpr int LF_MAX_SPLIT = 64;    // data-row splits per tile and step
 constexpr int QUANT_BITS = 40;      // fixed-point resolution of resampling weights
 constexpr int NPRIMES = 1024;       // primes table for N-d Halton
 constexpr int SOBOL_MAXDIM = 21201; // rows of Joe and Kuo's table
@@ -112,6 +113,7 @@ struct Dev {                    // pointers carved from the workspace
   float *xab;                   // packed data tiles ([tile][lane][A | B | y])
   uint4 *xbf;                   // packed BF16 32-row tiles (BF16 trajectories)
   int bf16;                     // trajectory gradients on BF16 MFMA
+  int *status;                  // [0]: a label other than 0 / 1 met by the BF16 packing
   float *theta, *grad;          // current state, B*Jcap x DS
   float *theta_t, *p_t, *grad_t;// trajectory buffers
   float *theta_n;               // theta' of the next leapfrog step, written by the split
@@ -156,6 +158,7 @@ struct Dev {                    // pointers carved from the workspace
   int4 *lf_items;               // [group][nmax][lf_grid] (posterior, tile, split | S << 16, first item of tile)
   int *lf_count;                // [group][nmax] items of a launch
   int ngroups;                  // feature-tile groups (one leapfrog launch each per step)
+  int split_cap;                // most data-row splits per tile in a step
   int group_c2[MAX_C2];         // C2 of group g
   int c2_group[MAX_C2 + 1];     // group of C2
   int lf_goff[MAX_C2];          // first partial-gradient slot of group g (groups own disjoint slots)
@@ -188,19 +191,22 @@ hipError_t launch_pack_one(const Dev &D, const void *X, const float *y, int x_dt
                            const HostPost &P, hipStream_t st);
 hipError_t launch_pack_bf16(const Dev &D, const void *X, const float *y, int x_dtype,
                             const HostPost &P, hipStream_t st);
-// Resident leapfrog work groups (8 waves each) per compute unit.  The FP32
-// kernel for up to 8 feature tiles is built for two (at most 128 VGPRs, LDS at
-// most 80 KB); wider FP32 problems and the BF16 kernel (about 170 VGPRs at
-// d = 100) run one.
+// BF16 leapfrog kernel: four waves of 32 particles per work group.
+constexpr int B32_WAVES = 4;
+constexpr int B32_WG = 64 * B32_WAVES;
+
+// Resident leapfrog work groups per compute unit.  The FP32 kernel (8 waves)
+// for up to 8 feature tiles is built for two (at most 128 VGPRs, LDS at most
+// 80 KB), wider FP32 problems run one; the BF16 kernel (4 waves) runs two up
+// to 10 feature tiles (at most 256 registers per lane, two LDS stages of at
+// most 80 KB) and one beyond (its accumulators need more registers).
 __host__ __device__ constexpr int lf_groups_per_cu(bool bf16, int c2) {
-  return (!bf16 && c2 <= 8) ? 2 : 1;
+  return bf16 ? (c2 <= 10 ? 2 : 1) : (c2 <= 8 ? 2 : 1);
 }
 
-// uint4 per lane and 32-row tile in the BF16 packing: [A: 2 KC | B: C2 | y: 1] (+1 if even)
-__host__ __device__ constexpr int bf16_lane_stride(int c2) {
-  return ((2 * ((c2 + 1) / 2) + c2 + 1) % 2 == 0) ? 2 * ((c2 + 1) / 2) + c2 + 2
-                                                   : 2 * ((c2 + 1) / 2) + c2 + 1;
-}
+// uint4 per lane and 32-row tile in the BF16 packing: [A1: C2 | A2: 2 ceil(C2/2)],
+// plus one zero slot when that is even
+__host__ __device__ constexpr int bf16_lane_stride(int c2) { return (c2 + 2 * ((c2 + 1) / 2)) | 1; }
 hipError_t fill_f32(float *p, long long n, float v, hipStream_t st);
 hipError_t fill_i32(int *p, long long n, int v, hipStream_t st);
 hipError_t fill_f64(double *p, long long n, double v, hipStream_t st);

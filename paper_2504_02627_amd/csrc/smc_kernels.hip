@@ -134,17 +134,28 @@ hipError_t launch_pack_one(const Dev &D, const void *X, const float *y, int x_dt
 }
 
 // ---------------------------------------------------------------------------
-// Packing for BF16 trajectory gradients (v_mfma_f32_16x16x32_bf16), per
-// 32-row data tile T and lane l, in 16-byte slots (8 bfloat16 or 4 floats):
-//   A, half h in {0,1}, chunk c < KC: X[32T + 16h + l%16][32c + 8(l/16) + e];
-//   B, feature tile ct < C2:          X[n_e][16ct + l%16], with n_e = 32T +
-//        4(l/16) + e for e < 4 and 32T + 16 + 4(l/16) + e - 4 for e >= 4 (the
-//        rows whose residuals the lane holds after GEMM1 on the two halves);
-//   y: one slot of eight bfloat16 labels, element e = 4h + i holding
-//        y[32T + 16h + 4(l/16) + i] (1/2 beyond N; 0, 1 and 1/2 are exact), so
-//        the tile loop reads them with one 16-byte LDS read;
-//   a zero pad slot when the count is even (odd lane stride: no LDS bank
-//   conflicts).  Values are rounded to bfloat16 to nearest even.
+// Packing for BF16 trajectory gradients (v_mfma_f32_32x32x16_bf16, 32
+// particles per wave).  Each row carries the sign of its label,
+// x~_n = (2 y_n - 1) x_n: then y_n - sigmoid(x_n . theta) =
+// (2 y_n - 1) sigmoid(-x~_n . theta), so the tile loop needs no labels and the
+// residual of a well-classified row comes out with full relative precision
+// (no 1 - sigmoid cancellation).  The sign flip is exact in bfloat16 and
+// round-to-nearest-even is symmetric, so the rounded operands and products
+// are those of X, theta' and R = y - sigmoid rounded to bfloat16.
+// Per 32-row data tile T and lane l (h = l / 32), in 16-byte slots of eight
+// bfloat16:
+//   A of GEMM1 (Z^T = X~ Theta'^T), K-step c < C2:
+//        x~[32T + l%32][16c + 8h + e];
+//   A of GEMM2 (G^T = X~^T R^T), feature tile f < NF = ceil(C2/2), K-step q:
+//        x~[32T + 16q + 8(e>>2) + 4h + (e&3)][phi(f, l%32)],
+//        phi(f, i) = 32f + 16(i>>4) + 8((i>>2)&1) + 4((i>>3)&1) + (i&3).
+//   The row order of GEMM2's K follows GEMM1's output layout (lane l, register
+//   v holds row 8(v/4) + 4h + v%4), and phi makes GEMM2's output register v of
+//   tile f hold feature 32f + 16(v>>3) + 8h + (v&7): the layout of theta' in
+//   GEMM1's B operand (K-step c = 2f + (v>>3), element v&7).
+//   Slots: [A1: C2 | A2: 2 NF ([f][q])] plus a zero slot when that is even
+//   (odd lane stride: conflict-free 16-byte LDS reads).  Rows past N are zero.
+// A label other than 0 or 1 sets *bad (the precision form needs binary y).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint16_t bf16_rne(float f) {
   uint32_t u = __float_as_uint(f);
@@ -159,9 +170,14 @@ __device__ __forceinline__ uint16_t to_bf16<float>(float v) { return bf16_rne(v)
 template <>
 __device__ __forceinline__ uint16_t to_bf16<uint16_t>(uint16_t v) { return v; }
 
+__host__ __device__ constexpr int b32_phi(int f, int i) {
+  return 32 * f + 16 * (i >> 4) + 8 * ((i >> 2) & 1) + 4 * ((i >> 3) & 1) + (i & 3);
+}
+
 template <typename T>
 __global__ void k_pack_bf16(const T *__restrict__ X, const float *__restrict__ y, int N, int d,
-                            int C2, int KC, int NT2, int LS, uint4 *__restrict__ xbf) {
+                            int C2, int NF, int NT2, int LS, uint4 *__restrict__ xbf,
+                            int *__restrict__ bad) {
   const long long tot = (long long)NT2 * 64 * LS;
   for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < tot;
        idx += (long long)gridDim.x * blockDim.x) {
@@ -169,29 +185,28 @@ __global__ void k_pack_bf16(const T *__restrict__ X, const float *__restrict__ y
     const long long r = idx / LS;
     const int lane = (int)(r % 64);
     const int tl = (int)(r / 64);
-    const int g = lane >> 4, lm = lane & 15;
+    const int h = lane >> 5, i = lane & 31;
     uint32_t w[4] = {0, 0, 0, 0};
-    if (slot < 2 * KC + C2) {
+    if (slot < C2 + 2 * NF) {
       uint16_t v[8];
       for (int e = 0; e < 8; ++e) {
         int n, k;
-        if (slot < 2 * KC) {
-          const int h = slot / KC, c = slot % KC;
-          n = 32 * tl + 16 * h + lm;
-          k = 32 * c + 8 * g + e;
+        if (slot < C2) {
+          n = 32 * tl + i;
+          k = 16 * slot + 8 * h + e;
         } else {
-          const int ct = slot - 2 * KC;
-          n = 32 * tl + (e < 4 ? 4 * g + e : 16 + 4 * g + (e - 4));
-          k = 16 * ct + lm;
+          const int f = (slot - C2) >> 1, q = (slot - C2) & 1;
+          n = 32 * tl + 16 * q + 8 * (e >> 2) + 4 * h + (e & 3);
+          k = b32_phi(f, i);
         }
-        v[e] = (n < N && k < d) ? to_bf16<T>(X[(long long)n * d + k]) : (uint16_t)0;
-      }
-      for (int q = 0; q < 4; ++q) w[q] = (uint32_t)v[2 * q] | ((uint32_t)v[2 * q + 1] << 16);
-    } else if (slot == 2 * KC + C2) {
-      uint16_t v[8];
-      for (int e = 0; e < 8; ++e) {
-        const int n = 32 * tl + 16 * (e >> 2) + 4 * g + (e & 3);
-        v[e] = bf16_rne(n < N ? y[n] : 0.5f);
+        uint16_t u = 0;
+        if (n < N && k < d) {
+          const float yn = y[n];
+          if (yn != 0.f && yn != 1.f) *bad = 1;
+          u = to_bf16<T>(X[(long long)n * d + k]);
+          if (yn == 0.f) u ^= 0x8000u;  // sign of the label (exact)
+        }
+        v[e] = u;
       }
       for (int q = 0; q < 4; ++q) w[q] = (uint32_t)v[2 * q] | ((uint32_t)v[2 * q + 1] << 16);
     }
@@ -207,10 +222,10 @@ hipError_t launch_pack_bf16(const Dev &D, const void *X, const float *y, int x_d
   if (grid > 65535) grid = 65535;
   if (x_dtype == 0)
     hipLaunchKernelGGL(k_pack_bf16<float>, dim3(grid), dim3(256), 0, st, (const float *)X, y, P.N,
-                       P.d, P.C2, P.KC, P.NT2, LS, D.xbf + P.xbf);
+                       P.d, P.C2, P.KC, P.NT2, LS, D.xbf + P.xbf, D.status);
   else
     hipLaunchKernelGGL(k_pack_bf16<uint16_t>, dim3(grid), dim3(256), 0, st, (const uint16_t *)X, y,
-                       P.N, P.d, P.C2, P.KC, P.NT2, LS, D.xbf + P.xbf);
+                       P.N, P.d, P.C2, P.KC, P.NT2, LS, D.xbf + P.xbf, D.status);
   return hipGetLastError();
 }
 
@@ -328,8 +343,6 @@ struct Plan {
   int b, tile, split, S, wbase;
 };
 
-constexpr int LF_MAX_SPLIT = 64;
-
 // Plan of the leapfrog launches at step s, written once per iteration by
 // k_lf_plan from the active counts (one work group per step and feature-tile
 // group).  About lf_target times the resident work groups per compute unit
@@ -381,7 +394,7 @@ __global__ __launch_bounds__(PLAN_THREADS) void k_lf_plan(Dev D) {
         const int NU = lf_units(D, P);
         long long G = (share * T * NU) / U;  // this posterior's share of the items
         if (G < T || D.lf_nosplit) G = T;
-        const long long cap = (long long)T * (NU < LF_MAX_SPLIT ? NU : LF_MAX_SPLIT);
+        const long long cap = (long long)T * (NU < D.split_cap ? NU : D.split_cap);
         if (G > cap) G = cap;
         base = (int)(G / T);
         extra = (int)(G % T);
@@ -512,25 +525,17 @@ __device__ __forceinline__ void lf_finish(const Dev &D, long long row, int k, fl
   D.grad_t[e] = gn;
 }
 
-// FIN: the plan has one split per tile (small data sets), so the item holds
-// its particles' whole likelihood gradient and finishes the step itself
-// (prior, second half kick, or the gradient only for zero_eps = 2), exactly as
-// the split reduction does; no reduction launch follows.
-template <int C2, bool FIN>
-__global__ __launch_bounds__(WG, 2 * lf_groups_per_cu(false, C2)) void k_lf_partial(Dev D, int s, int zero_eps) {
+// One work item of the FP32 fused step (posterior, particle tile, data-row
+// split): each wave's 16 particles' partial likelihood gradient over the
+// split's rows, in the output layout of GEMM2 (gacc[ct][rr]: particle slot
+// 16 wave + 4 (lane / 16) + rr, feature 16 ct + lane % 16).  given: theta'
+// of this step was formed by the previous reduction (theta_n).
+template <int C2>
+__device__ __forceinline__ void lf_unit_f32(const Dev &D, const Plan &pl, int s, int zero_eps,
+                                            bool given, float4 (&xs)[2][Tiles<C2>::STAGE],
+                                            v4f (&gacc)[SUB][C2]) {
   constexpr int K1 = 4 * C2;
   using TL = Tiles<C2>;
-  __shared__ float4 xs[2][TL::STAGE];
-  __shared__ Plan spl;
-  if (threadIdx.x == 0) {
-    Plan pl;
-    if (!lf_item(D, C2, s, blockIdx.x, pl)) pl.b = -1;
-    spl = pl;
-  }
-  __syncthreads();
-  const Plan pl = spl;
-  if (pl.b < 0) return;
-
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, kq = lane >> 4;
   const Post P = D.posts[pl.b];
   const float eps = zero_eps ? 0.f : (float)D.ps[pl.b].eps;
@@ -548,7 +553,6 @@ __global__ __launch_bounds__(WG, 2 * lf_groups_per_cu(false, C2)) void k_lf_part
   // the first step of the split path the previous reduction has written it
   // (the same arithmetic), so one array is read instead of three
   float th[SUB][K1];
-  const bool given = !FIN && s > 0 && !zero_eps;
 #pragma unroll
   for (int sb = 0; sb < SUB; ++sb) {
     const int slot = pl.tile * TJ + (wave * SUB + sb) * 16 + (lane & 15);
@@ -568,7 +572,6 @@ __global__ __launch_bounds__(WG, 2 * lf_groups_per_cu(false, C2)) void k_lf_part
     }
   }
 
-  v4f gacc[SUB][C2];
 #pragma unroll
   for (int sb = 0; sb < SUB; ++sb)
 #pragma unroll
@@ -613,8 +616,50 @@ __global__ __launch_bounds__(WG, 2 * lf_groups_per_cu(false, C2)) void k_lf_part
     __syncthreads();
     cur ^= 1;
   }
+}
+
+// Partial gradient of an FP32 work item into a [TJ][DS] slot.
+template <int C2>
+__device__ __forceinline__ void lf_store_f32(const Dev &D, float *gp, const v4f (&gacc)[SUB][C2]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, kq = lane >> 4;
+#pragma unroll
+  for (int sb = 0; sb < SUB; ++sb)
+#pragma unroll
+    for (int ct = 0; ct < C2; ++ct)
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int slot = (wave * SUB + sb) * 16 + 4 * kq + rr;
+        gp[(long long)slot * D.DS + 16 * ct + (lane & 15)] = gacc[sb][ct][rr];
+      }
+}
+
+// FIN: the plan has one split per tile (small data sets), so the item holds
+// its particles' whole likelihood gradient and finishes the step itself
+// (prior, second half kick, or the gradient only for zero_eps = 2), exactly as
+// the split reduction does; no reduction launch follows.
+template <int C2, bool FIN>
+__global__ __launch_bounds__(WG, 2 * lf_groups_per_cu(false, C2)) void k_lf_partial(Dev D, int s, int zero_eps) {
+  using TL = Tiles<C2>;
+  __shared__ float4 xs[2][TL::STAGE];
+  __shared__ Plan spl;
+  if (threadIdx.x == 0) {
+    Plan pl;
+    if (!lf_item(D, C2, s, blockIdx.x, pl)) pl.b = -1;
+    spl = pl;
+  }
+  __syncthreads();
+  const Plan pl = spl;
+  if (pl.b < 0) return;
+  v4f gacc[SUB][C2];
+  lf_unit_f32<C2>(D, pl, s, zero_eps, !FIN && s > 0 && !zero_eps, xs, gacc);
 
   if constexpr (FIN) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, kq = lane >> 4;
+    const Post P = D.posts[pl.b];
+    const float eps = zero_eps ? 0.f : (float)D.ps[pl.b].eps;
+    const float he = 0.5f * eps;
+    const float *minv = D.minv + (long long)pl.b * D.DS;
+    const int *perm = D.perm + P.row0;
 #pragma unroll
     for (int sb = 0; sb < SUB; ++sb)
 #pragma unroll
@@ -629,16 +674,7 @@ __global__ __launch_bounds__(WG, 2 * lf_groups_per_cu(false, C2)) void k_lf_part
     return;
   }
   // partial gradient of this split: gpart[group's first slot + work item][slot][k]
-  float *gp = D.gpart + (long long)(D.lf_goff[D.c2_group[C2]] + blockIdx.x) * TJ * D.DS;
-#pragma unroll
-  for (int sb = 0; sb < SUB; ++sb)
-#pragma unroll
-    for (int ct = 0; ct < C2; ++ct)
-#pragma unroll
-      for (int rr = 0; rr < 4; ++rr) {
-        const int slot = (wave * SUB + sb) * 16 + 4 * kq + rr;
-        gp[(long long)slot * D.DS + 16 * ct + (lane & 15)] = gacc[sb][ct][rr];
-      }
+  lf_store_f32<C2>(D, D.gpart + (long long)(D.lf_goff[D.c2_group[C2]] + blockIdx.x) * TJ * D.DS, gacc);
 }
 
 // ---------------------------------------------------------------------------
@@ -846,84 +882,205 @@ hipError_t launch_traj(const Dev &D, int c2, hipStream_t st) {
 
 // ---------------------------------------------------------------------------
 // Fused leapfrog step with BF16 trajectory gradients (precision form):
-// theta' and X in bfloat16 on v_mfma_f32_16x16x32_bf16 with FP32
-// accumulation; the residual R is rounded to bfloat16 as the A operand of the
-// second product.  Per 32-row data tile and wave (16 particles):
-//   GEMM1 on the two 16-row halves, KC MFMAs each (K = 32 features);
-//   R = y - sigmoid(Z) on the 8 accumulator values of the lane (rows
-//   4(l/16)+i of both halves), packed as the lane's 8 K-values of GEMM2;
-//   GEMM2: C2 MFMAs (K = 32 data rows, N = 16 features).
+// theta', X and R in bfloat16 on v_mfma_f32_32x32x16_bf16 with FP32
+// accumulation.  Work item as in k_lf_partial (posterior, 128-particle tile,
+// data-row split); a work group is four waves of 32 particles.  Per 32-row
+// data tile and wave:
+//   GEMM1  Z~^T (32 rows x 32 particles) = X~ Theta'^T, C2 MFMAs (K = 16
+//          features each);
+//   R = sigmoid(-Z~) on the lane's 16 accumulator values (with the label
+//          signs folded into X~, this is (2y - 1)(y - sigmoid(Z))), rounded
+//          to bfloat16 as GEMM2's B operand (two K-steps of 16 rows);
+//   GEMM2  G^T (32 features x 32 particles) += X~^T R^T, 2 NF MFMAs.
+// theta' stays in registers as GEMM1's B operand; G's registers line up with
+// it, so the step's end needs no shuffle.  Data tiles are staged through two
+// named LDS buffers by direct global-to-LDS loads (global_load_lds_dwordx4);
+// because the buffers are distinct objects, the compiler need not wait for
+// the next stage's loads before reading the current buffer, and the
+// prefetch holds no registers.  Two tiles per stage up to a lane stride of 20
+// slots (four KB each), one beyond.
 // The drift, the partials and the reduction are those of the FP32 kernel.
 // Exactness of the weights does not depend on the gradient's precision: the
 // leapfrog map with any position-only force field is volume preserving and
 // reversible, and the energies are recomputed from the FP32 data.
 // ---------------------------------------------------------------------------
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef float v16f __attribute__((ext_vector_type(16)));
 
 __device__ __forceinline__ v8bf as_v8bf(uint4 u) { return __builtin_bit_cast(v8bf, u); }
 
 template <int C2>
-struct TilesBF {
-  static constexpr int KC = (C2 + 1) / 2;
-  static constexpr int LSTR = bf16_lane_stride(C2);  // uint4 per lane and 32-row tile
-  static constexpr int TILE = 64 * LSTR;
-  static constexpr int STAGE = 2 * TILE;
-  static constexpr int NINST = STAGE / 64;
+struct B32 {
+  static constexpr int NF = (C2 + 1) / 2;          // 32-feature tiles of GEMM2
+  static constexpr int LS = bf16_lane_stride(C2);  // uint4 per lane and 32-row tile
+  static constexpr int TILE = 64 * LS;             // uint4 per tile
+  static constexpr int STT = LS <= 20 ? 2 : 1;     // tiles per stage
+  static constexpr int STAGE = STT * TILE;
+  static constexpr int NINST = STAGE / 64;         // wave-wide 16-byte loads per stage
 };
 
-
-// Register-staged prefetch of the BF16 tile loop.  A stage (two 32-row
-// tiles, 2 TILE uint4, contiguous in the packing) is loaded by all 512
-// threads with consecutive 16-byte global loads into registers while the
-// waves compute on the other LDS buffer, then written to LDS after the
-// compute.  (Direct global-to-LDS loads would save the registers, but the
-// compiler must assume such a load may alias any LDS read and waits for it
-// before the first operand read, so the prefetch would never overlap.)
+// Direct loads of the stage starting at data tile t into `buf` (tiles past
+// the split's last one are skipped; wave-uniform guard).
 template <int C2>
-struct StageRegs {
-  static constexpr int N = 2 * TilesBF<C2>::TILE;           // uint4 per stage
-  static constexpr int K = (N + WG - 1) / WG;               // uint4 per thread
-  // one vector value (not an array) so that it lives in registers
-  typedef unsigned int vec __attribute__((ext_vector_type(4 * K)));
-  vec v;
-};
-
-// The loads are unconditional (indices clamped to the split's last tile and
-// to the stage), so no branch separates a load from its use and the compiler
-// keeps them all in flight; only the LDS stores are guarded.  Requires t < t1.
-template <int C2>
-__device__ __forceinline__ void stage_load_bf(StageRegs<C2> &r, const uint4 *__restrict__ xbf, int t,
-                                              int t1, int tid) {
-  using TL = TilesBF<C2>;
+__device__ __forceinline__ void b32_issue(uint4 *__restrict__ buf, const uint4 *__restrict__ xbf,
+                                          int t, int t1, int wave, int lane) {
+  using TL = B32<C2>;
+  const uint4 *src = xbf + (long long)t * TL::TILE + lane;
 #pragma unroll
-  for (int k = 0; k < StageRegs<C2>::K; ++k) {
-    const int idx = min(tid + k * WG, StageRegs<C2>::N - 1);
-    const int tile = min(t + idx / TL::TILE, t1 - 1);
-    const uint4 u = xbf[(long long)tile * TL::TILE + idx % TL::TILE];
-    r.v[4 * k + 0] = u.x;
-    r.v[4 * k + 1] = u.y;
-    r.v[4 * k + 2] = u.z;
-    r.v[4 * k + 3] = u.w;
+  for (int k = 0; k < (TL::NINST + B32_WAVES - 1) / B32_WAVES; ++k) {
+    const int m = wave + k * B32_WAVES;
+    if (m < TL::NINST && t + m / TL::LS < t1)
+      __builtin_amdgcn_global_load_lds((const void *)(src + 64 * m), (lds_void *)(buf + 64 * m), 16,
+                                       0, 0);
   }
 }
 
-template <int C2>
-__device__ __forceinline__ void stage_store_bf(uint4 *xs, const StageRegs<C2> &r, int t, int t1,
-                                               int tid) {
-  using TL = TilesBF<C2>;
+// R = sigmoid(-z~) = 1 / (1 + 2^(z~ log2 e)), hardware exp2 and reciprocal,
+// rounded to bfloat16 (nearest even) as GEMM2's two B-operand K-steps.
+__device__ __forceinline__ void b32_residual(const v16f &z, v8bf &r0, v8bf &r1) {
 #pragma unroll
-  for (int k = 0; k < StageRegs<C2>::K; ++k) {
-    const int idx = tid + k * WG;
-    if (idx < StageRegs<C2>::N && t + idx / TL::TILE < t1)
-      xs[idx] = make_uint4(r.v[4 * k + 0], r.v[4 * k + 1], r.v[4 * k + 2], r.v[4 * k + 3]);
+  for (int v = 0; v < 8; ++v) {
+    r0[v] = (__bf16)__builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(z[v] * 1.4426950408889634f));
+    r1[v] = (__bf16)__builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(z[8 + v] * 1.4426950408889634f));
   }
 }
+
+// The tiles of one stage in buffer xs (lane's slots at xs + lane * LS).
+template <int C2>
+__device__ __forceinline__ void b32_stage(const uint4 *__restrict__ xs, int ntt, const v8bf (&thb)[C2],
+                                          v16f (&g)[B32<C2>::NF]) {
+  using TL = B32<C2>;
+  constexpr int NF = TL::NF;
+  if (ntt == 2) {
+    // both tiles' GEMM1 first: the first tile's residuals overlap the second's MFMAs
+    const uint4 *x0 = xs, *x1 = xs + TL::TILE;
+    v16f z0 = {}, z1 = {};
+#pragma unroll
+    for (int c = 0; c < C2; ++c) z0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_v8bf(x0[c]), thb[c], z0, 0, 0, 0);
+#pragma unroll
+    for (int c = 0; c < C2; ++c) z1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_v8bf(x1[c]), thb[c], z1, 0, 0, 0);
+    v8bf r0, r1;
+    b32_residual(z0, r0, r1);
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      g[f] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_v8bf(x0[C2 + 2 * f]), r0, g[f], 0, 0, 0);
+      g[f] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_v8bf(x0[C2 + 2 * f + 1]), r1, g[f], 0, 0, 0);
+    }
+    b32_residual(z1, r0, r1);
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      g[f] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_v8bf(x1[C2 + 2 * f]), r0, g[f], 0, 0, 0);
+      g[f] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_v8bf(x1[C2 + 2 * f + 1]), r1, g[f], 0, 0, 0);
+    }
+  } else {
+    v16f z = {};
+#pragma unroll
+    for (int c = 0; c < C2; ++c) z = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_v8bf(xs[c]), thb[c], z, 0, 0, 0);
+    v8bf r0, r1;
+    b32_residual(z, r0, r1);
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      g[f] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_v8bf(xs[C2 + 2 * f]), r0, g[f], 0, 0, 0);
+      g[f] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_v8bf(xs[C2 + 2 * f + 1]), r1, g[f], 0, 0, 0);
+    }
+  }
+}
+
+// One work item of the BF16 fused step: the partial gradient of this wave's
+// 32 particles over the split's rows; register v of g[f] holds feature
+// 32f + 16(v>>3) + 8h + (v&7) of particle slot 32 wave + lane % 32.
+template <int C2>
+__device__ __forceinline__ void lf_unit_b32(const Dev &D, const Plan &pl, int s, int zero_eps,
+                                            bool given, uint4 *__restrict__ bufA,
+                                            uint4 *__restrict__ bufB, v16f (&g)[B32<C2>::NF]) {
+  using TL = B32<C2>;
+  constexpr int NF = TL::NF;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, h = lane >> 5;
+  const Post P = D.posts[pl.b];
+  const float eps = zero_eps ? 0.f : (float)D.ps[pl.b].eps;
+  const float he = 0.5f * eps;
+  const float *minv = D.minv + (long long)pl.b * D.DS;
+  const int *perm = D.perm + P.row0;
+
+  const int t0 = (int)((long long)pl.split * P.NT2 / pl.S);
+  const int t1 = (int)((long long)(pl.split + 1) * P.NT2 / pl.S);
+  const uint4 *xbf = D.xbf + P.xbf;
+  if (t0 < t1) b32_issue<C2>(bufA, xbf, t0, t1, wave, lane);
+
+  // theta' (bfloat16, B operand of GEMM1): K-step c holds features 16c + 8h + e
+  // of particle slot 32 wave + lane % 32; after the first step of the split
+  // path the previous reduction has formed it (the same arithmetic)
+  const int slot = wave * 32 + (lane & 31);
+  const long long rowp = P.row0 + perm[pl.tile * TJ + slot];
+  v8bf thb[C2];
+#pragma unroll
+  for (int c = 0; c < C2; ++c) {
+    const long long base = rowp * D.DS + 16 * c + 8 * h;
+    const int kb = 16 * c + 8 * h;
+    if (given) {
+      const float4 a = *reinterpret_cast<const float4 *>(D.theta_n + base);
+      const float4 b = *reinterpret_cast<const float4 *>(D.theta_n + base + 4);
+      const float v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+      for (int e = 0; e < 8; ++e) thb[c][e] = (__bf16)v[e];
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float t0v = D.theta_t[base + e], p0 = D.p_t[base + e], g0 = D.grad_t[base + e];
+        const float ph = fmaf(he, g0, p0);
+        // eps = 0 (gradient at the given theta): t0 + 0 * ph = t0 for finite ph
+        thb[c][e] = (__bf16)fmaf(eps * minv[kb + e], ph, t0v);
+      }
+    }
+  }
+
+#pragma unroll
+  for (int f = 0; f < NF; ++f) g[f] = v16f{};
+
+  __syncthreads();  // the first stage has landed (the compiler waits for the loads here)
+  for (int t = t0; t < t1;) {
+    // stage in bufA; the next one goes to bufB meanwhile
+    int nt = t + TL::STT;
+    if (nt < t1) b32_issue<C2>(bufB, xbf, nt, t1, wave, lane);
+    b32_stage<C2>(bufA + lane * TL::LS, min(TL::STT, t1 - t), thb, g);
+    __syncthreads();
+    t = nt;
+    if (t >= t1) break;
+    nt = t + TL::STT;
+    if (nt < t1) b32_issue<C2>(bufA, xbf, nt, t1, wave, lane);
+    b32_stage<C2>(bufB + lane * TL::LS, min(TL::STT, t1 - t), thb, g);
+    __syncthreads();
+    t = nt;
+  }
+}
+
+// Partial gradient of a BF16 work item into a [TJ][DS] slot.
+template <int C2>
+__device__ __forceinline__ void lf_store_b32(const Dev &D, float *gp0, const v16f (&g)[B32<C2>::NF]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, h = lane >> 5;
+  float *gp = gp0 + (long long)(wave * 32 + (lane & 31)) * D.DS;
+#pragma unroll
+  for (int f = 0; f < B32<C2>::NF; ++f)
+#pragma unroll
+    for (int hv = 0; hv < 2; ++hv) {
+      float4 *o = reinterpret_cast<float4 *>(gp + 32 * f + 16 * hv + 8 * h);
+      o[0] = make_float4(g[f][8 * hv + 0], g[f][8 * hv + 1], g[f][8 * hv + 2], g[f][8 * hv + 3]);
+      o[1] = make_float4(g[f][8 * hv + 4], g[f][8 * hv + 5], g[f][8 * hv + 6], g[f][8 * hv + 7]);
+    }
+}
+
+// Resident groups per compute unit = waves per SIMD (four waves per group);
+// the one-split variant finishes the step in registers: one group per
+// compute unit beyond 7 feature tiles.
+template <int C2, bool FIN>
+constexpr int b32_groups() { return FIN ? (C2 <= 7 ? 2 : 1) : lf_groups_per_cu(true, C2); }
 
 template <int C2, bool FIN>
-__global__ __launch_bounds__(WG) void k_lf_partial_bf16(Dev D, int s, int zero_eps) {
-  using TL = TilesBF<C2>;
-  constexpr int KC = TL::KC;
-  __shared__ uint4 xs[2][TL::STAGE];
+__global__ __launch_bounds__(B32_WG, (b32_groups<C2, FIN>())) void k_lf_partial_bf16(Dev D, int s, int zero_eps) {
+  using TL = B32<C2>;
+  constexpr int NF = TL::NF;
+  __shared__ uint4 bufA[TL::STAGE];
+  __shared__ uint4 bufB[TL::STAGE];
   __shared__ Plan spl;
   if (threadIdx.x == 0) {
     Plan pl;
@@ -933,99 +1090,27 @@ __global__ __launch_bounds__(WG) void k_lf_partial_bf16(Dev D, int s, int zero_e
   __syncthreads();
   const Plan pl = spl;
   if (pl.b < 0) return;
+  v16f g[NF];
+  lf_unit_b32<C2>(D, pl, s, zero_eps, !FIN && s > 0 && !zero_eps, bufA, bufB, g);
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4;
-  const Post P = D.posts[pl.b];
-  const float eps = zero_eps ? 0.f : (float)D.ps[pl.b].eps;
-  const float he = 0.5f * eps;
-  const float *minv = D.minv + (long long)pl.b * D.DS;
-  const int *perm = D.perm + P.row0;
-
-  // the first stage of data tiles is in flight while theta' is formed
-  const int t0 = (int)((long long)pl.split * P.NT2 / pl.S);
-  const int t1 = (int)((long long)(pl.split + 1) * P.NT2 / pl.S);
-  const uint4 *xbf = D.xbf + P.xbf;
-  StageRegs<C2> pre;
-  if (t0 < t1) stage_load_bf<C2>(pre, xbf, t0, t1, tid);
-
-  // theta' (bfloat16, B operand of GEMM1): chunk c holds features 32c + 8g + e
-  v8bf thb[KC];
-  {
-    const int slot = pl.tile * TJ + wave * 16 + (lane & 15);
-    const long long base = (long long)(P.row0 + perm[slot]) * D.DS;
-    // (reading the reduction's theta' here instead measured slower: the
-    // loop's register allocation and schedule changed)
-#pragma unroll
-    for (int c = 0; c < KC; ++c) {
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int k = 32 * c + 8 * g + e;
-        const float t0 = D.theta_t[base + k], p0 = D.p_t[base + k], g0 = D.grad_t[base + k];
-        const float ph = fmaf(he, g0, p0);
-        thb[c][e] = (__bf16)fmaf(eps * minv[k], ph, t0);
-      }
-    }
-  }
-
-  v4f gacc[C2];
-#pragma unroll
-  for (int ct = 0; ct < C2; ++ct) gacc[ct] = v4f{0.f, 0.f, 0.f, 0.f};
-
-  if (t0 < t1) stage_store_bf<C2>(xs[0], pre, t0, t1, tid);
-  __syncthreads();
-  int cur = 0;
-  for (int t = t0; t < t1; t += 2) {
-    const bool more = t + 2 < t1;
-    if (more) stage_load_bf<C2>(pre, xbf, t + 2, t1, tid);  // in flight during the compute
-    const int ntt = (t + 1 < t1) ? 2 : 1;
-    for (int tt = 0; tt < ntt; ++tt) {
-      const uint4 *xl = xs[cur] + tt * TL::TILE + lane * TL::LSTR;
-      v4f z0 = {0.f, 0.f, 0.f, 0.f}, z1 = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int c = 0; c < KC; ++c) {
-        z0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_v8bf(xl[c]), thb[c], z0, 0, 0, 0);
-        z1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_v8bf(xl[KC + c]), thb[c], z1, 0, 0, 0);
-      }
-      // the eight labels, bfloat16 pairs (exact) in one 16-byte read
-      const uint4 yu = xl[2 * KC + C2];
-      v8bf ra;
-      ra[0] = (__bf16)(__uint_as_float(yu.x << 16) - sigmoidf_fast(z0[0]));
-      ra[1] = (__bf16)(__uint_as_float(yu.x & 0xffff0000u) - sigmoidf_fast(z0[1]));
-      ra[2] = (__bf16)(__uint_as_float(yu.y << 16) - sigmoidf_fast(z0[2]));
-      ra[3] = (__bf16)(__uint_as_float(yu.y & 0xffff0000u) - sigmoidf_fast(z0[3]));
-      ra[4] = (__bf16)(__uint_as_float(yu.z << 16) - sigmoidf_fast(z1[0]));
-      ra[5] = (__bf16)(__uint_as_float(yu.z & 0xffff0000u) - sigmoidf_fast(z1[1]));
-      ra[6] = (__bf16)(__uint_as_float(yu.w << 16) - sigmoidf_fast(z1[2]));
-      ra[7] = (__bf16)(__uint_as_float(yu.w & 0xffff0000u) - sigmoidf_fast(z1[3]));
-#pragma unroll
-      for (int ct = 0; ct < C2; ++ct)
-        gacc[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ra, as_v8bf(xl[2 * KC + ct]), gacc[ct], 0, 0, 0);
-    }
-    // the other buffer was released by the barrier that ended the previous stage
-    if (more) stage_store_bf<C2>(xs[cur ^ 1], pre, t + 2, t1, tid);
-    __syncthreads();
-    cur ^= 1;
-  }
-
+  // register v of tile f: feature 32f + 16(v>>3) + 8h + (v&7)
   if constexpr (FIN) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, h = lane >> 5;
+    const Post P = D.posts[pl.b];
+    const long long rowp = P.row0 + D.perm[P.row0 + pl.tile * TJ + wave * 32 + (lane & 31)];
+    if (D.n[rowp] <= s) return;
+    const float eps = zero_eps ? 0.f : (float)D.ps[pl.b].eps;
+    const float he = 0.5f * eps;
+    const float *minv = D.minv + (long long)pl.b * D.DS;
 #pragma unroll
-    for (int rr = 0; rr < 4; ++rr) {
-      const long long row = P.row0 + perm[pl.tile * TJ + wave * 16 + 4 * g + rr];
-      if (D.n[row] <= s) continue;
+    for (int f = 0; f < NF; ++f)
 #pragma unroll
-      for (int ct = 0; ct < C2; ++ct)
-        lf_finish(D, row, 16 * ct + (lane & 15), gacc[ct][rr], eps, he, minv, zero_eps);
-    }
+      for (int v = 0; v < 16; ++v)
+        lf_finish(D, rowp, 32 * f + 16 * (v >> 3) + 8 * h + (v & 7), g[f][v], eps, he, minv,
+                  zero_eps);
     return;
   }
-  float *gp = D.gpart + (long long)(D.lf_goff[D.c2_group[C2]] + blockIdx.x) * TJ * D.DS;
-#pragma unroll
-  for (int ct = 0; ct < C2; ++ct)
-#pragma unroll
-    for (int rr = 0; rr < 4; ++rr) {
-      const int slot = wave * 16 + 4 * g + rr;
-      gp[(long long)slot * D.DS + 16 * ct + (lane & 15)] = gacc[ct][rr];
-    }
+  lf_store_b32<C2>(D, D.gpart + (long long)(D.lf_goff[D.c2_group[C2]] + blockIdx.x) * TJ * D.DS, g);
 }
 
 // grid: (B * tiles per posterior, slices of 256 float4 of a tile's 128 x d
@@ -1045,24 +1130,23 @@ __global__ __launch_bounds__(RED_THREADS) void k_lf_reduce(Dev D, int s, int zer
   const int dq = 4 * P.C2;  // float4 per particle row
   const int idx = blockIdx.y * RED_THREADS + threadIdx.x;
   if (idx >= tj * dq || tile >= q.w) return;
-  Plan pl;
-  pl.S = q.y + (tile < q.z ? 1 : 0);
-  pl.wbase = D.lf_goff[D.c2_group[P.C2]] + q.x + tile * q.y + (tile < q.z ? tile : q.z);
+  const int S = q.y + (tile < q.z ? 1 : 0);
+  const int wbase = D.lf_goff[D.c2_group[P.C2]] + q.x + tile * q.y + (tile < q.z ? tile : q.z);
   const int slot = idx / dq, k4 = idx - slot * dq;
   const int j = D.perm[P.row0 + tile * tj + slot];
-  const float4 *g0p = reinterpret_cast<const float4 *>(D.gpart + (long long)pl.wbase * tj * D.DS);
+  const float4 *g0p = reinterpret_cast<const float4 *>(D.gpart + (long long)wbase * tj * D.DS);
   const long long sstride = (long long)tj * D.DS / 4;  // float4 between splits
   const long long o4 = (long long)slot * D.DS / 4 + k4;
   // ordered sum over the splits: ((p0 + p1) + p2) + ...
   float4 G = g0p[o4];
-  for (int sp0 = 1; sp0 < pl.S; sp0 += RED_ROUND) {
+  for (int sp0 = 1; sp0 < S; sp0 += RED_ROUND) {
     float4 v[RED_ROUND];
 #pragma unroll
     for (int u = 0; u < RED_ROUND; ++u)
-      if (sp0 + u < pl.S) v[u] = g0p[(sp0 + u) * sstride + o4];
+      if (sp0 + u < S) v[u] = g0p[(sp0 + u) * sstride + o4];
 #pragma unroll
     for (int u = 0; u < RED_ROUND; ++u)
-      if (sp0 + u < pl.S) {
+      if (sp0 + u < S) {
         G.x += v[u].x;
         G.y += v[u].y;
         G.z += v[u].z;
@@ -1113,10 +1197,10 @@ __global__ __launch_bounds__(RED_THREADS) void k_lf_reduce(Dev D, int s, int zer
 template <int C2>
 static hipError_t launch_lf_c2(const Dev &D, int step, int zero_eps, hipStream_t st) {
   if (D.bf16 && D.lf_nosplit)
-    hipLaunchKernelGGL((k_lf_partial_bf16<C2, true>), dim3(D.lf_grid), dim3(WG), 0, st, D, step,
+    hipLaunchKernelGGL((k_lf_partial_bf16<C2, true>), dim3(D.lf_grid), dim3(B32_WG), 0, st, D, step,
                        zero_eps);
   else if (D.bf16)
-    hipLaunchKernelGGL((k_lf_partial_bf16<C2, false>), dim3(D.lf_grid), dim3(WG), 0, st, D, step,
+    hipLaunchKernelGGL((k_lf_partial_bf16<C2, false>), dim3(D.lf_grid), dim3(B32_WG), 0, st, D, step,
                        zero_eps);
   else if (D.lf_nosplit)
     hipLaunchKernelGGL((k_lf_partial<C2, true>), dim3(D.lf_grid), dim3(WG), 0, st, D, step,

@@ -42,8 +42,9 @@ def test_struct_sizes_match_c_layout():
     from paper_2504_02627_amd import chees
     # natural alignment: these sizes follow from the field lists of the header
     # ... flow_lr, num_iterations (+pad), sobol_table, sobol_dims (+pad)
+    # ... sobol_dims, lf_items, lf_split_cap (+pad)
     assert ctypes.sizeof(chees.Params) == (4 * 8 + 8 * 8 + 4 + 4 + 8 + 8 + 3 * 4 + 4 + 8 + 4 + 4
-                                           + 8 + 4 + 4)
+                                           + 8 + 4 + 2 * 4 + 4)
     assert ctypes.sizeof(chees.Stats) == 8 * 8 + 4 + 4 + 8
     assert ctypes.sizeof(chees.Inject) == 3 * 8
     # num_posteriors (+pad), n_rows, dims, X, y, x_dtype (+pad), prior_var,
@@ -128,3 +129,19 @@ def test_noalloc_resampling_validates_without_gpu():
     assert lib.resample_indices_noalloc(None, 16, fake, 0, fake, None) == -1
     assert lib.resample_indices_noalloc(fake, 0, fake, 0, fake, None) == -1
     assert lib.resample_indices_noalloc(fake, 16, fake, 2, fake, None) == -1
+
+
+def test_launch_tuning_is_validated():
+    from paper_2504_02627_amd import chees
+    lib = _lib()
+    n = (ctypes.c_int32 * 1)(200)
+    d = (ctypes.c_int32 * 1)(5)
+    X = (ctypes.c_void_p * 1)(0x1000)
+    y = (ctypes.c_void_p * 1)(0x2000)
+    prob = chees.Problem(1, n, d, X, y, 0, 1.0)
+    for bad in (dict(lf_split_cap=65), dict(lf_split_cap=-1), dict(lf_items=4097), dict(lf_items=-3)):
+        par = chees.make_params(256, **bad)
+        assert lib.smc_workspace_bytes(ctypes.byref(prob), ctypes.byref(par)) == 0, bad
+    for good in (dict(lf_split_cap=1), dict(lf_items=4096, lf_split_cap=64)):
+        par = chees.make_params(256, **good)
+        assert lib.smc_workspace_bytes(ctypes.byref(prob), ctypes.byref(par)) > 0, good
