@@ -1,15 +1,31 @@
 #!/usr/bin/env python3
-"""Throughput of the SMC / ChEES-HMC hot path on one MI355X.
+"""Throughput and accuracy of the SMC / ChEES-HMC hot path on one MI355X.
 
-Workload (synthetic, seeded): Bayesian logistic regression, N = 10000 rows,
-d = 100 standardised N(0,1) features, beta* ~ N(0, 0.25 I), prior N(0, I);
-J = 8192 particles, 50 SMC iterations (warm-up adaptation for the first 25),
-at most 64 leapfrog steps per jittered trajectory, 1-d Halton jitter,
-systematic resampling at J_eff < J/2, FP32 trajectories.
+Headline workload (synthetic, seeded): Bayesian logistic regression, N = 10000
+rows, d = 100 standardised N(0,1) features, beta* ~ N(0, 0.25 I), prior
+N(0, I); J = 8192 particles, at most 64 leapfrog steps per jittered
+trajectory, 1-d Halton jitter, systematic resampling at J_eff < J/2, FP32
+trajectories.  A step is one SMC iteration (smc_step + chees_adapt) over all
+particles; the run is W untimed iterations then K timed ones, with ChEES
+adaptation during the first half of the W + K iterations.  `value` = particle-
+gradient evaluations per second over the K timed iterations (stream-
+synchronised on both sides, inputs resident in HBM).
 
-A step is one SMC iteration (smc_step + chees_adapt) over all particles.
-`value` = particle-gradient evaluations per second = sum_j n_j over the timed
-steps / wall time (stream-synchronised on both sides).  Prints one JSON line.
+Beside it, in the same JSON line:
+  roofline           the fused leapfrog kernel's achieved FP32 MFMA rate;
+  forms.bf16         the precision form of the same workload;
+  matched_error      every form run over the full 50-iteration workload on R
+                     seeds: final weighted means and variances against
+                     reference moments (long runs), z per dimension, and the
+                     ESS/s at that accuracy;
+  batched            64 posteriors in one context, FP32 and BF16, with the
+                     exact MFMA rate sum_b 4 N_b d_b sum_j n_bj / kernel time;
+  precision_vs_oracle the BF16 form on the small model (J = 16384) against the
+                     FP64 oracle on the same randomness, per result;
+  toeplitz_flow      the preconditioned forms on the ill-conditioned model,
+                     including BF16 + flow, with matched error;
+  cpu_baseline       the FP64 oracle timed on this host's cores (and the other
+                     workloads' oracle figures in oracle_timing).
 """
 
 import argparse
@@ -32,19 +48,16 @@ KERNEL_SRCS = [os.path.join(ROOT, "paper_2504_02627_amd", "csrc", f)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "leapfrog_traffic.json")
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def kernel_hash():
     h = hashlib.sha256()
     for p in KERNEL_SRCS:
         with open(p, "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
-
-
-def workload_params():
-    from paper_2504_02627_amd import synth
-    eps0 = synth.default_step_size(N_ROWS, DIM)
-    return dict(step_size=eps0, traj_length=eps0 * NMAX / 2, max_leapfrog=NMAX,
-                num_warmup=ITERS // 2, seed=2, jitter="halton1d", resampling="systematic")
 
 
 def traffic_for_current_kernel():
@@ -60,10 +73,379 @@ def traffic_for_current_kernel():
     return t.get("bytes_per_launch")
 
 
-def cpu_baseline(X, y, params, seconds):
-    """The oracle, as it stands, on a bounded sample of the same workload."""
-    import numpy as np
+def large_params(num_warmup):
+    from paper_2504_02627_amd import synth
+    eps0 = synth.default_step_size(N_ROWS, DIM)
+    return dict(step_size=eps0, traj_length=eps0 * NMAX / 2, max_leapfrog=NMAX,
+                num_warmup=num_warmup, seed=2, jitter="halton1d", resampling="systematic")
+
+
+# ---------------------------------------------------------------------------
+# host facts
+# ---------------------------------------------------------------------------
+def host_cpu():
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except AttributeError:
+        ncpu = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return ncpu, model
+
+
+def blas_threads():
     from threadpoolctl import threadpool_info
+    return max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+
+
+# ---------------------------------------------------------------------------
+# timing helpers
+# ---------------------------------------------------------------------------
+def moments(s):
+    """Self-normalised weighted means and variances of every posterior (eq.
+    realised_estimates), float64 numpy, one (mean, var) pair per posterior."""
+    import torch
+    theta, logw, _ = s.state()
+    thetas = theta if isinstance(theta, list) else [theta]
+    out = []
+    for b, th in enumerate(thetas):
+        w = torch.softmax(logw[b * s.J:(b + 1) * s.J], 0)
+        t = th.double()
+        m = (w[:, None] * t).sum(0)
+        v = (w[:, None] * (t - m) ** 2).sum(0)
+        out.append((m.cpu().numpy(), v.cpu().numpy()))
+    return out
+
+
+def timed_run(Xs, ys, J, params, warm, steps, graph=True):
+    """W untimed + K timed iterations (captured-graph replay, or eager calls).
+    Returns the sampler (still open) and (seconds, grad evals, ESS sum)."""
+    import torch
+    from paper_2504_02627_amd import chees
+    s = chees.Sampler(Xs, ys, J, **params)
+    if graph:
+        s.run(warm)
+    else:
+        for _ in range(warm):
+            s.step(stats=False)
+            s.adapt(stats=False)
+    torch.cuda.synchronize()
+    c0 = s.counters()
+    t0 = time.perf_counter()
+    if graph:
+        s.run(steps)
+    else:
+        for _ in range(steps):
+            s.step(stats=False)
+            s.adapt(stats=False)
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    c1 = s.counters()
+    return s, T, c1["grad_evals"] - c0["grad_evals"], c1["ess_sum"] - c0["ess_sum"]
+
+
+def kernel_pass(Xs, ys, J, params, warm, steps, per_posterior_flops=None):
+    """The same run again, eager, with HIP events around every leapfrog,
+    reduction and log-likelihood launch on the sampler's stream.  Optionally
+    sums the exact flops sum_b 4 N_b d_b sum_j n_bj of the timed steps."""
+    import torch
+    from paper_2504_02627_amd import chees
+    s = chees.Sampler(Xs, ys, J, **params)
+    for _ in range(warm):
+        s.step(stats=False)
+        s.adapt(stats=False)
+    s.set_timing(True)
+    s.timing()
+    flops = 0.0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s.step(stats=False)
+        s.adapt(stats=False)
+        if per_posterior_flops is not None:
+            tr = s.trace()
+            n = tr["n"].view(s.B, tr["jcap"])[:, :J].sum(1).double().cpu().numpy()
+            flops += float((n * per_posterior_flops).sum())
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    tm = s.timing()
+    s.close()
+    return tm, flops, T
+
+
+# ---------------------------------------------------------------------------
+# matched posterior error
+# ---------------------------------------------------------------------------
+def reference_moments(Xs, ys, J, params, runs, iters, pool):
+    """Reference posterior moments: `runs` independent long runs (seeds 7777 +
+    r) of the given form with 2J particles, each averaging its weighted
+    moments over its last `pool` iterations; their mean, and the standard
+    error of that mean from the spread between runs."""
+    import numpy as np
+    from paper_2504_02627_amd import chees
+    ms, vs = [], []
+    for r in range(runs):
+        s = chees.Sampler(Xs, ys, 2 * J, **dict(params, seed=7777 + r, num_warmup=iters // 2))
+        am, av = [], []
+        for k in range(iters):
+            s.step(stats=False)
+            s.adapt(stats=False)
+            if k >= iters - pool:
+                m, v = moments(s)[0]
+                am.append(m)
+                av.append(v)
+        s.close()
+        ms.append(np.mean(am, 0))
+        vs.append(np.mean(av, 0))
+    ms, vs = np.array(ms), np.array(vs)
+    se = lambda a: a.std(0, ddof=1) / math.sqrt(len(a)) if len(a) > 1 else np.zeros(a.shape[1])
+    return dict(mean=ms.mean(0), var=vs.mean(0), se_mean=se(ms), se_var=se(vs), runs=runs,
+                iters=iters, pool=pool)
+
+
+def replicate_form(Xs, ys, J, params, seeds, iters, burn):
+    """One form over the full workload on every seed: captured-graph replay of
+    all `iters` iterations (timed), the final moments, ESS/s, evals/s, and the
+    ESS per gradient evaluation after `burn` iterations (eager replay of the
+    first seed with statistics)."""
+    import numpy as np
+    import torch
+    from paper_2504_02627_amd import chees
+    fm, fv, Ts, evs, esss = [], [], [], [], []
+    for sd in seeds:
+        s = chees.Sampler(Xs, ys, J, **dict(params, seed=sd))
+        torch.cuda.synchronize()
+        c0 = s.counters()
+        t0 = time.perf_counter()
+        s.run(iters)
+        torch.cuda.synchronize()
+        Ts.append(time.perf_counter() - t0)
+        c1 = s.counters()
+        evs.append(c1["grad_evals"] - c0["grad_evals"])
+        esss.append(c1["ess_sum"] - c0["ess_sum"])
+        m, v = moments(s)[0]
+        fm.append(m)
+        fv.append(v)
+        s.close()
+    # ESS per gradient evaluation after burn-in (paper's unit, n_j + 1 per particle)
+    s = chees.Sampler(Xs, ys, J, **dict(params, seed=seeds[0]))
+    ess_post, ge_post = 0.0, 0
+    for k in range(iters):
+        st = s.step()
+        s.adapt(stats=False)
+        if k >= burn:
+            ess_post += st["ess"]
+            ge_post += st["grad_evals"] + J
+    s.close()
+    T = float(np.sum(Ts))
+    return dict(final_mean=np.array(fm), final_var=np.array(fv), seconds=T,
+                ms_per_iteration=1e3 * T / (len(seeds) * iters),
+                evals_per_s=float(np.sum(evs)) / T, ess_per_s=float(np.sum(esss)) / T,
+                ess_per_grad_eval_after_burn_in=ess_post / max(1, ge_post))
+
+
+def matched(ref, rep, label):
+    """z of the replicate-averaged final moments against the reference,
+    per dimension, with the Monte Carlo SE of both.  Pass: at most 2 of the
+    d dimensions beyond 3 SE for the means and for the variances (a correct
+    sampler exceeds 3 SE in 0.27 % of dimensions; P(>= 3 of 100) = 0.26 %)."""
+    import numpy as np
+    R = rep["final_mean"].shape[0]
+    out = {"form": label, "seeds": R}
+    for key, refk, sek, arr in (("mean", "mean", "se_mean", rep["final_mean"]),
+                                ("var", "var", "se_var", rep["final_var"])):
+        se = np.sqrt(arr.var(0, ddof=1) / R + ref[sek] ** 2)
+        z = (arr.mean(0) - ref[refk]) / np.maximum(se, 1e-300)
+        beyond = int(np.sum(np.abs(z) > 3.0))
+        out[f"{key}_max_abs_z"] = float(np.max(np.abs(z)))
+        out[f"{key}_dims_beyond_3se"] = beyond
+        scale = np.sqrt(ref["var"]) if key == "mean" else ref["var"]
+        out[f"{key}_rms_error_rel"] = float(np.sqrt(np.mean(((arr - ref[refk]) / scale) ** 2)))
+    out["pass_3se"] = out["mean_dims_beyond_3se"] <= 2 and out["var_dims_beyond_3se"] <= 2
+    for k in ("ms_per_iteration", "evals_per_s", "ess_per_s", "ess_per_grad_eval_after_burn_in"):
+        out[k] = rep[k]
+    return out
+
+
+# ---------------------------------------------------------------------------
+# workloads
+# ---------------------------------------------------------------------------
+def headline(args, Xd, yd):
+    """FP32 and BF16 forms of the large workload: timed region, kernel pass."""
+    warm, steps = args.warmup, args.steps
+    params = large_params(max(1, (warm + steps) // 2))
+    out = {}
+    for prec in ("f32",) + (() if args.no_bf16 else ("bf16",)):
+        p = dict(params, precision=prec)
+        s, T, evals, ess = timed_run(Xd, yd, PARTICLES, p, warm, steps, graph=not args.eager)
+        s.close()
+        s1, T1, evals1, _ = timed_run(Xd, yd, PARTICLES, p, warm, steps, graph=args.eager)
+        s1.close()
+        tm, _, T2 = kernel_pass(Xd, yd, PARTICLES, p, warm, steps)
+        if evals1 != evals:
+            raise RuntimeError("the replayed pass did not repeat the timed run")
+        log(f"{prec}: {steps} timed iterations in {T:.3f} s ({1e3 * T / steps:.3f} ms/iteration)")
+        flops = 4.0 * N_ROWS * DIM * evals
+        lf_s = tm["leapfrog_ms"] / 1e3
+        out[prec] = dict(T=T, evals=evals, ess=ess, T_other=T1, T_instr=T2, tm=tm,
+                         achieved=flops / lf_s / 1e12 if lf_s > 0 else 0.0)
+    return params, out
+
+
+def batched(args):
+    """64 posteriors, N_b ~ U[500, 20000], d_b ~ U[10, 200], J = 1024 each."""
+    import numpy as np
+    import torch
+    from paper_2504_02627_amd import autotune, synth
+    dev = torch.device("cuda:0")
+    data = synth.batched_logistic(64)
+    Xs = [torch.from_numpy(X).to(dev) for X, _, _ in data]
+    ys = [torch.from_numpy(y).to(dev) for _, y, _ in data]
+    eps = min(synth.default_step_size(X.shape[0], X.shape[1]) for X, _, _ in data)
+    iters = args.other_iters
+    base = dict(step_size=eps, traj_length=eps * 32, max_leapfrog=64, num_warmup=iters // 2, seed=4)
+    nd = np.array([4.0 * X.shape[0] * X.shape[1] for X, _, _ in data])
+    out = {"workload": "64 logistic posteriors, N_b ~ U[500, 20000], d_b ~ U[10, 200], J = 1024 "
+                       f"each, one context, {iters} SMC iterations ({iters // 2} adapting)",
+           "flops_per_eval_note": "exact: sum_b 4 N_b d_b sum_j n_bj over the timed iterations"}
+    for prec in ("f32", "bf16"):
+        tuned = autotune.lookup([X.shape[1] for X in Xs], [X.shape[0] for X in Xs], 1024, prec, 64)
+        p = dict(base, precision=prec, **tuned)
+        s, T, evals, ess = timed_run(Xs, ys, 1024, p, 1, iters - 1)
+        s.close()
+        tm, flops, _ = kernel_pass(Xs, ys, 1024, p, 1, iters - 1, per_posterior_flops=nd)
+        peak = PEAK_FP32_MFMA_TFLOPS if prec == "f32" else PEAK_BF16_MFMA_TFLOPS
+        ach = flops / (tm["leapfrog_ms"] / 1e3) / 1e12 if tm["leapfrog_ms"] > 0 else 0.0
+        out[prec] = {"ms_per_iteration": 1e3 * T / (iters - 1), "evals_per_s": evals / T,
+                     "ess_per_s": ess / T, "launch_setting": tuned or "default",
+                     "leapfrog_kernel": {"achieved": round(ach, 2), "peak": peak, "unit": "TFLOP/s",
+                                         "frac": round(ach / peak, 4),
+                                         "flops_per_iteration": flops / (iters - 1),
+                                         "launches_per_iteration": tm["leapfrog_launches"] / (iters - 1),
+                                         "ms_per_iteration": tm["leapfrog_ms"] / (iters - 1)},
+                     "reduce_ms_per_iteration": tm["reduce_ms"] / (iters - 1),
+                     "loglik_ms_per_iteration": tm["loglik_ms"] / (iters - 1)}
+        log(f"batched {prec}: {out[prec]['ms_per_iteration']:.2f} ms/iteration, "
+            f"leapfrog {ach:.1f} TFLOP/s")
+    return out
+
+
+def precision_vs_oracle(args):
+    """The BF16 form on the small model (N = 200, d = 5, J = 16384, X in FP32
+    for the energies) against the exact FP64 oracle on the same Philox
+    randomness: per result after one iteration (trajectories, log-weights,
+    J_eff, log Z) and after `k` iterations (weighted moments, log Z)."""
+    import numpy as np
+    import torch
+    from oracle import philox, smc as O
+    from paper_2504_02627_amd import chees, synth
+    dev = torch.device("cuda:0")
+    X, y, _ = synth.small_logistic()
+    J, K = 16384, args.oracle_small_iters
+    e5 = synth.default_step_size(200, 5)
+    p = dict(step_size=e5, traj_length=e5 * 32, max_leapfrog=64, num_warmup=K, seed=11)
+    th0 = philox.normals_np(p["seed"], J, 0, philox.STREAM_INIT, 5).astype(np.float32)
+    s = chees.Sampler(torch.from_numpy(X).to(dev), torch.from_numpy(y).to(dev), J, precision="bf16",
+                      theta0=torch.from_numpy(th0).to(dev), **p)
+    o = O.OracleSMC(O.LogisticRegression(X.astype(np.float64), y.astype(np.float64)), J,
+                    theta0=th0.astype(np.float64), **p)
+    t0 = time.perf_counter()
+    res = {"workload": f"logistic N=200 d=5, J={J}, BF16 trajectory gradients, FP32 energies; "
+                       "oracle: exact FP64 (no BF16 emulation), same Philox streams",
+           "per_iteration": []}
+    for k in range(K):
+        st = s.step()
+        s.adapt(stats=False)
+        ost = o.step()
+        o.adapt()
+        if k == 0:
+            tr = s.trace()
+            th1 = tr["theta_prop"].cpu().numpy()[:J, :5].astype(np.float64)
+            p1 = tr["p_final"].cpu().numpy()[:J, :5].astype(np.float64)
+            num = lambda a, b: np.max(np.abs(a - b), 1) / np.maximum(np.max(np.abs(b), 1), 1e-30)
+            same_n = bool(np.array_equal(tr["n"].cpu().numpy()[:J], ost["n"]))
+            _, lw, _ = s.state()
+            lw = lw.cpu().numpy()
+            scale = np.abs(ost["H0"]) + np.abs(ost["H1"])
+            fin = np.isfinite(ost["dh"])
+            res["first_iteration"] = {
+                "step_counts_identical": same_n,
+                "trajectory_theta_rel_err_max": float(np.max(num(th1, ost["theta_prop"]))),
+                "trajectory_theta_rel_err_median": float(np.median(num(th1, ost["theta_prop"]))),
+                "trajectory_p_rel_err_max": float(np.max(num(p1, ost["p1"]))),
+                "logw_err_rel_to_H_max": float(np.max(np.abs(lw[fin] - o.logw[fin]) / scale[fin])),
+                "ess_rel_err": abs(st["ess"] - ost["ess"]) / ost["ess"],
+                "log_z_abs_err": abs(st["log_z"] - o.log_evidence())}
+        res["per_iteration"].append({"k": k + 1, "resampled_same": bool(st["resampled"]) == bool(ost["resampled"]),
+                                     "ess_rel_err": abs(st["ess"] - ost["ess"]) / ost["ess"]})
+    (m, v), = moments(s)
+    om, ov = o.moments()
+    res[f"after_{K}_iterations"] = {
+        "mean_abs_err_in_posterior_sd_max": float(np.max(np.abs(m - om) / np.sqrt(ov))),
+        "var_rel_err_max": float(np.max(np.abs(v / ov - 1))),
+        "log_z_abs_err": abs(s.log_evidence() - o.log_evidence()),
+        "note": "divergence here also carries discrete decisions (resampling, jitter ties) that "
+                "FP32 / BF16 rounding flips; per_iteration shows where the runs stop matching"}
+    res["oracle_seconds"] = time.perf_counter() - t0
+    s.close()
+    return res
+
+
+def toeplitz_forms(args):
+    """Preconditioned forms on the Toeplitz model (N = 5000, d = 100, rows
+    ~ N(0, S), S_ij = 0.95^|i-j|; J = 4096; 50 iterations, 25 adapting): ESS/s
+    beside each form's posterior error against reference moments."""
+    import torch
+    from paper_2504_02627_amd import synth
+    dev = torch.device("cuda:0")
+    X, y, _ = synth.toeplitz_logistic()
+    Xd, yd = torch.from_numpy(X).to(dev), torch.from_numpy(y).to(dev)
+    e0 = synth.default_step_size(5000, 100)
+    base = dict(max_leapfrog=64, num_warmup=ITERS // 2, adapt_step_size=True)
+    flow = dict(step_size=0.3, traj_length=2.4, precond="flow", flow_layers=4, flow_train_steps=10,
+                flow_lr=2e-5)
+    forms = {
+        "unit_mass_f32 (plain FP32, the judge)": dict(step_size=e0, traj_length=e0 * 32),
+        "unit_mass_bf16": dict(step_size=e0, traj_length=e0 * 32, precision="bf16"),
+        "diagonal_mass_f32": dict(step_size=0.05, traj_length=1.6, precond="diag"),
+        "flow_base_only_f32": dict(step_size=0.3, traj_length=2.4, precond="flow", flow_layers=0),
+        "flow_4x128_f32": flow,
+        "flow_4x128_bf16 (BF16 + flow, the headline form)": dict(flow, precision="bf16"),
+    }
+    seeds = [3 + 100 * r for r in range(args.replicates)]
+    log("toeplitz: reference moments (diagonal mass, long runs)")
+    ref = reference_moments(Xd, yd, 4096, dict(base, **forms["diagonal_mass_f32"]),
+                            args.ref_runs, args.ref_iters, args.ref_iters // 3)
+    out = {"workload": "logistic N=5000, d=100, rows ~ N(0, S), S_ij = 0.95^|i-j|, J=4096, "
+                       f"{ITERS} SMC iterations (25 adapting), {len(seeds)} seeds per form",
+           "reference": f"diagonal-mass FP32 runs with 2J particles, {args.ref_runs} seeds x "
+                        f"{args.ref_iters} iterations, moments averaged over the last third",
+           "forms": {}}
+    for name, f in forms.items():
+        rep = replicate_form(Xd, yd, 4096, dict(base, **f), seeds, ITERS, ITERS // 2)
+        out["forms"][name] = matched(ref, rep, name)
+        log(f"toeplitz {name}: {rep['ms_per_iteration']:.2f} ms/iteration, "
+            f"ESS/s {rep['ess_per_s'] / 1e6:.3f} M, pass {out['forms'][name]['pass_3se']}")
+    plain = out["forms"]["unit_mass_f32 (plain FP32, the judge)"]
+    head = out["forms"]["flow_4x128_bf16 (BF16 + flow, the headline form)"]
+    out["headline"] = {
+        "bf16_flow_ess_per_s_over_plain_f32": head["ess_per_s"] / plain["ess_per_s"],
+        "bf16_flow_matched_error": head["pass_3se"], "plain_f32_matched_error": plain["pass_3se"],
+        "verdict": ("BF16 + flow beats plain FP32 in ESS/s at matched error"
+                    if head["ess_per_s"] > plain["ess_per_s"] and head["pass_3se"] and plain["pass_3se"]
+                    else "BF16 + flow does NOT beat plain FP32 in ESS/s at matched error on this run")}
+    return out
+
+
+def cpu_baseline(X, y, params, seconds):
+    """The oracle, as it stands, on a bounded sample of the headline workload."""
+    import numpy as np
     from oracle import philox, smc as O
     Js = 512
     t = O.LogisticRegression(X.astype(np.float64), y.astype(np.float64))
@@ -79,237 +461,60 @@ def cpu_baseline(X, y, params, seconds):
         if time.perf_counter() - t0 >= seconds or iters >= ITERS:
             break
     dt = time.perf_counter() - t0
-    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    threads = blas_threads()
+    ncpu, model = host_cpu()
     return {"value": evals / dt, "unit": "particle-gradient evals/s", "cores": int(threads),
-            "kind": "oracle",
-            "sample": f"{Js} particles of the same workload, first {iters} SMC iterations "
-                      f"({evals} particle-gradient evals in {dt:.1f} s, FP64 numpy, "
-                      f"{threads} BLAS threads)"}
+            "kind": "oracle", "host_cpus": ncpu, "cpu_model": model,
+            "sample": f"{Js} particles of the headline workload, first {iters} SMC iterations "
+                      f"({evals} particle-gradient evals in {dt:.1f} s, FP64 numpy, {threads} BLAS "
+                      f"threads on {ncpu} available CPUs)"}
 
 
-def _steps(s, n):
-    for _ in range(n):
-        s.step(stats=False)
-        s.adapt(stats=False)
-
-
-def _moments(s):
-    import torch
-    theta, logw, _ = s.state()
-    w = torch.softmax(logw, 0)
-    th = theta.double()
-    mean = (w[:, None] * th).sum(0)
-    var = (w[:, None] * (th - mean) ** 2).sum(0)
-    return mean.cpu().numpy(), var.cpu().numpy()
-
-
-def run_form(Xd, yd, params, precision, args):
-    """One form of the sampler on the workload.
-
-    Pass 1 (the timed region of `value`): warm-up, then the timed iterations
-    replayed from the captured iteration graph (smc_run), with no per-kernel
-    instrumentation.  Pass 2: the same with eager smc_step + chees_adapt calls.
-    Pass 3: the same seed from scratch -- the run is deterministic, so it
-    repeats exactly the same kernels -- eager, with HIP events around every
-    leapfrog, reduction and log-likelihood launch on the sampler's stream, for
-    the per-kernel averages.  Replicates with other seeds give the
-    spread of the final posterior moments (untimed)."""
-    import torch
-    from paper_2504_02627_amd import chees
-
-    def timed(seed, instrument, graph):
-        s = chees.Sampler(Xd, yd, PARTICLES, precision=precision, **dict(params, seed=seed))
-        if graph:
-            s.run(args.warmup)          # the first call captures the iteration graph
-        else:
-            _steps(s, args.warmup)
-        torch.cuda.synchronize()
-        c0 = s.counters()
-        if instrument:
-            s.set_timing(True)
-            s.timing()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        if graph:
-            s.run(args.steps)
-        else:
-            _steps(s, args.steps)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        tm = s.timing() if instrument else None
-        c1 = s.counters()
-        return s, t1 - t0, c1["grad_evals"] - c0["grad_evals"], c1["ess_sum"] - c0["ess_sum"], tm
-
-    s, T, evals, ess_sum, _ = timed(params["seed"], False, not args.eager)
-    print(f"[bench] {precision}: timed {args.steps} steps in {T:.3f} s", file=sys.stderr, flush=True)
-    moments = [_moments(s)]
-    s.close()
-    s1, T1, evals1, _, _ = timed(params["seed"], False, args.eager)
-    s1.close()
-    s2, T2, evals2, _, tm = timed(params["seed"], True, False)
-    s2.close()
-    if evals2 != evals or evals1 != evals:
-        raise RuntimeError("the replayed passes did not repeat the timed run")
-    for r in range(1, args.replicates):
-        sr = chees.Sampler(Xd, yd, PARTICLES, precision=precision,
-                           **dict(params, seed=params["seed"] + 1000 * r))
-        sr.run(args.warmup + args.steps)
-        moments.append(_moments(sr))
-        sr.close()
-    print(f"[bench] {precision}: instrumented pass {T2:.3f} s, {len(moments)} replicates",
-          file=sys.stderr, flush=True)
-    return {"evals": evals, "ess_sum": ess_sum, "seconds": T, "timing": tm,
-            "other_mode_seconds": T1, "instrumented_seconds": T2, "moments": moments}
-
-
-def long_reference(Xd, yd, params, precision, iters, pool):
-    """Posterior moments from one long run (seed 7777, twice the particles): the
-    weighted means and variances averaged over the last `pool` of `iters` SMC
-    iterations."""
+def oracle_timing(args):
+    """The oracle on the other workloads (host cores as available, and one
+    thread): the small model in full (J = 256, 20 iterations), the small model
+    at J = 16384 and the Toeplitz model at J = 4096 on bounded samples."""
     import numpy as np
-    from paper_2504_02627_amd import chees
-    s = chees.Sampler(Xd, yd, 2 * PARTICLES, precision=precision, **dict(params, seed=7777))
-    ms, vs = [], []
-    for k in range(iters):
-        s.step(stats=False)
-        s.adapt(stats=False)
-        if k >= iters - pool:
-            m, v = _moments(s)
-            ms.append(m)
-            vs.append(v)
-    s.close()
-    return np.mean(ms, 0), np.mean(vs, 0)
-
-
-def moment_match(ref, a, b, ta, tb):
-    """Posterior error of the two forms at the end of the workload, over R
-    replicate seeds each, against the long-run reference moments `ref`:
-    RMS over dimensions and replicates of (mean - ref_mean) / ref_sd (bias and
-    spread together), the same for the variances relative to ref_var, the
-    per-dimension two-sample z of the forms' replicate-averaged means, and the
-    efficiency at matched error (T_a err_a^2) / (T_b err_b^2)."""
-    import numpy as np
-    rm, rv = ref
-    sd = np.sqrt(rv)
-    ma = np.array([m for m, _ in a]); mb = np.array([m for m, _ in b])
-    va = np.array([v for _, v in a]); vb = np.array([v for _, v in b])
-    R = len(a)
-    ea = float(np.sqrt(np.mean(((ma - rm) / sd) ** 2)))
-    eb = float(np.sqrt(np.mean(((mb - rm) / sd) ** 2)))
-    out = {"replicates": R, "reference": "FP32 form, 2J particles, seed 7777, moments averaged "
-                                         "over the last third of a long run",
-           "mean_error_rms_ref_sd": [ea, eb],
-           "var_error_rms_rel": [float(np.sqrt(np.mean((va / rv - 1) ** 2))),
-                                 float(np.sqrt(np.mean((vb / rv - 1) ** 2)))],
-           "efficiency_at_matched_error_vs_f32": float((ta * ea ** 2) / (tb * eb ** 2))}
-    if R >= 2:
-        sa, sb = ma.std(0, ddof=1), mb.std(0, ddof=1)
-        z = np.abs(ma.mean(0) - mb.mean(0)) / np.sqrt(sa ** 2 / R + sb ** 2 / R)
-        out.update({"max_abs_z_between_forms": float(z.max()),
-                    "frac_dims_within_3se_between_forms": float(np.mean(z <= 3.0))})
-    return out
-
-
-def run_workload(Xs, ys, J, params, iters, burn):
-    """One sampler over `iters` SMC iterations (captured-graph replay for the
-    wall time, then the same seed again eagerly with per-kernel events).
-    Returns throughput, ESS figures after `burn` iterations and kernel times."""
-    import torch
-    from paper_2504_02627_amd import chees
-    s = chees.Sampler(Xs, ys, J, **params)
-    s.run(1)
-    torch.cuda.synchronize()
-    c0 = s.counters()
-    t0 = time.perf_counter()
-    s.run(iters - 1)
-    torch.cuda.synchronize()
-    T = time.perf_counter() - t0
-    c1 = s.counters()
-    s.close()
-    s = chees.Sampler(Xs, ys, J, **params)
-    s.set_timing(True)
-    ess_post, ge_post = 0.0, 0
-    for k in range(iters):
-        st = s.step()
-        s.adapt(stats=False)
-        if k >= burn:
-            ess_post += st["ess"]
-            ge_post += st["grad_evals"] + J * s.B
-    tm = s.timing()
-    s.close()
-    evals = c1["grad_evals"] - c0["grad_evals"]
-    return {"ms_per_iteration": 1e3 * T / (iters - 1), "evals_per_s": evals / T,
-            "ess_per_s": (c1["ess_sum"] - c0["ess_sum"]) / T,
-            "ess_per_grad_eval_after_burn_in": ess_post / max(1, ge_post),
-            "kernel_ms_per_iteration": {k[:-3]: round(v / iters, 4) for k, v in tm.items()
-                                        if k.endswith("_ms")},
-            "leapfrog_launches": tm["leapfrog_launches"]}
-
-
-def other_workloads(args):
-    """The batched form, the precision form on the small model and the flow
-    preconditioner on the Toeplitz model, with their comparison forms."""
-    import numpy as np
-    import torch
+    from threadpoolctl import threadpool_limits
+    from oracle import philox, smc as O
     from paper_2504_02627_amd import synth
-    dev = torch.device("cuda:0")
-    out = {}
-    # batched form: 64 posteriors, N ~ U[500, 20000], d ~ U[10, 200], J = 1024 each
-    data = synth.batched_logistic(64)
-    Xs = [torch.from_numpy(X).to(dev) for X, _, _ in data]
-    ys = [torch.from_numpy(y).to(dev) for _, y, _ in data]
-    eps = min(synth.default_step_size(X.shape[0], X.shape[1]) for X, _, _ in data)
-    p = dict(step_size=eps, traj_length=eps * 32, max_leapfrog=64, num_warmup=25, seed=4)
-    r = run_workload(Xs, ys, 1024, p, args.other_iters, args.other_iters // 2)
-    r["workload"] = ("64 logistic posteriors, N_b ~ U[500, 20000], d_b ~ U[10, 200], J = 1024 "
-                     "each, FP32 trajectories, one context")
-    r["leapfrog_kernel_note"] = ("achieved TFLOP/s not reported: the flop count per launch "
-                                 "mixes posteriors of different N_b d_b")
-    out["batched_64_posteriors"] = r
-    print("[bench] batched form done", file=sys.stderr, flush=True)
-    # precision form on the small model: N = 200, d = 5, J = 16384
+
+    def run(X, y, J, p, max_iters, seconds):
+        t = O.LogisticRegression(X.astype(np.float64), y.astype(np.float64))
+        o = O.OracleSMC(t, J, theta0=philox.normals_np(p["seed"], J, 0, philox.STREAM_INIT,
+                                                        X.shape[1]), **p)
+        ev, it = 0, 0
+        t0 = time.perf_counter()
+        while it < max_iters:
+            st = o.step()
+            o.adapt()
+            ev += st["grad_evals"]
+            it += 1
+            if time.perf_counter() - t0 >= seconds:
+                break
+        dt = time.perf_counter() - t0
+        return {"evals_per_s": ev / dt, "iterations": it, "seconds": dt,
+                "ms_per_iteration": 1e3 * dt / it}
+
     X, y, _ = synth.small_logistic()
-    Xd, yd = torch.from_numpy(X).to(dev), torch.from_numpy(y).to(dev)
     e5 = synth.default_step_size(200, 5)
-    p = dict(step_size=e5, traj_length=e5 * 32, max_leapfrog=64, num_warmup=10, seed=1,
-             adapt_step_size=True)
-    out["small_model_J16384"] = {
-        prec: run_workload(Xd if prec == "f32" else Xd.to(torch.bfloat16), yd, 16384,
-                           dict(p, precision=prec), 20, 10)
-        for prec in ("f32", "bf16")}
-    # the same with one leapfrog launch per step instead of whole trajectories
-    os.environ["CHEES_SMC_PER_STEP"] = "1"
-    try:
-        out["small_model_J16384"]["f32_per_step_launches"] = run_workload(
-            Xd, yd, 16384, dict(p, precision="f32"), 20, 10)
-    finally:
-        del os.environ["CHEES_SMC_PER_STEP"]
-    out["small_model_J16384"]["workload"] = ("logistic N=200, d=5, J=16384, 20 iterations; bf16: "
-                                             "X stored in bfloat16; whole trajectories in one "
-                                             "launch unless named per-step")
-    # the small model at J = 256 (latency-bound: 16 waves)
-    out["small_model_J256"] = run_workload(Xd, yd, 256, dict(p, precision="f32"), 20, 10)
-    out["small_model_J256"]["workload"] = "logistic N=200, d=5, J=256, 20 iterations, FP32"
-    print("[bench] small model done", file=sys.stderr, flush=True)
-    # flow preconditioner on the Toeplitz model: N = 5000, d = 100, J = 4096
-    X, y, _ = synth.toeplitz_logistic()
-    Xd, yd = torch.from_numpy(X).to(dev), torch.from_numpy(y).to(dev)
+    ps = dict(step_size=e5, traj_length=e5 * 32, max_leapfrog=64, num_warmup=10, seed=1,
+              adapt_step_size=True)
+    ncpu, model = host_cpu()
+    out = {"host_cpus": ncpu, "cpu_model": model, "blas_threads": blas_threads()}
+    out["small_J256_full"] = run(X, y, 256, ps, 20, 1e9)
+    out["small_J16384"] = dict(run(X, y, 16384, ps, 20, args.oracle_seconds),
+                               note="bounded sample: the first iterations of 20")
+    Xt, yt, _ = synth.toeplitz_logistic()
     e0 = synth.default_step_size(5000, 100)
-    base = dict(max_leapfrog=64, num_warmup=25, seed=3, adapt_step_size=True)
-    forms = {
-        "unit_mass": dict(step_size=e0, traj_length=e0 * 32),
-        "diagonal_mass": dict(step_size=0.05, traj_length=1.6, precond="diag"),
-        "flow_base_only": dict(step_size=0.3, traj_length=2.4, precond="flow", flow_layers=0),
-        "flow_4x128_trained": dict(step_size=0.3, traj_length=2.4, precond="flow", flow_layers=4,
-                                   flow_train_steps=10, flow_lr=2e-5),
-    }
-    fl = {}
-    for name, f in forms.items():
-        fl[name] = run_workload(Xd, yd, 4096, dict(base, **f), 50, 25)
-    fl["workload"] = ("logistic N=5000, d=100, rows ~ N(0, S), S_ij = 0.95^|i-j|, J=4096, "
-                      "50 iterations (25 warm-up), FP32 likelihood")
-    out["toeplitz_flow"] = fl
-    print("[bench] flow forms done", file=sys.stderr, flush=True)
+    pt = dict(step_size=e0, traj_length=e0 * 32, max_leapfrog=64, num_warmup=25, seed=3,
+              adapt_step_size=True)
+    out["toeplitz_J4096"] = dict(run(Xt, yt, 4096, pt, 50, 1.0),
+                                 note="first iteration of 50 (about 13 s each on 8 cores); "
+                                      "the full run extrapolates to 50 x ms_per_iteration")
+    with threadpool_limits(1):
+        out["one_thread_small_J16384"] = dict(run(X, y, 16384, ps, 20, args.oracle_seconds / 2),
+                                              threads=1)
     return out
 
 
@@ -319,17 +524,18 @@ def main():
     ap.add_argument("--steps", type=int, default=ITERS - 5)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--oracle-seconds", type=float, default=12.0)
+    ap.add_argument("--oracle-small-iters", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bf16", action="store_true", help="skip the BF16 precision form")
     ap.add_argument("--no-other", action="store_true",
-                    help="skip the batched, small-model and flow workloads")
-    ap.add_argument("--other-iters", type=int, default=50)
+                    help="skip matched error, the batched, small-model and Toeplitz workloads")
+    ap.add_argument("--other-iters", type=int, default=25)
     ap.add_argument("--eager", action="store_true",
                     help="time eager step/adapt calls for `value` (default: graph replay)")
-    ap.add_argument("--ref-iters", type=int, default=300,
-                    help="iterations of the long reference runs (last third pooled)")
-    ap.add_argument("--replicates", type=int, default=10,
-                    help="seeds per form for the posterior-error comparison")
+    ap.add_argument("--replicates", type=int, default=8, help="seeds per form (matched error)")
+    ap.add_argument("--ref-runs", type=int, default=8)
+    ap.add_argument("--ref-iters", type=int, default=150)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of known size (counter scaling)")
     args = ap.parse_args()
@@ -345,7 +551,7 @@ def main():
 
     import numpy as np
     import torch
-    from paper_2504_02627_amd import chees, synth
+    from paper_2504_02627_amd import synth
 
     dev = torch.device("cuda:0")
     if args.copy_calibration:
@@ -359,85 +565,96 @@ def main():
         return
 
     X, y, _ = synth.large_logistic()
-    params = workload_params()
-    Xd = torch.from_numpy(X).to(dev)
-    yd = torch.from_numpy(y).to(dev)
-
-    f32 = run_form(Xd, yd, params, "f32", args)
-    flops = 4.0 * N_ROWS * DIM * f32["evals"]
-    tm = f32["timing"]
-    lf_s = tm["leapfrog_ms"] / 1e3
-    achieved = flops / lf_s / 1e12 if lf_s > 0 else 0.0
+    Xd, yd = torch.from_numpy(X).to(dev), torch.from_numpy(y).to(dev)
+    params, H = headline(args, Xd, yd)
+    f32 = H["f32"]
+    tm = f32["tm"]
+    T = f32["T"]
     launches = max(1, tm["leapfrog_launches"])
-    traffic = traffic_for_current_kernel()
-    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_FP32_MFMA_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4),
-                "traffic": traffic,
+    flops = 4.0 * N_ROWS * DIM * f32["evals"]
+    roofline = {"bound": "mfma", "achieved": round(f32["achieved"], 2), "peak": PEAK_FP32_MFMA_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(f32["achieved"] / PEAK_FP32_MFMA_TFLOPS, 4),
+                "traffic": traffic_for_current_kernel(),
                 "kernel": "k_lf_partial<7>: fused leapfrog step (drift, X theta'^T -> sigmoid -> "
                           "R X on v_mfma_f32_16x16x4f32) over a data-row split",
                 "algorithmic_flops_per_launch": flops / launches,
                 "avg_launch_ms": tm["leapfrog_ms"] / launches, "launches": tm["leapfrog_launches"],
                 "flop_unit": "4 N d per particle-gradient evaluation",
-                "timing_pass": "HIP events on the sampler stream, same-seed replay of the timed steps "
-                               f"({1e3 * f32['instrumented_seconds'] / args.steps:.3f} ms/step with events)",
-                "other_kernels_ms_per_step": {
-                    "k_lf_reduce": tm["reduce_ms"] / args.steps,
-                    "k_loglik": tm["loglik_ms"] / args.steps}}
-    T = f32["seconds"]
+                "timing_pass": "HIP events on the sampler stream, same-seed eager replay of the timed "
+                               f"iterations ({1e3 * f32['T_instr'] / args.steps:.3f} ms/iteration "
+                               "with events)",
+                "other_kernels_ms_per_step": {"k_lf_reduce": tm["reduce_ms"] / args.steps,
+                                              "k_loglik": tm["loglik_ms"] / args.steps}}
+    total = args.warmup + args.steps
     out = {
         "metric": METRIC, "value": f32["evals"] / T, "unit": "particle-gradient evals/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * T / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"logistic regression N={N_ROWS} d={DIM}, J={PARTICLES} particles, "
-                               f"{ITERS} SMC iterations (warm-up {args.warmup} + timed {args.steps}), "
-                               f"<= {NMAX} leapfrog steps, 1-d Halton jitter, systematic resampling",
+                               f"{total} SMC iterations run (warm-up {args.warmup} untimed + "
+                               f"{args.steps} timed; ChEES adaptation for the first "
+                               f"{params['num_warmup']}), <= {NMAX} leapfrog steps, 1-d Halton "
+                               f"jitter, systematic resampling",
                    "particles": PARTICLES, "rows": N_ROWS, "dim": DIM, "max_leapfrog": NMAX,
+                   "iterations_run": total, "adapting_iterations": params["num_warmup"],
                    "parallelism": "single GPU"},
-        "ms_per_step_other_mode": 1e3 * f32["other_mode_seconds"] / args.steps,
+        "ms_per_step_other_mode": 1e3 * f32["T_other"] / args.steps,
         "launch_mode": "eager smc_step + chees_adapt" if args.eager else
                        "captured iteration graph (smc_run); other mode = eager calls",
-        "ess_per_s": f32["ess_sum"] / T,
-        "ess_per_grad_eval": f32["ess_sum"] / (f32["evals"] + PARTICLES * args.steps),
+        "ess_per_s": f32["ess"] / T,
+        "ess_per_grad_eval": f32["ess"] / (f32["evals"] + PARTICLES * args.steps),
         "roofline": roofline,
     }
-    if not args.no_bf16:
-        bf = run_form(Xd, yd, params, "bf16", args)
-        tb = bf["timing"]
-        fl_b = 4.0 * N_ROWS * DIM * bf["evals"]
-        ach_b = fl_b / (tb["leapfrog_ms"] / 1e3) / 1e12 if tb["leapfrog_ms"] > 0 else 0.0
-        print("[bench] long-run reference moments ...", file=sys.stderr, flush=True)
-        ref = long_reference(Xd, yd, params, "f32", args.ref_iters, args.ref_iters // 3)
-        ref_b = long_reference(Xd, yd, params, "bf16", args.ref_iters, args.ref_iters // 3)
-        z = moment_match(ref, f32["moments"], bf["moments"], T, bf["seconds"])
-        z["bf16_long_run_vs_reference_mean_rms_sd"] = float(
-            np.sqrt(np.mean((ref_b[0] - ref[0]) ** 2 / ref[1])))
-        z["bf16_long_run_vs_reference_var_rms_rel"] = float(
-            np.sqrt(np.mean((ref_b[1] / ref[1] - 1) ** 2)))
+    if "bf16" in H:
+        b = H["bf16"]
+        tb = b["tm"]
         out["forms"] = {"bf16": {
-            "what": "same workload and target: X held in FP32 for the energies (compensated "
-                    "FP32 sums, weights exact for the FP32-data posterior) and in bfloat16 for "
-                    "the trajectory gradients on v_mfma_f32_16x16x32_bf16 (FP32 accumulation); "
-                    "LSE/ESS/evidence FP64",
-            "value": bf["evals"] / bf["seconds"], "unit": "particle-gradient evals/s",
-            "ms_per_step": 1e3 * bf["seconds"] / args.steps,
-            "ess_per_s": bf["ess_sum"] / bf["seconds"],
-            "speedup_vs_f32_evals": (bf["evals"] / bf["seconds"]) / (f32["evals"] / T),
-            "speedup_vs_f32_ess_per_s": (bf["ess_sum"] / bf["seconds"]) / (f32["ess_sum"] / T),
-            "leapfrog_kernel": {"achieved": round(ach_b, 2), "peak": PEAK_BF16_MFMA_TFLOPS,
-                                "unit": "TFLOP/s", "frac": round(ach_b / PEAK_BF16_MFMA_TFLOPS, 4),
-                                "avg_launch_ms": tb["leapfrog_ms"] / max(1, tb["leapfrog_launches"])},
+            "what": "same workload and target: X in FP32 for the energies (compensated FP32 sums, "
+                    "weights exact for the FP32-data posterior) and in bfloat16, label signs folded "
+                    "in, for the trajectory gradients on v_mfma_f32_32x32x16_bf16 (FP32 "
+                    "accumulation, 32 particles per wave); LSE/ESS/evidence FP64",
+            "value": b["evals"] / b["T"], "unit": "particle-gradient evals/s",
+            "ms_per_step": 1e3 * b["T"] / args.steps, "ess_per_s": b["ess"] / b["T"],
+            "speedup_vs_f32_evals": (b["evals"] / b["T"]) / (f32["evals"] / T),
+            "leapfrog_kernel": {"achieved": round(b["achieved"], 2), "peak": PEAK_BF16_MFMA_TFLOPS,
+                                "unit": "TFLOP/s",
+                                "frac": round(b["achieved"] / PEAK_BF16_MFMA_TFLOPS, 4),
+                                "avg_launch_ms": tb["leapfrog_ms"] / max(1, tb["leapfrog_launches"]),
+                                "launches": tb["leapfrog_launches"]},
             "other_kernels_ms_per_step": {"k_lf_reduce": tb["reduce_ms"] / args.steps,
                                           "k_loglik": tb["loglik_ms"] / args.steps},
-            "instrumented_ms_per_step": 1e3 * bf["instrumented_seconds"] / args.steps,
-            "ms_per_step_other_mode": 1e3 * bf["other_mode_seconds"] / args.steps,
-            "posterior_vs_f32": z,
-        }}
+            "ms_per_step_other_mode": 1e3 * b["T_other"] / args.steps}}
     if not args.no_other:
-        out["other_workloads"] = other_workloads(args)
+        # every form of the large workload over the full 50 iterations
+        log("matched error: large workload reference (FP32 long runs)")
+        full = large_params(ITERS // 2)
+        seeds = [2 + 1000 * r for r in range(args.replicates)]
+        ref = reference_moments(Xd, yd, PARTICLES, dict(full, precision="f32"), args.ref_runs,
+                                args.ref_iters, args.ref_iters // 3)
+        me = {"workload": f"large workload, {ITERS} SMC iterations (25 adapting), "
+                          f"{len(seeds)} seeds per form",
+              "reference": f"plain FP32 with 2J particles, {args.ref_runs} seeds x {args.ref_iters} "
+                           "iterations, moments averaged over the last third",
+              "criterion": "a form passes when at most 2 of the 100 dimensions lie beyond 3 MC SE "
+                           "for the means and for the variances", "forms": {}}
+        for prec in ("f32",) + (() if args.no_bf16 else ("bf16",)):
+            rep = replicate_form(Xd, yd, PARTICLES, dict(full, precision=prec), seeds, ITERS, ITERS // 2)
+            me["forms"][prec] = matched(ref, rep, prec)
+            log(f"matched error {prec}: pass {me['forms'][prec]['pass_3se']}, "
+                f"ESS/s {rep['ess_per_s'] / 1e6:.3f} M")
+        if "bf16" in me["forms"]:
+            me["bf16_over_f32_ess_per_s"] = me["forms"]["bf16"]["ess_per_s"] / me["forms"]["f32"]["ess_per_s"]
+        out["matched_error"] = me
+        out["batched"] = batched(args)
+        out["precision_vs_oracle"] = precision_vs_oracle(args)
+        log("precision vs oracle done")
+        out["toeplitz_flow"] = toeplitz_forms(args)
     if not args.no_cpu_baseline:
-        print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(X, y, params, args.cpu_seconds)
+        if not args.no_other:
+            out["oracle_timing"] = oracle_timing(args)
     print(json.dumps(out), flush=True)
 
 
