@@ -45,7 +45,8 @@ typedef enum {
   SMC_EDEVICE = -2,     /* a HIP call failed (see smc_last_error)          */
   SMC_EDEGENERATE = -3, /* every log-weight is -inf or NaN                 */
   SMC_ESTATE = -4,      /* calls out of order (e.g. chees_adapt before a step) */
-  SMC_ENOMEM = -5       /* workspace smaller than smc_workspace_bytes      */
+  SMC_ENOMEM = -5,      /* workspace smaller than smc_workspace_bytes      */
+  SMC_WADAPTIVE = 1     /* success with a warning: see log_evidence        */
 } smc_status;
 
 /* data type of X */
@@ -358,7 +359,13 @@ smc_status resample_indices_noalloc(const double *w, int32_t J, const double *u,
 
 /* log Z_hat = C + LSE(log w), C the sum of LSE(log w) over past resamplings
  * (the standard SMC evidence estimator).  Synchronises.  log_z_host: posterior
- * 0; per_posterior_host: nullable host [B]. */
+ * 0; per_posterior_host: nullable host [B].  Returns SMC_WADAPTIVE (positive:
+ * the estimates are written) when some move of this context, under
+ * SMC_PRECOND_FLOW, used couplings fitted to the very population it moved:
+ * the weights then no longer correct for a fixed proposal, so the estimate is
+ * adaptive and biased (measured upward, a few tenths in log Z); a context whose
+ * couplings only ever came from smc_set_flow, or that never fitted
+ * (flow_train_steps 0), returns SMC_OK.  smc_last_error names the count. */
 smc_status log_evidence(smc_ctx *ctx, double *log_z_host, double *per_posterior_host);
 
 /* Copy the state into caller DEVICE buffers (each nullable): theta (B*J) x d_b

@@ -13,8 +13,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libchees_smc.so")
 
 SMC_OK, SMC_EINVAL, SMC_EDEVICE, SMC_EDEGENERATE, SMC_ESTATE, SMC_ENOMEM = 0, -1, -2, -3, -4, -5
+SMC_WADAPTIVE = 1
 STATUS = {0: "SMC_OK", -1: "SMC_EINVAL", -2: "SMC_EDEVICE", -3: "SMC_EDEGENERATE",
-          -4: "SMC_ESTATE", -5: "SMC_ENOMEM"}
+          -4: "SMC_ESTATE", -5: "SMC_ENOMEM", 1: "SMC_WADAPTIVE"}
 SMC_F32, SMC_BF16 = 0, 1
 JITTER = {"halton1d": 0, "none": 1, "haltonNd": 2, "uniform": 3, "haltonNd_inv": 4,
           "primes": 5, "primes_inv": 6, "golden": 7, "equidistant": 8,
@@ -308,6 +309,7 @@ class Sampler:
         elif tune not in (None, "cache"):
             raise ValueError("tune: None or 'cache'")
         self.tuned = {k: params.get(k, 0) for k in ("lf_items", "lf_split_cap")}
+        self.evidence_adaptive = False
         self.params = make_params(self.J, **params)
         nbytes = self.lib.smc_workspace_bytes(ctypes.byref(self.prob), ctypes.byref(self.params))
         if nbytes == 0:
@@ -371,10 +373,15 @@ class Sampler:
         return anc
 
     def log_evidence(self, per_posterior=False):
+        """log Z_hat of posterior 0 (or the list over posteriors).  Sets
+        evidence_adaptive: True when a flow move used couplings fitted to the
+        population it moved, so that the estimate is adaptive and biased."""
         lz = ctypes.c_double()
         per = (ctypes.c_double * self.B)()
         rc = self.lib.log_evidence(self.ctx, ctypes.byref(lz), per)
-        self._check(rc, "log_evidence")
+        self.evidence_adaptive = rc == SMC_WADAPTIVE
+        if rc != SMC_WADAPTIVE:
+            self._check(rc, "log_evidence")
         return list(per) if per_posterior else lz.value
 
     def state(self):

@@ -985,9 +985,14 @@ __global__ void k_flow_reset(Dev D, FlowNet F) {
   if (blockIdx.x == 0 && threadIdx.x == 0) D.fstate[1] = 0;
 }
 
-// Count the Adam steps of an iteration's fit (after its last k_flow_adam).
+// Count the Adam steps of an iteration's fit (after its last k_flow_adam), and
+// the iterations whose move used couplings fitted to the population it moved
+// (never reset: the evidence estimate carries every such iteration).
 __global__ void k_flow_tick(Dev D, int steps) {
-  if (!D.ps[0].resampled) D.fstate[1] += steps;
+  if (!D.ps[0].resampled) {
+    D.fstate[1] += steps;
+    D.fstate[2] += 1;
+  }
 }
 
 // The gradient the last Adam step used: the ordered sum of the chunk partials.

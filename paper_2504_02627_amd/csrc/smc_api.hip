@@ -1059,6 +1059,9 @@ smc_status log_evidence(smc_ctx *ctx, double *log_z_host, double *per_posterior_
   if (!ctx) return SMC_EINVAL;
   CK(hipMemcpyAsync(ctx->ps_host.data(), ctx->D.ps, ctx->D.B * sizeof(PState),
                     hipMemcpyDeviceToHost, ctx->st));
+  int fitted = 0;
+  if (ctx->D.flow)
+    CK(hipMemcpyAsync(&fitted, ctx->D.fstate + 2, sizeof(int), hipMemcpyDeviceToHost, ctx->st));
   CK(hipStreamSynchronize(ctx->st));
   smc_status r = SMC_OK;
   for (int b = 0; b < ctx->D.B; ++b) {
@@ -1067,6 +1070,12 @@ smc_status log_evidence(smc_ctx *ctx, double *log_z_host, double *per_posterior_
     if (!(S.S > 0.0)) r = SMC_EDEGENERATE;
     if (b == 0 && log_z_host) *log_z_host = lz;
     if (per_posterior_host) per_posterior_host[b] = lz;
+  }
+  if (r == SMC_OK && fitted > 0) {
+    ctx->err = "log_evidence: " + std::to_string(fitted) +
+               " move(s) used flow couplings fitted to the population they moved; the estimate "
+               "carries the bias of that adaptation";
+    r = SMC_WADAPTIVE;
   }
   return r;
 }

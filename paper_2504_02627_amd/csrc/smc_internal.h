@@ -177,7 +177,7 @@ struct Dev {                    // pointers carved from the workspace
   float *fbias;                 // BF16-rounded biases (flat offsets)
   float *fgrad, *fadm, *fadv;   // parameter gradient and Adam moments
   float *ftape;                 // per particle and layer activations
-  int *fstate;                  // [1]: Adam steps taken by the fit
+  int *fstate;                  // [1]: Adam steps taken by the fit; [2]: fitted moves
 };
 
 // Host copy of one posterior's packing sizes.

@@ -192,3 +192,25 @@ def test_flow_with_no_training_and_identity_couplings_is_a_dense_mass():
     assert e <= 1e-5
     np.testing.assert_allclose(tr["logdet"].cpu().numpy()[:J], np.sum(np.log(np.diag(L))),
                                rtol=1e-5)
+
+
+def test_evidence_is_flagged_adaptive_after_a_fit():
+    """log_evidence returns SMC_WADAPTIVE once a move used couplings fitted to
+    the population it moved (the estimate is then adaptive); without a fit the
+    same estimate comes back with SMC_OK.  The value is the evidence
+    bookkeeping either way."""
+    from paper_2504_02627_amd import chees
+    N, d, J = 300, 7, 256
+    lz = {}
+    for ntrain in (0, 3):
+        X, y, theta0, params, s, t, rng = _setup(N, d, J, 12, ntrain, 1e-3, ess_frac=0.0)
+        s.log_evidence()
+        assert not s.evidence_adaptive
+        s.step()
+        lz[ntrain] = s.log_evidence()
+        rc = s.lib.log_evidence(s.ctx, None, None)
+        log(f"[flow evidence] train steps {ntrain}: log Z {lz[ntrain]:.6f} status {rc}")
+        assert s.evidence_adaptive == (ntrain > 0)
+        assert rc == (chees.SMC_WADAPTIVE if ntrain > 0 else chees.SMC_OK)
+        assert math.isfinite(lz[ntrain])
+        s.close()
