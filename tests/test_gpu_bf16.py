@@ -1,5 +1,5 @@
 """Precision form: trajectory gradients with theta', X and the residual in
-bfloat16 on v_mfma_f32_16x16x32_bf16 (FP32 accumulation); energies for the
+bfloat16 on the BF16 matrix cores (FP32 accumulation); energies for the
 weights recomputed in FP32 with compensated sums; LSE, ESS and evidence in
 FP64.  The oracle's BF16 mode (grad_bf16) rounds the same operands and sums
 exactly.
@@ -11,8 +11,10 @@ Bars:
   * energies: Delta H of the device's own end points equals the exact FP64
     Delta H at those points within 1e-5 (|H0| + |H1|) -- the weights stay exact;
   * jitter, step counts and resampling ancestors: bit-exact;
-  * trajectories: error against the BF16-emulating oracle and against the
-    exact FP64 oracle stated (logged) and bounded.
+  * trajectories: against the BF16-emulating oracle to the bars of
+    check_bf16_trajectories (median, 75th percentile and maximum over the
+    particles: rounding-tie flips are rare but carry to the end point);
+    against the exact FP64 oracle stated (logged) and bounded.
 """
 
 import numpy as np
@@ -20,7 +22,7 @@ import pytest
 
 from oracle import smc as O
 from paper_2504_02627_amd import synth
-from tests._gpu_common import dev, log, rel_rows, to_dev
+from tests._gpu_common import check_bf16_trajectories, dev, log, rel_each, rel_rows, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -111,11 +113,13 @@ def test_bf16_energies_exact_at_device_end_points(N, d, J):
     assert np.all(err <= 1e-5 * (np.abs(H0) + np.abs(H1)))
     # trajectories: BF16 vs BF16-emulating oracle, and vs the exact oracle
     e_emul = rel_rows(th1, ost["theta_prop"])
+    log("  " + check_bf16_trajectories({"theta": rel_each(th1, ost["theta_prop"]),
+                                        "p": rel_each(p1, ost["p1"])}))
     ox = O.OracleSMC(t, J, theta0=theta0.astype(np.float64), **params)
     oxs = ox.step(momenta=xi.astype(np.float64), resample_u=float(u0[0]))
     e_exact = rel_rows(th1, oxs["theta_prop"])
     log(f"  trajectory rel err vs BF16-emulating oracle {e_emul:.2e}, vs exact FP64 oracle {e_exact:.2e}")
-    assert e_emul <= 5e-3 and e_exact <= 5e-2
+    assert e_exact <= 5e-2
 
 
 def test_bf16_batched_mixed_widths_runs_and_weights_exact():
