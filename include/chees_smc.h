@@ -287,7 +287,10 @@ smc_status smc_init(const smc_problem *prob, const smc_params *par, void *worksp
  * 1, n_max) (Alg. smc_ChEES), run the leapfrog trajectories, compute Delta H
  * and alpha (eq. HMC_accept_reject), update log w += -Delta H (SMC-ChEES) or
  * accept iff u < alpha (MH mode), and the ChEES statistics.  stats: nullable
- * host pointer; non-NULL synchronises the stream and fills it. */
+ * host pointer; non-NULL synchronises the stream and fills it.  Once the
+ * adaptation has ended, the first step synchronises once to read L and eps
+ * and from then on launches only the leapfrog steps the longest trajectory
+ * can need (see smc_run). */
 smc_status smc_step(smc_ctx *ctx, const smc_inject *inject, smc_stats *stats);
 
 /* Warm-up adaptation after step k (Alg. smc_ChEES): k < M_warmup: Adam
@@ -297,12 +300,18 @@ smc_status smc_step(smc_ctx *ctx, const smc_inject *inject, smc_stats *stats);
 smc_status chees_adapt(smc_ctx *ctx, smc_stats *stats);
 
 /* `iterations` SMC iterations, each smc_step (randomness from the library's
- * Philox streams, nothing injected) followed by chees_adapt, with no host
- * synchronisation.  The first call captures one iteration's launches as a
- * HIP graph on a private stream; every call replays it on the context's
- * stream, once per iteration.  Results are identical to the same number of
- * smc_step + chees_adapt calls.  Per-kernel timing does not cover it.
- * SMC_ESTATE after a smc_step not yet followed by chees_adapt. */
+ * Philox streams, nothing injected) followed by chees_adapt.  The first call
+ * captures one iteration's launches as a HIP graph on a private stream; every
+ * call replays it on the context's stream, once per iteration, without host
+ * synchronisation.  Once the adaptation has ended (num_warmup iterations),
+ * the call that crosses that point synchronises once, reads L and eps, and
+ * captures a second graph whose leapfrog launches stop at the longest
+ * trajectory those values allow (min(max(ceil(h_max L / eps), 1), n_max),
+ * h_max the jitter's largest value: 1.1 for SMC_JITTER equidistant with
+ * offset, else 1); smc_set_params and smc_load drop the bound.
+ * Results are identical to the same number of smc_step + chees_adapt calls.
+ * Per-kernel timing does not cover it.  SMC_ESTATE after a smc_step not yet
+ * followed by chees_adapt. */
 smc_status smc_run(smc_ctx *ctx, int32_t iterations);
 
 /* Flow preconditioner (SMC_PRECOND_FLOW).  Parameters form one flat FP32

@@ -38,11 +38,15 @@ struct smc_ctx {
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   std::vector<std::pair<int, size_t>> ev_marks;  // (kind, index of the start event)
-  // one SMC iteration (step + adaptation) captured as a graph for smc_run
+  // one SMC iteration (step + adaptation) captured as a graph for smc_run:
+  // with n_max leapfrog launches, and (once the adaptation has frozen L and
+  // eps) with as many launches as the longest trajectory can need
   FlowNet F{};
   hipStream_t cap_st = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr, graph_b = nullptr;
+  hipGraphExec_t gexec = nullptr, gexec_b = nullptr;
+  int nl_b = 0;        // leapfrog launches of the bounded graph (0: none)
+  int frozen = 0;      // L and eps are final and nl_b has been set
   // side streams on which the launches of several feature-tile groups run
   // side by side (created at smc_init when there is more than one group)
   hipStream_t side[MAX_SIDE] = {};
@@ -52,6 +56,8 @@ struct smc_ctx {
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (graph) (void)hipGraphDestroy(graph);
+    if (gexec_b) (void)hipGraphExecDestroy(gexec_b);
+    if (graph_b) (void)hipGraphDestroy(graph_b);
     if (cap_st) (void)hipStreamDestroy(cap_st);
     for (int i = 0; i < MAX_SIDE; ++i) {
       if (side[i]) (void)hipStreamDestroy(side[i]);
@@ -267,7 +273,10 @@ void plan(const smc_problem *pr, const smc_params *pa, Layout &L) {
     h.C2 = (h.d + 15) / 16;
     h.C1 = 4 * h.C2;
     h.NT = (h.N + 15) / 16;
-    h.NT2 = (h.N + 31) / 32;
+    {
+      const int stt = bf16_stage_tiles(h.C2);
+      h.NT2 = ((h.N + 31) / 32 + stt - 1) / stt * stt;
+    }
     h.KC = (h.C2 + 1) / 2;
     h.xab = xoff;
     h.xbf = xboff;
@@ -832,7 +841,8 @@ hipError_t for_groups(smc_ctx *ctx, int n, Fn fn) {
 
 namespace {
 // Every launch of one smc_step (no host synchronisation, no memset, no copy).
-smc_status enqueue_step(smc_ctx *ctx, const smc_inject *inject) {
+// nl: leapfrog launches (n_max, or fewer when no trajectory can be longer).
+smc_status enqueue_step(smc_ctx *ctx, const smc_inject *inject, int nl) {
   const Dev &D = ctx->D;
   size_t ei = 0;
   CK(launch_begin_step(D, 1, inject ? inject->resample_u : nullptr, 1, ctx->st));
@@ -854,7 +864,7 @@ smc_status enqueue_step(smc_ctx *ctx, const smc_inject *inject) {
   CK(launch_sort(D, ctx->st));
   if (D.target) {
     // synthetic target: one fused drift / gradient / kick launch per step
-    for (int s = 0; s < D.nmax; ++s) {
+    for (int s = 0; s < nl; ++s) {
       CK(timed_begin(ctx, 0, ei));
       CK(launch_target_step(D, s, 0, ctx->st));
       CK(timed_end(ctx, ei));
@@ -877,14 +887,14 @@ smc_status enqueue_step(smc_ctx *ctx, const smc_inject *inject) {
     // after the last step
     CK(for_groups(ctx, (int)ctx->c2s.size(), [&](int g, hipStream_t stream) {
       hipError_t e = hipSuccess;
-      for (int s = 0; s < D.nmax && e == hipSuccess; ++s) {
+      for (int s = 0; s < nl && e == hipSuccess; ++s) {
         e = launch_lf_partial(D, ctx->c2s[g], s, 0, stream);
         if (e == hipSuccess && !D.lf_nosplit) e = launch_lf_reduce(D, s, 0, stream, ctx->c2s[g]);
       }
       return e;
     }));
   }
-  for (int s = 0; s < (D.target || D.traj || lanes ? 0 : D.nmax); ++s) {
+  for (int s = 0; s < (D.target || D.traj || lanes ? 0 : nl); ++s) {
     if (D.flow && s == 0) {  // one posterior, one group; later drifts join the kicks
       CK(timed_begin(ctx, 3, ei));
       CK(launch_flow_drift(D, F, s, ctx->st));
@@ -905,8 +915,7 @@ smc_status enqueue_step(smc_ctx *ctx, const smc_inject *inject) {
     }
     if (D.flow) {
       CK(timed_begin(ctx, 3, ei));
-      CK(s + 1 < D.nmax ? launch_flow_kick_drift(D, F, s, ctx->st)
-                        : launch_flow_kick(D, F, s, ctx->st));
+      CK(s + 1 < nl ? launch_flow_kick_drift(D, F, s, ctx->st) : launch_flow_kick(D, F, s, ctx->st));
       CK(timed_end(ctx, ei));
     }
   }
@@ -926,9 +935,95 @@ smc_status enqueue_step(smc_ctx *ctx, const smc_inject *inject) {
 }
 }  // namespace
 
+namespace {
+// Capture one iteration (step with nl leapfrog launches, then the adaptation)
+// on a private stream; kernel arguments are fixed for the life of the
+// context, so the graph stays valid.
+smc_status capture_iteration(smc_ctx *ctx, int nl, hipGraph_t *graph, hipGraphExec_t *gexec) {
+  if (!ctx->cap_st) CK(hipStreamCreateWithFlags(&ctx->cap_st, hipStreamNonBlocking));
+  const hipStream_t user = ctx->st;
+  const int timing = ctx->timing;
+  ctx->st = ctx->cap_st;
+  ctx->timing = 0;
+  hipError_t e = hipStreamBeginCapture(ctx->cap_st, hipStreamCaptureModeThreadLocal);
+  smc_status r = SMC_EDEVICE;
+  if (e == hipSuccess) {
+    r = enqueue_step(ctx, nullptr, nl);
+    if (r == SMC_OK && launch_adapt(ctx->D, ctx->cap_st) != hipSuccess) r = SMC_EDEVICE;
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(ctx->cap_st, &g);
+    if (e == hipSuccess && r == SMC_OK) {
+      e = hipGraphInstantiate(gexec, g, nullptr, nullptr, 0);
+      if (e == hipSuccess) *graph = g;
+    }
+    if (e != hipSuccess || r != SMC_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      *gexec = nullptr;
+    }
+  }
+  ctx->st = user;
+  ctx->timing = timing;
+  if (e != hipSuccess) {
+    ctx->err = std::string("graph capture of an iteration: ") + hipGetErrorString(e);
+    return SMC_EDEVICE;
+  }
+  return r;
+}
+
+void drop_bounded(smc_ctx *ctx) {
+  if (ctx->gexec_b) (void)hipGraphExecDestroy(ctx->gexec_b);
+  if (ctx->graph_b) (void)hipGraphDestroy(ctx->graph_b);
+  ctx->gexec_b = nullptr;
+  ctx->graph_b = nullptr;
+  ctx->nl_b = 0;
+  ctx->frozen = 0;
+}
+
+// Once every posterior's adaptation has ended (its last adaptation ran at
+// iteration k >= num_warmup), L and eps no longer change: each n_j =
+// min(max(ceil(h_j L / eps), 1), n_max) with h_j <= h_max is at most
+// min(max(ceil(h_max L / eps), 1), n_max) (binary64 rounding is monotone), and
+// later leapfrog launches would find no active particle.  One synchronisation
+// reads L and eps and sets nl_b (smc_run then captures a graph with that many
+// launches; smc_step launches that many).
+smc_status freeze_bound(smc_ctx *ctx) {
+  const Dev &D = ctx->D;
+  CK(hipMemcpyAsync(ctx->ps_host.data(), D.ps, D.B * sizeof(PState), hipMemcpyDeviceToHost,
+                    ctx->st));
+  CK(hipStreamSynchronize(ctx->st));
+  const double hmax = D.jitter == 9 ? 1.0 + 0.1 : 1.0;  // scheme 9 adds 0.1 u to (y + 1) / J
+  int nl = 1;
+  for (int b = 0; b < D.B; ++b) {
+    const PState &S = ctx->ps_host[b];
+    if (S.adapted_k < D.num_warmup) return SMC_OK;  // still adapting: keep the full graph
+    double nn = ceil(hmax * S.L / S.eps);
+    nn = fmin(fmax(nn, 1.0), (double)D.nmax);
+    nl = std::max(nl, (int)nn);
+  }
+  ctx->frozen = 1;
+  ctx->nl_b = nl;
+  return SMC_OK;
+}
+
+// Leapfrog launches of the next iteration: n_max until the adaptation has
+// ended, then the bound (checked once, when the iteration count first
+// reaches num_warmup with no step pending).
+smc_status launch_count(smc_ctx *ctx, int *nl) {
+  if (!ctx->frozen && !ctx->stepped && ctx->steps >= ctx->D.num_warmup) {
+    const smc_status r = freeze_bound(ctx);
+    if (r != SMC_OK) return r;
+  }
+  *nl = ctx->frozen ? ctx->nl_b : ctx->D.nmax;
+  return SMC_OK;
+}
+}  // namespace
+
 smc_status smc_step(smc_ctx *ctx, const smc_inject *inject, smc_stats *stats) {
   if (!ctx) return SMC_EINVAL;
-  const smc_status r = enqueue_step(ctx, inject);
+  int nl = ctx->D.nmax;
+  smc_status r = launch_count(ctx, &nl);
+  if (r != SMC_OK) return r;
+  r = enqueue_step(ctx, inject, nl);
   if (r != SMC_OK) return r;
   ctx->stepped = 1;
   ctx->steps += 1;
@@ -943,39 +1038,37 @@ smc_status smc_run(smc_ctx *ctx, int32_t iterations) {
     return SMC_ESTATE;
   }
   if (!ctx->gexec) {
-    // capture on a private stream; kernel arguments are fixed for the life of
-    // the context, so the graph stays valid
-    if (!ctx->cap_st) CK(hipStreamCreateWithFlags(&ctx->cap_st, hipStreamNonBlocking));
-    const hipStream_t user = ctx->st;
-    const int timing = ctx->timing;
-    ctx->st = ctx->cap_st;
-    ctx->timing = 0;
-    hipError_t e = hipStreamBeginCapture(ctx->cap_st, hipStreamCaptureModeThreadLocal);
-    smc_status r = SMC_EDEVICE;
-    if (e == hipSuccess) {
-      r = enqueue_step(ctx, nullptr);
-      if (r == SMC_OK && launch_adapt(ctx->D, ctx->cap_st) != hipSuccess) r = SMC_EDEVICE;
-      hipGraph_t g = nullptr;
-      e = hipStreamEndCapture(ctx->cap_st, &g);
-      if (e == hipSuccess && r == SMC_OK) {
-        e = hipGraphInstantiate(&ctx->gexec, g, nullptr, nullptr, 0);
-        if (e == hipSuccess) ctx->graph = g;
-      }
-      if (e != hipSuccess || r != SMC_OK) {
-        if (g) (void)hipGraphDestroy(g);
-        ctx->gexec = nullptr;
-      }
-    }
-    ctx->st = user;
-    ctx->timing = timing;
-    if (e != hipSuccess) {
-      ctx->err = std::string("graph capture of an iteration: ") + hipGetErrorString(e);
-      return SMC_EDEVICE;
-    }
+    smc_status r = capture_iteration(ctx, ctx->D.nmax, &ctx->graph, &ctx->gexec);
     if (r != SMC_OK) return r;
   }
-  for (int i = 0; i < iterations; ++i) CK(hipGraphLaunch(ctx->gexec, ctx->st));
-  ctx->steps += iterations;
+  int left = iterations;
+  while (left > 0) {
+    if (!ctx->frozen) {
+      // iterations whose adaptation may still move L or eps (iteration k adapts
+      // while k <= num_warmup; ctx->steps iterations have run)
+      const int adapting = ctx->D.num_warmup - ctx->steps;
+      if (adapting > 0) {
+        const int n = std::min(left, adapting);
+        for (int i = 0; i < n; ++i) CK(hipGraphLaunch(ctx->gexec, ctx->st));
+        ctx->steps += n;
+        left -= n;
+        continue;
+      }
+    }
+    int nl = ctx->D.nmax;
+    smc_status r = launch_count(ctx, &nl);
+    if (r != SMC_OK) return r;
+    if (nl < ctx->D.nmax && !ctx->gexec_b) {
+      r = capture_iteration(ctx, nl, &ctx->graph_b, &ctx->gexec_b);
+      if (r != SMC_OK) return r;
+    }
+    // without a bound (adaptation not ended on the device: a restored or
+    // re-parameterised state) the full graph runs
+    hipGraphExec_t g = nl < ctx->D.nmax ? ctx->gexec_b : ctx->gexec;
+    for (int i = 0; i < left; ++i) CK(hipGraphLaunch(g, ctx->st));
+    ctx->steps += left;
+    left = 0;
+  }
   return SMC_OK;
 }
 
@@ -1162,6 +1255,7 @@ smc_status smc_get_timing(smc_ctx *ctx, smc_timing *out) {
 
 smc_status smc_set_params(smc_ctx *ctx, double L, double eps) {
   if (!ctx || !(L > 0.0) || !(eps > 0.0)) return SMC_EINVAL;
+  drop_bounded(ctx);  // the launch bound depends on L and eps
   CK(launch_set_params(ctx->D, L, eps, ctx->st));
   return SMC_OK;
 }
@@ -1307,6 +1401,7 @@ smc_status smc_load(smc_ctx *ctx, const void *buf, size_t bytes) {
   CK(hipStreamSynchronize(ctx->st));
   ctx->steps = img.steps;
   ctx->stepped = 0;
+  drop_bounded(ctx);  // the restored L and eps decide the launch bound afresh
   return SMC_OK;
 }
 

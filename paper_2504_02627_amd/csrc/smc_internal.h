@@ -207,6 +207,10 @@ __host__ __device__ constexpr int lf_groups_per_cu(bool bf16, int c2) {
 // uint4 per lane and 32-row tile in the BF16 packing: [A1: C2 | A2: 2 ceil(C2/2)],
 // plus one zero slot when that is even
 __host__ __device__ constexpr int bf16_lane_stride(int c2) { return (c2 + 2 * ((c2 + 1) / 2)) | 1; }
+// 32-row data tiles per LDS stage of the BF16 kernel: two up to a lane stride
+// of 20 slots, one beyond; a posterior's tiles are padded to whole stages
+// (the pad rows are zero and add nothing).
+__host__ __device__ constexpr int bf16_stage_tiles(int c2) { return bf16_lane_stride(c2) <= 20 ? 2 : 1; }
 hipError_t fill_f32(float *p, long long n, float v, hipStream_t st);
 hipError_t fill_i32(int *p, long long n, int v, hipStream_t st);
 hipError_t fill_f64(double *p, long long n, double v, hipStream_t st);

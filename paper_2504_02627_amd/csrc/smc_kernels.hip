@@ -354,9 +354,11 @@ struct Plan {
 // tile, tiles with one more split, active tiles); per launch lf_items holds
 // each item's (posterior, tile, split | S << 16, first item of its tile).
 
-// data tiles of a posterior in the leapfrog kernels: 16-row tiles (FP32) or
-// 32-row tiles (BF16)
-__device__ __forceinline__ int lf_units(const Dev &D, const Post &P) { return D.bf16 ? P.NT2 : P.NT; }
+// data units of a posterior in the leapfrog kernels: 16-row tiles (FP32) or
+// LDS stages of 32-row tiles (BF16)
+__device__ __forceinline__ int lf_units(const Dev &D, const Post &P) {
+  return D.bf16 ? P.NT2 / bf16_stage_tiles(P.C2) : P.NT;
+}
 
 constexpr int PLAN_THREADS = 256;
 
@@ -914,22 +916,22 @@ struct B32 {
   static constexpr int NF = (C2 + 1) / 2;          // 32-feature tiles of GEMM2
   static constexpr int LS = bf16_lane_stride(C2);  // uint4 per lane and 32-row tile
   static constexpr int TILE = 64 * LS;             // uint4 per tile
-  static constexpr int STT = LS <= 20 ? 2 : 1;     // tiles per stage
+  static constexpr int STT = bf16_stage_tiles(C2);  // tiles per stage
   static constexpr int STAGE = STT * TILE;
   static constexpr int NINST = STAGE / 64;         // wave-wide 16-byte loads per stage
 };
 
-// Direct loads of the stage starting at data tile t into `buf` (tiles past
-// the split's last one are skipped; wave-uniform guard).
+// Direct loads of the stage starting at data tile t into `buf` (every tile of
+// a stage exists: the tile count is padded to whole stages).
 template <int C2>
 __device__ __forceinline__ void b32_issue(uint4 *__restrict__ buf, const uint4 *__restrict__ xbf,
-                                          int t, int t1, int wave, int lane) {
+                                          int t, int wave, int lane) {
   using TL = B32<C2>;
   const uint4 *src = xbf + (long long)t * TL::TILE + lane;
 #pragma unroll
   for (int k = 0; k < (TL::NINST + B32_WAVES - 1) / B32_WAVES; ++k) {
     const int m = wave + k * B32_WAVES;
-    if (m < TL::NINST && t + m / TL::LS < t1)
+    if (m < TL::NINST)
       __builtin_amdgcn_global_load_lds((const void *)(src + 64 * m), (lds_void *)(buf + 64 * m), 16,
                                        0, 0);
   }
@@ -945,13 +947,13 @@ __device__ __forceinline__ void b32_residual(const v16f &z, v8bf &r0, v8bf &r1) 
   }
 }
 
-// The tiles of one stage in buffer xs (lane's slots at xs + lane * LS).
+// The STT tiles of one stage in buffer xs (lane's slots at xs + lane * LS).
 template <int C2>
-__device__ __forceinline__ void b32_stage(const uint4 *__restrict__ xs, int ntt, const v8bf (&thb)[C2],
+__device__ __forceinline__ void b32_stage(const uint4 *__restrict__ xs, const v8bf (&thb)[C2],
                                           v16f (&g)[B32<C2>::NF]) {
   using TL = B32<C2>;
   constexpr int NF = TL::NF;
-  if (ntt == 2) {
+  if constexpr (TL::STT == 2) {
     // both tiles' GEMM1 first: the first tile's residuals overlap the second's MFMAs
     const uint4 *x0 = xs, *x1 = xs + TL::TILE;
     v16f z0 = {}, z1 = {};
@@ -1002,10 +1004,19 @@ __device__ __forceinline__ void lf_unit_b32(const Dev &D, const Plan &pl, int s,
   const float *minv = D.minv + (long long)pl.b * D.DS;
   const int *perm = D.perm + P.row0;
 
-  const int t0 = (int)((long long)pl.split * P.NT2 / pl.S);
-  const int t1 = (int)((long long)(pl.split + 1) * P.NT2 / pl.S);
+  // the split's stages [s0, s1) of STT tiles each (the tile count is padded to
+  // whole stages)
+  const int ns = P.NT2 / TL::STT;
+  const int s0 = (int)((long long)pl.split * ns / pl.S);
+  const int s1 = (int)((long long)(pl.split + 1) * ns / pl.S);
   const uint4 *xbf = D.xbf + P.xbf;
-  if (t0 < t1) b32_issue<C2>(bufA, xbf, t0, t1, wave, lane);
+  // an odd stage count runs its first stage from bufB before the loop, so
+  // that the loop body always holds two stages (no exit in its middle)
+  const bool odd = (s1 - s0) & 1;
+  if (odd)
+    b32_issue<C2>(bufB, xbf, s0 * TL::STT, wave, lane);
+  else if (s0 < s1)
+    b32_issue<C2>(bufA, xbf, s0 * TL::STT, wave, lane);
 
   // theta' (bfloat16, B operand of GEMM1): K-step c holds features 16c + 8h + e
   // of particle slot 32 wave + lane % 32; after the first step of the split
@@ -1038,19 +1049,20 @@ __device__ __forceinline__ void lf_unit_b32(const Dev &D, const Plan &pl, int s,
   for (int f = 0; f < NF; ++f) g[f] = v16f{};
 
   __syncthreads();  // the first stage has landed (the compiler waits for the loads here)
-  for (int t = t0; t < t1;) {
-    // stage in bufA; the next one goes to bufB meanwhile
-    int nt = t + TL::STT;
-    if (nt < t1) b32_issue<C2>(bufB, xbf, nt, t1, wave, lane);
-    b32_stage<C2>(bufA + lane * TL::LS, min(TL::STT, t1 - t), thb, g);
+  if (odd) {
+    if (s0 + 1 < s1) b32_issue<C2>(bufA, xbf, (s0 + 1) * TL::STT, wave, lane);
+    b32_stage<C2>(bufB + lane * TL::LS, thb, g);
     __syncthreads();
-    t = nt;
-    if (t >= t1) break;
-    nt = t + TL::STT;
-    if (nt < t1) b32_issue<C2>(bufA, xbf, nt, t1, wave, lane);
-    b32_stage<C2>(bufB + lane * TL::LS, min(TL::STT, t1 - t), thb, g);
+  }
+  for (int st = s0 + (odd ? 1 : 0); st < s1; st += 2) {
+    // stage st in bufA (stage st + 1 exists: the remaining count is even);
+    // stage st + 1 goes to bufB meanwhile
+    b32_issue<C2>(bufB, xbf, (st + 1) * TL::STT, wave, lane);
+    b32_stage<C2>(bufA + lane * TL::LS, thb, g);
     __syncthreads();
-    t = nt;
+    if (st + 2 < s1) b32_issue<C2>(bufA, xbf, (st + 2) * TL::STT, wave, lane);
+    b32_stage<C2>(bufB + lane * TL::LS, thb, g);
+    __syncthreads();
   }
 }
 
