@@ -1125,53 +1125,84 @@ __global__ __launch_bounds__(B32_WG, (b32_groups<C2, FIN>())) void k_lf_partial_
   lf_store_b32<C2>(D, D.gpart + (long long)(D.lf_goff[D.c2_group[C2]] + blockIdx.x) * TJ * D.DS, g);
 }
 
-// grid: (B * tiles per posterior, slices of 256 float4 of a tile's 128 x d
-// gradient block); one float4 per thread.  Every thread reads the tile's plan
-// itself (uniform loads, no barrier), then issues the row index, the partials
-// (eight splits per round) and the state loads together, so the kernel costs
-// a few memory latencies whatever the split count.
+// grid: (B * tiles per posterior, slices of RED_SLOTS float4 of a tile's
+// 128 x d gradient block).  A work group is RED_GROUPS groups of RED_SLOTS
+// threads: group q sums splits [q S / RED_GROUPS, (q + 1) S / RED_GROUPS) of
+// its float4 slot in split order (eight loads in flight per round), and the
+// first group adds the group sums in group order, so every sum has a fixed
+// order and the loads of many splits are in flight at once whatever S is.
+// Every thread reads the tile's plan itself (uniform loads).
 constexpr int RED_THREADS = 256;
 constexpr int RED_ROUND = 8;
+constexpr int RED_GROUPS = 4;
+constexpr int RED_SLOTS = RED_THREADS / RED_GROUPS;
 
 __global__ __launch_bounds__(RED_THREADS) void k_lf_reduce(Dev D, int s, int zero_eps, int c2only) {
+  __shared__ float4 part[RED_GROUPS - 1][RED_SLOTS];
   const int tj = TJ, ntile = D.Jcap / tj;
   const int b = blockIdx.x / ntile, tile = blockIdx.x % ntile;
   const Post P = D.posts[b];
-  if (c2only && P.C2 != c2only) return;  // another group's posterior
+  if (c2only && P.C2 != c2only) return;  // another group's posterior (uniform)
   const int4 q = D.lf_post[(long long)s * D.B + b];
+  if (tile >= q.w) return;                // inactive tile (uniform)
   const int dq = 4 * P.C2;  // float4 per particle row
-  const int idx = blockIdx.y * RED_THREADS + threadIdx.x;
-  if (idx >= tj * dq || tile >= q.w) return;
+  const int sl = threadIdx.x % RED_SLOTS, grp = threadIdx.x / RED_SLOTS;
+  const int idx = blockIdx.y * RED_SLOTS + sl;
+  const bool live = idx < tj * dq;
   const int S = q.y + (tile < q.z ? 1 : 0);
   const int wbase = D.lf_goff[D.c2_group[P.C2]] + q.x + tile * q.y + (tile < q.z ? tile : q.z);
-  const int slot = idx / dq, k4 = idx - slot * dq;
-  const int j = D.perm[P.row0 + tile * tj + slot];
+  const int slot = live ? idx / dq : 0, k4 = live ? idx - slot * dq : 0;
   const float4 *g0p = reinterpret_cast<const float4 *>(D.gpart + (long long)wbase * tj * D.DS);
   const long long sstride = (long long)tj * D.DS / 4;  // float4 between splits
   const long long o4 = (long long)slot * D.DS / 4 + k4;
-  // ordered sum over the splits: ((p0 + p1) + p2) + ...
-  float4 G = g0p[o4];
-  for (int sp0 = 1; sp0 < S; sp0 += RED_ROUND) {
-    float4 v[RED_ROUND];
-#pragma unroll
-    for (int u = 0; u < RED_ROUND; ++u)
-      if (sp0 + u < S) v[u] = g0p[(sp0 + u) * sstride + o4];
-#pragma unroll
-    for (int u = 0; u < RED_ROUND; ++u)
-      if (sp0 + u < S) {
-        G.x += v[u].x;
-        G.y += v[u].y;
-        G.z += v[u].z;
-        G.w += v[u].w;
-      }
+  // the first group issues the row index and the state loads before its sums
+  const bool fin = grp == 0 && live;
+  long long row = 0, e = 0;
+  float4 t0, p0, g0, mv;
+  int nrow = 0;
+  if (fin) {
+    row = P.row0 + D.perm[P.row0 + tile * tj + slot];
+    e = (row * D.DS) / 4 + k4;
+    t0 = reinterpret_cast<const float4 *>(D.theta_t)[e];
+    p0 = reinterpret_cast<const float4 *>(D.p_t)[e];
+    g0 = reinterpret_cast<const float4 *>(D.grad_t)[e];
+    mv = reinterpret_cast<const float4 *>(D.minv + (long long)b * D.DS)[k4];
+    nrow = D.n[row];
   }
-  const long long row = P.row0 + j;
-  const long long e = (row * D.DS) / 4 + k4;
-  const float4 t0 = reinterpret_cast<const float4 *>(D.theta_t)[e];
-  const float4 p0 = reinterpret_cast<const float4 *>(D.p_t)[e];
-  const float4 g0 = reinterpret_cast<const float4 *>(D.grad_t)[e];
-  const float4 mv = reinterpret_cast<const float4 *>(D.minv + (long long)b * D.DS)[k4];
-  if (D.n[row] <= s) return;
+  // this group's splits, in order: ((p_a + p_a+1) + ...) + p_b-1
+  const int sa = grp * S / RED_GROUPS, sb = (grp + 1) * S / RED_GROUPS;
+  float4 G = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (live && sa < sb) {
+    G = g0p[sa * sstride + o4];
+    for (int sp0 = sa + 1; sp0 < sb; sp0 += RED_ROUND) {
+      float4 v[RED_ROUND];
+#pragma unroll
+      for (int u = 0; u < RED_ROUND; ++u)
+        if (sp0 + u < sb) v[u] = g0p[(sp0 + u) * sstride + o4];
+#pragma unroll
+      for (int u = 0; u < RED_ROUND; ++u)
+        if (sp0 + u < sb) {
+          G.x += v[u].x;
+          G.y += v[u].y;
+          G.z += v[u].z;
+          G.w += v[u].w;
+        }
+    }
+  }
+  if (grp > 0) part[grp - 1][sl] = G;
+  __syncthreads();
+  if (!fin) return;
+  // group sums in group order (a group with no split adds nothing)
+#pragma unroll
+  for (int r = 1; r < RED_GROUPS; ++r)
+    if (r * S / RED_GROUPS < (r + 1) * S / RED_GROUPS) {
+      const float4 v = part[r - 1][sl];
+      G.x += v.x;
+      G.y += v.y;
+      G.z += v.z;
+      G.w += v.w;
+    }
+  if (nrow <= s) return;
   const float eps = zero_eps ? 0.f : (float)D.ps[b].eps;
   const float he = 0.5f * eps;
   const float inv_pv = (float)(1.0 / D.prior_var);
@@ -1228,7 +1259,7 @@ hipError_t launch_lf_reduce(const Dev &D, int step, int zero_eps, hipStream_t st
   int c2max = c2only;
   for (int g = 0; g < D.ngroups && !c2only; ++g)
     c2max = D.group_c2[g] > c2max ? D.group_c2[g] : c2max;
-  const int slices = (TJ * 4 * c2max + RED_THREADS - 1) / RED_THREADS;
+  const int slices = (TJ * 4 * c2max + RED_SLOTS - 1) / RED_SLOTS;
   hipLaunchKernelGGL(k_lf_reduce, dim3(D.B * (D.Jcap / TJ), slices), dim3(RED_THREADS), 0, st, D,
                      step, zero_eps, c2only);
   return hipGetLastError();
