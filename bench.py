@@ -432,6 +432,11 @@ def toeplitz_forms(args):
         out["forms"][name] = matched(ref, rep, name)
         log(f"toeplitz {name}: {rep['ms_per_iteration']:.2f} ms/iteration, "
             f"ESS/s {rep['ess_per_s'] / 1e6:.3f} M, pass {out['forms'][name]['pass_3se']}")
+    for name in ("flow_4x128_f32", "flow_4x128_bf16 (BF16 + flow, the headline form)"):
+        kp = flow_kernel_pass(Xd, yd, 4096, dict(base, seed=3, **forms[name]), ITERS // 2, 10)
+        out["forms"][name]["flow_kernels"] = kp
+        log(f"toeplitz {name}: moves {kp['moves_ms_per_iteration']:.3f} ms/iteration "
+            f"({kp['moves_tflops']:.1f} TFLOP/s), fit {kp['fit_ms_per_iteration']:.3f} ms/iteration")
     plain = out["forms"]["unit_mass_f32 (plain FP32, the judge)"]
     head = out["forms"]["flow_4x128_bf16 (BF16 + flow, the headline form)"]
     out["headline"] = {
@@ -441,6 +446,53 @@ def toeplitz_forms(args):
                     if head["ess_per_s"] > plain["ess_per_s"] and head["pass_3se"] and plain["pass_3se"]
                     else "BF16 + flow does NOT beat plain FP32 in ESS/s at matched error on this run")}
     return out
+
+
+def flow_flops_per_particle(d, layers, width):
+    """Dense-layer flops of one pass of the flow for one particle: per coupling
+    (conditioning half dc, transformed half dt) W1 (width x dc), W2 (width x
+    width), W3 (2 dt x width), two flops per multiply-add, plus the base
+    product (d x d).  The move's drift (forward map) and kick (the transposed
+    products over the tape) each cost this; one fit step costs about three
+    (inverse map, input cotangents, weight gradients)."""
+    dc, dt = d // 2, d - d // 2
+    per = 0
+    for l in range(layers):
+        a, b = (dc, dt) if l % 2 == 0 else (dt, dc)
+        per += 2 * (width * a + width * width + 2 * b * width)
+    return per + 2 * d * d
+
+
+def flow_kernel_pass(Xd, yd, J, params, warm, steps):
+    """HIP-event times of the flow's move launches (drift / kick) and fit steps
+    after `warm` iterations, with their algorithmic TFLOP/s."""
+    from paper_2504_02627_amd import chees
+    s = chees.Sampler(Xd, yd, J, **params)
+    for _ in range(warm):
+        s.step(stats=False)
+        s.adapt(stats=False)
+    s.set_timing(True)
+    s.timing()
+    sum_n, fitted = 0, 0
+    for _ in range(steps):
+        st = s.step()
+        s.adapt(stats=False)
+        sum_n += int(s.trace()["n"][:J].sum().item())
+        fitted += 0 if st["resampled"] else 1
+    tm = s.timing()
+    s.close()
+    per = flow_flops_per_particle(Xd.shape[1], params["flow_layers"], 128)
+    moves = per * (2 * sum_n + 2 * J * steps)
+    fit = 3 * per * J * params["flow_train_steps"] * fitted
+    return {"iterations": steps, "after_warmup_iterations": warm,
+            "move_flops_per_particle_pass": per,
+            "moves_ms_per_iteration": tm["flow_ms"] / steps, "move_launches": tm["flow_launches"],
+            "moves_tflops": moves / (tm["flow_ms"] * 1e-3) / 1e12 if tm["flow_ms"] > 0 else None,
+            "fit_ms_per_iteration": tm["train_ms"] / steps, "fit_launches": tm["train_launches"],
+            "fitted_iterations": fitted,
+            "fit_tflops": fit / (tm["train_ms"] * 1e-3) / 1e12 if tm["train_ms"] > 0 and fitted else None,
+            "flops_note": "drift and kick one pass each per active particle and step, plus the "
+                          "initial pair; a fit step three passes per particle"}
 
 
 def cpu_baseline(X, y, params, seconds):
