@@ -1288,8 +1288,9 @@ hipError_t launch_lf_partial(const Dev &D, int c2, int step, int zero_eps, hipSt
 // ---------------------------------------------------------------------------
 // Log-likelihood at the trajectory end points, recomputed for the energies:
 //   sum_n [ y_n z_n - log(1 + e^{z_n}) ],  z = X theta'   (Sec. IV model)
-// GEMM1 as above (A part of the packed tiles only), accurate expf/log1pf and
-// a Neumaier-compensated FP32 sum per lane; the four lanes of a particle are
+// GEMM1 as above (A part of the packed tiles only), softplus from the hardware
+// exp2 and log2 (softplusf_hw: absolute error a few 1e-8 per term) and a
+// Neumaier-compensated FP32 sum per lane; the four lanes of a particle are
 // merged with error-free TwoSum, the splits in order by the weights kernel.
 // ---------------------------------------------------------------------------
 struct Neu {

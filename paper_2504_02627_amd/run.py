@@ -5,7 +5,8 @@ Per iteration: J_eff after the move and the one that decided resampling, the
 resampling flag, mean acceptance, mean and largest n_j, gradient evaluations,
 L and eps used, the ChEES estimate and its gradient, log Z_hat, and the wall
 time of the iteration (step + adaptation, synchronised).  A checkpoint of the
-final state can be written (smc_save) and a run resumed from one (smc_load).
+final state can be written (smc_save; the run's schedule beside it in FILE.json)
+and a run resumed from one (smc_load), keeping the interrupted run's schedule.
 
 Workloads (seeded, see synth.py): small (N = 200, d = 5), large (N = 10000,
 d = 100), toeplitz (N = 5000, d = 100, rows correlated 0.95^|i-j|), batched
@@ -81,13 +82,22 @@ def main(argv=None):
     if a.precision == "bf16":
         Xd = [X.to(torch.bfloat16) for X in Xd]
     yd = [torch.from_numpy(y).to(dev) for y in ys]
+    # the schedule of the whole run (warm-up boundary, jitter columns K) comes
+    # from the checkpoint's own record when resuming, so that a resumed run
+    # continues the interrupted one rather than starting another schedule
+    sched = dict(num_warmup=a.iterations // 2, num_iterations=a.iterations, jitter=a.jitter)
+    if a.resume:
+        with open(a.resume + ".json") as f:
+            rec = json.load(f)
+        if rec["jitter"] != a.jitter:
+            raise SystemExit(f"--resume: the checkpoint ran jitter {rec['jitter']}, not {a.jitter}")
+        sched.update(num_warmup=rec["num_warmup"], num_iterations=rec["num_iterations"])
     s = chees.Sampler(Xd if len(Xd) > 1 else Xd[0], yd if len(yd) > 1 else yd[0], J,
-                      step_size=eps, traj_length=L,
-                      max_leapfrog=a.max_leapfrog, num_warmup=a.iterations // 2,
-                      jitter=a.jitter, precision=a.precision, precond=a.precond,
+                      step_size=eps, traj_length=L, max_leapfrog=a.max_leapfrog,
+                      precision=a.precision, precond=a.precond,
                       adapt_step_size=a.adapt_step_size, flow_layers=a.flow_layers,
-                      flow_train_steps=a.flow_train_steps, flow_lr=a.flow_lr,
-                      num_iterations=a.iterations, seed=a.seed)
+                      flow_train_steps=a.flow_train_steps, flow_lr=a.flow_lr, seed=a.seed,
+                      **sched)
     if a.resume:
         with open(a.resume, "rb") as f:
             s.load(f.read())
@@ -110,6 +120,8 @@ def main(argv=None):
     if a.save:
         with open(a.save, "wb") as f:
             f.write(s.save())
+        with open(a.save + ".json", "w") as f:
+            json.dump(sched, f)
     if out is not sys.stdout:
         out.close()
     s.close()

@@ -112,6 +112,9 @@ def test_runner_logs_every_iteration_and_resumes(tmp_path):
     assert all(0 < r["ess"] <= 2048 and 1 <= r["n_max"] <= 64 for r in recs)
     assert recs == [dict(r, wall_ms=x["wall_ms"]) for r, x in
                     zip([json.loads(l) for l in open(first)], recs)]
+    # the run's schedule is recorded beside the image and governs the resume
+    assert json.load(open(str(ck) + ".json")) == dict(num_warmup=3, num_iterations=6,
+                                                      jitter="halton1d")
     # resume from the checkpoint for the same schedule: iterations 7.. of a 6 + 6 run
     run.main(common + ["--jsonl", str(second), "--resume", str(ck)])
     more = [json.loads(l) for l in open(second)]
