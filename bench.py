@@ -417,6 +417,8 @@ def toeplitz_forms(args):
         "flow_base_only_f32": dict(step_size=0.3, traj_length=2.4, precond="flow", flow_layers=0),
         "flow_4x128_f32": flow,
         "flow_4x128_bf16 (BF16 + flow, the headline form)": dict(flow, precision="bf16"),
+        # the same fit budget per iteration in three Adam steps instead of ten
+        "flow_4x128_bf16_fit3": dict(flow, precision="bf16", flow_train_steps=3, flow_lr=6.7e-5),
     }
     seeds = [3 + 100 * r for r in range(args.replicates)]
     log("toeplitz: reference moments (diagonal mass, long runs)")
@@ -432,7 +434,8 @@ def toeplitz_forms(args):
         out["forms"][name] = matched(ref, rep, name)
         log(f"toeplitz {name}: {rep['ms_per_iteration']:.2f} ms/iteration, "
             f"ESS/s {rep['ess_per_s'] / 1e6:.3f} M, pass {out['forms'][name]['pass_3se']}")
-    for name in ("flow_4x128_f32", "flow_4x128_bf16 (BF16 + flow, the headline form)"):
+    for name in ("flow_4x128_f32", "flow_4x128_bf16 (BF16 + flow, the headline form)",
+                 "flow_4x128_bf16_fit3"):
         kp = flow_kernel_pass(Xd, yd, 4096, dict(base, seed=3, **forms[name]), ITERS // 2, 10)
         out["forms"][name]["flow_kernels"] = kp
         log(f"toeplitz {name}: moves {kp['moves_ms_per_iteration']:.3f} ms/iteration "

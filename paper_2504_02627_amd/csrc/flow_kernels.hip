@@ -19,8 +19,16 @@
 // activations, held in LDS, as B; the weights are pre-packed in the A-operand
 // order so that each lane reads four K-steps with one 16-byte load.  The
 // per-layer activations the backward passes need sit in a per-particle tape
-// in global memory.  Training uses the FP32 parameters; the moves use the
-// weights rounded to bfloat16 (held as FP32 operands) with FP32 arithmetic.
+// in global memory.  Training uses the FP32 parameters on
+// v_mfma_f32_16x16x4f32.  The moves use the weights rounded to bfloat16 on
+// v_mfma_f32_16x16x32_bf16: the weights are exact bfloat16 operands, and each
+// FP32 activation enters as the sum of three bfloat16 parts (hi, mid, lo;
+// split once per layer into LDS planes), so every product is exact and the
+// sums accumulate in FP32 -- the FP32 arithmetic of the weights' values, at
+// three bfloat16 products per 32 inputs instead of eight FP32 ones per 4.
+// The moves need that precision: the latent start z0 = T^-1(theta_0) and the
+// end point theta' = T(z') must come from the same map to FP32 rounding, or
+// the weights would not be those of the latent target.
 #pragma clang fp contract(off)
 
 #include <math.h>
@@ -41,6 +49,8 @@ constexpr int NT = 512;            // threads per block: one wave per 16-row out
 constexpr int LPP = NT / PB;       // lanes per particle in the element-wise parts
 constexpr int XP = MAXD + 17;      // LDS pitch of state rows: a padded K chunk stays in the row
 constexpr int HP = FH + 1;         // LDS pitch of hidden rows
+constexpr int BKP = 232;           // bfloat16 plane pitch: >= 32 ceil(MAXD / 32), 8 x odd for
+                                   // conflict-free 16-byte reads
 constexpr int KSPLIT = FKSPLIT;
 
 // Position of coordinate c of theta in the coupling state x: even
@@ -63,7 +73,10 @@ __device__ __forceinline__ int pk_index(int u, int k, int K16) {
   return (((u >> 4) * (K16 >> 4) + (k >> 4)) * 64 + lane) * 4 + (kk >> 2);
 }
 
+static_assert(BKP >= 32 * ((MAXD + 31) / 32) && BKP % 8 == 0 && (BKP / 8) % 2 == 1, "plane pitch");
+
 struct BlockLDS {
+  uint16_t bs[3][PB][BKP];  // an input of a move layer split into three bfloat16 planes
   float xs[PB][XP];   // coupling state x (or its cotangent)
   float h1[PB][HP];
   float h2[PB][HP];
@@ -207,24 +220,155 @@ __device__ void mdense(const float *Ap, int M, int K, const float *bias, const f
   }
 }
 
+// Element A[u][k] of an M x K bfloat16-exact matrix in the packed A-operand
+// order of v_mfma_f32_16x16x32_bf16: [u/16][k/32][lane][e] with lane =
+// u%16 + 16 ((k%32)/8), e = k%8, so that lane l's 16 bytes at (tile, chunk)
+// hold A[16 tile + l%16][32 chunk + 8 (l/16) + e], e = 0..7.
+__device__ __forceinline__ int pk16_index(int u, int k, int C32) {
+  return (((u >> 4) * C32 + (k >> 5)) * 64 + (u & 15) + 16 * ((k & 31) >> 3)) * 8 + (k & 7);
+}
+
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+// v = hi + mid + lo in bfloat16 (round to nearest even each), exact to a
+// unit in the last place of FP32.
+__device__ __forceinline__ void split3(float v, uint16_t &h, uint16_t &m, uint16_t &l) {
+  h = bf16_bits(v);
+  const float r1 = v - __uint_as_float((uint32_t)h << 16);
+  m = bf16_bits(r1);
+  const float r2 = r1 - __uint_as_float((uint32_t)m << 16);
+  l = bf16_bits(r2);
+}
+
+// NTL output tiles of one wave from the bfloat16 weights (Ab: the layer's
+// packed array) and the three planes of the input (lane (pn, kq) reads eight
+// consecutive inputs of particle pn per plane and chunk).
+template <int NTL>
+__device__ __forceinline__ void mdense_tiles_bf(const uint4 *Ab, int t, int M, int C32,
+                                                const float *bias, const BlockLDS &S, float *out,
+                                                int outs, int mode, float *tp, const float *ax,
+                                                int pn, int kq, int lane) {
+  int tt[NTL];
+  float4 axq[NTL];
+  float bq[NTL][4];
+  v4f acc[NTL];
+  const uint4 *ap[NTL];
+#pragma unroll
+  for (int g = 0; g < NTL; ++g) {
+    tt[g] = t + g * (NT / 64);
+    const int u0 = 16 * tt[g] + 4 * kq;
+    axq[g] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (ax && u0 + 3 < M) axq[g] = *reinterpret_cast<const float4 *>(ax + u0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) bq[g][i] = (bias && u0 + i < M) ? bias[u0 + i] : 0.f;
+    acc[g] = v4f{0.f, 0.f, 0.f, 0.f};
+    ap[g] = Ab + (long long)tt[g] * C32 * 64 + lane;
+  }
+  for (int c = 0; c < C32; ++c) {
+    uint4 a[NTL];
+#pragma unroll
+    for (int g = 0; g < NTL; ++g) a[g] = ap[g][c * 64];
+    const int ko = 32 * c + 8 * kq;
+    const v8bf b0 = *reinterpret_cast<const v8bf *>(&S.bs[0][pn][ko]);
+    const v8bf b1 = *reinterpret_cast<const v8bf *>(&S.bs[1][pn][ko]);
+    const v8bf b2 = *reinterpret_cast<const v8bf *>(&S.bs[2][pn][ko]);
+#pragma unroll
+    for (int g = 0; g < NTL; ++g) {
+      const v8bf av = __builtin_bit_cast(v8bf, a[g]);
+      acc[g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b2, acc[g], 0, 0, 0);
+      acc[g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b1, acc[g], 0, 0, 0);
+      acc[g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b0, acc[g], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int g = 0; g < NTL; ++g)
+    mdense_out(tt[g], acc[g], axq[g], bq[g], M, bias, out, outs, mode, tp, ax, pn, kq);
+}
+
+constexpr int MAXC32 = (MAXD + 31) / 32;  // 32-input chunks of the widest layer input
+
+// One move layer (bfloat16-exact weights, packed by pk16_index) for the
+// block's 16 particles, with the semantics of mdense.  The input rows are
+// first split into the three planes (every thread, one barrier); the caller
+// synchronises before (input complete) and after (planes free) as for mdense.
+// When every wave has at most one output tile (layers up to 128 wide), the
+// wave's weights, biases and tape values do not depend on the input and are
+// loaded before the split, so their latency passes with the split's barrier.
+__device__ void mdense_bf(const uint16_t *Ab16, int M, int K, const float *bias, const float *in,
+                          int ins, float *out, int outs, int mode, BlockLDS &S, int toff, int aoff,
+                          int wave, int lane) {
+  const int T = (M + 15) >> 4, C32 = (K + 31) >> 5, KP = 32 * C32;
+  const int tid = wave * 64 + lane;
+  const int pn = lane & 15, kq = lane >> 4;
+  float *tp = (toff >= 0 && S.tw[pn]) ? S.tw[pn] + toff : nullptr;
+  const float *ax = mode == ST_DTANH ? S.tr[pn] + aoff : nullptr;
+  const uint4 *Ab = reinterpret_cast<const uint4 *>(Ab16);
+  constexpr int NW = NT / 64;
+  const bool one = T <= NW;
+  uint4 apre[MAXC32];
+  float4 axq = make_float4(0.f, 0.f, 0.f, 0.f);
+  float bq[4] = {0.f, 0.f, 0.f, 0.f};
+  if (one && wave < T) {
+    const int u0 = 16 * wave + 4 * kq;
+    if (ax && u0 + 3 < M) axq = *reinterpret_cast<const float4 *>(ax + u0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) bq[i] = (bias && u0 + i < M) ? bias[u0 + i] : 0.f;
+    const uint4 *ap = Ab + (long long)wave * C32 * 64 + lane;
+#pragma unroll
+    for (int c = 0; c < MAXC32; ++c)
+      if (c < C32) apre[c] = ap[c * 64];
+  }
+  for (int i = tid; i < PB * KP; i += NT) {
+    const int q = i / KP, k = i % KP;
+    const float v = k < K ? in[q * ins + k] : 0.f;
+    split3(v, S.bs[0][q][k], S.bs[1][q][k], S.bs[2][q][k]);
+  }
+  __syncthreads();
+  if (one) {
+    if (wave >= T) return;
+    v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int c = 0; c < MAXC32; ++c) {
+      if (c >= C32) break;
+      const int ko = 32 * c + 8 * kq;
+      const v8bf av = __builtin_bit_cast(v8bf, apre[c]);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+          av, *reinterpret_cast<const v8bf *>(&S.bs[2][pn][ko]), acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+          av, *reinterpret_cast<const v8bf *>(&S.bs[1][pn][ko]), acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+          av, *reinterpret_cast<const v8bf *>(&S.bs[0][pn][ko]), acc, 0, 0, 0);
+    }
+    mdense_out(wave, acc, axq, bq, M, bias, out, outs, mode, tp, ax, pn, kq);
+    return;
+  }
+  const bool pair = mode == ST_DTANH || mode == ST_ADD;
+  for (int t = wave; t < T; t += (pair ? 2 : 1) * NW) {
+    if (pair && t + NW < T)
+      mdense_tiles_bf<2>(Ab, t, M, C32, bias, S, out, outs, mode, tp, ax, pn, kq, lane);
+    else
+      mdense_tiles_bf<1>(Ab, t, M, C32, bias, S, out, outs, mode, tp, ax, pn, kq, lane);
+  }
+}
+
 // Forward map of the block's particles (xs: latent z on entry, coupled x on
 // exit), with the move tape [h1 | h2 | s | x_T before the update] per layer;
 // returns the thread's partial sum of s (particle tid / 16).
-__device__ float forward_couplings(const FlowNet &F, const float *Ap, const float *bias,
+__device__ float forward_couplings(const FlowNet &F, const uint16_t *Ap, const float *bias,
                                    BlockLDS &S, int wave, int lane, int tid) {
   const int p = tid / LPP, r = tid % LPP;
   float ldp = 0.f;
   for (int l = 0; l < F.L; ++l) {
     const FlowLayerDesc &Y = F.ly[l];
     const int lo = l * F.tape_stride;
-    mdense(Ap + Y.pW1, FH, Y.dc, bias + Y.ob1, &S.xs[0][Y.C0], XP, &S.h1[0][0], HP, ST_TANH, S,
-           lo, 0, wave, lane);
+    mdense_bf(Ap + 2 * Y.pW1, FH, Y.dc, bias + Y.ob1, &S.xs[0][Y.C0], XP, &S.h1[0][0], HP, ST_TANH,
+              S, lo, 0, wave, lane);
     __syncthreads();
-    mdense(Ap + Y.pW2, FH, FH, bias + Y.ob2, &S.h1[0][0], HP, &S.h2[0][0], HP, ST_TANH, S,
-           lo + FH, 0, wave, lane);
+    mdense_bf(Ap + 2 * Y.pW2, FH, FH, bias + Y.ob2, &S.h1[0][0], HP, &S.h2[0][0], HP, ST_TANH, S,
+              lo + FH, 0, wave, lane);
     __syncthreads();
-    mdense(Ap + Y.pW3, 2 * Y.dt, FH, bias + Y.ob3, &S.h2[0][0], HP, &S.ob[0][0], XP, ST_PLAIN, S,
-           -1, 0, wave, lane);
+    mdense_bf(Ap + 2 * Y.pW3, 2 * Y.dt, FH, bias + Y.ob3, &S.h2[0][0], HP, &S.ob[0][0], XP,
+              ST_PLAIN, S, -1, 0, wave, lane);
     __syncthreads();
     float *tp = S.tw[p] ? S.tw[p] + lo + 2 * FH : nullptr;
     for (int f = r; f < Y.dt; f += LPP) {
@@ -246,7 +390,7 @@ __device__ float forward_couplings(const FlowNet &F, const float *Ap, const floa
 // Cotangent of z from the cotangent of x after the couplings (in xs), by
 // reverse accumulation over the move tape; the log-determinant adds 1 to the
 // cotangent of every s.  Bp: the transposed weights, packed.
-__device__ void vjp_couplings(const FlowNet &F, const float *Bp, BlockLDS &S, int wave, int lane,
+__device__ void vjp_couplings(const FlowNet &F, const uint16_t *Bp, BlockLDS &S, int wave, int lane,
                               int tid) {
   const int p = tid / LPP, r = tid % LPP;
   for (int l = F.L - 1; l >= 0; --l) {
@@ -262,14 +406,14 @@ __device__ void vjp_couplings(const FlowNet &F, const float *Bp, BlockLDS &S, in
       S.xs[p][Y.T0 + f] = gy * es;
     }
     __syncthreads();
-    mdense(Bp + Y.qW3, FH, 2 * Y.dt, nullptr, &S.ob[0][0], XP, &S.h2[0][0], HP, ST_DTANH, S, -1,
-           lo + FH, wave, lane);
+    mdense_bf(Bp + 2 * Y.qW3, FH, 2 * Y.dt, nullptr, &S.ob[0][0], XP, &S.h2[0][0], HP, ST_DTANH, S,
+              -1, lo + FH, wave, lane);
     __syncthreads();
-    mdense(Bp + Y.qW2, FH, FH, nullptr, &S.h2[0][0], HP, &S.h1[0][0], HP, ST_DTANH, S, -1, lo,
-           wave, lane);
+    mdense_bf(Bp + 2 * Y.qW2, FH, FH, nullptr, &S.h2[0][0], HP, &S.h1[0][0], HP, ST_DTANH, S, -1, lo,
+              wave, lane);
     __syncthreads();
-    mdense(Bp + Y.qW1, Y.dc, FH, nullptr, &S.h1[0][0], HP, &S.xs[0][Y.C0], XP, ST_ADD, S, -1, 0,
-           wave, lane);
+    mdense_bf(Bp + 2 * Y.qW1, Y.dc, FH, nullptr, &S.h1[0][0], HP, &S.xs[0][Y.C0], XP, ST_ADD, S, -1,
+              0, wave, lane);
     __syncthreads();
   }
 }
@@ -365,12 +509,14 @@ __global__ void k_flow_adam(Dev D, FlowNet F, int step, int update, const float 
       }
       if (o >= 0) {
         const int u = (i - o) / cols, k = (i - o) % cols;
-        const int fi = pf + pk_index(u, k, (cols + 15) / 16 * 16);
-        const int bi = pb + pk_index(k, u, (rows + 15) / 16 * 16);
-        D.fpk[fi] = pv;
-        D.fbk[fi] = hb;
-        D.fpk[bi] = pv;
-        D.fbk[bi] = hb;
+        D.fpk[pf + pk_index(u, k, (cols + 15) / 16 * 16)] = pv;
+        D.fpk[pb + pk_index(k, u, (rows + 15) / 16 * 16)] = pv;
+        // the moves' bfloat16 copies, in the region of the FP32 layout (at most
+        // half of it: K padded to 32 in bfloat16 against 16 in FP32)
+        uint16_t *wb = reinterpret_cast<uint16_t *>(D.fbk);
+        const uint16_t hbits = bf16_bits(pv);
+        wb[2 * pf + pk16_index(u, k, (cols + 31) / 32)] = hbits;
+        wb[2 * pb + pk16_index(k, u, (rows + 31) / 32)] = hbits;
         weight = true;
       }
     }
@@ -817,14 +963,15 @@ __global__ __launch_bounds__(NT) void k_flow_inverse(Dev D, FlowNet F) {
   float ldp = r == 0 ? -D.fbase[0] : 0.f;
   for (int l = F.L - 1; l >= 0; --l) {
     const FlowLayerDesc &Y = F.ly[l];
-    mdense(D.fbk + Y.pW1, FH, Y.dc, D.fbias + Y.ob1, &S.xs[0][Y.C0], XP, &S.h1[0][0], HP, ST_TANH,
-           S, -1, 0, wave, lane);
+    const uint16_t *Wb = reinterpret_cast<const uint16_t *>(D.fbk);
+    mdense_bf(Wb + 2 * Y.pW1, FH, Y.dc, D.fbias + Y.ob1, &S.xs[0][Y.C0], XP, &S.h1[0][0], HP,
+              ST_TANH, S, -1, 0, wave, lane);
     __syncthreads();
-    mdense(D.fbk + Y.pW2, FH, FH, D.fbias + Y.ob2, &S.h1[0][0], HP, &S.h2[0][0], HP, ST_TANH, S,
-           -1, 0, wave, lane);
+    mdense_bf(Wb + 2 * Y.pW2, FH, FH, D.fbias + Y.ob2, &S.h1[0][0], HP, &S.h2[0][0], HP, ST_TANH,
+              S, -1, 0, wave, lane);
     __syncthreads();
-    mdense(D.fbk + Y.pW3, 2 * Y.dt, FH, D.fbias + Y.ob3, &S.h2[0][0], HP, &S.ob[0][0], XP,
-           ST_PLAIN, S, -1, 0, wave, lane);
+    mdense_bf(Wb + 2 * Y.pW3, 2 * Y.dt, FH, D.fbias + Y.ob3, &S.h2[0][0], HP, &S.ob[0][0], XP,
+              ST_PLAIN, S, -1, 0, wave, lane);
     __syncthreads();
     for (int f = r; f < Y.dt; f += LPP) {
       const float s = tanhf(S.ob[p][f]);
@@ -906,7 +1053,8 @@ __device__ __forceinline__ void drift_body(const Dev &D, const FlowNet &F, Block
     S.xs[q][c] = z;
   }
   __syncthreads();
-  float ldp = forward_couplings(F, D.fbk, D.fbias, S, wave, lane, tid);
+  float ldp = forward_couplings(F, reinterpret_cast<const uint16_t *>(D.fbk), D.fbias, S, wave,
+                               lane, tid);
   if (init) return;
   mdense(D.fAf, F.d, F.d, nullptr, &S.xs[0][0], XP, &S.ob[0][0], XP, ST_PLAIN, S, -1, 0, wave, lane);
   if (r == 0) ldp += D.fbase[0];
@@ -943,7 +1091,7 @@ __device__ __forceinline__ void kick_body(const Dev &D, const FlowNet &F, BlockL
   __syncthreads();
   for (int i = tid; i < PB * XP; i += NT) (&S.ob[0][0])[i] = 0.f;
   __syncthreads();
-  vjp_couplings(F, D.fbk, S, wave, lane, tid);
+  vjp_couplings(F, reinterpret_cast<const uint16_t *>(D.fbk), S, wave, lane, tid);
   for (int i = tid; i < PB * F.d; i += NT) {
     const int q = i / F.d, c = i % F.d;
     const int j = S.rows[q];
