@@ -415,6 +415,8 @@ def toeplitz_forms(args):
         "unit_mass_bf16": dict(step_size=e0, traj_length=e0 * 32, precision="bf16"),
         "diagonal_mass_f32": dict(step_size=0.05, traj_length=1.6, precond="diag"),
         "flow_base_only_f32": dict(step_size=0.3, traj_length=2.4, precond="flow", flow_layers=0),
+        "flow_base_only_bf16": dict(step_size=0.3, traj_length=2.4, precond="flow", flow_layers=0,
+                                    precision="bf16"),
         "flow_4x128_f32": flow,
         "flow_4x128_bf16 (BF16 + flow, the headline form)": dict(flow, precision="bf16"),
         # the same fit budget per iteration in three Adam steps instead of ten
@@ -448,6 +450,11 @@ def toeplitz_forms(args):
         "verdict": ("BF16 + flow beats plain FP32 in ESS/s at matched error"
                     if head["ess_per_s"] > plain["ess_per_s"] and head["pass_3se"] and plain["pass_3se"]
                     else "BF16 + flow does NOT beat plain FP32 in ESS/s at matched error on this run")}
+    # every BF16 flow form (couplings or the base map alone) that passes,
+    # against plain FP32 (which may itself fail at 50 iterations)
+    out["headline"]["bf16_flow_forms_passing"] = {
+        k: {"ess_per_s_over_plain_f32": v["ess_per_s"] / plain["ess_per_s"]}
+        for k, v in out["forms"].items() if "flow" in k and "bf16" in k and v["pass_3se"]}
     return out
 
 
