@@ -533,15 +533,24 @@ __global__ void k_flow_adam(Dev D, FlowNet F, int step, int update, const float 
 // the three base products (x -> L u, its transpose for the latent gradient,
 // theta - m -> x via L^-1, with u_c = x_q(c)) and log|det L|.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_flow_cov(Dev D, FlowNet F) {
-  // one 16 x 16 tile of C and one of FCOV_CH particle chunks per block (its
-  // partial sum goes to its own slice); 64 particles staged at a time
-  __shared__ double Xa[64][17], Xb[64][17];
-  __shared__ double Wc[64];
-  const int d = F.d, nt = (d + 15) / 16;
-  const int ta = blockIdx.x / nt, tb = blockIdx.x % nt, ch = blockIdx.y;
-  if (tb > ta) return;  // lower triangle of tiles
-  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+constexpr int FCOV_G = 4;  // particle groups of 256 threads per covariance block
+
+__global__ __launch_bounds__(256 * FCOV_G) void k_flow_cov(Dev D, FlowNet F) {
+  // one 16 x 16 tile of the lower triangle of C and one of FCOV_CH particle
+  // chunks per block (its partial sum goes to its own slice); each of the
+  // FCOV_G thread groups takes every FCOV_G-th slab of 64 particles of the
+  // chunk, and the group sums are added in group order
+  __shared__ double Xa[FCOV_G][64][17], Xb[FCOV_G][64][17];
+  __shared__ double Wc[FCOV_G][64];
+  __shared__ double red[FCOV_G - 1][256];
+  const int d = F.d;
+  const int bt = blockIdx.x;
+  int ta = (int)((sqrt(8.0 * bt + 1.0) - 1.0) * 0.5);
+  while (ta * (ta + 1) / 2 > bt) --ta;
+  while ((ta + 1) * (ta + 2) / 2 <= bt) ++ta;
+  const int tb = bt - ta * (ta + 1) / 2, ch = blockIdx.y;
+  const int g = threadIdx.x >> 8, t = threadIdx.x & 255;
+  const int ty = t >> 4, tx = t & 15;
   const int c = 16 * ta + ty, k = 16 * tb + tx;
   const PState &PS = D.ps[0];
   const int rs = PS.resampled;
@@ -549,48 +558,54 @@ __global__ __launch_bounds__(256) void k_flow_cov(Dev D, FlowNet F) {
   const double *mean = D.means;
   const int per = ((D.J + FCOV_CH - 1) / FCOV_CH + 63) / 64 * 64;
   const int jb = ch * per, je = min(D.J, jb + per);
+  const int nit = (max(je - jb, 0) + 64 * FCOV_G - 1) / (64 * FCOV_G);
   double acc = 0.0;
-  for (int j0 = jb; j0 < je; j0 += 64) {
-    for (int i = threadIdx.x; i < 64 * 16; i += 256) {
+  for (int it = 0; it < nit; ++it) {
+    const int j0 = jb + 64 * (g + FCOV_G * it);
+    for (int i = t; i < 64 * 16; i += 256) {
       const int jj = i >> 4, cc = i & 15, j = j0 + jj;
       const int ca = 16 * ta + cc, cb = 16 * tb + cc;
-      Xa[jj][cc] = (j < je && ca < d) ? (double)src[(long long)j * D.DS + ca] - mean[ca] : 0.0;
-      Xb[jj][cc] = (j < je && cb < d) ? (double)src[(long long)j * D.DS + cb] - mean[cb] : 0.0;
+      Xa[g][jj][cc] = (j < je && ca < d) ? (double)src[(long long)j * D.DS + ca] - mean[ca] : 0.0;
+      Xb[g][jj][cc] = (j < je && cb < d) ? (double)src[(long long)j * D.DS + cb] - mean[cb] : 0.0;
     }
-    if (threadIdx.x < 64) {
-      const int j = j0 + threadIdx.x;
+    if (t < 64) {
+      const int j = j0 + t;
       double w = 0.0;
       if (j < je) {
         const double lw = D.logw[j];
         w = rs ? 1.0 / D.J : ((lw == lw && lw > -INFINITY) ? exp(lw - PS.m) / PS.S : 0.0);
       }
-      Wc[threadIdx.x] = w;
+      Wc[g][t] = w;
     }
     __syncthreads();
-    for (int jj = 0; jj < 64; ++jj) acc += Wc[jj] * (Xa[jj][ty] * Xb[jj][tx]);
+    for (int jj = 0; jj < 64; ++jj) acc += Wc[g][jj] * (Xa[g][jj][ty] * Xb[g][jj][tx]);
     __syncthreads();
   }
-  if (c < d && k < d) {
+  if (g > 0) red[g - 1][t] = acc;
+  __syncthreads();
+  if (g == 0 && c < d && k < d) {
+    for (int q = 0; q < FCOV_G - 1; ++q) acc += red[q][t];
     double *out = D.fcov + (long long)ch * d * d;
     out[(long long)c * d + k] = acc;
     out[(long long)k * d + c] = acc;
   }
 }
 
-// C = sum of the chunk partials in chunk order, shrunk: n/(n+5) C + 1e-3 5/(n+5) I.
-__device__ __forceinline__ double flow_shrunk_cov(const Dev &D, int d, int i, double sc, double sh) {
+// C = sum of the chunk partials in chunk order, shrunk: n/(n+5) C + 1e-3 5/(n+5) I,
+// into fLd (d x d, FP64), the factorisations' input.
+__global__ __launch_bounds__(256) void k_flow_covsum(Dev D, FlowNet F) {
+  const int d = F.d, i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= d * d) return;
+  const double n = D.ps[0].ess_before;
+  const double sc = n / (n + 5.0), sh = 1e-3 * (5.0 / (n + 5.0));
   double v = 0.0;
   for (int ch = 0; ch < FCOV_CH; ++ch) v += D.fcov[(long long)ch * d * d + i];
-  return sc * v + ((i / d == i % d) ? sh : 0.0);
+  D.fLd[i] = sc * v + ((i / d == i % d) ? sh : 0.0);
 }
 
 __global__ __launch_bounds__(256) void k_flow_chol(Dev D, FlowNet F) {
   const int d = F.d, tid = threadIdx.x;
-  double *A = D.fLd, *X = D.fLi;
-  const double n = D.ps[0].ess_before;
-  const double sc = n / (n + 5.0), sh = 1e-3 * (5.0 / (n + 5.0));
-  for (int i = tid; i < d * d; i += 256) A[i] = flow_shrunk_cov(D, d, i, sc, sh);
-  __syncthreads();
+  double *A = D.fLd, *X = D.fLi;  // A: the shrunk covariance, factorised in place
   // right-looking Cholesky, lower triangle in place
   for (int k = 0; k < d; ++k) {
     if (tid == 0) A[(long long)k * d + k] = sqrt(A[(long long)k * d + k]);
@@ -678,10 +693,9 @@ __global__ __launch_bounds__(FCHOL_NT) void k_flow_chol_lds(Dev D, FlowNet F) {
   __shared__ double sd[FCHOL_LDS], isd[FCHOL_LDS], sq[FCHOL_LDS], rs[FCHOL_LDS];
   const int d = F.d, tid = threadIdx.x, P = d | 1, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const double n = D.ps[0].ess_before;
-  const double sc = n / (n + 5.0), sh = 1e-3 * (5.0 / (n + 5.0));
+  const double *C = D.fLd;                    // the shrunk covariance
   for (int c = tid; c < d; c += FCHOL_NT) {
-    const double x = flow_shrunk_cov(D, d, c * d + c, sc, sh);
+    const double x = C[c * d + c];
     sd[c] = sqrt(x);
     isd[c] = 1.0 / sd[c];
   }
@@ -696,8 +710,8 @@ __global__ __launch_bounds__(FCHOL_NT) void k_flow_chol_lds(Dev D, FlowNet F) {
       double x0 = 0.0, x1 = 0.0;
       if (i < d) {
         const double isi = isd[i];
-        if (lane < d) x0 = flow_shrunk_cov(D, d, i * d + lane, sc, sh) * isi * is0;
-        if (lane + 64 < d) x1 = flow_shrunk_cov(D, d, i * d + lane + 64, sc, sh) * isi * is1;
+        if (lane < d) x0 = C[i * d + lane] * isi * is0;
+        if (lane + 64 < d) x1 = C[i * d + lane + 64] * isi * is1;
         if (i == 0) {                           // v_0: row 0 of C_s
           if (lane < d) M[lane] = x0;
           if (lane + 64 < d) M[lane + 64] = x1;
@@ -1237,7 +1251,8 @@ hipError_t launch_flow_publish(const Dev &D, const FlowNet &F, hipStream_t st) {
 
 hipError_t launch_flow_base(const Dev &D, const FlowNet &F, hipStream_t st) {
   const int nt = (F.d + 15) / 16;
-  hipLaunchKernelGGL(k_flow_cov, dim3(nt * nt, FCOV_CH), dim3(256), 0, st, D, F);
+  hipLaunchKernelGGL(k_flow_cov, dim3(nt * (nt + 1) / 2, FCOV_CH), dim3(256 * FCOV_G), 0, st, D, F);
+  hipLaunchKernelGGL(k_flow_covsum, dim3((F.d * F.d + 255) / 256), dim3(256), 0, st, D, F);
   if (F.d <= FCHOL_LDS)
     hipLaunchKernelGGL(k_flow_chol_lds, dim3(1), dim3(FCHOL_NT), 0, st, D, F);
   else
