@@ -73,6 +73,7 @@ __device__ __forceinline__ int pk_index(int u, int k, int K16) {
   return (((u >> 4) * (K16 >> 4) + (k >> 4)) * 64 + lane) * 4 + (kk >> 2);
 }
 
+static_assert(NT % PB == 0 && LPP % 2 == 0, "row-parallel loops: LPP threads per particle");
 static_assert(BKP >= 32 * ((MAXD + 31) / 32) && BKP % 8 == 0 && (BKP / 8) % 2 == 1, "plane pitch");
 
 struct BlockLDS {
@@ -231,13 +232,22 @@ __device__ __forceinline__ int pk16_index(int u, int k, int C32) {
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
 // v = hi + mid + lo in bfloat16 (round to nearest even each), exact to a
-// unit in the last place of FP32.
-__device__ __forceinline__ void split3(float v, uint16_t &h, uint16_t &m, uint16_t &l) {
-  h = bf16_bits(v);
-  const float r1 = v - __uint_as_float((uint32_t)h << 16);
-  m = bf16_bits(r1);
-  const float r2 = r1 - __uint_as_float((uint32_t)m << 16);
-  l = bf16_bits(r2);
+// unit in the last place of FP32; two values at a time (element 0 in the low
+// halves), by the hardware's pair conversion, which rounds as bf16_bits does.
+typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
+typedef float v2f __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t bf16_pair(float a, float b) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((v2f){a, b}, v2bf));
+}
+
+__device__ __forceinline__ void split3_pair(float v0, float v1, uint32_t &h, uint32_t &m,
+                                            uint32_t &l) {
+  h = bf16_pair(v0, v1);
+  const float r0 = v0 - __uint_as_float(h << 16), r1 = v1 - __uint_as_float(h & 0xFFFF0000u);
+  m = bf16_pair(r0, r1);
+  const float q0 = r0 - __uint_as_float(m << 16), q1 = r1 - __uint_as_float(m & 0xFFFF0000u);
+  l = bf16_pair(q0, q1);
 }
 
 // NTL output tiles of one wave from the bfloat16 weights (Ab: the layer's
@@ -318,10 +328,18 @@ __device__ void mdense_bf(const uint16_t *Ab16, int M, int K, const float *bias,
     for (int c = 0; c < MAXC32; ++c)
       if (c < C32) apre[c] = ap[c * 64];
   }
-  for (int i = tid; i < PB * KP; i += NT) {
-    const int q = i / KP, k = i % KP;
-    const float v = k < K ? in[q * ins + k] : 0.f;
-    split3(v, S.bs[0][q][k], S.bs[1][q][k], S.bs[2][q][k]);
+  {
+    // LPP threads per particle row, two neighbouring inputs each: one 32-bit
+    // store per plane, no division by the run-time row length
+    const int q = tid / LPP;
+    const float *row = in + q * ins;
+    for (int k = 2 * (tid % LPP); k < KP; k += 2 * LPP) {
+      uint32_t h, m, l;
+      split3_pair(k < K ? row[k] : 0.f, k + 1 < K ? row[k + 1] : 0.f, h, m, l);
+      *reinterpret_cast<uint32_t *>(&S.bs[0][q][k]) = h;
+      *reinterpret_cast<uint32_t *>(&S.bs[1][q][k]) = m;
+      *reinterpret_cast<uint32_t *>(&S.bs[2][q][k]) = l;
+    }
   }
   __syncthreads();
   if (one) {
@@ -807,8 +825,7 @@ __global__ __launch_bounds__(NT) void k_flow_train(Dev D, FlowNet F) {
   }
   clear_rows(S, tid);
   __syncthreads();
-  for (int i = tid; i < PB * F.d; i += NT) {
-    const int q = i / F.d, c = i % F.d;
+  for (int q = tid / LPP, c = tid % LPP; c < F.d; c += LPP) {
     const int j = S.rows[q];
     S.ob[q][c] = j >= 0 ? src[(long long)j * D.DS + c] - D.fm[c] : 0.f;
   }
@@ -1024,8 +1041,7 @@ __global__ __launch_bounds__(NT) void k_flow_inverse(Dev D, FlowNet F) {
   }
   clear_rows(S, tid);
   __syncthreads();
-  for (int i = tid; i < PB * F.d; i += NT) {
-    const int q = i / F.d, c = i % F.d;
+  for (int q = tid / LPP, c = tid % LPP; c < F.d; c += LPP) {
     const int j = S.rows[q];
     S.ob[q][c] = j >= 0 ? D.theta_t[(long long)j * D.DS + c] - D.fm[c] : 0.f;
   }
@@ -1108,10 +1124,9 @@ __device__ __forceinline__ void drift_body(const Dev &D, const FlowNet &F, Block
   const int p = tid / LPP, r = tid % LPP;
   const float eps = (float)D.ps[0].eps;
   const float he = 0.5f * eps;
-  for (int i = tid; i < PB * D.DS; i += NT) {
-    const int q = i / D.DS, c = i % D.DS;
+  for (int q = tid / LPP, c = tid % LPP; c < F.d; c += LPP) {
     const int j = S.rows[q];
-    if (j < 0 || c >= F.d) continue;
+    if (j < 0) continue;
     const long long e = (long long)j * D.DS + c;
     float z;
     if (init) {
@@ -1153,8 +1168,7 @@ __device__ __forceinline__ void kick_body(const Dev &D, const FlowNet &F, BlockL
                                           int tid) {
   const int lane = tid & 63, wave = tid >> 6;
   const float he = 0.5f * (float)D.ps[0].eps;
-  for (int i = tid; i < PB * F.d; i += NT) {
-    const int q = i / F.d, c = i % F.d;
+  for (int q = tid / LPP, c = tid % LPP; c < F.d; c += LPP) {
     const int j = S.rows[q];
     S.ob[q][c] = j >= 0 ? D.grad_t[(long long)j * D.DS + c] : 0.f;
   }
@@ -1164,8 +1178,7 @@ __device__ __forceinline__ void kick_body(const Dev &D, const FlowNet &F, BlockL
   for (int i = tid; i < PB * XP; i += NT) (&S.ob[0][0])[i] = 0.f;
   __syncthreads();
   vjp_couplings(F, reinterpret_cast<const uint16_t *>(D.fbk), S, wave, lane, tid);
-  for (int i = tid; i < PB * F.d; i += NT) {
-    const int q = i / F.d, c = i % F.d;
+  for (int q = tid / LPP, c = tid % LPP; c < F.d; c += LPP) {
     const int j = S.rows[q];
     if (j < 0) continue;
     const long long e = (long long)j * D.DS + c;
