@@ -772,22 +772,24 @@ __global__ __launch_bounds__(FCHOL_NT) void k_flow_chol_lds(Dev D, FlowNet F) {
   for (int c = tid; c < d; c += FCHOL_NT) {
     sq[c] = sqrt(M[c * P + c]);                 // delta_c^1/2
     rs[c] = 1.0 / sq[c];
+    rc[c] = log(sq[c] * sd[c]);                 // log L_cc (rc is free again)
   }
   __syncthreads();
   const int K16 = (d + 15) / 16 * 16;
-  for (int e = tid; e < d * d; e += FCHOL_NT) {
-    const int c = e / d, k = e % d;
-    const double l = k < c ? M[k * P + c] * rs[k] * sd[c] : (k == c ? sq[c] * sd[c] : 0.0);
-    const double li = k < c ? M[c * P + k] * rs[c] * isd[k] : (k == c ? rs[c] * isd[c] : 0.0);
-    D.fL[e] = (float)l;
-    D.fAf[pk_index(c, xpos(k, d), K16)] = (float)l;          // theta - m = L u, u_k = x_q(k)
-    D.fAb[pk_index(xpos(k, d), c, K16)] = (float)l;          // cotangent of x: L^T g
-    D.fAi[pk_index(xpos(c, d), k, K16)] = (float)li;         // x_q(c) = (L^-1 (theta - m))_c
-  }
+  // row c of L and of L^-1: wave w takes rows w, w + FCHOL_W, ..., lanes the columns
+  for (int c = w; c < d; c += FCHOL_W)
+    for (int k = lane; k < d; k += 64) {
+      const double l = k < c ? M[k * P + c] * rs[k] * sd[c] : (k == c ? sq[c] * sd[c] : 0.0);
+      const double li = k < c ? M[c * P + k] * rs[c] * isd[k] : (k == c ? rs[c] * isd[c] : 0.0);
+      D.fL[c * d + k] = (float)l;
+      D.fAf[pk_index(c, xpos(k, d), K16)] = (float)l;        // theta - m = L u, u_k = x_q(k)
+      D.fAb[pk_index(xpos(k, d), c, K16)] = (float)l;        // cotangent of x: L^T g
+      D.fAi[pk_index(xpos(c, d), k, K16)] = (float)li;       // x_q(c) = (L^-1 (theta - m))_c
+    }
   for (int c = tid; c < D.DS; c += FCHOL_NT) D.fm[c] = c < d ? (float)D.means[c] : 0.f;
   if (tid == 0) {
     double s = 0.0;
-    for (int c = 0; c < d; ++c) s += log(sq[c] * sd[c]);
+    for (int c = 0; c < d; ++c) s += rc[c];
     D.fbase[0] = (float)s;
   }
 }
