@@ -159,6 +159,36 @@ def test_flow_iteration_parity(N, d, J, seed, layers):
         Pprev = prm
 
 
+@pytest.mark.parametrize("d", [2, 63, 64, 65, 127])
+def test_base_map_at_the_register_layout_edges(d):
+    """The base map alone (no couplings) at dimensions around the one-work-group
+    factorisation's register layout (lane l holds columns l and l + 64 of a
+    row; 16 waves of 8 rows): m and L of the pre-move population against the
+    oracle's FP64 standardisation, the latent start z0 = L^-1 (theta0 - m) and
+    log|det L| of one iteration."""
+    N, J, seed = 300, 256, 20 + d
+    X, y, theta0, params, s, t, rng = _setup(N, d, J, seed, 0, 1e-3, ess_frac=0.0,
+                                             flow_layers=0)
+    lw0 = s.state()[1].cpu().numpy()
+    xi = rng.standard_normal((J, d)).astype(np.float32)
+    st = s.step(momenta=to_dev(xi), resample_u=to_dev(np.array([0.5])))
+    assert not st["resampled"]
+    tr = s.trace()
+    _, m_dev, L_dev = (v.cpu().numpy().astype(np.float64) for v in s.flow())
+    th0 = theta0.astype(np.float64)
+    ref = F.standardise(th0, lw0, st["ess_before"])
+    np.testing.assert_allclose(m_dev, ref.m, rtol=1e-6, atol=1e-7)
+    np.testing.assert_allclose(L_dev, ref.L, rtol=1e-5, atol=1e-6 * np.abs(ref.L).max())
+    z0, ldi = F.inverse([], F.Base(m_dev, L_dev), th0)
+    z0_dev = tr["latent0"].cpu().numpy()[:J, :d].astype(np.float64)
+    ez0 = rel_rows(z0_dev, z0)
+    ld0_dev = tr["logdet0"].cpu().numpy()[:J].astype(np.float64)
+    log(f"[base map d={d}] L rel err {np.max(np.abs(L_dev - ref.L)) / np.abs(ref.L).max():.2e}; "
+        f"z0 rel err {ez0:.2e}; max |logdet0 err| {np.max(np.abs(ld0_dev + ldi)):.2e}")
+    assert ez0 <= 1e-5
+    assert np.all(np.abs(ld0_dev + ldi) <= 1e-5 * (1 + np.abs(ldi)))
+
+
 def test_flow_with_no_training_and_identity_couplings_is_a_dense_mass():
     """Zero couplings (set through smc_set_flow) and no training: T(z) = m +
     L u with u_c = z_q(c).  The latent leapfrog is then the plain leapfrog in
