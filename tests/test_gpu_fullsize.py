@@ -41,8 +41,8 @@ def test_full_size_sampled_particles(precision):
     Xd = to_dev(X)
     s = chees.Sampler(Xd.to(torch.bfloat16) if bf else Xd, to_dev(y), J,
                       theta0=to_dev(theta0), precision=precision, **params)
-    sample = np.unique(np.concatenate([np.linspace(0, J - 1, 96).astype(int),
-                                       rng.integers(0, J, 8)]))
+    sample = np.unique(np.concatenate([np.linspace(0, J - 1, 512).astype(int),
+                                       rng.integers(0, J, 32)]))
     theta_prev = theta0.astype(np.float64)
     L, eps = params["traj_length"], eps0
     for k in (1, 2):
