@@ -15,7 +15,7 @@ of its own end points.
 Flow: the Toeplitz model (N = 5000, d = 100, rows correlated 0.95^|i-j|),
 J = 4096, four affine couplings of width 128 with couplings set from the host
 (seeded, non-trivial), no fit.  The oracle forms its own base map from its own
-initial weights; 64 sampled particles' z0 at 1e-5, z', theta', p' at 1e-5
+initial weights; 256 sampled particles' z0 at 1e-5, z', theta', p' at 1e-5
 (FP32) or to the BF16 bars, and Delta H at 1e-5 (|H0| + |H1|).
 
 One iteration without resampling (ess_frac = 0), so every particle moves from
@@ -156,7 +156,7 @@ def test_flow_full_size_iteration(precision):
     h = O.halton_1d(1, J)
     _, n = O.step_counts(h, params["traj_length"], eps, params["max_leapfrog"])
     np.testing.assert_array_equal(tr["n"].cpu().numpy()[:J], n)
-    sel = np.unique(np.r_[np.argmax(n), np.argmin(n), rng.integers(0, J, 62)])
+    sel = np.unique(np.r_[np.argmax(n), np.argmin(n), rng.integers(0, J, 254)])
     z0, ldi = F.inverse(psb, base, th0[sel])
     z0_dev = tr["latent0"].cpu().numpy()[:J, :d][sel].astype(np.float64)
     ez0 = rel_rows(z0_dev, z0)
