@@ -34,7 +34,7 @@ def _same(a, b):
 
 
 @pytest.mark.parametrize("precision,precond", [("f32", "none"), ("bf16", "none"), ("f32", "diag"),
-                                               ("f32", "flow")])
+                                               ("f32", "flow"), ("bf16", "flow")])
 def test_graph_replays_match_eager(precision, precond):
     import torch
     from paper_2504_02627_amd import chees
