@@ -73,6 +73,48 @@ def traffic_for_current_kernel():
     return t.get("bytes_per_launch")
 
 
+TRAFFIC_COMMAND = ("rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) -d <dir> -o f --output-format csv -- "
+                   "python bench.py --no-cpu-baseline --no-other --replicates 1 --ref-iters 3 "
+                   "--ref-runs 1 --no-bf16 --steps 2 --warmup 1; scale from rocprofv3 --pmc "
+                   "FETCH_SIZE / WRITE_SIZE -- python bench.py --copy-calibration (256 MiB device copy)")
+
+
+def write_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, path=TRAFFIC_FILE):
+    """HBM bytes per launch of the headline leapfrog kernel from the four
+    rocprofv3 counter runs of TRAFFIC_COMMAND (FETCH_SIZE / WRITE_SIZE in KiB
+    per dispatch), each scaled by what the same counter reads for the 256 MiB
+    device copy of --copy-calibration; written with the current source hash."""
+    import csv
+    import glob
+
+    def per_dispatch(d, counter, match):
+        f = glob.glob(os.path.join(d, "*counter_collection.csv"))[0]
+        v = {}
+        for r in csv.DictReader(open(f)):
+            if r["Counter_Name"] == counter and match(r["Kernel_Name"]):
+                v[r["Dispatch_Id"]] = v.get(r["Dispatch_Id"], 0.0) + 1024.0 * float(r["Counter_Value"])
+        return list(v.values())
+
+    lf = lambda n: "k_lf_partial<7, false>" in n
+    cp = lambda n: "copyBuffer" in n
+    fetch, write = per_dispatch(fetch_dir, "FETCH_SIZE", lf), per_dispatch(write_dir, "WRITE_SIZE", lf)
+    # scale = bytes the copy moves / bytes the counter reports for it
+    copy_bytes = 256 << 20
+    fs = copy_bytes / (sum(per_dispatch(copy_fetch_dir, "FETCH_SIZE", cp)) / 3)
+    ws = copy_bytes / (sum(per_dispatch(copy_write_dir, "WRITE_SIZE", cp)) / 3)
+    fb, wb = sum(fetch) / len(fetch) * fs, sum(write) / len(write) * ws
+    t = {"kernel": "void smc::k_lf_partial<7, false>", "kernel_sha256_16": kernel_hash(),
+         "bytes_per_launch": int(round(fb + wb)), "fetch_bytes_per_launch": int(round(fb)),
+         "write_bytes_per_launch": int(round(wb)),
+         "full_activity_fetch_bytes": int(round(max(fetch) * fs)),
+         "full_activity_write_bytes": int(round(max(write) * ws)),
+         "fetch_scale": round(fs, 4), "write_scale": round(ws, 4), "launches_sampled": len(fetch),
+         "command": TRAFFIC_COMMAND}
+    with open(path, "w") as f:
+        json.dump(t, f, indent=1)
+    return t
+
+
 def large_params(num_warmup):
     from paper_2504_02627_amd import synth
     eps0 = synth.default_step_size(N_ROWS, DIM)
@@ -603,7 +645,12 @@ def main():
     ap.add_argument("--ref-iters", type=int, default=600)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of known size (counter scaling)")
+    ap.add_argument("--traffic-from", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
+                    help="write the leapfrog traffic file from the four counter-run directories")
     args = ap.parse_args()
+    if args.traffic_from:
+        print(json.dumps(write_traffic(*args.traffic_from)))
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         if int(os.environ.get("RANK", "0")) == 0:

@@ -83,7 +83,7 @@ struct Layout {
   std::vector<int3> groups;  // (C2, first item, item count) of the log-likelihood pass
   size_t total = 0;
   // byte offsets
-  size_t o_posts, o_ps, o_xab, o_xbf, o_theta, o_grad, o_theta_t, o_p_t, o_grad_t, o_theta_n;
+  size_t o_posts, o_ps, o_xab, o_xbf, o_xb3, o_theta, o_grad, o_theta_t, o_p_t, o_grad_t, o_theta_n;
   size_t o_logpi, o_logpi_t, o_logw, o_h, o_l, o_H0, o_dH, o_alpha, o_ca, o_cg;
   size_t o_n, o_perm, o_active, o_anc, o_acc, o_cdf, o_gpart, o_llpart;
   size_t o_redp = 0, o_redc = 0, o_sortc = 0, o_status = 0;
@@ -262,7 +262,7 @@ void plan(const smc_problem *pr, const smc_params *pa, Layout &L) {
   L.Jcap = (L.J + TJ - 1) / TJ * TJ;
   L.nmax = pa->max_leapfrog;
   int maxc2 = 1;
-  long long xoff = 0, uoff = 0, xboff = 0;
+  long long xoff = 0, uoff = 0, xboff = 0, x3off = 0;
   const bool bf16 = pa->precision == SMC_PRECISION_BF16;
   L.hp.resize(B);
   L.posts.resize(B);
@@ -280,8 +280,12 @@ void plan(const smc_problem *pr, const smc_params *pa, Layout &L) {
     h.KC = (h.C2 + 1) / 2;
     h.xab = xoff;
     h.xbf = xboff;
+    h.xb3 = x3off;
     xoff += (long long)h.NT * 64 * (8 * h.C2 + 4);
-    if (bf16) xboff += (long long)h.NT2 * 64 * bf16_lane_stride(h.C2);
+    if (bf16) {
+      xboff += (long long)h.NT2 * 64 * bf16_lane_stride(h.C2);
+      x3off += (long long)h.NT2 * 64 * b3_lane_stride(h.C2);
+    }
     maxc2 = std::max(maxc2, h.C2);
     Post &p = L.posts[b];
     memset(&p, 0, sizeof(p));
@@ -293,6 +297,7 @@ void plan(const smc_problem *pr, const smc_params *pa, Layout &L) {
     p.row0 = b * L.Jcap;
     p.xab = h.xab;
     p.xbf = h.xbf;
+    p.xb3 = h.xb3;
     p.NT2 = h.NT2;
     p.KC = h.KC;
     p.uoff = uoff;
@@ -367,6 +372,7 @@ void plan(const smc_problem *pr, const smc_params *pa, Layout &L) {
   L.o_ps = take(c, B * sizeof(PState));
   L.o_xab = take(c, xoff * sizeof(float));
   L.o_xbf = take(c, xboff * 16);
+  L.o_xb3 = take(c, x3off * 16);
   L.o_theta = take(c, st);
   L.o_grad = take(c, st);
   L.o_theta_t = take(c, st);
@@ -557,6 +563,7 @@ smc_status smc_init(const smc_problem *prob, const smc_params *par, void *worksp
   D.ps = (PState *)(w + L.o_ps);
   D.xab = (float *)(w + L.o_xab);
   D.xbf = (uint4 *)(w + L.o_xbf);
+  D.xb3 = (uint4 *)(w + L.o_xb3);
   D.bf16 = par->precision == SMC_PRECISION_BF16 ? 1 : 0;
   D.status = (int *)(w + L.o_status);
   D.theta = (float *)(w + L.o_theta);

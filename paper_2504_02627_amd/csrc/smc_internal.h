@@ -75,6 +75,7 @@ struct Post {
   int ll_base;     // first work item of this posterior in the log-likelihood plan
   long long xab;     // float offset into the packed X tiles
   long long xbf;     // uint4 offset into the packed BF16 tiles
+  long long xb3;     // uint4 offset into the three-plane BF16 tiles of the energies
   long long uoff;    // offset of this posterior's block in caller (B*J) x d_b arrays
 };
 
@@ -112,6 +113,7 @@ struct Dev {                    // pointers carved from the workspace
   uint64_t seed;
   float *xab;                   // packed data tiles ([tile][lane][A | B | y])
   uint4 *xbf;                   // packed BF16 32-row tiles (BF16 trajectories)
+  uint4 *xb3;                   // X~ = hi + mid + lo in bfloat16, 32-row tiles (BF16 energies)
   int bf16;                     // trajectory gradients on BF16 MFMA
   int *status;                  // [0]: a label other than 0 / 1 met by the BF16 packing
   float *theta, *grad;          // current state, B*Jcap x DS
@@ -170,7 +172,8 @@ struct Dev {                    // pointers carved from the workspace
   float *fL;                    // L, row-major d x d
   float *fAf, *fAb, *fAi;       // packed base products: L P^T, P L^T, P L^-1
   double *fcov, *fLd, *fLi;     // weighted covariance [FCOV_CH][d][d] (partials over
-                                // particle chunks), Cholesky factor, inverse (FP64)
+                                // particle chunks); the shrunk covariance (factorised
+                                // in place for d > 128); L^-1 for d > 128 (FP64)
   float *fbase;                 // [0]: log|det L|
   float *fp;                    // FP32 parameters (flat)
   float *fpk, *fbk;             // packed weights (and transposes): FP32, bfloat16-rounded
@@ -183,7 +186,7 @@ struct Dev {                    // pointers carved from the workspace
 // Host copy of one posterior's packing sizes.
 struct HostPost {
   int N, d, C1, C2, NT, NT2, KC;
-  long long xab, xbf;
+  long long xab, xbf, xb3;
 };
 
 // Launchers (smc_kernels.hip).  All stream-ordered.
@@ -211,6 +214,9 @@ __host__ __device__ constexpr int bf16_lane_stride(int c2) { return (c2 + 2 * ((
 // of 20 slots, one beyond; a posterior's tiles are padded to whole stages
 // (the pad rows are zero and add nothing).
 __host__ __device__ constexpr int bf16_stage_tiles(int c2) { return bf16_lane_stride(c2) <= 20 ? 2 : 1; }
+// uint4 per lane and 32-row tile of the three-plane energy packing: the hi,
+// mid and lo planes of GEMM1's A operand (C2 slots each), odd lane stride
+__host__ __device__ constexpr int b3_lane_stride(int c2) { return (3 * c2) | 1; }
 hipError_t fill_f32(float *p, long long n, float v, hipStream_t st);
 hipError_t fill_i32(int *p, long long n, int v, hipStream_t st);
 hipError_t fill_f64(double *p, long long n, double v, hipStream_t st);

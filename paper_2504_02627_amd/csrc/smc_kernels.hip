@@ -214,6 +214,48 @@ __global__ void k_pack_bf16(const T *__restrict__ X, const float *__restrict__ y
   }
 }
 
+// Three-plane packing for the precision form's energies: X~ (label sign
+// folded, as above) written exactly as hi + mid + lo, each the bfloat16
+// rounding (nearest even) of what the previous parts leave (the remainders
+// are exact in FP32, and the last one has at most eight significant bits).
+// Layout per 32-row tile and lane l: slots [hi: C2 | mid: C2 | lo: C2] (+ a
+// zero slot, odd stride), slot c of a plane holding features 16c + 8h + e
+// (h = l / 32, e = 0..7) of row 32 T + l % 32: GEMM1's A operand.
+template <typename T>
+__global__ void k_pack_b3(const T *__restrict__ X, const float *__restrict__ y, int N, int d, int C2,
+                          int NT2, int LS, uint4 *__restrict__ xb3) {
+  const long long tot = (long long)NT2 * 64 * LS;
+  for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < tot;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const int slot = (int)(idx % LS);
+    const long long r = idx / LS;
+    const int lane = (int)(r % 64);
+    const int tl = (int)(r / 64);
+    const int h = lane >> 5, n = 32 * tl + (lane & 31);
+    uint32_t w[4] = {0, 0, 0, 0};
+    if (slot < 3 * C2) {
+      const int plane = slot / C2, c = slot % C2;
+      uint16_t v[8];
+      for (int e = 0; e < 8; ++e) {
+        const int k = 16 * c + 8 * h + e;
+        uint16_t u = 0;
+        if (n < N && k < d) {
+          float x = to_f32<T>(X[(long long)n * d + k]);
+          if (y[n] == 0.f) x = -x;                      // sign of the label (exact)
+          const uint16_t hi = bf16_rne(x);
+          const float r1 = x - __uint_as_float((uint32_t)hi << 16);
+          const uint16_t mid = bf16_rne(r1);
+          const float r2 = r1 - __uint_as_float((uint32_t)mid << 16);
+          u = plane == 0 ? hi : (plane == 1 ? mid : bf16_rne(r2));
+        }
+        v[e] = u;
+      }
+      for (int q = 0; q < 4; ++q) w[q] = (uint32_t)v[2 * q] | ((uint32_t)v[2 * q + 1] << 16);
+    }
+    xb3[idx] = make_uint4(w[0], w[1], w[2], w[3]);
+  }
+}
+
 hipError_t launch_pack_bf16(const Dev &D, const void *X, const float *y, int x_dtype,
                             const HostPost &P, hipStream_t st) {
   const int LS = bf16_lane_stride(P.C2);
@@ -226,6 +268,16 @@ hipError_t launch_pack_bf16(const Dev &D, const void *X, const float *y, int x_d
   else
     hipLaunchKernelGGL(k_pack_bf16<uint16_t>, dim3(grid), dim3(256), 0, st, (const uint16_t *)X, y,
                        P.N, P.d, P.C2, P.KC, P.NT2, LS, D.xbf + P.xbf, D.status);
+  const int LS3 = b3_lane_stride(P.C2);
+  const long long tot3 = (long long)P.NT2 * 64 * LS3;
+  int grid3 = (int)((tot3 + 255) / 256);
+  if (grid3 > 65535) grid3 = 65535;
+  if (x_dtype == 0)
+    hipLaunchKernelGGL(k_pack_b3<float>, dim3(grid3), dim3(256), 0, st, (const float *)X, y, P.N,
+                       P.d, P.C2, P.NT2, LS3, D.xb3 + P.xb3);
+  else
+    hipLaunchKernelGGL(k_pack_b3<uint16_t>, dim3(grid3), dim3(256), 0, st, (const uint16_t *)X, y,
+                       P.N, P.d, P.C2, P.NT2, LS3, D.xb3 + P.xb3);
   return hipGetLastError();
 }
 
@@ -1391,6 +1443,106 @@ __global__ __launch_bounds__(WG) void k_loglik(Dev D, int first) {
   }
 }
 
+// The same terms for the precision form, GEMM1 on v_mfma_f32_32x32x16_bf16:
+// X~ in its three exact bfloat16 planes (k_pack_b3) and theta' split the same
+// way in registers; of the nine plane products per K-step the six of order
+// 2^-16 of the full product or larger are taken (hi hi, hi mid, mid hi,
+// hi lo, mid mid, lo hi; mid lo, lo mid and lo lo are of order 2^-24 or
+// smaller, below the FP32 rounding of the sum), accumulated in FP32.  With the label sign folded into X~, every
+// row contributes -softplus(-z~).  Each wave takes 32 particles (a work
+// group the TJ particles of its tile); one 32-row tile per LDS stage, double
+// buffered by direct global-to-LDS loads.  Lane l, register v of the
+// accumulator holds row 8 (v/4) + 4 (l/32) + v%4 of particle l % 32; the two
+// lanes of a particle merge their Neumaier sums with TwoSum at the end.
+template <int C2>
+__global__ __launch_bounds__(B32_WG) void k_loglik_b3(Dev D, int first) {
+  constexpr int LS = b3_lane_stride(C2);
+  constexpr int TILE = 64 * LS;   // uint4 per 32-row tile
+  __shared__ uint4 xs[2][TILE];
+  const int4 it = D.ll_items[first + blockIdx.x];
+  const int b = it.x, tile = it.y, split = it.z;
+  const Post P = D.posts[b];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, h = lane >> 5;
+  const int S = P.ll_splits;
+  const int t0 = (int)((long long)split * P.NT2 / S);
+  const int t1 = (int)((long long)(split + 1) * P.NT2 / S);
+  const uint4 *xb = D.xb3 + P.xb3;
+  auto issue = [&](uint4 *buf, int t) {
+    const uint4 *src = xb + (long long)t * TILE + lane;
+#pragma unroll
+    for (int k = 0; k < (LS + B32_WAVES - 1) / B32_WAVES; ++k) {
+      const int m = wave + k * B32_WAVES;
+      if (m < LS)
+        __builtin_amdgcn_global_load_lds((const void *)(src + 64 * m), (lds_void *)(buf + 64 * m), 16,
+                                         0, 0);
+    }
+  };
+  if (t0 < t1) issue(xs[0], t0);
+  // theta' in three planes, B-operand layout: K-step c holds features
+  // 16c + 8h + e of particle slot 32 wave + l % 32
+  const long long base = (long long)(P.row0 + tile * TJ + wave * 32 + (lane & 31)) * D.DS;
+  v8bf th[3][C2];
+#pragma unroll
+  for (int c = 0; c < C2; ++c) {
+    const float4 a = *reinterpret_cast<const float4 *>(D.theta_t + base + 16 * c + 8 * h);
+    const float4 q = *reinterpret_cast<const float4 *>(D.theta_t + base + 16 * c + 8 * h + 4);
+    const float v[8] = {a.x, a.y, a.z, a.w, q.x, q.y, q.z, q.w};
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const uint16_t hi = bf16_rne(v[e]);
+      const float r1 = v[e] - __uint_as_float((uint32_t)hi << 16);
+      const uint16_t mid = bf16_rne(r1);
+      const float r2 = r1 - __uint_as_float((uint32_t)mid << 16);
+      th[0][c][e] = __builtin_bit_cast(__bf16, hi);
+      th[1][c][e] = __builtin_bit_cast(__bf16, mid);
+      th[2][c][e] = __builtin_bit_cast(__bf16, bf16_rne(r2));
+    }
+  }
+  Neu acc = Neu{0.f, 0.f};
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  int cur = 0;
+  for (int t = t0; t < t1; ++t) {
+    if (t + 1 < t1) issue(xs[cur ^ 1], t + 1);
+    const uint4 *xl = xs[cur] + lane * LS;
+    v16f z = {};
+#pragma unroll
+    for (int c = 0; c < C2; ++c) {
+      const v8bf ah = as_v8bf(xl[c]), am = as_v8bf(xl[C2 + c]), al = as_v8bf(xl[2 * C2 + c]);
+      z = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, th[0][c], z, 0, 0, 0);
+      z = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, th[1][c], z, 0, 0, 0);
+      z = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, th[0][c], z, 0, 0, 0);
+      z = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, th[2][c], z, 0, 0, 0);
+      z = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, th[1][c], z, 0, 0, 0);
+      z = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, th[0][c], z, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int n = 32 * t + 8 * (v >> 2) + 4 * h + (v & 3);
+      neu_add(acc, n < P.N ? -softplusf_hw(-z[v]) : 0.f);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    cur ^= 1;
+  }
+  // the two lanes of a particle (h = 0, 1), in a fixed order
+  Neu o;
+  o.s = __shfl_xor(acc.s, 32, 64);
+  o.c = __shfl_xor(acc.c, 32, 64);
+  const Neu m = h ? neu_merge(o, acc) : neu_merge(acc, o);
+  if (h == 0) {
+    const long long row = P.row0 + tile * TJ + wave * 32 + lane;
+    D.llpart[(long long)split * D.B * D.Jcap + row] = make_float2(m.s, m.c);
+  }
+}
+
+template <int C2>
+static hipError_t launch_ll_b3(const Dev &D, int first, int count, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_loglik_b3<C2>, dim3(count), dim3(B32_WG), 0, st, D, first);
+  return hipGetLastError();
+}
+
 template <int C2>
 static hipError_t launch_ll_c2(const Dev &D, int first, int count, hipStream_t st) {
   if (count <= 0) return hipSuccess;
@@ -1400,6 +1552,24 @@ static hipError_t launch_ll_c2(const Dev &D, int first, int count, hipStream_t s
 
 // items [first, first + count) all belong to posteriors with this C2
 hipError_t launch_loglik(const Dev &D, int c2, int first, int count, hipStream_t st) {
+  if (D.bf16) {  // the precision form: three-plane BF16 products
+    switch (c2) {
+      case 1: return launch_ll_b3<1>(D, first, count, st);
+      case 2: return launch_ll_b3<2>(D, first, count, st);
+      case 3: return launch_ll_b3<3>(D, first, count, st);
+      case 4: return launch_ll_b3<4>(D, first, count, st);
+      case 5: return launch_ll_b3<5>(D, first, count, st);
+      case 6: return launch_ll_b3<6>(D, first, count, st);
+      case 7: return launch_ll_b3<7>(D, first, count, st);
+      case 8: return launch_ll_b3<8>(D, first, count, st);
+      case 9: return launch_ll_b3<9>(D, first, count, st);
+      case 10: return launch_ll_b3<10>(D, first, count, st);
+      case 11: return launch_ll_b3<11>(D, first, count, st);
+      case 12: return launch_ll_b3<12>(D, first, count, st);
+      case 13: return launch_ll_b3<13>(D, first, count, st);
+    }
+    return hipErrorInvalidValue;
+  }
   switch (c2) {
     case 1: return launch_ll_c2<1>(D, first, count, st);
     case 2: return launch_ll_c2<2>(D, first, count, st);
@@ -2270,8 +2440,11 @@ hipError_t launch_chees(const Dev &D, hipStream_t st) {
 // squared deviations) over the same column chunks as the ChEES means.  The
 // mean lands in the first half of `means`, which the ChEES statistics
 // overwrite later in the step.
+constexpr int MASS_ROWS = 1024;  // row weights held in LDS per round
+
 __global__ __launch_bounds__(256) void k_mass_colsum(Dev D, int pass) {
   __shared__ double sh[4][64];
+  __shared__ double wr[MASS_ROWS];   // normalised weights of this round's rows
   const int b = blockIdx.y, ch = blockIdx.x;
   const int rl = threadIdx.x >> 6, cl = threadIdx.x & 63;
   const PState &S = D.ps[b];
@@ -2281,18 +2454,36 @@ __global__ __launch_bounds__(256) void k_mass_colsum(Dev D, int pass) {
   const double *mean = D.means + (long long)b * 2 * D.DS;
   const int rows_per = (D.J + D.col_chunks - 1) / D.col_chunks;
   const int r0 = ch * rows_per, r1 = min(D.J, r0 + rows_per);
-  for (int cg = 0; cg * 64 < D.DS; ++cg) {
-    const int c = cg * 64 + cl;
-    double acc = 0.0;
-    if (c < D.DS)
-      for (int r = r0 + rl; r < r1; r += 4) {
-        const long long row = (long long)b * D.Jcap + r;
-        const double lw = D.logw[row];
-        const double w = rs ? uni : ((lw == lw && lw > -INFINITY) ? exp(lw - m) * inv : 0.0);
-        const double x = (double)src[row * D.DS + c];
-        acc += pass == 0 ? w * x : w * ((x - mean[c]) * (x - mean[c]));
-      }
-    sh[rl][cl] = acc;
+  constexpr int MAXCG = (32 * ((MAX_C2 + 1) / 2) + 63) / 64;  // widest state row
+  double acc[MAXCG];
+#pragma unroll
+  for (int g = 0; g < MAXCG; ++g) acc[g] = 0.0;
+  // each row's weight once per block (one exponential per row, not per
+  // column), then every thread's rows in the same order as before
+  for (int rb = r0; rb < r1; rb += MASS_ROWS) {
+    const int re = min(r1, rb + MASS_ROWS);
+    __syncthreads();
+    for (int r = rb + (int)threadIdx.x; r < re; r += 256) {
+      const double lw = D.logw[(long long)b * D.Jcap + r];
+      wr[r - rb] = rs ? uni : ((lw == lw && lw > -INFINITY) ? exp(lw - m) * inv : 0.0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int g = 0; g < MAXCG; ++g) {
+      const int c = g * 64 + cl;
+      if (c < D.DS)
+        for (int r = rb + rl; r < re; r += 4) {
+          const long long row = (long long)b * D.Jcap + r;
+          const double w = wr[r - rb];
+          const double x = (double)src[row * D.DS + c];
+          acc[g] += pass == 0 ? w * x : w * ((x - mean[c]) * (x - mean[c]));
+        }
+    }
+  }
+#pragma unroll
+  for (int g = 0; g < MAXCG; ++g) {
+    const int c = g * 64 + cl;
+    sh[rl][cl] = acc[g];
     __syncthreads();
     if (rl == 0 && c < D.DS)
       D.colpart[((long long)b * D.col_chunks + ch) * 2 * D.DS + c] =
