@@ -1026,6 +1026,36 @@ __device__ __forceinline__ void b32_stage(const uint4 *__restrict__ xs, const v8
       g[f] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_v8bf(x1[C2 + 2 * f]), r0, g[f], 0, 0, 0);
       g[f] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_v8bf(x1[C2 + 2 * f + 1]), r1, g[f], 0, 0, 0);
     }
+    // issue order (scheduling groups: 0x008 MFMA, 0x002 VALU, 0x400
+    // transcendental, 0x100 LDS read): the first tile's residuals between
+    // the second tile's GEMM1 MFMAs, the second tile's between the first
+    // tile's GEMM2 MFMAs, so that a wave's VALU work runs while its own MFMAs
+    // execute; each phase reads the next phase's LDS operands
+    constexpr int RV = 40, RT = 32;  // VALU and transcendental ops per tile's residuals
+    constexpr int V1 = (RV + C2 - 1) / C2, T1 = (RT + C2 - 1) / C2;
+    constexpr int V2 = (RV + 2 * NF - 1) / (2 * NF), T2 = (RT + 2 * NF - 1) / (2 * NF);
+    constexpr int D1 = (2 * NF + C2 - 1) / C2;
+    __builtin_amdgcn_sched_group_barrier(0x100, C2, 0);
+#pragma unroll
+    for (int c = 0; c < C2; ++c) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+    }
+#pragma unroll
+    for (int c = 0; c < C2; ++c) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x100, D1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x002, V1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x400, T1, 0);
+    }
+#pragma unroll
+    for (int f = 0; f < 2 * NF; ++f) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x002, V2, 0);
+      __builtin_amdgcn_sched_group_barrier(0x400, T2, 0);
+    }
+    __builtin_amdgcn_sched_group_barrier(0x008, 2 * NF, 0);
   } else {
     v16f z = {};
 #pragma unroll
