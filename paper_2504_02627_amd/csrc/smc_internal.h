@@ -210,10 +210,14 @@ __host__ __device__ constexpr int lf_groups_per_cu(bool bf16, int c2) {
 // uint4 per lane and 32-row tile in the BF16 packing: [A1: C2 | A2: 2 ceil(C2/2)],
 // plus one zero slot when that is even
 __host__ __device__ constexpr int bf16_lane_stride(int c2) { return (c2 + 2 * ((c2 + 1) / 2)) | 1; }
-// 32-row data tiles per LDS stage of the BF16 kernel: two up to a lane stride
-// of 20 slots, one beyond; a posterior's tiles are padded to whole stages
-// (the pad rows are zero and add nothing).
-__host__ __device__ constexpr int bf16_stage_tiles(int c2) { return bf16_lane_stride(c2) <= 20 ? 2 : 1; }
+// 32-row data tiles per LDS stage of the BF16 kernel: two when the two stages
+// of the resident work groups fit the compute unit's 160 KB of LDS (up to 9
+// feature tiles at two groups per compute unit, 11-13 at one), one otherwise
+// (10); a posterior's tiles are padded to whole stages (the pad rows are zero
+// and add nothing).
+__host__ __device__ constexpr int bf16_stage_tiles(int c2) {
+  return 2 * 2 * 64 * bf16_lane_stride(c2) * 16 * lf_groups_per_cu(true, c2) <= 160 * 1024 ? 2 : 1;
+}
 // uint4 per lane and 32-row tile of the three-plane energy packing: the hi,
 // mid and lo planes of GEMM1's A operand (C2 slots each), odd lane stride
 __host__ __device__ constexpr int b3_lane_stride(int c2) { return (3 * c2) | 1; }

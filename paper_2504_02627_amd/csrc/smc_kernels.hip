@@ -951,8 +951,9 @@ hipError_t launch_traj(const Dev &D, int c2, hipStream_t st) {
 // named LDS buffers by direct global-to-LDS loads (global_load_lds_dwordx4);
 // because the buffers are distinct objects, the compiler need not wait for
 // the next stage's loads before reading the current buffer, and the
-// prefetch holds no registers.  Two tiles per stage up to a lane stride of 20
-// slots (four KB each), one beyond.
+// prefetch holds no registers.  Two tiles per stage wherever both stages of
+// the resident work groups fit the LDS (every width but 10 feature tiles),
+// one otherwise.
 // The drift, the partials and the reduction are those of the FP32 kernel.
 // Exactness of the weights does not depend on the gradient's precision: the
 // leapfrog map with any position-only force field is volume preserving and
