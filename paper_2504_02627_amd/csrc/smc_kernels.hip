@@ -1106,18 +1106,29 @@ __device__ __forceinline__ void lf_unit_b32(const Dev &D, const Plan &pl, int s,
   // path the previous reduction has formed it (the same arithmetic)
   const int slot = wave * 32 + (lane & 31);
   const long long rowp = P.row0 + perm[pl.tile * TJ + slot];
+  // the branch sits outside the K-step loops, so that all of a path's loads
+  // are issued before the first conversion waits for them
   v8bf thb[C2];
+  const float *trow = D.theta_n + rowp * D.DS + 8 * h;
+  if (given) {
+    float4 raw[C2][2];
 #pragma unroll
-  for (int c = 0; c < C2; ++c) {
-    const long long base = rowp * D.DS + 16 * c + 8 * h;
-    const int kb = 16 * c + 8 * h;
-    if (given) {
-      const float4 a = *reinterpret_cast<const float4 *>(D.theta_n + base);
-      const float4 b = *reinterpret_cast<const float4 *>(D.theta_n + base + 4);
-      const float v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+    for (int c = 0; c < C2; ++c) {
+      raw[c][0] = *reinterpret_cast<const float4 *>(trow + 16 * c);
+      raw[c][1] = *reinterpret_cast<const float4 *>(trow + 16 * c + 4);
+    }
+#pragma unroll
+    for (int c = 0; c < C2; ++c) {
+      const float v[8] = {raw[c][0].x, raw[c][0].y, raw[c][0].z, raw[c][0].w,
+                          raw[c][1].x, raw[c][1].y, raw[c][1].z, raw[c][1].w};
 #pragma unroll
       for (int e = 0; e < 8; ++e) thb[c][e] = (__bf16)v[e];
-    } else {
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < C2; ++c) {
+      const long long base = rowp * D.DS + 16 * c + 8 * h;
+      const int kb = 16 * c + 8 * h;
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const float t0v = D.theta_t[base + e], p0 = D.p_t[base + e], g0 = D.grad_t[base + e];
