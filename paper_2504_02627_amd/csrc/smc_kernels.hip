@@ -992,6 +992,13 @@ __device__ __forceinline__ void b32_issue(uint4 *__restrict__ buf, const uint4 *
 
 // R = sigmoid(-z~) = 1 / (1 + 2^(z~ log2 e)), hardware exp2 and reciprocal,
 // rounded to bfloat16 (nearest even) as GEMM2's two B-operand K-steps.
+// One K-step half of the residuals (values 8 H .. 8 H + 7 of the tile's 16).
+template <int H>
+__device__ __forceinline__ void b32_residual_half(const v16f &z, v8bf &r) {
+#pragma unroll
+  for (int v = 0; v < 8; ++v)
+    r[v] = (__bf16)__builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(z[8 * H + v] * 1.4426950408889634f));
+}
 __device__ __forceinline__ void b32_residual(const v16f &z, v8bf &r0, v8bf &r1) {
 #pragma unroll
   for (int v = 0; v < 8; ++v) {
@@ -1014,28 +1021,37 @@ __device__ __forceinline__ void b32_stage(const uint4 *__restrict__ xs, const v8
     for (int c = 0; c < C2; ++c) z0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_v8bf(x0[c]), thb[c], z0, 0, 0, 0);
 #pragma unroll
     for (int c = 0; c < C2; ++c) z1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_v8bf(x1[c]), thb[c], z1, 0, 0, 0);
-    v8bf r0, r1;
-    b32_residual(z0, r0, r1);
+    // each g[f] takes tile a's K-steps 0 and 1, then tile b's, as in the
+    // one-tile stage; the first K-steps of all f go before the second ones,
+    // so that each residual half is due only when its K-step starts
+    v8bf ra0, ra1, rb0, rb1;
+    b32_residual_half<0>(z0, ra0);
+    b32_residual_half<1>(z0, ra1);
 #pragma unroll
-    for (int f = 0; f < NF; ++f) {
-      g[f] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_v8bf(x0[C2 + 2 * f]), r0, g[f], 0, 0, 0);
-      g[f] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_v8bf(x0[C2 + 2 * f + 1]), r1, g[f], 0, 0, 0);
-    }
-    b32_residual(z1, r0, r1);
+    for (int f = 0; f < NF; ++f)
+      g[f] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_v8bf(x0[C2 + 2 * f]), ra0, g[f], 0, 0, 0);
 #pragma unroll
-    for (int f = 0; f < NF; ++f) {
-      g[f] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_v8bf(x1[C2 + 2 * f]), r0, g[f], 0, 0, 0);
-      g[f] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_v8bf(x1[C2 + 2 * f + 1]), r1, g[f], 0, 0, 0);
-    }
+    for (int f = 0; f < NF; ++f)
+      g[f] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_v8bf(x0[C2 + 2 * f + 1]), ra1, g[f], 0, 0, 0);
+    b32_residual_half<0>(z1, rb0);
+    b32_residual_half<1>(z1, rb1);
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+      g[f] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_v8bf(x1[C2 + 2 * f]), rb0, g[f], 0, 0, 0);
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+      g[f] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_v8bf(x1[C2 + 2 * f + 1]), rb1, g[f], 0, 0, 0);
     // issue order (scheduling groups: 0x008 MFMA, 0x002 VALU, 0x400
-    // transcendental, 0x100 LDS read): the first tile's residuals between
-    // the second tile's GEMM1 MFMAs, the second tile's between the first
-    // tile's GEMM2 MFMAs, so that a wave's VALU work runs while its own MFMAs
-    // execute; each phase reads the next phase's LDS operands
-    constexpr int RV = 40, RT = 32;  // VALU and transcendental ops per tile's residuals
-    constexpr int V1 = (RV + C2 - 1) / C2, T1 = (RT + C2 - 1) / C2;
-    constexpr int V2 = (RV + 2 * NF - 1) / (2 * NF), T2 = (RT + 2 * NF - 1) / (2 * NF);
-    constexpr int D1 = (2 * NF + C2 - 1) / C2;
+    // transcendental, 0x100 LDS read): tile a's GEMM1 (reading tile b's GEMM1
+    // operands), tile b's GEMM1 beside the first half of tile a's residuals,
+    // then the GEMM2 K-steps of a (0, 1) and b (0) each beside the next
+    // residual half (a: second; b: first, second), then b's K-step 1; a wave's
+    // VALU work runs while its own MFMAs execute, and each phase reads the
+    // next phase's LDS operands
+    constexpr int HV = 20, HT = 16;  // VALU and transcendental ops per residual half
+    constexpr int V1 = (HV + C2 - 1) / C2, T1 = (HT + C2 - 1) / C2;
+    constexpr int V2 = (HV + NF - 1) / NF, T2 = (HT + NF - 1) / NF;
+    constexpr int D1 = (2 * NF + C2 - 1) / C2, D2 = 2;
     __builtin_amdgcn_sched_group_barrier(0x100, C2, 0);
 #pragma unroll
     for (int c = 0; c < C2; ++c) {
@@ -1050,13 +1066,13 @@ __device__ __forceinline__ void b32_stage(const uint4 *__restrict__ xs, const v8
       __builtin_amdgcn_sched_group_barrier(0x400, T1, 0);
     }
 #pragma unroll
-    for (int f = 0; f < 2 * NF; ++f) {
+    for (int f = 0; f < 3 * NF; ++f) {
       __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x100, D2, 0);
       __builtin_amdgcn_sched_group_barrier(0x002, V2, 0);
       __builtin_amdgcn_sched_group_barrier(0x400, T2, 0);
     }
-    __builtin_amdgcn_sched_group_barrier(0x008, 2 * NF, 0);
+    __builtin_amdgcn_sched_group_barrier(0x008, NF, 0);
   } else {
     v16f z = {};
 #pragma unroll
@@ -1235,9 +1251,10 @@ __global__ __launch_bounds__(RED_THREADS) void k_lf_reduce(Dev D, int s, int zer
   __shared__ float4 part[RED_GROUPS - 1][RED_SLOTS];
   const int tj = TJ, ntile = D.Jcap / tj;
   const int b = blockIdx.x / ntile, tile = blockIdx.x % ntile;
+  // both records in one round trip (every work group reads both anyway)
   const Post P = D.posts[b];
-  if (c2only && P.C2 != c2only) return;  // another group's posterior (uniform)
   const int4 q = D.lf_post[(long long)s * D.B + b];
+  if (c2only && P.C2 != c2only) return;  // another group's posterior (uniform)
   if (tile >= q.w) return;                // inactive tile (uniform)
   const int dq = 4 * P.C2;  // float4 per particle row
   const int sl = threadIdx.x % RED_SLOTS, grp = threadIdx.x / RED_SLOTS;
