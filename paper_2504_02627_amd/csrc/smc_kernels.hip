@@ -991,14 +991,15 @@ __device__ __forceinline__ void b32_issue(uint4 *__restrict__ buf, const uint4 *
 }
 
 // R = sigmoid(-z~) = 1 / (1 + 2^(z~ log2 e)), hardware exp2 and reciprocal,
-// rounded to bfloat16 (nearest even) as GEMM2's two B-operand K-steps.
-// One K-step half of the residuals (values 8 H .. 8 H + 7 of the tile's 16).
+// rounded to bfloat16 (nearest even) as GEMM2's B operand: half H holds the
+// lane's values 8 H .. 8 H + 7 (GEMM2's K-step H).
 template <int H>
 __device__ __forceinline__ void b32_residual_half(const v16f &z, v8bf &r) {
 #pragma unroll
   for (int v = 0; v < 8; ++v)
     r[v] = (__bf16)__builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(z[8 * H + v] * 1.4426950408889634f));
 }
+// Both halves together (the single-tile stage).
 __device__ __forceinline__ void b32_residual(const v16f &z, v8bf &r0, v8bf &r1) {
 #pragma unroll
   for (int v = 0; v < 8; ++v) {
