@@ -1252,10 +1252,9 @@ __global__ __launch_bounds__(RED_THREADS) void k_lf_reduce(Dev D, int s, int zer
   __shared__ float4 part[RED_GROUPS - 1][RED_SLOTS];
   const int tj = TJ, ntile = D.Jcap / tj;
   const int b = blockIdx.x / ntile, tile = blockIdx.x % ntile;
-  // both records in one round trip (every work group reads both anyway)
   const Post P = D.posts[b];
-  const int4 q = D.lf_post[(long long)s * D.B + b];
   if (c2only && P.C2 != c2only) return;  // another group's posterior (uniform)
+  const int4 q = D.lf_post[(long long)s * D.B + b];
   if (tile >= q.w) return;                // inactive tile (uniform)
   const int dq = 4 * P.C2;  // float4 per particle row
   const int sl = threadIdx.x % RED_SLOTS, grp = threadIdx.x / RED_SLOTS;
