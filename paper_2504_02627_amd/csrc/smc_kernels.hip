@@ -1560,10 +1560,8 @@ __global__ __launch_bounds__(B32_WG) void k_loglik_b3(Dev D, int first) {
   Neu acc = Neu{0.f, 0.f};
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  int cur = 0;
-  for (int t = t0; t < t1; ++t) {
-    if (t + 1 < t1) issue(xs[cur ^ 1], t + 1);
-    const uint4 *xl = xs[cur] + lane * LS;
+  // Z~ of one staged tile: the six plane products per K-step
+  auto gemm = [&](const uint4 *xl) {
     v16f z = {};
 #pragma unroll
     for (int c = 0; c < C2; ++c) {
@@ -1575,14 +1573,38 @@ __global__ __launch_bounds__(B32_WG) void k_loglik_b3(Dev D, int first) {
       z = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, th[1][c], z, 0, 0, 0);
       z = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, th[0][c], z, 0, 0, 0);
     }
+    return z;
+  };
+  // the rows of tile t into the compensated sum, in row order; a pad row
+  // (z~ = 0, a finite term) adds a zero, written as a product so that the
+  // term is computed without a branch
+  auto rows = [&](const v16f &z, int t) {
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const int n = 32 * t + 8 * (v >> 2) + 4 * h + (v & 3);
-      neu_add(acc, n < P.N ? -softplusf_hw(-z[v]) : 0.f);
+      neu_add(acc, -softplusf_hw(-z[v]) * (n < P.N ? 1.f : 0.f));
     }
+  };
+  // software pipeline: tile t's products beside tile t - 1's softplus terms
+  // (independent work, so a wave's VALU runs while its MFMAs execute); the
+  // terms enter the sum in the same order as tile by tile
+  if (t0 < t1) {
+    int cur = 0;
+    if (t0 + 1 < t1) issue(xs[1], t0 + 1);
+    v16f zp = gemm(xs[0] + lane * LS);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    cur ^= 1;
+    cur = 1;
+    for (int t = t0 + 1; t < t1; ++t) {
+      if (t + 1 < t1) issue(xs[cur ^ 1], t + 1);
+      const v16f z = gemm(xs[cur] + lane * LS);
+      rows(zp, t - 1);
+      zp = z;
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      cur ^= 1;
+    }
+    rows(zp, t1 - 1);
   }
   // the two lanes of a particle (h = 0, 1), in a fixed order
   Neu o;
