@@ -119,7 +119,8 @@ struct Dev {                    // pointers carved from the workspace
   float *theta, *grad;          // current state, B*Jcap x DS
   float *theta_t, *p_t, *grad_t;// trajectory buffers
   float *theta_n;               // theta' of the next leapfrog step, written by the split
-                                // reduction (valid for the particles it finished)
+                                // reduction (valid for the particles it finished);
+                                // bfloat16, B*Jcap x DS, in the precision form
   double *logpi, *logpi_t, *logw;
   double *h, *l, *H0, *dH, *alpha, *ca, *cg;
   int *n, *perm, *active, *anc, *accepted;

@@ -1126,21 +1126,12 @@ __device__ __forceinline__ void lf_unit_b32(const Dev &D, const Plan &pl, int s,
   // the branch sits outside the K-step loops, so that all of a path's loads
   // are issued before the first conversion waits for them
   v8bf thb[C2];
-  const float *trow = D.theta_n + rowp * D.DS + 8 * h;
   if (given) {
-    float4 raw[C2][2];
+    // bfloat16 theta' from the reduction, 8 features (16 bytes) per K-step
+    const uint4 *trow =
+        reinterpret_cast<const uint4 *>(reinterpret_cast<const uint16_t *>(D.theta_n) + rowp * D.DS + 8 * h);
 #pragma unroll
-    for (int c = 0; c < C2; ++c) {
-      raw[c][0] = *reinterpret_cast<const float4 *>(trow + 16 * c);
-      raw[c][1] = *reinterpret_cast<const float4 *>(trow + 16 * c + 4);
-    }
-#pragma unroll
-    for (int c = 0; c < C2; ++c) {
-      const float v[8] = {raw[c][0].x, raw[c][0].y, raw[c][0].z, raw[c][0].w,
-                          raw[c][1].x, raw[c][1].y, raw[c][1].z, raw[c][1].w};
-#pragma unroll
-      for (int e = 0; e < 8; ++e) thb[c][e] = (__bf16)v[e];
-    }
+    for (int c = 0; c < C2; ++c) thb[c] = as_v8bf(trow[2 * c]);
   } else {
 #pragma unroll
     for (int c = 0; c < C2; ++c) {
@@ -1344,7 +1335,16 @@ __global__ __launch_bounds__(RED_THREADS) void k_lf_reduce(Dev D, int s, int zer
 #define LF_NEXT(c) tn.c = fmaf(eps * mv.c, fmaf(he, gn.c, pn.c), th1.c);
     LF_NEXT(x) LF_NEXT(y) LF_NEXT(z) LF_NEXT(w)
 #undef LF_NEXT
-    reinterpret_cast<float4 *>(D.theta_n)[e] = tn;
+    if (D.bf16) {
+      // the precision form's leapfrog reads theta' as its bfloat16 operand:
+      // rounded here (nearest even, the conversion the kernel would apply),
+      // half the bytes for every split item that reads it
+      typedef __bf16 v4bf __attribute__((ext_vector_type(4)));
+      const v4bf tb = {(__bf16)tn.x, (__bf16)tn.y, (__bf16)tn.z, (__bf16)tn.w};
+      reinterpret_cast<uint2 *>(D.theta_n)[e] = __builtin_bit_cast(uint2, tb);
+    } else {
+      reinterpret_cast<float4 *>(D.theta_n)[e] = tn;
+    }
   }
 }
 
