@@ -1205,7 +1205,8 @@ __global__ __launch_bounds__(B32_WG, (b32_groups<C2, FIN>())) void k_lf_partial_
   const Plan pl = spl;
   if (pl.b < 0) return;
   v16f g[NF];
-  lf_unit_b32<C2>(D, pl, s, zero_eps, !FIN && s > 0 && !zero_eps, bufA, bufB, g);
+  // theta' in bfloat16 from the set-up (first step) or the split reduction
+  lf_unit_b32<C2>(D, pl, s, zero_eps, !FIN && !zero_eps, bufA, bufB, g);
 
   // register v of tile f: feature 32f + 16(v>>3) + 8h + (v&7)
   if constexpr (FIN) {
@@ -2090,6 +2091,13 @@ __global__ __launch_bounds__(256) void k_setup(Dev D, const float *__restrict__ 
   // momenta: lane q covers columns 4q .. 4q+3 (one Philox block); the kinetic
   // energy is accumulated from the values written
   double kin = 0.0;
+  // precision form: theta' of the first leapfrog step in bfloat16, as the
+  // split reduction forms it for the later steps (the same FP32 arithmetic
+  // as the leapfrog prologue); read from the array not written here
+  const bool first_theta = D.bf16 && !D.flow && !D.traj && !D.target;
+  const float eps1 = (float)S.eps, he1 = 0.5f * eps1;
+  const float *t_src = resampled ? D.theta_t : D.theta;
+  const float *g_src = resampled ? D.grad_t : D.grad;
   for (int q = lane; q * 4 < D.DS; q += LPR) {
     double xi[4] = {0, 0, 0, 0};
     if (4 * q < P.d) {
@@ -2109,6 +2117,10 @@ __global__ __launch_bounds__(256) void k_setup(Dev D, const float *__restrict__ 
         kin += (double)mv[c] * (double)pv * (double)pv;
       }
       D.p_t[o + c] = pv;
+      if (first_theta) {
+        const float tn = fmaf(eps1 * mv[c], fmaf(he1, g_src[o + c], pv), t_src[o + c]);
+        reinterpret_cast<__bf16 *>(D.theta_n)[o + c] = (__bf16)tn;
+      }
     }
   }
   const double K0 = 0.5 * seg_sum<LPR>(kin);
