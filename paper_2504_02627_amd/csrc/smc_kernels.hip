@@ -1119,8 +1119,10 @@ __device__ __forceinline__ void lf_unit_b32(const Dev &D, const Plan &pl, int s,
     b32_issue<C2>(bufA, xbf, s0 * TL::STT, wave, lane);
 
   // theta' (bfloat16, B operand of GEMM1): K-step c holds features 16c + 8h + e
-  // of particle slot 32 wave + lane % 32; after the first step of the split
-  // path the previous reduction has formed it (the same arithmetic)
+  // of particle slot 32 wave + lane % 32; on the split path the set-up (first
+  // step) or the previous reduction (later steps) has formed it with the
+  // arithmetic of the other branch, which the one-split and gradient-only
+  // launches use
   const int slot = wave * 32 + (lane & 31);
   const long long rowp = P.row0 + perm[pl.tile * TJ + slot];
   // the branch sits outside the K-step loops, so that all of a path's loads
